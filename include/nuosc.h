@@ -1,0 +1,180 @@
+/*
+ * nuosc -- bulb-model neutrino flavor evolution on MI355X (gfx950).
+ *
+ * C ABI of the library libnuosc.so.  No C++ types cross this boundary and no
+ * exception escapes it.  Every call returns a nuosc_status; the message of the
+ * last failure on a handle is available from nuosc_last_error().
+ *
+ * The problem is the one stated in Noormofidi, arXiv 1907.05560:
+ *   - flavor wavefunction of n = 2 or 3 complex amplitudes per beam (eq 3.1),
+ *     evolved by the Schrodinger equation i dpsi/dl = (H0 + Hm + Hnunu) psi
+ *     (eq 3.2, eq 3.4 for the two-flavor form and the antineutrino map);
+ *   - bulb geometry: along the trajectory emitted at cos(theta_0) = u the
+ *     propagation cosine at radius r is c(r) = sqrt(1 - (R/r)^2 (1 - u^2))
+ *     (eq 3.14) and dl = dr / c (eq 3.3);
+ *   - neutrino self-interaction of the multi-angle bulb model (eq 3.8, 3.13,
+ *     3.15) or of the single-angle model (eq 3.16-3.17);
+ *   - Fermi-Dirac spectra (eq 4.1-4.2), vacuum term Delta = dm2 / 2E (eq 3.5-
+ *     3.6), matter potential (eq 3.7) given as lambda(r) = lambda0 (rref/r)^p;
+ *   - adaptive radial stepping with a global maximum error (Section 4.2.3) or
+ *     a fixed step.
+ *
+ * Beams.  A beam is (species s, trajectory j, energy bin k) with s = 0 for
+ * neutrinos born as nu_e and s = 1 for antineutrinos born as nubar_e; nu_x
+ * and nubar_x enter through the spectral weights.  The beam index is
+ *     b = (s * NA + j) * NE + k,      NA = max(n_angle, 1),
+ * and the number of beams is NB = 2 * NE * NA.  Energy bins sit at the
+ * midpoints of [e_min, e_max]; emission-angle bins at the midpoints of
+ * cos(theta_0) in (0, 1].
+ *
+ * Frame.  Amplitudes are held in the frame co-rotating with the flavor-
+ * diagonal part of the matter and self-interaction Hamiltonian of each
+ * trajectory: psi = exp(-i sigma Phi_j) psi~ with sigma = +1 (nu), -1 (nubar)
+ * and an FP64 phase Phi_j (n components) per trajectory.  Probabilities
+ * |psi_a|^2 are the same in both frames.  NUOSC_FRAME_LAB keeps Phi = 0.
+ *
+ * Host state layout (nuosc_get_state / nuosc_set_state), always FP64:
+ *     psi[a][2][NB]   component a, then re/im, then beam b;
+ *     phase[NA][n]    co-rotating phase of trajectory j, component a.
+ *
+ * Units: r in km, Hamiltonians in km^-1, energies in MeV, dm2 in eV^2.
+ *
+ * Threading.  A handle is not thread-safe.  Distinct handles on distinct
+ * streams are independent.  All work of a handle is ordered on its stream.
+ */
+#ifndef NUOSC_H
+#define NUOSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NUOSC_OK = 0,
+    NUOSC_E_INVALID = -1,       /* invalid argument or parameter set */
+    NUOSC_E_NOMEM = -2,         /* device or host allocation failed */
+    NUOSC_E_DEVICE = -3,        /* a HIP runtime call failed */
+    NUOSC_E_NONFINITE = -4,     /* the step error became NaN or infinite */
+    NUOSC_E_STEP_UNDERFLOW = -5,/* adaptive step fell below 1e-14 r */
+    NUOSC_E_LIMIT = -6,         /* max_steps or max_wall_s reached */
+    NUOSC_E_BUSY = -7           /* batch has no free slot or memory */
+} nuosc_status;
+
+enum { NUOSC_RK4_FIXED = 0, NUOSC_RK_DP54 = 1 };
+enum { NUOSC_FP64 = 0, NUOSC_FP32_AMP = 1 };
+enum { NUOSC_FRAME_COROTATING = 0, NUOSC_FRAME_LAB = 1 };
+
+/* Parameters of one run.  Field names follow the configuration keywords of the
+ * paper's Appendix A.3 (given in brackets). */
+typedef struct nuosc_params {
+    int32_t n_flavors;             /* [Flvs] 2 or 3 */
+    int32_t n_energy;              /* [Ebins] >= 1 */
+    double  e_min_mev, e_max_mev;  /* [E0] [E1] energy range, 0 <= e_min < e_max */
+    int32_t n_angle;               /* [Abins] emission angles; 0 => single-angle model */
+    double  lum_erg_s[4];          /* [Lve Lv_e Lvt Lv_t] nu_e, nubar_e, nu_x, nubar_x */
+    double  mean_e_mev[4];         /* mean energies <E> of the same four species */
+    double  eta[4];                /* [eta_ve ...] degeneracy parameters */
+    double  dm2_ev2, theta;        /* [dm2] [theta] two flavors; dm2 < 0 = inverted */
+    double  dm2_21_ev2, dm2_31_ev2;/* three flavors (PDG); dm2_31 < 0 = inverted */
+    double  theta12, theta13, theta23, delta_cp;
+    double  lambda0_km;            /* matter potential lambda(r) = lambda0 (rref/r)^p */
+    double  lambda_rref_km;
+    double  lambda_power;
+    double  mu0_km;                /* self-interaction strength at the neutrinosphere */
+    double  r_nu_km;               /* [Rv] neutrinosphere radius R */
+    double  r_start_km, r_end_km;  /* [R0] [Rn], R <= r_start < r_end */
+    int32_t integrator;            /* NUOSC_RK4_FIXED or NUOSC_RK_DP54 */
+    int64_t n_fixed_steps;         /* RK4: equal steps from r_start to r_end */
+    double  rtol;                  /* [eps0] DP54: max-norm error tolerance */
+    double  dr_init_km;            /* [dr] first adaptive step */
+    double  dr_max_km;             /* [max_dr] step cap */
+    double  safety;                /* [ksi] controller safety factor in (0, 1] */
+    int64_t max_steps;             /* [Ts] attempted-step limit, 0 = none */
+    double  max_wall_s;            /* [Tn] wall-clock limit of one evolve call, 0 = none */
+    int32_t precision;             /* NUOSC_FP64 or NUOSC_FP32_AMP */
+    int32_t frame;                 /* NUOSC_FRAME_COROTATING (default) or NUOSC_FRAME_LAB */
+} nuosc_params;
+
+typedef struct nuosc_handle nuosc_handle;
+
+/* Fill *p with the two-flavor single-angle defaults (1e51 erg/s, <E> 11/16/25
+ * MeV, eta 0, dm2 -2.4e-3 eV^2, theta 0.1, lambda0 1e4 km^-1 (10 km/r)^3,
+ * mu0 1e5 km^-1, R 10 km, 10 -> 250 km, RK4 with 1e4 steps, FP64). */
+void nuosc_default_params(nuosc_params* p);
+
+/* Device bytes nuosc_create needs for these parameters (state buffers,
+ * tables, reduction scratch).  Returns 0 for an invalid parameter set. */
+size_t nuosc_footprint_bytes(const nuosc_params* p);
+
+/* Create a run in its initial state (every beam in its birth flavor at
+ * r_start, phases zero).
+ *   hip_stream        hipStream_t to order all work on, borrowed; NULL =>
+ *                     the library creates and owns a stream.
+ *   device_workspace  optional device memory of at least
+ *                     nuosc_footprint_bytes(p) bytes owned by the caller and
+ *                     kept alive until nuosc_destroy; NULL => the library
+ *                     allocates and owns its buffers.
+ * On failure *out is NULL and nothing is leaked. */
+nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream,
+                          void* device_workspace, size_t workspace_bytes,
+                          nuosc_handle** out);
+
+/* Make n_attempts step attempts (accepted or rejected; RK4 steps are always
+ * accepted).  Attempts after the run reached r_end do nothing.  *n_accepted
+ * (nullable) receives the number accepted by this call.  Returns
+ * NUOSC_E_NONFINITE / NUOSC_E_STEP_UNDERFLOW when the run stopped on that
+ * condition (state left at the last accepted step) and NUOSC_E_LIMIT when
+ * max_steps was reached.  Synchronises the stream before returning. */
+nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted);
+
+/* Queue n_attempts step attempts on the stream without waiting and without
+ * reading back any status (for timing loops and graph replay).  The status
+ * is picked up by the next nuosc_step / nuosc_stats call. */
+nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts);
+
+/* Evolve until r = min(r_target, r_end) (the last step is clipped to land on
+ * it), or until max_steps / max_wall_s is reached (NUOSC_E_LIMIT). */
+nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km);
+
+/* Angle moments of the current state at the current radius:
+ *   J0 = sum_j w_j S_j,  J1 = sum_j w_j c_j S_j  (multi-angle, eq 3.13-3.15)
+ *   J0 = D(r/R) S_0,     J1 = 0                  (single angle, eq 3.16-3.17)
+ * with S_j = sum_k [g_k rho(nu) - gbar_k conj(rho(nubar))], rho = 2 psi psi^+
+ * in the lab frame.  j0, j1: n*n complex each, row-major, interleaved re/im
+ * (host memory, written).  r_km (nullable) receives the radius. */
+nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km);
+
+/* Survival probabilities P_b = |psi_b,1|^2 of every beam (host, NB doubles). */
+nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out);
+
+/* Checkpoint: copy the state to / from host buffers laid out as described
+ * above (psi: n*2*NB doubles, phase: NA*n doubles).  set_state also sets the
+ * radius and the next adaptive step, resets the step counters and recomputes
+ * the moments of the new state.  In FP32_AMP runs the amplitudes are stored
+ * in FP32 (set_state rounds them). */
+nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase);
+nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* phase,
+                             double r_km, double dr_km);
+
+/* Step statistics (each pointer nullable). */
+nuosc_status nuosc_stats(nuosc_handle* h, int64_t* accepted, int64_t* rejected,
+                         double* r_km, double* dr_km);
+
+/* Number of beams NB and trajectories NA of the run. */
+int64_t nuosc_num_beams(const nuosc_handle* h);
+int32_t nuosc_num_traj(const nuosc_handle* h);
+
+/* Message of the last failure on h (or of the last failed create when h is
+ * NULL); valid until the next call on the same handle. */
+const char* nuosc_last_error(const nuosc_handle* h);
+
+/* Release the handle and everything it owns.  NULL-safe. */
+void nuosc_destroy(nuosc_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

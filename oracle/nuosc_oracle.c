@@ -1,0 +1,669 @@
+/*
+ * Oracle for the bulb-model neutrino flavor evolution -- TEST INFRASTRUCTURE.
+ *
+ * Plain FP64 C written from the paper (Noormofidi, "Simulating Nonlinear
+ * Neutrino Oscillations on Next-Generation Many-Core Architectures", arXiv
+ * 1907.05560).  Only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  No blocking, fusion or reordering beyond what the
+ * equations state; every sum runs in one fixed, documented order:
+ *   - per-trajectory sums over energy ascending, all neutrinos first, then all
+ *     antineutrinos;
+ *   - angle moments over trajectories ascending, J0 and J1 in the same loop.
+ * Build with -O2 -fno-fast-math -ffp-contract=off.
+ *
+ * Readings of the paper that this file takes (each is also stated where used):
+ *   A  emission-angle bins at midpoints u_j = (j + 1/2)/N_A of cos(theta_0).
+ *   B  Fermi-Dirac denominator exp(E/T - eta) + 1 (eq 4.1 is garbled).
+ *   C  spectra normalised on (0, inf); beam weights divided by the fixed
+ *      reference number luminosity 1e51 erg/s / 11 MeV.
+ *   D  three flavors: PDG mixing matrix, matter term diag(lambda, 0, 0),
+ *      antineutrinos use the complex conjugate vacuum Hamiltonian.
+ *   E  every Hamiltonian is made traceless.
+ *   F  density matrix rho = 2 psi psi^dagger (eq 3.9 up to its trace part).
+ *   G  the coupling mu0 absorbs the prefactor eq 3.8 omits; the single-angle
+ *      model multiplies it by D(r/R) (eq 3.16-3.17).
+ *   H  evolution in the frame co-rotating with the flavor-diagonal part of
+ *      the matter and self-interaction terms (see rhs()).
+ *   I  embedded pair: Dormand-Prince 5(4), FSAL, advancing the 5th-order
+ *      solution.
+ *   J  step control: safety 0.9, growth factor in [0.2, 5], no growth right
+ *      after a rejection, step capped at dr_max, last step clipped to r_end.
+ *   K  step error: max over beams, components and re/im parts of
+ *      |h sum_i e_i k_i| / rtol; the co-rotating phases are excluded.
+ *   N  only nu_e-born and nubar_e-born beams are evolved; the nu_x flavors
+ *      enter through the weights (unitarity of the flavor basis).
+ */
+#include "nuosc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- complex */
+typedef struct { double re, im; } cplx;
+
+static cplx c_make(double re, double im) { cplx z; z.re = re; z.im = im; return z; }
+static cplx c_add(cplx a, cplx b) { return c_make(a.re + b.re, a.im + b.im); }
+static cplx c_sub(cplx a, cplx b) { return c_make(a.re - b.re, a.im - b.im); }
+static cplx c_mul(cplx a, cplx b) { return c_make(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+static cplx c_conj(cplx a) { return c_make(a.re, -a.im); }
+static cplx c_scale(cplx a, double s) { return c_make(a.re * s, a.im * s); }
+static cplx c_expi(double phi) { return c_make(cos(phi), sin(phi)); }
+
+/* ---------------------------------------------------------------- constants */
+/* hbar*c = 197.3269804 MeV fm (CODATA 2018) = 1.973269804e-10 eV km.
+ * Vacuum frequency (eq 3.6): Delta = dm2 / (2E), i.e. in km^-1 with E in MeV
+ * and dm2 in eV^2: Delta = dm2 / (2 * 1e6 * E * hbar c[eV km]). */
+static const double HBARC_EV_KM = 1.973269804e-10;
+double or_vacuum_coefficient(void) { return 1.0 / (2.0e6 * HBARC_EV_KM); }
+
+/* Reference number luminosity used to normalise the beam weights (reading C):
+ * 1e51 erg/s carried at a mean energy of 11 MeV. */
+static const double LREF_ERG_S = 1e51;
+static const double EREF_MEV = 11.0;
+
+/* ---------------------------------------------------------------- run */
+struct or_run {
+    or_params p;
+    int n;          /* flavors */
+    int ne;         /* energy bins */
+    int na;         /* trajectories: N_A, or 1 for the single-angle model */
+    int ma;         /* 1 = multi-angle bulb model, 0 = single angle */
+    int64_t nb;     /* beams = 2 * ne * na */
+    int64_t ylen;   /* 2*n*nb amplitude reals followed by n*na phases */
+    double* energy; /* [ne] */
+    double* g;      /* [ne] neutrino weight */
+    double* gbar;   /* [ne] antineutrino weight */
+    cplx* hvac;     /* [ne][n][n] neutrino vacuum Hamiltonian */
+    double* y;      /* state */
+    double* k[7];   /* stage derivatives */
+    double* ytmp;
+    /* per-evaluation work */
+    cplx* S;        /* [na][n][n] per-trajectory lab-frame sums */
+    double* c;      /* [na] */
+    double* w;      /* [na] */
+    /* stepping */
+    double r, h;
+    int64_t istep;  /* RK4 steps taken */
+    int64_t nacc, nrej;
+    int last_rejected;
+    int k1_valid;   /* Dormand-Prince first-same-as-last derivative held in k[0] */
+    int done;
+};
+
+int64_t or_num_beams(const or_run* R) { return R->nb; }
+int32_t or_num_traj(const or_run* R) { return R->na; }
+int64_t or_state_len(const or_run* R) { return R->ylen; }
+
+/* ------------------------------------------------------------ spectra (eq 4.1-4.2) */
+/* F_k(eta) = int_0^inf x^k / (exp(x - eta) + 1) dx, composite Simpson rule on
+ * [0, max(eta, 0) + 120]; the integrand is smooth and the tail is below 1e-50. */
+double or_fermi_integral(int k, double eta)
+{
+    const double X = (eta > 0.0 ? eta : 0.0) + 120.0;
+    const int64_t N = 400000; /* even */
+    const double h = X / (double)N;
+    double s = 0.0;
+    for (int64_t i = 0; i <= N; ++i) {
+        double x = h * (double)i;
+        double f = pow(x, (double)k) / (exp(x - eta) + 1.0);
+        double wgt = (i == 0 || i == N) ? 1.0 : ((i % 2) ? 4.0 : 2.0);
+        s += wgt * f;
+    }
+    return s * h / 3.0;
+}
+
+/* <E> = T F3(eta) / F2(eta) for the spectrum of eq 4.1, so T = <E> F2 / F3. */
+double or_temperature(double mean_e, double eta)
+{
+    return mean_e * or_fermi_integral(2, eta) / or_fermi_integral(3, eta);
+}
+
+/* Normalised Fermi-Dirac spectrum, eq 4.1 with reading B; f2 = F_2(eta). */
+static double spectrum(double e, double t, double eta, double f2)
+{
+    return e * e / (f2 * t * t * t * (exp(e / t - eta) + 1.0));
+}
+
+double or_spectrum(double e, double t, double eta)
+{
+    return spectrum(e, t, eta, or_fermi_integral(2, eta));
+}
+
+/* ------------------------------------------------------------ geometry */
+/* Single-angle geometric factor, eq 3.17: D(x) = 1/2 [1 - sqrt(1 - 1/x^2)]^2. */
+double or_dilution(double x)
+{
+    double s = 1.0 - sqrt(1.0 - 1.0 / (x * x));
+    return 0.5 * s * s;
+}
+
+/* Multi-angle: c_j(r) = cos(theta) at radius r of the trajectory emitted at
+ * cos(theta_0) = u_j (eq 3.14), and the quadrature weight of d cos(theta') from
+ * eq 3.15 with d cos^2(theta_0) = 2 u du: w_j = (R/r)^2 u_j du / c_j.
+ * Single angle: the radial test ray, c = 1, and w[0] returns D(r/R). */
+static void geometry(const or_run* R, double r, double* c, double* w)
+{
+    const double Rn = R->p.r_nu_km;
+    if (!R->ma) {
+        c[0] = 1.0;
+        w[0] = or_dilution(r / Rn);
+        return;
+    }
+    const double x = (Rn / r) * (Rn / r);
+    const double du = 1.0 / (double)R->na;
+    for (int j = 0; j < R->na; ++j) {
+        double u = ((double)j + 0.5) * du;          /* reading A */
+        c[j] = sqrt(1.0 - x * (1.0 - u * u));
+        w[j] = x * u * du / c[j];
+    }
+}
+
+void or_geometry(const or_run* R, double r, double* c, double* w) { geometry(R, r, c, w); }
+
+/* ------------------------------------------------------------ Hamiltonian pieces */
+static double matter_potential(const or_run* R, double r)
+{
+    return R->p.lambda0_km * pow(R->p.lambda_rref_km / r, R->p.lambda_power);
+}
+
+/* Vacuum Hamiltonian of a neutrino of energy e (MeV), made traceless.
+ * Two flavors, eq 3.5: (Delta/2) [[-cos 2theta, sin 2theta], [sin 2theta, cos 2theta]].
+ * Three flavors (reading D): U diag(0, kappa dm21/E, kappa dm31/E) U^dagger
+ * minus its trace, with U = R23 U13(delta) R12 (PDG). */
+static void vacuum_hamiltonian(const or_params* p, double e, cplx* h)
+{
+    const double kappa = or_vacuum_coefficient();
+    if (p->n_flavors == 2) {
+        double d = kappa * p->dm2_ev2 / e;
+        double c2 = cos(2.0 * p->theta), s2 = sin(2.0 * p->theta);
+        h[0] = c_make(-0.5 * d * c2, 0.0);
+        h[1] = c_make(0.5 * d * s2, 0.0);
+        h[2] = c_make(0.5 * d * s2, 0.0);
+        h[3] = c_make(0.5 * d * c2, 0.0);
+        return;
+    }
+    double c12 = cos(p->theta12), s12 = sin(p->theta12);
+    double c13 = cos(p->theta13), s13 = sin(p->theta13);
+    double c23 = cos(p->theta23), s23 = sin(p->theta23);
+    cplx r12[9] = {c_make(c12, 0), c_make(s12, 0), c_make(0, 0),
+                   c_make(-s12, 0), c_make(c12, 0), c_make(0, 0),
+                   c_make(0, 0), c_make(0, 0), c_make(1, 0)};
+    cplx u13[9] = {c_make(c13, 0), c_make(0, 0), c_scale(c_expi(-p->delta_cp), s13),
+                   c_make(0, 0), c_make(1, 0), c_make(0, 0),
+                   c_scale(c_expi(p->delta_cp), -s13), c_make(0, 0), c_make(c13, 0)};
+    cplx r23[9] = {c_make(1, 0), c_make(0, 0), c_make(0, 0),
+                   c_make(0, 0), c_make(c23, 0), c_make(s23, 0),
+                   c_make(0, 0), c_make(-s23, 0), c_make(c23, 0)};
+    cplx t[9], U[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = c_make(0, 0);
+            for (int m = 0; m < 3; ++m) s = c_add(s, c_mul(u13[a * 3 + m], r12[m * 3 + b]));
+            t[a * 3 + b] = s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = c_make(0, 0);
+            for (int m = 0; m < 3; ++m) s = c_add(s, c_mul(r23[a * 3 + m], t[m * 3 + b]));
+            U[a * 3 + b] = s;
+        }
+    double m[3] = {0.0, kappa * p->dm2_21_ev2 / e, kappa * p->dm2_31_ev2 / e};
+    double tr3 = (m[0] + m[1] + m[2]) / 3.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx s = c_make(0, 0);
+            for (int i = 0; i < 3; ++i)
+                s = c_add(s, c_scale(c_mul(U[a * 3 + i], c_conj(U[b * 3 + i])), m[i]));
+            if (a == b) s = c_sub(s, c_make(tr3, 0.0));
+            h[a * 3 + b] = s;
+        }
+}
+
+void or_tables(const or_run* R, double* energy, double* g, double* gbar, double* hvac)
+{
+    const int n = R->n;
+    for (int k = 0; k < R->ne; ++k) {
+        if (energy) energy[k] = R->energy[k];
+        if (g) g[k] = R->g[k];
+        if (gbar) gbar[k] = R->gbar[k];
+        if (hvac)
+            for (int i = 0; i < n * n; ++i) {
+                hvac[(k * n * n + i) * 2 + 0] = R->hvac[k * n * n + i].re;
+                hvac[(k * n * n + i) * 2 + 1] = R->hvac[k * n * n + i].im;
+            }
+    }
+}
+
+/* ------------------------------------------------------------ create / destroy */
+or_run* or_create(const or_params* p)
+{
+    if (!p || (p->n_flavors != 2 && p->n_flavors != 3) || p->n_energy < 1 || p->n_angle < 0)
+        return NULL;
+    or_run* R = (or_run*)calloc(1, sizeof(or_run));
+    R->p = *p;
+    R->n = p->n_flavors;
+    R->ne = p->n_energy;
+    R->ma = p->n_angle > 0;
+    R->na = R->ma ? p->n_angle : 1;
+    R->nb = 2 * (int64_t)R->ne * R->na;
+    R->ylen = 2 * (int64_t)R->n * R->nb + (int64_t)R->n * R->na;
+    const int n = R->n;
+
+    R->energy = (double*)calloc(R->ne, sizeof(double));
+    R->g = (double*)calloc(R->ne, sizeof(double));
+    R->gbar = (double*)calloc(R->ne, sizeof(double));
+    R->hvac = (cplx*)calloc((size_t)R->ne * n * n, sizeof(cplx));
+    R->y = (double*)calloc(R->ylen, sizeof(double));
+    for (int i = 0; i < 7; ++i) R->k[i] = (double*)calloc(R->ylen, sizeof(double));
+    R->ytmp = (double*)calloc(R->ylen, sizeof(double));
+    R->S = (cplx*)calloc((size_t)R->na * n * n, sizeof(cplx));
+    R->c = (double*)calloc(R->na, sizeof(double));
+    R->w = (double*)calloc(R->na, sizeof(double));
+
+    /* Energy bins at midpoints of [E0, E1]. */
+    const double de = (p->e_max_mev - p->e_min_mev) / (double)R->ne;
+    double temp[4], f2[4];
+    for (int s = 0; s < 4; ++s) {
+        f2[s] = or_fermi_integral(2, p->eta[s]);
+        temp[s] = p->mean_e_mev[s] * f2[s] / or_fermi_integral(3, p->eta[s]);
+    }
+    /* Number luminosity of species s relative to the reference (reading C). */
+    double nrel[4];
+    for (int s = 0; s < 4; ++s)
+        nrel[s] = (p->lum_erg_s[s] / LREF_ERG_S) * (EREF_MEV / p->mean_e_mev[s]);
+    for (int k = 0; k < R->ne; ++k) {
+        double e = p->e_min_mev + ((double)k + 0.5) * de;
+        R->energy[k] = e;
+        /* Reading N: nu_mu and nu_tau both carry the nu_x spectrum, so the sum
+         * of eq 3.8 over initial flavors reduces to (n_e - n_x) rho_e plus a
+         * multiple of the identity, which drops out of the traceless H. */
+        double fe = spectrum(e, temp[0], p->eta[0], f2[0]);
+        double fx = spectrum(e, temp[2], p->eta[2], f2[2]);
+        double fbe = spectrum(e, temp[1], p->eta[1], f2[1]);
+        double fbx = spectrum(e, temp[3], p->eta[3], f2[3]);
+        R->g[k] = de * (nrel[0] * fe - nrel[2] * fx);
+        R->gbar[k] = de * (nrel[1] * fbe - nrel[3] * fbx);
+        vacuum_hamiltonian(p, e, &R->hvac[(size_t)k * n * n]);
+    }
+
+    /* Initial state: every beam in its birth flavor (component 0), phases 0. */
+    for (int64_t b = 0; b < R->nb; ++b) R->y[(b * n + 0) * 2 + 0] = 1.0;
+    R->r = p->r_start_km;
+    R->h = p->dr_init_km;
+    if (R->h > p->dr_max_km) R->h = p->dr_max_km;
+    if (R->r + R->h > p->r_end_km) R->h = p->r_end_km - R->r;
+    return R;
+}
+
+void or_destroy(or_run* R)
+{
+    if (!R) return;
+    free(R->energy); free(R->g); free(R->gbar); free(R->hvac); free(R->y);
+    for (int i = 0; i < 7; ++i) free(R->k[i]);
+    free(R->ytmp); free(R->S); free(R->c); free(R->w);
+    free(R);
+}
+
+/* ------------------------------------------------------------ state access */
+int or_get_state(const or_run* R, double* psi, double* phase)
+{
+    const int n = R->n;
+    if (psi)
+        for (int a = 0; a < n; ++a)
+            for (int64_t b = 0; b < R->nb; ++b) {
+                psi[((int64_t)a * 2 + 0) * R->nb + b] = R->y[(b * n + a) * 2 + 0];
+                psi[((int64_t)a * 2 + 1) * R->nb + b] = R->y[(b * n + a) * 2 + 1];
+            }
+    if (phase)
+        memcpy(phase, R->y + 2 * (int64_t)n * R->nb, sizeof(double) * (size_t)n * R->na);
+    return 0;
+}
+
+int or_set_state(or_run* R, const double* psi, const double* phase, double r_km)
+{
+    const int n = R->n;
+    if (psi)
+        for (int a = 0; a < n; ++a)
+            for (int64_t b = 0; b < R->nb; ++b) {
+                R->y[(b * n + a) * 2 + 0] = psi[((int64_t)a * 2 + 0) * R->nb + b];
+                R->y[(b * n + a) * 2 + 1] = psi[((int64_t)a * 2 + 1) * R->nb + b];
+            }
+    if (phase)
+        memcpy(R->y + 2 * (int64_t)n * R->nb, phase, sizeof(double) * (size_t)n * R->na);
+    R->r = r_km;
+    R->k1_valid = 0;
+    R->done = 0;
+    return 0;
+}
+
+/* ------------------------------------------------------------ physics */
+/* Amplitude of flavor component a of beam b inside flat state y. */
+static cplx amp(const or_run* R, const double* y, int64_t b, int a)
+{
+    return c_make(y[(b * R->n + a) * 2 + 0], y[(b * R->n + a) * 2 + 1]);
+}
+
+/* Angle moments (eq 3.13 factorised, eq 3.16 for the single-angle model).
+ *
+ * For every trajectory j, with beams in the co-rotating frame (reading H):
+ * the lab-frame amplitude is psi = exp(-i sigma Phi_j) psi~ (sigma = +1 for
+ * neutrinos, -1 for antineutrinos), so the lab-frame density matrix of
+ * eq 3.9 (reading F: rho = 2 psi psi^dagger) has elements
+ *   rho_ab = 2 exp(-i sigma (Phi_a - Phi_b)) psi~_a conj(psi~_b).
+ * The integrand of eq 3.8 is rho_nu g - conj(rho_nubar) gbar, therefore
+ *   S_j = 2 exp(-i (Phi_a - Phi_b)) sum_k [g_k psi~_a conj(psi~_b)
+ *                                  - gbar_k conj(psibar~_a conj(psibar~_b))].
+ * The kernel (1 - cos(theta) cos(theta')) of eq 3.13 splits into
+ *   J0 = sum_j w_j S_j  and  J1 = sum_j w_j c_j S_j,
+ * so that H_nunu on trajectory i is mu0 * traceless(J0 - c_i J1).
+ * Single angle: J0 = D(r/R) S_0 and J1 = 0 (c = 1 for the radial ray). */
+static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cplx* J1)
+{
+    const int n = R->n, ne = R->ne, na = R->na;
+    const double* phase = y + 2 * (int64_t)n * R->nb;
+    geometry(R, r, R->c, R->w);
+    for (int j = 0; j < na; ++j) {
+        cplx acc[9];
+        for (int i = 0; i < n * n; ++i) acc[i] = c_make(0, 0);
+        for (int k = 0; k < ne; ++k) {
+            int64_t b = (int64_t)(0 * na + j) * ne + k;
+            for (int a = 0; a < n; ++a)
+                for (int c = 0; c < n; ++c) {
+                    cplx rho = c_mul(amp(R, y, b, a), c_conj(amp(R, y, b, c)));
+                    acc[a * n + c] = c_add(acc[a * n + c], c_scale(rho, R->g[k]));
+                }
+        }
+        for (int k = 0; k < ne; ++k) {
+            int64_t b = (int64_t)(1 * na + j) * ne + k;
+            for (int a = 0; a < n; ++a)
+                for (int c = 0; c < n; ++c) {
+                    cplx rho = c_mul(amp(R, y, b, a), c_conj(amp(R, y, b, c)));
+                    acc[a * n + c] = c_sub(acc[a * n + c], c_scale(c_conj(rho), R->gbar[k]));
+                }
+        }
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                double dphi = phase[j * n + a] - phase[j * n + c];
+                R->S[(j * n + a) * n + c] = c_scale(c_mul(c_expi(-dphi), acc[a * n + c]), 2.0);
+            }
+    }
+    for (int i = 0; i < n * n; ++i) { J0[i] = c_make(0, 0); J1[i] = c_make(0, 0); }
+    if (!R->ma) {
+        for (int i = 0; i < n * n; ++i) J0[i] = c_scale(R->S[i], R->w[0]);
+        return;
+    }
+    for (int j = 0; j < na; ++j)
+        for (int i = 0; i < n * n; ++i) {
+            J0[i] = c_add(J0[i], c_scale(R->S[j * n * n + i], R->w[j]));
+            J1[i] = c_add(J1[i], c_scale(R->S[j * n * n + i], R->w[j] * R->c[j]));
+        }
+}
+
+/* H_nunu = mu0 * traceless(J0 - c J1)  (readings E, G). */
+static void collective(const or_run* R, const cplx* J0, const cplx* J1, double c, cplx* C)
+{
+    const int n = R->n;
+    for (int i = 0; i < n * n; ++i) C[i] = c_sub(J0[i], c_scale(J1[i], c));
+    double tr = 0.0;
+    for (int a = 0; a < n; ++a) tr += C[a * n + a].re;
+    for (int a = 0; a < n; ++a) C[a * n + a].re -= tr / (double)n;
+    for (int i = 0; i < n * n; ++i) C[i] = c_scale(C[i], R->p.mu0_km);
+}
+
+/* Right-hand side of the flavor evolution (eq 3.2 with the bulb geometry).
+ *
+ * Along trajectory j the path length is l = r cos(theta) (eq 3.3), so
+ * d psi / dr = -i H psi / c_j.  The Hamiltonian (readings D, E) is
+ *   neutrino:      H  = H_vac(E) + H_m(r) + H_nunu
+ *   antineutrino:  Hb = conj(H_vac(E)) - H_m(r) - conj(H_nunu)      (eq 3.4)
+ * with H_m = lambda(r) * traceless(diag(1, 0[, 0])).
+ *
+ * Co-rotating frame (reading H).  Let G_j = diag(H_m + H_nunu) / c_j (real,
+ * the same for every energy on trajectory j) and dPhi_j/dr = G_j.  Writing
+ * psi = exp(-i sigma Phi_j) psi~ with sigma = +1 (nu), -1 (nubar), the
+ * antineutrino diagonal is -(H_m + H_nunu)_aa, so both species evolve as
+ *   d psi~ / dr = -i K~ psi~,
+ *   K~_ab = exp(i sigma (Phi_a - Phi_b)) H_ab / c_j   (a != b),
+ *   K~_aa = H_aa / c_j - sigma G_a = (H_vac)_aa / c_j.
+ * The last equality is exact: the frame removes the matter and self-
+ * interaction diagonal, which carries the large terms near the neutrinosphere.
+ * In the lab frame Phi = G = 0 and K~ = H / c_j. */
+static void rhs(const or_run* R, double r, const double* y, double* dy)
+{
+    const int n = R->n, ne = R->ne, na = R->na;
+    const int corot = (R->p.frame == 0);
+    const double* phase = y + 2 * (int64_t)n * R->nb;
+    double* dphase = dy + 2 * (int64_t)n * R->nb;
+    cplx J0[9], J1[9];
+    moments_at(R, r, y, J0, J1); /* also leaves c_j, w_j in R->c, R->w */
+    const double lam = matter_potential(R, r);
+
+    for (int j = 0; j < na; ++j) {
+        const double cj = R->c[j];
+        cplx C[9], Hm[9];
+        collective(R, J0, J1, cj, C);
+        for (int i = 0; i < n * n; ++i) Hm[i] = c_make(0, 0);
+        for (int a = 0; a < n; ++a) Hm[a * n + a] = c_make(lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / (double)n), 0.0);
+        double G[3] = {0, 0, 0};
+        if (corot)
+            for (int a = 0; a < n; ++a) G[a] = (Hm[a * n + a].re + C[a * n + a].re) / cj;
+        for (int a = 0; a < n; ++a) dphase[j * n + a] = G[a];
+
+        for (int s = 0; s < 2; ++s) {
+            const double sigma = (s == 0) ? 1.0 : -1.0;
+            cplx rot[9]; /* exp(i sigma (Phi_a - Phi_b)) */
+            for (int a = 0; a < n; ++a)
+                for (int c = 0; c < n; ++c)
+                    rot[a * n + c] = c_expi(sigma * (phase[j * n + a] - phase[j * n + c]));
+            for (int k = 0; k < ne; ++k) {
+                const cplx* hv = &R->hvac[(size_t)k * n * n];
+                cplx K[9];
+                for (int a = 0; a < n; ++a)
+                    for (int c = 0; c < n; ++c) {
+                        cplx H;
+                        if (s == 0)
+                            H = c_add(c_add(hv[a * n + c], Hm[a * n + c]), C[a * n + c]);
+                        else
+                            H = c_sub(c_sub(c_conj(hv[a * n + c]), Hm[a * n + c]), c_conj(C[a * n + c]));
+                        if (a != c)
+                            K[a * n + c] = c_scale(c_mul(rot[a * n + c], H), 1.0 / cj);
+                        else if (corot)
+                            K[a * n + c] = c_make(hv[a * n + a].re / cj, 0.0);
+                        else
+                            K[a * n + c] = c_make(H.re / cj, 0.0);
+                    }
+                int64_t b = (int64_t)(s * na + j) * ne + k;
+                for (int a = 0; a < n; ++a) {
+                    cplx acc = c_make(0, 0);
+                    for (int c = 0; c < n; ++c) acc = c_add(acc, c_mul(K[a * n + c], amp(R, y, b, c)));
+                    /* -i * acc */
+                    dy[(b * n + a) * 2 + 0] = acc.im;
+                    dy[(b * n + a) * 2 + 1] = -acc.re;
+                }
+            }
+        }
+    }
+}
+
+void or_rhs(const or_run* R, double r, const double* y, double* dydr) { rhs(R, r, y, dydr); }
+
+static void write_moments(const cplx* J, double* out, int n)
+{
+    for (int i = 0; i < n * n; ++i) { out[2 * i] = J[i].re; out[2 * i + 1] = J[i].im; }
+}
+
+void or_moments(const or_run* R, double* j0, double* j1)
+{
+    cplx J0[9], J1[9];
+    moments_at(R, R->r, R->y, J0, J1);
+    if (j0) write_moments(J0, j0, R->n);
+    if (j1) write_moments(J1, j1, R->n);
+}
+
+void or_collective(const or_run* R, double* out)
+{
+    const int n = R->n;
+    cplx J0[9], J1[9];
+    moments_at(R, R->r, R->y, J0, J1);
+    for (int j = 0; j < R->na; ++j) {
+        cplx C[9];
+        collective(R, J0, J1, R->c[j], C);
+        write_moments(C, out + (size_t)j * n * n * 2, n);
+    }
+}
+
+/* ------------------------------------------------------------ integrators */
+/* Y = y + h * sum_{i < m} a[i] k[i]  (coefficient sum first, ascending i). */
+static void stage_state(const or_run* R, const double* y, double h, const double* a, int m, double* Y)
+{
+    for (int64_t q = 0; q < R->ylen; ++q) {
+        double acc = 0.0;
+        for (int i = 0; i < m; ++i) acc += a[i] * R->k[i][q];
+        Y[q] = y[q] + h * acc;
+    }
+}
+
+/* Classic fourth-order Runge-Kutta with N equal steps from r_start to r_end;
+ * step n starts at r_start + n h, h = (r_end - r_start) / N. */
+int or_step_rk4(or_run* R, int64_t nsteps)
+{
+    static const double A[4][3] = {{0, 0, 0}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 1.0}};
+    static const double C[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double h = (R->p.r_end_km - R->p.r_start_km) / (double)R->p.n_fixed_steps;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (R->istep >= R->p.n_fixed_steps) { R->done = 1; return OR_DONE; }
+        const double r = R->p.r_start_km + (double)R->istep * h;
+        for (int i = 0; i < 4; ++i) {
+            stage_state(R, R->y, h, A[i], i, R->ytmp);
+            rhs(R, r + C[i] * h, R->ytmp, R->k[i]);
+        }
+        stage_state(R, R->y, h, B, 4, R->ytmp);
+        memcpy(R->y, R->ytmp, sizeof(double) * (size_t)R->ylen);
+        R->istep += 1;
+        R->nacc += 1;
+        R->r = R->p.r_start_km + (double)R->istep * h;
+        R->h = h;
+        for (int64_t q = 0; q < R->ylen; ++q)
+            if (!isfinite(R->y[q])) return OR_NONFINITE;
+    }
+    return OR_OK;
+}
+
+/* Dormand & Prince (1980) RK5(4)7M coefficients. */
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+/* e = b(5th order) - b(4th order) */
+static const double DP_E[7] = {71.0 / 57600.0, 0.0, -71.0 / 16695.0, 71.0 / 1920.0,
+                               -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
+
+void or_dp54_tableau(double* c, double* a, double* e)
+{
+    for (int i = 0; i < 7; ++i) {
+        c[i] = DP_C[i];
+        e[i] = DP_E[i];
+        for (int j = 0; j < 6; ++j) a[i * 6 + j] = DP_A[i][j];
+    }
+}
+
+/* One attempt of the embedded pair with the controller of readings J and K. */
+static int dp54_attempt(or_run* R)
+{
+    const int64_t namp = 2 * (int64_t)R->n * R->nb;
+    const double r = R->r, h = R->h;
+    if (!R->k1_valid) { rhs(R, r, R->y, R->k[0]); R->k1_valid = 1; }
+    for (int i = 1; i < 7; ++i) {
+        stage_state(R, R->y, h, DP_A[i], i, R->ytmp);
+        rhs(R, r + DP_C[i] * h, R->ytmp, R->k[i]);
+    }
+    /* ytmp now holds stage 7 = the 5th-order solution (a_7j = b_j). */
+    double err = 0.0;
+    int finite = 1;
+    for (int64_t q = 0; q < namp; ++q) {
+        double acc = 0.0;
+        for (int i = 0; i < 7; ++i) acc += DP_E[i] * R->k[i][q];
+        double d = fabs(h * acc) / R->p.rtol;
+        if (!isfinite(d)) finite = 0;
+        else if (d > err) err = d;
+    }
+    if (!finite) return OR_NONFINITE;
+
+    const double fmin = 0.2, fmax = 5.0;
+    double fac;
+    if (err <= 1.0) {
+        memcpy(R->y, R->ytmp, sizeof(double) * (size_t)R->ylen);
+        memcpy(R->k[0], R->k[6], sizeof(double) * (size_t)R->ylen);
+        R->r = r + h;
+        R->nacc += 1;
+        fac = (err == 0.0) ? fmax : R->p.safety * pow(err, -0.2);
+        if (fac > fmax) fac = fmax;
+        if (fac < fmin) fac = fmin;
+        if (R->last_rejected && fac > 1.0) fac = 1.0;
+        R->last_rejected = 0;
+    } else {
+        R->nrej += 1;
+        fac = R->p.safety * pow(err, -0.2);
+        if (fac < fmin) fac = fmin;
+        R->last_rejected = 1;
+    }
+    /* The underflow test applies to the controller's proposal; the clip to
+     * r_end may legitimately leave a last step of any size. */
+    double hn = h * fac;
+    if (hn > R->p.dr_max_km) hn = R->p.dr_max_km;
+    if (R->r >= R->p.r_end_km) { R->done = 1; R->h = hn; return OR_DONE; }
+    if (hn < 1e-14 * R->r) { R->h = hn; return OR_UNDERFLOW; }
+    if (R->r + hn > R->p.r_end_km) hn = R->p.r_end_km - R->r;
+    R->h = hn;
+    return OR_OK;
+}
+
+int or_step_dp54(or_run* R, int64_t nattempts)
+{
+    for (int64_t s = 0; s < nattempts; ++s) {
+        if (R->done) return OR_DONE;
+        int st = dp54_attempt(R);
+        if (st != OR_OK) return st;
+    }
+    return OR_OK;
+}
+
+int or_evolve_dp54(or_run* R, double r_target, int64_t max_attempts)
+{
+    double save_end = R->p.r_end_km;
+    if (r_target < save_end) R->p.r_end_km = r_target;
+    if (R->r + R->h > R->p.r_end_km) R->h = R->p.r_end_km - R->r;
+    int st = OR_OK;
+    for (int64_t s = 0; (max_attempts <= 0 || s < max_attempts); ++s) {
+        if (R->r >= R->p.r_end_km) { st = OR_DONE; break; }
+        st = dp54_attempt(R);
+        if (st != OR_OK) break;
+    }
+    R->p.r_end_km = save_end;
+    if (R->r < save_end) R->done = 0;
+    return st;
+}
+
+/* ------------------------------------------------------------ output */
+void or_probabilities(const or_run* R, double* p)
+{
+    for (int64_t b = 0; b < R->nb; ++b) {
+        cplx z = amp(R, R->y, b, 0);
+        p[b] = z.re * z.re + z.im * z.im;
+    }
+}
+
+void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr)
+{
+    if (accepted) *accepted = R->nacc;
+    if (rejected) *rejected = R->nrej;
+    if (r) *r = R->r;
+    if (dr) *dr = R->h;
+}

@@ -1,0 +1,276 @@
+"""ctypes wrapper of the FP64 CPU oracle -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The library it loads is built from
+``oracle/nuosc_oracle.c`` alone (see ``build()``); it shares no code with the
+HIP path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nuosc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("n_flavors", C.c_int32),
+        ("n_energy", C.c_int32),
+        ("e_min_mev", C.c_double),
+        ("e_max_mev", C.c_double),
+        ("n_angle", C.c_int32),
+        ("lum_erg_s", C.c_double * 4),
+        ("mean_e_mev", C.c_double * 4),
+        ("eta", C.c_double * 4),
+        ("dm2_ev2", C.c_double),
+        ("theta", C.c_double),
+        ("dm2_21_ev2", C.c_double),
+        ("dm2_31_ev2", C.c_double),
+        ("theta12", C.c_double),
+        ("theta13", C.c_double),
+        ("theta23", C.c_double),
+        ("delta_cp", C.c_double),
+        ("lambda0_km", C.c_double),
+        ("lambda_rref_km", C.c_double),
+        ("lambda_power", C.c_double),
+        ("mu0_km", C.c_double),
+        ("r_nu_km", C.c_double),
+        ("r_start_km", C.c_double),
+        ("r_end_km", C.c_double),
+        ("integrator", C.c_int32),
+        ("n_fixed_steps", C.c_int64),
+        ("rtol", C.c_double),
+        ("dr_init_km", C.c_double),
+        ("dr_max_km", C.c_double),
+        ("safety", C.c_double),
+        ("frame", C.c_int32),
+    ]
+
+
+_lib: Optional[C.CDLL] = None
+
+_P = C.POINTER(C.c_double)
+_I64P = C.POINTER(C.c_int64)
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.POINTER(_Params)]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_num_beams.restype = C.c_int64
+        L.or_num_beams.argtypes = [C.c_void_p]
+        L.or_num_traj.restype = C.c_int32
+        L.or_num_traj.argtypes = [C.c_void_p]
+        L.or_state_len.restype = C.c_int64
+        L.or_state_len.argtypes = [C.c_void_p]
+        L.or_get_state.argtypes = [C.c_void_p, _P, _P]
+        L.or_set_state.argtypes = [C.c_void_p, _P, _P, C.c_double]
+        L.or_moments.argtypes = [C.c_void_p, _P, _P]
+        L.or_collective.argtypes = [C.c_void_p, _P]
+        L.or_rhs.argtypes = [C.c_void_p, C.c_double, _P, _P]
+        L.or_step_rk4.restype = C.c_int
+        L.or_step_rk4.argtypes = [C.c_void_p, C.c_int64]
+        L.or_step_dp54.restype = C.c_int
+        L.or_step_dp54.argtypes = [C.c_void_p, C.c_int64]
+        L.or_evolve_dp54.restype = C.c_int
+        L.or_evolve_dp54.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        L.or_probabilities.argtypes = [C.c_void_p, _P]
+        L.or_stats.argtypes = [C.c_void_p, _I64P, _I64P, _P, _P]
+        L.or_fermi_integral.restype = C.c_double
+        L.or_fermi_integral.argtypes = [C.c_int, C.c_double]
+        L.or_temperature.restype = C.c_double
+        L.or_temperature.argtypes = [C.c_double, C.c_double]
+        L.or_spectrum.restype = C.c_double
+        L.or_spectrum.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_dilution.restype = C.c_double
+        L.or_dilution.argtypes = [C.c_double]
+        L.or_geometry.argtypes = [C.c_void_p, C.c_double, _P, _P]
+        L.or_tables.argtypes = [C.c_void_p, _P, _P, _P, _P]
+        L.or_vacuum_coefficient.restype = C.c_double
+        L.or_dp54_tableau.argtypes = [_P, _P, _P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_P)
+
+
+def params_from(w: Dict) -> _Params:
+    p = _Params()
+    for name, ctype in _Params._fields_:
+        if name not in w:
+            continue
+        v = w[name]
+        if hasattr(ctype, "_length_"):
+            getattr(p, name)[:] = [float(x) for x in v]
+        else:
+            setattr(p, name, v)
+    return p
+
+
+OK, DONE, NONFINITE, UNDERFLOW = 0, 1, -4, -5
+
+
+class Run:
+    """One oracle run of a workload dict (see paper_1907_05560_amd.workloads)."""
+
+    def __init__(self, w: Dict):
+        self.w = dict(w)
+        self._p = params_from(self.w)
+        self.h = lib().or_create(C.byref(self._p))
+        if not self.h:
+            raise ValueError("oracle rejected the parameters")
+        self.n = int(self.w["n_flavors"])
+        self.nb = int(lib().or_num_beams(self.h))
+        self.na = int(lib().or_num_traj(self.h))
+
+    def close(self):
+        if self.h:
+            lib().or_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # state ------------------------------------------------------------
+    def get_state(self):
+        psi = np.empty((self.n, 2, self.nb))
+        ph = np.empty((self.na, self.n))
+        lib().or_get_state(self.h, _ptr(psi), _ptr(ph))
+        return psi, ph
+
+    def set_state(self, psi: np.ndarray, phase: Optional[np.ndarray], r: float):
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        assert psi.shape == (self.n, 2, self.nb)
+        if phase is None:
+            phase = np.zeros((self.na, self.n))
+        phase = np.ascontiguousarray(phase, dtype=np.float64)
+        assert phase.shape == (self.na, self.n)
+        lib().or_set_state(self.h, _ptr(psi), _ptr(phase), float(r))
+
+    def psi_complex(self) -> np.ndarray:
+        psi, _ = self.get_state()
+        return psi[:, 0, :] + 1j * psi[:, 1, :]
+
+    # physics ----------------------------------------------------------
+    def moments(self):
+        n = self.n
+        j0 = np.empty(n * n * 2)
+        j1 = np.empty(n * n * 2)
+        lib().or_moments(self.h, _ptr(j0), _ptr(j1))
+        return (j0[0::2] + 1j * j0[1::2]).reshape(n, n), (j1[0::2] + 1j * j1[1::2]).reshape(n, n)
+
+    def collective(self) -> np.ndarray:
+        n = self.n
+        out = np.empty(self.na * n * n * 2)
+        lib().or_collective(self.h, _ptr(out))
+        return (out[0::2] + 1j * out[1::2]).reshape(self.na, n, n)
+
+    def state_len(self) -> int:
+        return int(lib().or_state_len(self.h))
+
+    def rhs(self, r: float, y: np.ndarray) -> np.ndarray:
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        dy = np.empty_like(y)
+        lib().or_rhs(self.h, float(r), _ptr(y), _ptr(dy))
+        return dy
+
+    def geometry(self, r: float):
+        c = np.empty(self.na)
+        w = np.empty(self.na)
+        lib().or_geometry(self.h, float(r), _ptr(c), _ptr(w))
+        return c, w
+
+    def tables(self):
+        ne, n = int(self.w["n_energy"]), self.n
+        e = np.empty(ne)
+        g = np.empty(ne)
+        gb = np.empty(ne)
+        hv = np.empty(ne * n * n * 2)
+        lib().or_tables(self.h, _ptr(e), _ptr(g), _ptr(gb), _ptr(hv))
+        return e, g, gb, (hv[0::2] + 1j * hv[1::2]).reshape(ne, n, n)
+
+    # stepping ---------------------------------------------------------
+    def step_rk4(self, nsteps: int) -> int:
+        return int(lib().or_step_rk4(self.h, int(nsteps)))
+
+    def step_dp54(self, nattempts: int) -> int:
+        return int(lib().or_step_dp54(self.h, int(nattempts)))
+
+    def evolve_dp54(self, r_target: float, max_attempts: int = 0) -> int:
+        return int(lib().or_evolve_dp54(self.h, float(r_target), int(max_attempts)))
+
+    def run_to_end(self) -> int:
+        if int(self.w.get("integrator", 0)) == 0:
+            return self.step_rk4(int(self.w["n_fixed_steps"]))
+        return self.evolve_dp54(float(self.w["r_end_km"]))
+
+    def probabilities(self) -> np.ndarray:
+        p = np.empty(self.nb)
+        lib().or_probabilities(self.h, _ptr(p))
+        return p
+
+    def stats(self):
+        a = C.c_int64()
+        rj = C.c_int64()
+        r = C.c_double()
+        dr = C.c_double()
+        lib().or_stats(self.h, C.byref(a), C.byref(rj), C.byref(r), C.byref(dr))
+        return dict(accepted=a.value, rejected=rj.value, r_km=r.value, dr_km=dr.value)
+
+
+def fermi_integral(k: int, eta: float) -> float:
+    return float(lib().or_fermi_integral(int(k), float(eta)))
+
+
+def temperature(mean_e: float, eta: float) -> float:
+    return float(lib().or_temperature(float(mean_e), float(eta)))
+
+
+def spectrum(e: float, t: float, eta: float) -> float:
+    return float(lib().or_spectrum(float(e), float(t), float(eta)))
+
+
+def dilution(x: float) -> float:
+    return float(lib().or_dilution(float(x)))
+
+
+def dp54_tableau():
+    c = np.empty(7)
+    a = np.empty(42)
+    e = np.empty(7)
+    lib().or_dp54_tableau(_ptr(c), _ptr(a), _ptr(e))
+    return c, a.reshape(7, 6), e
+
+
+def vacuum_coefficient() -> float:
+    return float(lib().or_vacuum_coefficient())
