@@ -1,0 +1,611 @@
+// Host runtime and C ABI of libnuosc (see include/nuosc.h).
+//
+// The runtime validates a parameter set, builds the per-energy tables in FP64
+// (spectra eq 4.1-4.2, vacuum Hamiltonian eq 3.5-3.6), lays the run out in one
+// device allocation, and drives the stage kernels on the run's stream.  The
+// step controller runs on the device, so stepping needs no host round trip;
+// the host reads the control block only when a call returns.
+#include "../../include/nuosc.h"
+#include "nuosc_internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using nuosc::Control;
+using nuosc::RunConst;
+
+struct nuosc_handle {
+    nuosc_params p{};
+    RunConst rc{};
+    int S = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* ws = nullptr;
+    bool own_ws = false;
+    size_t ws_bytes = 0;
+    double* prob = nullptr;  // device [nb]
+    Control hctl{};
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double kHbarcEvKm = 1.973269804e-10;       // hbar c = 197.3269804 MeV fm
+constexpr double kLumRefErgS = 1e51;                 // reference number luminosity:
+constexpr double kEnergyRefMev = 11.0;               //   1e51 erg/s at 11 MeV
+
+// ---------------------------------------------------------------- spectra
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_m.
+void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w)
+{
+    x.resize(m);
+    w.resize(m);
+    for (int i = 0; i < m; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= m; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double dp = m * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                // recompute the derivative at the converged node
+                p0 = 1.0; p1 = z;
+                for (int k = 2; k <= m; ++k) {
+                    double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = m * (z * p1 - p0) / (z * z - 1.0);
+                x[i] = z;
+                w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+        }
+    }
+}
+
+// F_k(eta) = int_0^inf x^k / (e^{x - eta} + 1) dx (eq 4.2) by 16-point
+// Gauss-Legendre panels of width 1/4 on [0, max(eta, 0) + 90].
+double fermi_integral(int k, double eta)
+{
+    static std::vector<double> gx, gw;
+    if (gx.empty()) gauss_legendre(16, gx, gw);
+    const double top = std::max(eta, 0.0) + 90.0;
+    const double width = 0.25;
+    const int panels = (int)std::ceil(top / width);
+    double total = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        const double a = p * width, half = 0.5 * width;
+        double s = 0.0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            const double x = a + half * (1.0 + gx[i]);
+            s += gw[i] * std::pow(x, k) / (std::exp(x - eta) + 1.0);
+        }
+        total += half * s;
+    }
+    return total;
+}
+
+struct Tables {
+    std::vector<double> inv_e, g, gbar;
+    double vac[3][3][2];
+};
+
+bool build_tables(const nuosc_params& p, Tables& t)
+{
+    const int ne = p.n_energy, n = p.n_flavors;
+    t.inv_e.resize(ne);
+    t.g.resize(ne);
+    t.gbar.resize(ne);
+    double temp[4], f2[4], nrel[4];
+    for (int s = 0; s < 4; ++s) {
+        f2[s] = fermi_integral(2, p.eta[s]);
+        temp[s] = p.mean_e_mev[s] * f2[s] / fermi_integral(3, p.eta[s]);
+        nrel[s] = (p.lum_erg_s[s] / kLumRefErgS) * (kEnergyRefMev / p.mean_e_mev[s]);
+    }
+    auto spectrum = [&](int s, double e) {  // eq 4.1 (denominator exp(E/T - eta) + 1)
+        return e * e / (f2[s] * temp[s] * temp[s] * temp[s] * (std::exp(e / temp[s] - p.eta[s]) + 1.0));
+    };
+    const double de = (p.e_max_mev - p.e_min_mev) / ne;
+    for (int k = 0; k < ne; ++k) {
+        const double e = p.e_min_mev + (k + 0.5) * de;
+        t.inv_e[k] = 1.0 / e;
+        // nu_mu and nu_tau share the nu_x spectrum: the flavor sum of eq 3.8 reduces
+        // to (n_e - n_x) rho_e up to the identity, which a traceless H drops.
+        t.g[k] = de * (nrel[0] * spectrum(0, e) - nrel[2] * spectrum(2, e));
+        t.gbar[k] = de * (nrel[1] * spectrum(1, e) - nrel[3] * spectrum(3, e));
+    }
+    // Vacuum Hamiltonian H_vac(E) = vac / E, traceless, in km^-1 (E in MeV).
+    const double kappa = 1.0 / (2.0e6 * kHbarcEvKm);
+    std::memset(t.vac, 0, sizeof(t.vac));
+    if (n == 2) {
+        const double d = 0.5 * kappa * p.dm2_ev2;
+        t.vac[0][0][0] = -d * std::cos(2 * p.theta);
+        t.vac[1][1][0] = d * std::cos(2 * p.theta);
+        t.vac[0][1][0] = t.vac[1][0][0] = d * std::sin(2 * p.theta);
+    } else {
+        using cd = std::complex<double>;
+        const double c12 = std::cos(p.theta12), s12 = std::sin(p.theta12);
+        const double c13 = std::cos(p.theta13), s13 = std::sin(p.theta13);
+        const double c23 = std::cos(p.theta23), s23 = std::sin(p.theta23);
+        const cd ed = std::polar(1.0, p.delta_cp);  // e^{i delta}
+        // PMNS matrix (PDG parametrisation), rows e, mu, tau.
+        const cd U[3][3] = {
+            {c12 * c13, s12 * c13, s13 * std::conj(ed)},
+            {-s12 * c23 - c12 * s23 * s13 * ed, c12 * c23 - s12 * s23 * s13 * ed, s23 * c13},
+            {s12 * s23 - c12 * c23 * s13 * ed, -c12 * s23 - s12 * c23 * s13 * ed, c23 * c13}};
+        const double m2[3] = {0.0, kappa * p.dm2_21_ev2, kappa * p.dm2_31_ev2};
+        const double shift = (m2[1] + m2[2]) / 3.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                cd v = 0.0;
+                for (int i = 0; i < 3; ++i) v += U[a][i] * m2[i] * std::conj(U[b][i]);
+                if (a == b) v -= shift;
+                t.vac[a][b][0] = v.real();
+                t.vac[a][b][1] = v.imag();
+            }
+    }
+    for (int k = 0; k < ne; ++k)
+        if (!std::isfinite(t.g[k]) || !std::isfinite(t.gbar[k])) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------- layout
+struct Layout {
+    size_t psi[2], phase[2], inv_e, g, gbar, jhist, partial, errpart, ctrl, counter, prob, total;
+    int64_t nb, nb_pad;
+    int na;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+const char* validate(const nuosc_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->n_flavors != 2 && p->n_flavors != 3) return "n_flavors must be 2 or 3";
+    if (p->n_energy < 1) return "n_energy must be >= 1";
+    if (p->n_angle < 0) return "n_angle must be >= 0";
+    if (!(p->e_min_mev >= 0.0) || !(p->e_max_mev > p->e_min_mev)) return "need 0 <= e_min < e_max";
+    for (int s = 0; s < 4; ++s) {
+        if (!(p->mean_e_mev[s] > 0.0)) return "mean energies must be > 0";
+        if (!(p->lum_erg_s[s] >= 0.0)) return "luminosities must be >= 0";
+        if (!std::isfinite(p->eta[s])) return "eta must be finite";
+    }
+    if (!(p->r_nu_km > 0.0)) return "r_nu must be > 0";
+    if (!(p->r_start_km >= p->r_nu_km)) return "r_start must be >= r_nu";
+    if (!(p->r_end_km > p->r_start_km)) return "r_end must be > r_start";
+    if (p->integrator != NUOSC_RK4_FIXED && p->integrator != NUOSC_RK_DP54) return "unknown integrator";
+    if (p->integrator == NUOSC_RK4_FIXED && p->n_fixed_steps < 1) return "n_fixed_steps must be >= 1";
+    if (p->integrator == NUOSC_RK_DP54) {
+        if (!(p->rtol > 0.0)) return "rtol must be > 0";
+        if (!(p->dr_init_km > 0.0) || !(p->dr_max_km > 0.0)) return "dr_init and dr_max must be > 0";
+        if (!(p->safety > 0.0 && p->safety <= 1.0)) return "safety must be in (0, 1]";
+    }
+    if (p->precision != NUOSC_FP64 && p->precision != NUOSC_FP32_AMP) return "unknown precision";
+    if (p->frame != NUOSC_FRAME_COROTATING && p->frame != NUOSC_FRAME_LAB) return "unknown frame";
+    if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
+    const int64_t na = std::max(p->n_angle, 1);
+    if (2 * (int64_t)p->n_energy * na > ((int64_t)1 << 31)) return "too many beams";
+    return nullptr;
+}
+
+Layout make_layout(const nuosc_params& p)
+{
+    Layout L{};
+    const int n = p.n_flavors;
+    L.na = std::max(p.n_angle, 1);
+    L.nb = 2 * (int64_t)p.n_energy * L.na;
+    L.nb_pad = (int64_t)align_up((size_t)L.nb, 64);
+    const size_t tsz = p.precision == NUOSC_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    for (int b = 0; b < 2; ++b) L.psi[b] = take(2 * n * (size_t)L.nb_pad * tsz);
+    for (int b = 0; b < 2; ++b) L.phase[b] = take((size_t)L.na * n * 8);
+    L.inv_e = take((size_t)p.n_energy * 8);
+    L.g = take((size_t)p.n_energy * 8);
+    L.gbar = take((size_t)p.n_energy * 8);
+    L.jhist = take((size_t)nuosc::kMaxStages * 2 * n * n * 8);
+    L.partial = take((size_t)2 * n * n * L.na * 8);
+    L.errpart = take((size_t)L.na * 8);
+    L.ctrl = take(sizeof(Control));
+    L.counter = take(2 * sizeof(unsigned));
+    L.prob = take((size_t)L.nb * 8);
+    L.total = off;
+    return L;
+}
+
+nuosc_status fail(nuosc_handle* h, nuosc_status st, const std::string& msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+nuosc_status hip_fail(nuosc_handle* h, hipError_t e, const char* what)
+{
+    return fail(h, NUOSC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, call)                                          \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((h), e_, #call);   \
+    } while (0)
+
+nuosc_status read_control(nuosc_handle* h)
+{
+    HIP_TRY(h, hipMemcpyAsync(&h->hctl, h->rc.ctrl, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return NUOSC_OK;
+}
+
+nuosc_status write_control(nuosc_handle* h)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->rc.ctrl, &h->hctl, sizeof(Control), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return NUOSC_OK;
+}
+
+nuosc_status status_of(nuosc_handle* h)
+{
+    switch (h->hctl.status) {
+    case 0:
+    case 1: return NUOSC_OK;
+    case -4: return fail(h, NUOSC_E_NONFINITE, "step error is not finite");
+    case -5: return fail(h, NUOSC_E_STEP_UNDERFLOW, "adaptive step fell below 1e-14 r");
+    case -6: return fail(h, NUOSC_E_LIMIT, "max_steps reached");
+    default: return fail(h, NUOSC_E_DEVICE, "corrupt control block");
+    }
+}
+
+nuosc_status enqueue(nuosc_handle* h, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int st = 1; st <= h->S; ++st) HIP_TRY(h, nuosc::launch_stage(h->rc, st, h->stream));
+    return NUOSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nuosc_default_params(nuosc_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n_flavors = 2;
+    p->n_energy = 100;
+    p->e_min_mev = 1.0;
+    p->e_max_mev = 60.0;
+    p->n_angle = 0;
+    for (int s = 0; s < 4; ++s) { p->lum_erg_s[s] = 1e51; p->eta[s] = 0.0; }
+    p->mean_e_mev[0] = 11.0; p->mean_e_mev[1] = 16.0; p->mean_e_mev[2] = 25.0; p->mean_e_mev[3] = 25.0;
+    p->dm2_ev2 = -2.4e-3; p->theta = 0.1;
+    p->dm2_21_ev2 = 7.5e-5; p->dm2_31_ev2 = -2.4e-3;
+    p->theta12 = 0.59; p->theta13 = 0.15; p->theta23 = M_PI / 4; p->delta_cp = 0.0;
+    p->lambda0_km = 1e4; p->lambda_rref_km = 10.0; p->lambda_power = 3.0;
+    p->mu0_km = 1e5; p->r_nu_km = 10.0; p->r_start_km = 10.0; p->r_end_km = 250.0;
+    p->integrator = NUOSC_RK4_FIXED; p->n_fixed_steps = 10000;
+    p->rtol = 1e-9; p->dr_init_km = 1e-5; p->dr_max_km = 1.0; p->safety = 0.9;
+    p->precision = NUOSC_FP64; p->frame = NUOSC_FRAME_COROTATING;
+}
+
+size_t nuosc_footprint_bytes(const nuosc_params* p)
+{
+    if (validate(p)) return 0;
+    return make_layout(*p).total;
+}
+
+nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_workspace,
+                          size_t workspace_bytes, nuosc_handle** out)
+{
+    if (!out) return fail(nullptr, NUOSC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (const char* why = validate(p)) return fail(nullptr, NUOSC_E_INVALID, why);
+    Tables tab;
+    if (!build_tables(*p, tab)) return fail(nullptr, NUOSC_E_INVALID, "spectral tables are not finite");
+    const Layout L = make_layout(*p);
+    if (device_workspace && workspace_bytes < L.total)
+        return fail(nullptr, NUOSC_E_INVALID, "workspace smaller than nuosc_footprint_bytes");
+
+    nuosc_handle* h = new (std::nothrow) nuosc_handle();
+    if (!h) return fail(nullptr, NUOSC_E_NOMEM, "host allocation failed");
+    h->p = *p;
+    h->S = nuosc::num_stages(p->integrator);
+    auto bail = [&](nuosc_status st, const std::string& msg) {
+        g_create_error = msg;
+        nuosc_destroy(h);
+        return st;
+    };
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(NUOSC_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        h->own_stream = true;
+    }
+    if (device_workspace) {
+        h->ws = device_workspace;
+        h->ws_bytes = workspace_bytes;
+    } else {
+        hipError_t e = hipMalloc(&h->ws, L.total);
+        if (e != hipSuccess) return bail(NUOSC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        h->own_ws = true;
+        h->ws_bytes = L.total;
+    }
+    char* base = (char*)h->ws;
+    RunConst& rc = h->rc;
+    rc.n = p->n_flavors;
+    rc.ne = p->n_energy;
+    rc.na = L.na;
+    rc.ma = p->n_angle > 0;
+    rc.nb = L.nb;
+    rc.nb_pad = L.nb_pad;
+    rc.frame = p->frame;
+    rc.precision = p->precision;
+    rc.integrator = p->integrator;
+    rc.r_nu = p->r_nu_km;
+    rc.mu0 = p->mu0_km;
+    rc.lambda0 = p->lambda0_km;
+    rc.lambda_rref = p->lambda_rref_km;
+    rc.lambda_power = p->lambda_power;
+    rc.rtol = p->rtol;
+    rc.safety = p->safety;
+    rc.dr_max = p->dr_max_km;
+    rc.r_start = p->r_start_km;
+    rc.n_fixed = p->n_fixed_steps;
+    rc.h_fixed = p->integrator == NUOSC_RK4_FIXED ? (p->r_end_km - p->r_start_km) / (double)p->n_fixed_steps : 0.0;
+    rc.max_steps = p->max_steps;
+    std::memcpy(rc.vac, tab.vac, sizeof(rc.vac));
+    for (int b = 0; b < 2; ++b) {
+        rc.psi[b] = base + L.psi[b];
+        rc.phase[b] = (double*)(base + L.phase[b]);
+    }
+    rc.inv_e = (const double*)(base + L.inv_e);
+    rc.g = (const double*)(base + L.g);
+    rc.gbar = (const double*)(base + L.gbar);
+    rc.jhist = (double*)(base + L.jhist);
+    rc.partial = (double*)(base + L.partial);
+    rc.errpart = (double*)(base + L.errpart);
+    rc.ctrl = (Control*)(base + L.ctrl);
+    rc.counter = (unsigned*)(base + L.counter);
+    h->prob = (double*)(base + L.prob);
+
+    Control& c = h->hctl;
+    std::memset(&c, 0, sizeof(c));
+    c.r = p->r_start_km;
+    c.r_end = p->r_end_km;
+    if (p->integrator == NUOSC_RK4_FIXED) {
+        c.h = c.h_prop = rc.h_fixed;
+    } else {
+        c.h_prop = std::min(p->dr_init_km, p->dr_max_km);
+        c.h = std::min(c.h_prop, p->r_end_km - p->r_start_km);
+    }
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMemcpyAsync((void*)rc.inv_e, tab.inv_e.data(), tab.inv_e.size() * 8, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemcpyAsync((void*)rc.g, tab.g.data(), tab.g.size() * 8, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemcpyAsync((void*)rc.gbar, tab.gbar.data(), tab.gbar.size() * 8, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemsetAsync(rc.jhist, 0, (size_t)nuosc::kMaxStages * 2 * rc.n * rc.n * 8, h->stream));
+    chk(hipMemsetAsync(rc.counter, 0, 2 * sizeof(unsigned), h->stream));
+    chk(hipMemcpyAsync(rc.ctrl, &c, sizeof(Control), hipMemcpyHostToDevice, h->stream));
+    if (e == hipSuccess) e = nuosc::launch_init_state(rc, h->stream);
+    if (e == hipSuccess) e = nuosc::launch_stage(rc, 0, h->stream);  // J of the initial state
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(NUOSC_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    *out = h;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    if (n_attempts < 0) return fail(h, NUOSC_E_INVALID, "n_attempts must be >= 0");
+    return enqueue(h, n_attempts);
+}
+
+nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    if (n_attempts < 0) return fail(h, NUOSC_E_INVALID, "n_attempts must be >= 0");
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    const int64_t before = h->hctl.nacc;
+    st = enqueue(h, n_attempts);
+    if (st != NUOSC_OK) return st;
+    st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    if (n_accepted) *n_accepted = h->hctl.nacc - before;
+    return status_of(h);
+}
+
+nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    if (h->hctl.status < 0) return status_of(h);
+    const double target = std::min(r_target_km, h->p.r_end_km);
+    if (h->hctl.r >= target) return NUOSC_OK;
+    // resume towards the new target
+    h->hctl.r_end = target;
+    h->hctl.status = 0;
+    if (h->p.integrator == NUOSC_RK_DP54) h->hctl.h = std::min(h->hctl.h_prop, target - h->hctl.r);
+    st = write_control(h);
+    if (st != NUOSC_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    int64_t batch = 8;
+    for (;;) {
+        st = enqueue(h, batch);
+        if (st != NUOSC_OK) return st;
+        st = read_control(h);
+        if (st != NUOSC_OK) return st;
+        if (h->hctl.status != 0) break;
+        if (h->p.max_wall_s > 0) {
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > h->p.max_wall_s) return fail(h, NUOSC_E_LIMIT, "max_wall_s reached");
+        }
+        batch = std::min<int64_t>(batch * 2, 2048);
+    }
+    return status_of(h);
+}
+
+nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    HIP_TRY(h, nuosc::launch_stage(h->rc, 0, h->stream));
+    const int n = h->rc.n, nm = n * n;
+    std::vector<double> J(2 * nm);
+    HIP_TRY(h, hipMemcpyAsync(J.data(), h->rc.jhist, J.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    for (int m = 0; m < 2; ++m) {
+        double* out = m == 0 ? j0 : j1;
+        if (!out) continue;
+        const double* src = J.data() + m * nm;
+        for (int a = 0; a < n; ++a) {
+            out[(a * n + a) * 2] = src[a];
+            out[(a * n + a) * 2 + 1] = 0.0;
+        }
+        int u = 0;
+        for (int a = 0; a < n; ++a)
+            for (int b = a + 1; b < n; ++b, ++u) {
+                const double re = src[n + 2 * u], im = src[n + 2 * u + 1];
+                out[(a * n + b) * 2] = re;
+                out[(a * n + b) * 2 + 1] = im;
+                out[(b * n + a) * 2] = re;
+                out[(b * n + a) * 2 + 1] = -im;
+            }
+    }
+    if (r_km) *r_km = h->hctl.r;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out)
+{
+    if (!h || !p_out) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    HIP_TRY(h, nuosc::launch_probabilities(h->rc, h->prob, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(p_out, h->prob, (size_t)h->rc.nb * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    const RunConst& rc = h->rc;
+    const int cur = h->hctl.cur;
+    const size_t rows = 2 * (size_t)rc.n;
+    if (psi) {
+        if (rc.precision == NUOSC_FP64) {
+            HIP_TRY(h, hipMemcpy2DAsync(psi, rc.nb * 8, rc.psi[cur], rc.nb_pad * 8, rc.nb * 8, rows,
+                                        hipMemcpyDeviceToHost, h->stream));
+        } else {
+            std::vector<float> tmp(rows * rc.nb);
+            HIP_TRY(h, hipMemcpy2DAsync(tmp.data(), rc.nb * 4, rc.psi[cur], rc.nb_pad * 4, rc.nb * 4, rows,
+                                        hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            for (size_t i = 0; i < tmp.size(); ++i) psi[i] = tmp[i];
+        }
+    }
+    if (phase)
+        HIP_TRY(h, hipMemcpyAsync(phase, rc.phase[cur], (size_t)rc.na * rc.n * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* phase, double r_km, double dr_km)
+{
+    if (!h || !psi) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    if (!(r_km >= h->p.r_nu_km) || !(r_km <= h->p.r_end_km)) return fail(h, NUOSC_E_INVALID, "radius out of range");
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    const RunConst& rc = h->rc;
+    const int cur = h->hctl.cur;
+    const size_t rows = 2 * (size_t)rc.n;
+    if (rc.precision == NUOSC_FP64) {
+        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 8, psi, rc.nb * 8, rc.nb * 8, rows,
+                                    hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> tmp(rows * rc.nb);
+        for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)psi[i];
+        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 4, tmp.data(), rc.nb * 4, rc.nb * 4, rows,
+                                    hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    std::vector<double> ph((size_t)rc.na * rc.n, 0.0);
+    if (phase) std::memcpy(ph.data(), phase, ph.size() * 8);
+    HIP_TRY(h, hipMemcpyAsync(rc.phase[cur], ph.data(), ph.size() * 8, hipMemcpyHostToDevice, h->stream));
+    Control& c = h->hctl;
+    c.nacc = c.nrej = c.attempts = 0;
+    c.status = 0;
+    c.last_rejected = 0;
+    c.r_end = h->p.r_end_km;
+    if (h->p.integrator == NUOSC_RK4_FIXED) {
+        c.istep = (int64_t)std::llround((r_km - rc.r_start) / rc.h_fixed);
+        c.r = rc.r_start + (double)c.istep * rc.h_fixed;
+        c.h = c.h_prop = rc.h_fixed;
+        if (c.istep >= rc.n_fixed) c.status = 1;
+    } else {
+        c.r = r_km;
+        const double d = dr_km > 0 ? dr_km : h->p.dr_init_km;
+        c.h_prop = std::min(d, h->p.dr_max_km);
+        c.h = std::min(c.h_prop, h->p.r_end_km - r_km);
+        if (c.r >= h->p.r_end_km) c.status = 1;
+    }
+    st = write_control(h);
+    if (st != NUOSC_OK) return st;
+    if (c.status == 0) {
+        HIP_TRY(h, nuosc::launch_stage(rc, 0, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_stats(nuosc_handle* h, int64_t* accepted, int64_t* rejected, double* r_km, double* dr_km)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    nuosc_status st = read_control(h);
+    if (st != NUOSC_OK) return st;
+    if (accepted) *accepted = h->hctl.nacc;
+    if (rejected) *rejected = h->hctl.nrej;
+    if (r_km) *r_km = h->hctl.r;
+    if (dr_km) *dr_km = h->hctl.h_prop;
+    return status_of(h);
+}
+
+int64_t nuosc_num_beams(const nuosc_handle* h) { return h ? h->rc.nb : 0; }
+int32_t nuosc_num_traj(const nuosc_handle* h) { return h ? h->rc.na : 0; }
+
+const char* nuosc_last_error(const nuosc_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void nuosc_destroy(nuosc_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+"""Python binding of libnuosc (include/nuosc.h): argument marshalling only.
+
+Every step of the evolution runs in the library's HIP kernels; this module only
+converts workload dicts to ``nuosc_params``, passes host buffers and optional
+PyTorch device memory / streams, and checks status codes.  There is no CPU
+fallback: importing works without the library, but creating a run raises if
+``libnuosc.so`` has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnuosc.so")
+
+OK = 0
+E_INVALID, E_NOMEM, E_DEVICE, E_NONFINITE, E_STEP_UNDERFLOW, E_LIMIT, E_BUSY = -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NONFINITE",
+                -5: "STEP_UNDERFLOW", -6: "LIMIT", -7: "BUSY"}
+
+# Every function the C ABI exports (include/nuosc.h).
+EXPORTS = (
+    "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
+    "nuosc_enqueue_steps", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
+    "nuosc_get_state", "nuosc_set_state", "nuosc_stats", "nuosc_num_beams",
+    "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
+)
+
+
+class NuoscError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"nuosc {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_flavors", C.c_int32),
+        ("n_energy", C.c_int32),
+        ("e_min_mev", C.c_double),
+        ("e_max_mev", C.c_double),
+        ("n_angle", C.c_int32),
+        ("lum_erg_s", C.c_double * 4),
+        ("mean_e_mev", C.c_double * 4),
+        ("eta", C.c_double * 4),
+        ("dm2_ev2", C.c_double),
+        ("theta", C.c_double),
+        ("dm2_21_ev2", C.c_double),
+        ("dm2_31_ev2", C.c_double),
+        ("theta12", C.c_double),
+        ("theta13", C.c_double),
+        ("theta23", C.c_double),
+        ("delta_cp", C.c_double),
+        ("lambda0_km", C.c_double),
+        ("lambda_rref_km", C.c_double),
+        ("lambda_power", C.c_double),
+        ("mu0_km", C.c_double),
+        ("r_nu_km", C.c_double),
+        ("r_start_km", C.c_double),
+        ("r_end_km", C.c_double),
+        ("integrator", C.c_int32),
+        ("n_fixed_steps", C.c_int64),
+        ("rtol", C.c_double),
+        ("dr_init_km", C.c_double),
+        ("dr_max_km", C.c_double),
+        ("safety", C.c_double),
+        ("max_steps", C.c_int64),
+        ("max_wall_s", C.c_double),
+        ("precision", C.c_int32),
+        ("frame", C.c_int32),
+    ]
+
+
+_lib: Optional[C.CDLL] = None
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+
+
+def lib() -> C.CDLL:
+    """Load libnuosc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1907_05560_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    L.nuosc_default_params.argtypes = [C.POINTER(Params)]
+    L.nuosc_default_params.restype = None
+    L.nuosc_footprint_bytes.argtypes = [C.POINTER(Params)]
+    L.nuosc_footprint_bytes.restype = C.c_size_t
+    L.nuosc_create.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
+    L.nuosc_create.restype = C.c_int
+    L.nuosc_step.argtypes = [C.c_void_p, C.c_int64, _I64]
+    L.nuosc_step.restype = C.c_int
+    L.nuosc_enqueue_steps.argtypes = [C.c_void_p, C.c_int64]
+    L.nuosc_enqueue_steps.restype = C.c_int
+    L.nuosc_evolve.argtypes = [C.c_void_p, C.c_double]
+    L.nuosc_evolve.restype = C.c_int
+    L.nuosc_moments.argtypes = [C.c_void_p, _D, _D, _D]
+    L.nuosc_moments.restype = C.c_int
+    L.nuosc_probabilities.argtypes = [C.c_void_p, _D]
+    L.nuosc_probabilities.restype = C.c_int
+    L.nuosc_get_state.argtypes = [C.c_void_p, _D, _D]
+    L.nuosc_get_state.restype = C.c_int
+    L.nuosc_set_state.argtypes = [C.c_void_p, _D, _D, C.c_double, C.c_double]
+    L.nuosc_set_state.restype = C.c_int
+    L.nuosc_stats.argtypes = [C.c_void_p, _I64, _I64, _D, _D]
+    L.nuosc_stats.restype = C.c_int
+    L.nuosc_num_beams.argtypes = [C.c_void_p]
+    L.nuosc_num_beams.restype = C.c_int64
+    L.nuosc_num_traj.argtypes = [C.c_void_p]
+    L.nuosc_num_traj.restype = C.c_int32
+    L.nuosc_last_error.argtypes = [C.c_void_p]
+    L.nuosc_last_error.restype = C.c_char_p
+    L.nuosc_destroy.argtypes = [C.c_void_p]
+    L.nuosc_destroy.restype = None
+    _lib = L
+    return L
+
+
+def params_from(w: Dict) -> Params:
+    """nuosc_params from a workload dict (missing keys keep the C defaults)."""
+    p = Params()
+    lib().nuosc_default_params(C.byref(p))
+    for name, ctype in Params._fields_:
+        if name not in w:
+            continue
+        v = w[name]
+        if hasattr(ctype, "_length_"):
+            getattr(p, name)[:] = [float(x) for x in v]
+        else:
+            setattr(p, name, v)
+    return p
+
+
+def footprint_bytes(w: Dict) -> int:
+    return int(lib().nuosc_footprint_bytes(C.byref(params_from(w))))
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+class Run:
+    """One run on the GPU (a ``nuosc_handle``).
+
+    stream:    a HIP stream handle (int) to order work on, e.g.
+               ``torch.cuda.current_stream().cuda_stream``; None => own stream.
+    workspace: an optional device tensor (torch, uint8) of at least
+               ``footprint_bytes(w)`` bytes; kept alive by this object.
+    """
+
+    def __init__(self, w: Dict, stream: Optional[int] = None, workspace=None):
+        self.w = dict(w)
+        self._p = params_from(self.w)
+        self._ws = workspace
+        h = C.c_void_p()
+        ws_ptr = workspace.data_ptr() if workspace is not None else None
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        st = lib().nuosc_create(C.byref(self._p), stream, ws_ptr, ws_bytes, C.byref(h))
+        if st != OK:
+            raise NuoscError(st, lib().nuosc_last_error(None).decode())
+        self.h = h
+        self.n = int(self.w.get("n_flavors", 2))
+        self.nb = int(lib().nuosc_num_beams(h))
+        self.na = int(lib().nuosc_num_traj(h))
+
+    @classmethod
+    def with_torch(cls, w: Dict):
+        """Allocate the workspace with PyTorch and order work on torch's current stream."""
+        import torch
+
+        nbytes = footprint_bytes(w)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return cls(w, stream=torch.cuda.current_stream().cuda_stream, workspace=ws)
+
+    def _check(self, st: int) -> int:
+        if st != OK:
+            raise NuoscError(st, lib().nuosc_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nuosc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # stepping
+    def step(self, n_attempts: int, check: bool = True) -> Tuple[int, int]:
+        acc = C.c_int64()
+        st = lib().nuosc_step(self.h, int(n_attempts), C.byref(acc))
+        if check:
+            self._check(st)
+        return acc.value, st
+
+    def enqueue_steps(self, n_attempts: int):
+        self._check(lib().nuosc_enqueue_steps(self.h, int(n_attempts)))
+
+    def evolve(self, r_target: float, check: bool = True) -> int:
+        st = lib().nuosc_evolve(self.h, float(r_target))
+        if check:
+            self._check(st)
+        return st
+
+    # outputs
+    def moments(self):
+        n = self.n
+        j0 = np.empty(2 * n * n)
+        j1 = np.empty(2 * n * n)
+        r = C.c_double()
+        self._check(lib().nuosc_moments(self.h, _ptr(j0), _ptr(j1), C.byref(r)))
+        f = lambda a: (a[0::2] + 1j * a[1::2]).reshape(n, n)  # noqa: E731
+        return f(j0), f(j1), r.value
+
+    def probabilities(self) -> np.ndarray:
+        p = np.empty(self.nb)
+        self._check(lib().nuosc_probabilities(self.h, _ptr(p)))
+        return p
+
+    def get_state(self):
+        psi = np.empty((self.n, 2, self.nb))
+        ph = np.empty((self.na, self.n))
+        self._check(lib().nuosc_get_state(self.h, _ptr(psi), _ptr(ph)))
+        return psi, ph
+
+    def set_state(self, psi: np.ndarray, phase: Optional[np.ndarray], r_km: float, dr_km: float = 0.0):
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        assert psi.shape == (self.n, 2, self.nb)
+        ph = None if phase is None else np.ascontiguousarray(phase, dtype=np.float64)
+        if ph is not None:
+            assert ph.shape == (self.na, self.n)
+        self._check(lib().nuosc_set_state(self.h, _ptr(psi), None if ph is None else _ptr(ph),
+                                          float(r_km), float(dr_km)))
+
+    def psi_complex(self) -> np.ndarray:
+        psi, _ = self.get_state()
+        return psi[:, 0, :] + 1j * psi[:, 1, :]
+
+    def stats(self) -> Dict:
+        a, rj = C.c_int64(), C.c_int64()
+        r, dr = C.c_double(), C.c_double()
+        st = lib().nuosc_stats(self.h, C.byref(a), C.byref(rj), C.byref(r), C.byref(dr))
+        return dict(accepted=a.value, rejected=rj.value, r_km=r.value, dr_km=dr.value, status=st)

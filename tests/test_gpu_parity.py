@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Every case runs the same seeded workload on both sides and compares element
+by element.  Tolerances:
+  * FP64 path: survival probabilities within 1e-10 (relative, with a 1e-13
+    absolute floor for probabilities near zero) and amplitudes within 1e-10;
+    identical accepted/rejected step counts and radius.
+  * FP32-amplitude path: probabilities within 1e-4 absolute.
+The windows are chosen before the onset of collective instability or in the
+non-chaotic 50 -> 250 km single-angle run, where rounding differences of
+order 1e-16 are amplified by less than ~1e3 (measured on the oracle).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_05560_amd import nuosc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_runs(w, attempts, p_rtol=1e-10, psi_atol=1e-10, check_counts=True):
+    say(f"case: n={w['n_flavors']} NE={w['n_energy']} NA={w['n_angle']} int={w['integrator']} "
+        f"prec={w['precision']} attempts={attempts}")
+    with nuosc.Run(w) as run:
+        if w["integrator"] == W.RK4_FIXED:
+            run.step(attempts)
+        else:
+            run.step(attempts)
+        p = run.probabilities()
+        psi = run.psi_complex()
+        _, ph = run.get_state()
+        s = run.stats()
+    ref = O.Run(w)
+    if w["integrator"] == W.RK4_FIXED:
+        ref.step_rk4(attempts)
+    else:
+        ref.step_dp54(attempts)
+    pr = ref.probabilities()
+    psir = ref.psi_complex()
+    _, phr = ref.get_state()
+    sr = ref.stats()
+    if check_counts:
+        assert (s["accepted"], s["rejected"]) == (sr["accepted"], sr["rejected"]), (s, sr)
+        assert s["r_km"] == pytest.approx(sr["r_km"], rel=1e-13, abs=0)
+    np.testing.assert_allclose(p, pr, rtol=p_rtol, atol=1e-13)
+    np.testing.assert_allclose(psi, psir, rtol=0, atol=psi_atol)
+    np.testing.assert_allclose(ph, phr, rtol=1e-11, atol=1e-9)
+    return p, pr, s
+
+
+@pytest.mark.parametrize("n,ne,na,prec", [
+    (3, 37, 13, W.FP64), (2, 100, 0, W.FP64), (3, 200, 0, W.FP64), (2, 5, 7, W.FP64),
+    (3, 300, 3, W.FP64), (3, 37, 13, W.FP32_AMP), (2, 1, 1, W.FP64), (3, 1, 0, W.FP64),
+])
+def test_moments_of_random_states_match_the_oracle(n, ne, na, prec):
+    w = W.multi_angle_3f(ne, na)
+    w.update(n_flavors=n, precision=prec)
+    say(f"case: moments n={n} NE={ne} NA={na} prec={prec}")
+    with nuosc.Run(w) as run:
+        psi = W.random_states(n, run.nb, seed=100 + ne)
+        if prec == W.FP32_AMP:
+            psi = psi.astype(np.float32).astype(np.float64)
+        phase = W.random_phases(n, run.na, seed=200 + na)
+        run.set_state(psi, phase, 13.5)
+        j0, j1, r = run.moments()
+        psi_back, ph_back = run.get_state()
+    assert r == 13.5
+    np.testing.assert_array_equal(psi_back, psi)
+    np.testing.assert_array_equal(ph_back, phase)
+    ref = O.Run(w)
+    ref.set_state(psi, phase, 13.5)
+    k0, k1 = ref.moments()
+    scale = max(np.abs(k0).max(), 1e-300)
+    np.testing.assert_allclose(j0, k0, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(j1, k1, rtol=0, atol=1e-13 * scale)
+
+
+def test_single_angle_two_flavor_rk4_1e4_steps_from_50km():
+    # The two-flavor single-angle run with 1e4 fixed RK4 steps (started at 50 km,
+    # where the explicit step is stable), evolved to 250 km.
+    w = W.single_angle_2f()
+    w["r_start_km"] = 50.0
+    p, pr, s = _compare_runs(w, 10000)
+    assert s["r_km"] == 250.0
+    assert pr.min() < 1e-3  # the run contains full flavor conversion
+
+
+@pytest.mark.parametrize("n,ne,na", [(3, 37, 13), (2, 64, 5), (3, 130, 2), (2, 100, 0), (3, 257, 0)])
+def test_adaptive_window_from_the_neutrinosphere(n, ne, na):
+    w = W.multi_angle_3f(ne, na)
+    w["n_flavors"] = n
+    _compare_runs(w, 300)
+
+
+def test_adaptive_window_lab_frame():
+    w = W.multi_angle_3f(24, 6)
+    w.update(frame=W.FRAME_LAB, r_start_km=50.0, dr_init_km=1e-3)
+    _compare_runs(w, 200)
+
+
+def test_full_single_angle_adaptive_run_to_250km_agrees_within_its_sensitivity():
+    # 10 -> 250 km crosses the bipolar instability: a 1e-15 perturbation of one
+    # amplitude changes the final probabilities by ~2e-8 (oracle against itself),
+    # so the comparison uses 1e-6.
+    w = W.single_angle_2f()
+    w["integrator"] = W.RK_DP54
+    say("case: single-angle 2f DP54 10 -> 250 km")
+    with nuosc.Run(w) as run:
+        run.evolve(250.0)
+        p = run.probabilities()
+        s = run.stats()
+    ref = O.Run(w)
+    assert ref.run_to_end() == O.DONE
+    sr = ref.stats()
+    assert s["r_km"] == 250.0
+    assert abs(s["accepted"] - sr["accepted"]) <= 2
+    np.testing.assert_allclose(p, ref.probabilities(), rtol=0, atol=1e-6)
+
+
+def test_multi_angle_200x1000_window_at_full_size():
+    w = W.multi_angle_3f(200, 1000)
+    _compare_runs(w, 6)
+
+
+def test_multi_angle_400x4000_fp64_window_at_full_size():
+    w = W.multi_angle_3f_large(W.FP64)
+    _compare_runs(w, 2)
+
+
+def test_fp32_amplitudes_within_1e4_on_the_single_angle_run():
+    w = W.single_angle_2f()
+    w.update(r_start_km=50.0, precision=W.FP32_AMP)
+    say("case: single-angle 2f RK4 FP32 50 -> 250 km")
+    with nuosc.Run(w) as run:
+        run.step(10000)
+        p = run.probabilities()
+    ref = O.Run(dict(w, precision=W.FP64))
+    ref.step_rk4(10000)
+    err = np.abs(p - ref.probabilities())
+    say(f"fp32 single-angle: max {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e}")
+    assert err.max() <= 1e-4
+
+
+def test_fp32_amplitudes_within_1e4_on_a_multi_angle_window():
+    w = W.multi_angle_3f(64, 16)
+    w["precision"] = W.FP32_AMP
+    say("case: multi-angle FP32 window")
+    with nuosc.Run(w) as run:
+        run.step(300)
+        p = run.probabilities()
+        r = run.stats()["r_km"]
+    ref = O.Run(dict(w, precision=W.FP64))
+    ref.evolve_dp54(r)
+    assert ref.stats()["r_km"] == pytest.approx(r, rel=1e-12)
+    assert np.abs(p - ref.probabilities()).max() <= 1e-4
+
+
+def test_runs_are_bitwise_deterministic():
+    w = W.multi_angle_3f(50, 20)
+    out = []
+    for _ in range(2):
+        with nuosc.Run(w) as run:
+            run.step(50)
+            out.append((run.get_state(), run.moments()))
+    np.testing.assert_array_equal(out[0][0][0], out[1][0][0])
+    np.testing.assert_array_equal(out[0][0][1], out[1][0][1])
+    np.testing.assert_array_equal(out[0][1][0], out[1][1][0])
+
+
+def test_checkpoint_resume_is_bit_exact():
+    w = W.multi_angle_3f(40, 8)
+    with nuosc.Run(w) as a:
+        a.step(60)
+        psi, ph = a.get_state()
+        s = a.stats()
+        a.step(40)
+        final_a = a.get_state()
+    with nuosc.Run(w) as b:
+        b.set_state(psi, ph, s["r_km"], s["dr_km"])
+        b.step(40)
+        final_b = b.get_state()
+    np.testing.assert_array_equal(final_a[0], final_b[0])
+    np.testing.assert_array_equal(final_a[1], final_b[1])
+
+
+def test_evolve_stops_on_the_target_and_resumes():
+    w = W.multi_angle_3f(16, 4)
+    w.update(r_start_km=60.0, r_end_km=70.0, dr_init_km=1e-3)
+    with nuosc.Run(w) as run:
+        run.evolve(61.0)
+        assert run.stats()["r_km"] == 61.0
+        run.evolve(70.0)
+        s = run.stats()
+        assert s["r_km"] == 70.0
+        acc, st = run.step(5)
+        assert acc == 0 and st == nuosc.OK
+    ref = O.Run(w)
+    ref.evolve_dp54(61.0)
+    ref.evolve_dp54(70.0)
+    assert ref.stats()["accepted"] == s["accepted"]
+
+
+def test_step_underflow_and_limit_are_reported():
+    w = W.multi_angle_3f(8, 4)
+    w.update(rtol=1e-30)
+    with nuosc.Run(w) as run:
+        _, st = run.step(200, check=False)
+        assert st == nuosc.E_STEP_UNDERFLOW
+    w = W.multi_angle_3f(8, 4)
+    w.update(max_steps=10)
+    with nuosc.Run(w) as run:
+        _, st = run.step(20, check=False)
+        assert st == nuosc.E_LIMIT
+        assert run.stats()["accepted"] + run.stats()["rejected"] == 10
+
+
+def test_nonfinite_state_is_reported():
+    w = W.multi_angle_3f(8, 4)
+    with nuosc.Run(w) as run:
+        psi, ph = run.get_state()
+        psi[0, 0, 3] = np.nan
+        run.set_state(psi, ph, 10.0)
+        _, st = run.step(3, check=False)
+        assert st == nuosc.E_NONFINITE
