@@ -97,18 +97,23 @@ int64_t or_state_len(const or_run* R) { return R->ylen; }
 
 /* ------------------------------------------------------------ spectra (eq 4.1-4.2) */
 /* F_k(eta) = int_0^inf x^k / (exp(x - eta) + 1) dx, composite Simpson rule on
- * [0, max(eta, 0) + 120]; the integrand is smooth and the tail is below 1e-50. */
+ * [0, max(eta, 0) + 120]; the integrand is smooth and the tail is below 1e-50.
+ * The 4e5 weighted samples are added with Kahan's compensated summation so that
+ * rounding does not accumulate over the long sum. */
 double or_fermi_integral(int k, double eta)
 {
     const double X = (eta > 0.0 ? eta : 0.0) + 120.0;
     const int64_t N = 400000; /* even */
     const double h = X / (double)N;
-    double s = 0.0;
+    double s = 0.0, comp = 0.0;
     for (int64_t i = 0; i <= N; ++i) {
         double x = h * (double)i;
         double f = pow(x, (double)k) / (exp(x - eta) + 1.0);
         double wgt = (i == 0 || i == N) ? 1.0 : ((i % 2) ? 4.0 : 2.0);
-        s += wgt * f;
+        double term = wgt * f - comp;
+        double t = s + term;
+        comp = (t - s) - term;
+        s = t;
     }
     return s * h / 3.0;
 }
@@ -131,16 +136,20 @@ double or_spectrum(double e, double t, double eta)
 }
 
 /* ------------------------------------------------------------ geometry */
-/* Single-angle geometric factor, eq 3.17: D(x) = 1/2 [1 - sqrt(1 - 1/x^2)]^2. */
+/* Single-angle geometric factor, eq 3.17: D(x) = 1/2 [1 - sqrt(1 - 1/x^2)]^2,
+ * with 1 - 1/x^2 evaluated as (x - 1)(x + 1) / x^2 (exact subtraction near x = 1). */
 double or_dilution(double x)
 {
-    double s = 1.0 - sqrt(1.0 - 1.0 / (x * x));
+    double s = 1.0 - sqrt((x - 1.0) * (x + 1.0) / (x * x));
     return 0.5 * s * s;
 }
 
 /* Multi-angle: c_j(r) = cos(theta) at radius r of the trajectory emitted at
  * cos(theta_0) = u_j (eq 3.14), and the quadrature weight of d cos(theta') from
  * eq 3.15 with d cos^2(theta_0) = 2 u du: w_j = (R/r)^2 u_j du / c_j.
+ * Eq 3.14 is evaluated in the equivalent form c^2 = u^2 + (1 - u^2)(1 - (R/r)^2)
+ * with 1 - (R/r)^2 = (r - R)(r + R) / r^2: near the neutrinosphere the
+ * literal 1 - (R/r)^2 (1 - u^2) cancels to a few digits for small u.
  * Single angle: the radial test ray, c = 1, and w[0] returns D(r/R). */
 static void geometry(const or_run* R, double r, double* c, double* w)
 {
@@ -151,10 +160,11 @@ static void geometry(const or_run* R, double r, double* c, double* w)
         return;
     }
     const double x = (Rn / r) * (Rn / r);
+    const double y = (r - Rn) * (r + Rn) / (r * r);  /* 1 - (R/r)^2 */
     const double du = 1.0 / (double)R->na;
     for (int j = 0; j < R->na; ++j) {
         double u = ((double)j + 0.5) * du;          /* reading A */
-        c[j] = sqrt(1.0 - x * (1.0 - u * u));
+        c[j] = sqrt(u * u + (1.0 - u * u) * y);
         w[j] = x * u * du / c[j];
     }
 }

@@ -19,8 +19,21 @@ def test_cosines_at_the_neutrinosphere_equal_the_emission_cosines():
     run = _ma(37)
     c, w = run.geometry(10.0)
     u = (np.arange(37) + 0.5) / 37
-    np.testing.assert_allclose(c, u, rtol=0, atol=4e-15)  # 1 - (1 - u^2) cancels
-    assert np.all(np.abs(w * 37 - 1) <= 2e-15 / u ** 2)
+    np.testing.assert_allclose(c, u, rtol=3e-16)  # sqrt(fl(u^2)): one rounding
+    np.testing.assert_allclose(w, np.full(37, 1 / 37), rtol=4e-16)
+
+
+def test_cosines_near_the_neutrinosphere_keep_full_precision():
+    # c^2 = 1 - (R/r)^2 (1 - u^2) = u^2 + 2 d/R - ... for r = R + d: compare
+    # with the leading terms of the expansion at d = 1e-9 km, u = 1e-4.
+    w = W.multi_angle_3f(2, 5000)
+    run = O.Run(w)
+    r = 10.0 + 1e-9
+    c, _ = run.geometry(r)
+    u = (np.arange(5000) + 0.5) / 5000
+    eps = (r - 10.0) * (r + 10.0) / r ** 2   # exact to rounding for this r
+    np.testing.assert_allclose(c, np.sqrt(u ** 2 + (1 - u ** 2) * eps), rtol=1e-15)
+    assert c[0] ** 2 == pytest.approx(u[0] ** 2 + 2e-10, rel=1e-6)
 
 
 @pytest.mark.parametrize("r", [10.5, 15.0, 40.0, 250.0])

@@ -21,8 +21,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 def test_fermi_integrals_closed_forms_at_zero_degeneracy():
     # F_k(0) = (1 - 2^-k) k! zeta(k+1):  F_2(0) = 3 zeta(3) / 2,  F_3(0) = 7 pi^4 / 120.
-    assert O.fermi_integral(2, 0.0) == pytest.approx(1.5 * special.zeta(3), rel=1e-12)
-    assert O.fermi_integral(3, 0.0) == pytest.approx(7 * math.pi ** 4 / 120, rel=1e-12)
+    assert O.fermi_integral(2, 0.0) == pytest.approx(1.5 * special.zeta(3), rel=1e-14)
+    assert O.fermi_integral(3, 0.0) == pytest.approx(7 * math.pi ** 4 / 120, rel=1e-14)
 
 
 @pytest.mark.parametrize("eta", [-1.0, -3.0])
@@ -30,7 +30,7 @@ def test_fermi_integrals_closed_forms_at_zero_degeneracy():
 def test_fermi_integrals_series_for_negative_degeneracy(k, eta):
     # For eta < 0: F_k(eta) = k! sum_{n>=1} (-1)^(n+1) exp(n eta) / n^(k+1).
     series = math.factorial(k) * sum((-1) ** (m + 1) * math.exp(m * eta) / m ** (k + 1) for m in range(1, 200))
-    assert O.fermi_integral(k, eta) == pytest.approx(series, rel=1e-12)
+    assert O.fermi_integral(k, eta) == pytest.approx(series, rel=1e-14)
 
 
 def test_temperatures_match_values_printed_in_the_paper():
