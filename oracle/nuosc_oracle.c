@@ -524,6 +524,22 @@ void or_collective(const or_run* R, double* out)
 }
 
 /* ------------------------------------------------------------ integrators */
+/* Optional projection of every beam back to unit norm |psi|^2 = 1 (the scheme
+ * of the FP32-amplitude forms, which renormalise after each accepted step). */
+static void renormalize(or_run* R)
+{
+    const int n = R->n;
+    for (int64_t b = 0; b < R->nb; ++b) {
+        double s = 0.0;
+        for (int a = 0; a < n; ++a) {
+            cplx z = amp(R, R->y, b, a);
+            s += z.re * z.re + z.im * z.im;
+        }
+        double f = 1.0 / sqrt(s);
+        for (int a = 0; a < 2 * n; ++a) R->y[b * 2 * n + a] *= f;
+    }
+}
+
 /* Y = y + h * sum_{i < m} a[i] k[i]  (coefficient sum first, ascending i). */
 static void stage_state(const or_run* R, const double* y, double h, const double* a, int m, double* Y)
 {
@@ -551,6 +567,7 @@ int or_step_rk4(or_run* R, int64_t nsteps)
         }
         stage_state(R, R->y, h, B, 4, R->ytmp);
         memcpy(R->y, R->ytmp, sizeof(double) * (size_t)R->ylen);
+        if (R->p.renormalize) renormalize(R);
         R->istep += 1;
         R->nacc += 1;
         R->r = R->p.r_start_km + (double)R->istep * h;
@@ -611,6 +628,7 @@ static int dp54_attempt(or_run* R)
     if (err <= 1.0) {
         memcpy(R->y, R->ytmp, sizeof(double) * (size_t)R->ylen);
         memcpy(R->k[0], R->k[6], sizeof(double) * (size_t)R->ylen);
+        if (R->p.renormalize) { renormalize(R); R->k1_valid = 0; }
         R->r = r + h;
         R->nacc += 1;
         fac = (err == 0.0) ? fmax : R->p.safety * pow(err, -0.2);

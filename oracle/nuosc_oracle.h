@@ -36,6 +36,8 @@ typedef struct {
     int64_t n_fixed_steps;
     double  rtol, dr_init_km, dr_max_km, safety;
     int32_t frame;          /* 0 co-rotating, 1 lab */
+    int32_t renormalize;    /* 1: rescale every beam to unit norm after each
+                               accepted step (the FP32-amplitude scheme) */
 } or_params;
 
 typedef struct or_run or_run;

@@ -63,6 +63,7 @@ class _Params(C.Structure):
         ("dr_max_km", C.c_double),
         ("safety", C.c_double),
         ("frame", C.c_int32),
+        ("renormalize", C.c_int32),
     ]
 
 

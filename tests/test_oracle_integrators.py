@@ -146,3 +146,19 @@ def test_fixed_rk4_from_the_neutrinosphere_with_1e4_steps_is_unstable():
     w = W.single_angle_2f()
     run = O.Run(w)
     assert run.step_rk4(50) == O.NONFINITE
+
+
+def test_renormalised_scheme_rescales_a_linear_run():
+    # With mu0 = 0 the step map is linear in psi, so rescaling after every step
+    # gives the unrenormalised result divided by its final norm.
+    w = W.single_angle_2f()
+    w.update(mu0_km=0.0, r_start_km=20.0, r_end_km=60.0, n_fixed_steps=2000)
+    plain, renorm = O.Run(w), O.Run(dict(w, renormalize=1))
+    plain.step_rk4(2000)
+    renorm.step_rk4(2000)
+    z = plain.psi_complex()
+    norm = np.sqrt((np.abs(z) ** 2).sum(0))
+    assert np.abs(norm - 1).max() > 1e-9          # RK4 loses norm at this step
+    zr = renorm.psi_complex()
+    assert np.abs((np.abs(zr) ** 2).sum(0) - 1).max() <= 1e-15
+    np.testing.assert_allclose(zr, z / norm, rtol=0, atol=1e-14)
