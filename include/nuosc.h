@@ -64,7 +64,14 @@ typedef enum {
 } nuosc_status;
 
 enum { NUOSC_RK4_FIXED = 0, NUOSC_RK_DP54 = 1 };
-enum { NUOSC_FP64 = 0, NUOSC_FP32_AMP = 1 };
+/* Precision of a run.
+ *   NUOSC_FP64                amplitudes stored and advanced in FP64.
+ *   NUOSC_FP32_AMP            amplitudes stored and advanced in FP32, renormalised
+ *                             at every accepted step; moments, step error and
+ *                             co-rotating phases in FP64.
+ *   NUOSC_FP32_AMP_FP64_MATH  amplitudes stored in FP32 (renormalised every
+ *                             step), stage arithmetic in FP64 registers. */
+enum { NUOSC_FP64 = 0, NUOSC_FP32_AMP = 1, NUOSC_FP32_AMP_FP64_MATH = 2 };
 enum { NUOSC_FRAME_COROTATING = 0, NUOSC_FRAME_LAB = 1 };
 
 /* Parameters of one run.  Field names follow the configuration keywords of the
@@ -94,7 +101,7 @@ typedef struct nuosc_params {
     double  safety;                /* [ksi] controller safety factor in (0, 1] */
     int64_t max_steps;             /* [Ts] attempted-step limit, 0 = none */
     double  max_wall_s;            /* [Tn] wall-clock limit of one evolve call, 0 = none */
-    int32_t precision;             /* NUOSC_FP64 or NUOSC_FP32_AMP */
+    int32_t precision;             /* NUOSC_FP64, NUOSC_FP32_AMP or NUOSC_FP32_AMP_FP64_MATH */
     int32_t frame;                 /* NUOSC_FRAME_COROTATING (default) or NUOSC_FRAME_LAB */
 } nuosc_params;
 

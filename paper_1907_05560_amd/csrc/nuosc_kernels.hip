@@ -140,15 +140,18 @@ __device__ __forceinline__ void eval_k(const SpeciesMat<T, N>& M, T inv_e, const
 // w = D(r/R) of eq 3.17).
 __device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double r, double& c, double& w)
 {
+    // 1 - (R/r)^2 as (r - R)(r + R) / r^2: exact subtraction near the
+    // neutrinosphere, where 1 - (R/r)^2 (1 - u^2) would cancel for small u.
     const double x = (rc.r_nu / r) * (rc.r_nu / r);
+    const double y = (r - rc.r_nu) * (r + rc.r_nu) / (r * r);
     if (rc.ma) {
         const double du = 1.0 / (double)rc.na;
         const double u = ((double)j + 0.5) * du;
-        c = sqrt(1.0 - x * (1.0 - u * u));
+        c = sqrt(fma(1.0 - u * u, y, u * u));
         w = x * u * du / c;
     } else {
         c = 1.0;
-        const double s = 1.0 - sqrt(1.0 - x);
+        const double s = 1.0 - sqrt(y);
         w = 0.5 * s * s;
     }
 }
@@ -219,7 +222,8 @@ __device__ __forceinline__ void block_sum(double* v, double (*lds)[kBlock / 64])
 }
 
 // ------------------------------------------------------------------ stage kernel
-template <typename T, int N, bool MA, typename TAB, int I>
+// TS: type of the amplitudes in HBM; T: arithmetic type of the stage update.
+template <typename TS, typename T, int N, bool MA, typename TAB, int I>
 __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
 {
     constexpr int S = TAB::S;
@@ -323,8 +327,8 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         });
     });
 
-    const T* __restrict__ src = psi_ptr<T>(rc, cur);
-    T* __restrict__ dst = psi_ptr<T>(rc, cur ^ 1);
+    const TS* __restrict__ src = psi_ptr<TS>(rc, cur);
+    TS* __restrict__ dst = psi_ptr<TS>(rc, cur ^ 1);
     const int64_t ld = rc.nb_pad;
     double macc[NM];
 #pragma unroll
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         const int64_t b = ((int64_t)s * rc.na + j) * rc.ne + k;
         T y[2 * N];
 #pragma unroll
-        for (int q = 0; q < 2 * N; ++q) y[q] = src[q * ld + b];
+        for (int q = 0; q < 2 * N; ++q) y[q] = (T)src[q * ld + b];
         const T inv_e = (T)rc.inv_e[k];
 
         T kk[NST > 0 ? NST : 1][2 * N];
@@ -368,18 +372,19 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
                 for (int q = 0; q < 2 * N; ++q) Y[q] = fma(hA[NST][m], kk[m][q], Y[q]);
             }
         });
-        // FP32 amplitudes are renormalised whenever a new state is formed.
-        if constexpr (std::is_same<T, float>::value && (FINAL || (TAB::fsal && I == S - 1))) {
-            float nn = 0.f;
+        // FP32 amplitudes are renormalised whenever a new state is formed, and
+        // the moments of the new state are those of its stored FP32 values.
+        if constexpr (std::is_same<TS, float>::value && (FINAL || (TAB::fsal && I == S - 1))) {
+            T nn = 0;
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) nn = fma(Y[q], Y[q], nn);
-            const float sc = 1.0f / sqrtf(nn);
+            const T sc = T(1) / sqrt(nn);
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) Y[q] *= sc;
+            for (int q = 0; q < 2 * N; ++q) Y[q] = (T)(TS)(Y[q] * sc);
         }
         if constexpr (FINAL) {
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) dst[q * ld + b] = Y[q];
+            for (int q = 0; q < 2 * N; ++q) dst[q * ld + b] = (TS)Y[q];
             bool bad = false;
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) bad |= !isfinite((double)Y[q]);
@@ -572,36 +577,31 @@ __global__ void k_init(const RunConst rc)
 // ------------------------------------------------------------------ dispatch
 using StageFn = void (*)(const RunConst);
 
-template <typename T, int N, bool MA, typename TAB>
+template <typename TS, typename T, int N, bool MA, typename TAB>
 struct StageTable {
     template <int... Is>
     static constexpr std::array<StageFn, kMaxStages> make(std::integer_sequence<int, Is...>)
     {
-        return {{(Is <= TAB::S ? (StageFn)&k_stage<T, N, MA, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+        return {{(Is <= TAB::S ? (StageFn)&k_stage<TS, T, N, MA, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
     }
     static constexpr std::array<StageFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
-template <typename T, int N, bool MA, typename TAB>
-StageFn pick_stage(int stage)
-{
-    return StageTable<T, N, MA, TAB>::fns[stage];
-}
-
-template <typename T, int N, bool MA>
+template <typename TS, typename T, int N, bool MA>
 StageFn pick_tab(int integrator, int stage)
 {
-    return integrator == 0 ? pick_stage<T, N, MA, TabRK4>(stage) : pick_stage<T, N, MA, TabDP54>(stage);
+    return integrator == 0 ? StageTable<TS, T, N, MA, TabRK4>::fns[stage]
+                           : StageTable<TS, T, N, MA, TabDP54>::fns[stage];
 }
-template <typename T, int N>
+template <typename TS, typename T, int N>
 StageFn pick_ma(int ma, int integrator, int stage)
 {
-    return ma ? pick_tab<T, N, true>(integrator, stage) : pick_tab<T, N, false>(integrator, stage);
+    return ma ? pick_tab<TS, T, N, true>(integrator, stage) : pick_tab<TS, T, N, false>(integrator, stage);
 }
-template <typename T>
+template <typename TS, typename T>
 StageFn pick_n(int n, int ma, int integrator, int stage)
 {
-    return n == 2 ? pick_ma<T, 2>(ma, integrator, stage) : pick_ma<T, 3>(ma, integrator, stage);
+    return n == 2 ? pick_ma<TS, T, 2>(ma, integrator, stage) : pick_ma<TS, T, 3>(ma, integrator, stage);
 }
 
 }  // namespace
@@ -611,8 +611,13 @@ int num_stages(int integrator) { return integrator == 0 ? TabRK4::S : TabDP54::S
 hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s)
 {
     if (stage < 0 || stage > num_stages(rc.integrator)) return hipErrorInvalidValue;
-    StageFn fn = rc.precision == 0 ? pick_n<double>(rc.n, rc.ma, rc.integrator, stage)
-                                   : pick_n<float>(rc.n, rc.ma, rc.integrator, stage);
+    StageFn fn = nullptr;
+    switch (rc.precision) {
+    case 0: fn = pick_n<double, double>(rc.n, rc.ma, rc.integrator, stage); break;   // FP64
+    case 1: fn = pick_n<float, float>(rc.n, rc.ma, rc.integrator, stage); break;     // FP32 amplitudes
+    case 2: fn = pick_n<float, double>(rc.n, rc.ma, rc.integrator, stage); break;    // FP32 amplitudes, FP64 math
+    default: break;
+    }
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(rc.na), dim3(kBlock), 0, s, rc);
     return hipGetLastError();

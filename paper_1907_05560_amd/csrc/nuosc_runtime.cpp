@@ -194,7 +194,8 @@ const char* validate(const nuosc_params* p)
         if (!(p->dr_init_km > 0.0) || !(p->dr_max_km > 0.0)) return "dr_init and dr_max must be > 0";
         if (!(p->safety > 0.0 && p->safety <= 1.0)) return "safety must be in (0, 1]";
     }
-    if (p->precision != NUOSC_FP64 && p->precision != NUOSC_FP32_AMP) return "unknown precision";
+    if (p->precision != NUOSC_FP64 && p->precision != NUOSC_FP32_AMP && p->precision != NUOSC_FP32_AMP_FP64_MATH)
+        return "unknown precision";
     if (p->frame != NUOSC_FRAME_COROTATING && p->frame != NUOSC_FRAME_LAB) return "unknown frame";
     if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
     const int64_t na = std::max(p->n_angle, 1);

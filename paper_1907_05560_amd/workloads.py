@@ -37,6 +37,7 @@ RK4_FIXED = 0
 RK_DP54 = 1
 FP64 = 0
 FP32_AMP = 1
+FP32_AMP_FP64_MATH = 2
 FRAME_COROTATING = 0
 FRAME_LAB = 1
 

@@ -27,39 +27,47 @@ def say(msg):
     sys.stdout.flush()
 
 
-def _compare_runs(w, attempts, p_rtol=1e-10, psi_atol=1e-10, check_counts=True):
+def _compare_runs(w, attempts, p_rtol=1e-10, psi_atol=1e-10):
+    """Run `attempts` steps on the GPU, bring the oracle to the same radius and
+    compare.  Fixed-step runs land on the same radii by construction.  For the
+    adaptive pair, the step sizes of two implementations differ in the last
+    digits (the embedded error estimate cancels strongly), so the oracle
+    evolves to the GPU's final radius, clipping its last step there."""
     say(f"case: n={w['n_flavors']} NE={w['n_energy']} NA={w['n_angle']} int={w['integrator']} "
         f"prec={w['precision']} attempts={attempts}")
+    ref = O.Run(w)
     with nuosc.Run(w) as run:
+        run.step(attempts)
         if w["integrator"] == W.RK4_FIXED:
-            run.step(attempts)
+            ref.step_rk4(attempts)
         else:
-            run.step(attempts)
+            ref.step_dp54(attempts)
+            rg, ro = run.stats()["r_km"], ref.stats()["r_km"]
+            if rg < ro:
+                run.evolve(ro)
+            elif ro < rg:
+                ref.evolve_dp54(rg)
         p = run.probabilities()
         psi = run.psi_complex()
         _, ph = run.get_state()
         s = run.stats()
-    ref = O.Run(w)
-    if w["integrator"] == W.RK4_FIXED:
-        ref.step_rk4(attempts)
-    else:
-        ref.step_dp54(attempts)
     pr = ref.probabilities()
     psir = ref.psi_complex()
     _, phr = ref.get_state()
     sr = ref.stats()
-    if check_counts:
-        assert (s["accepted"], s["rejected"]) == (sr["accepted"], sr["rejected"]), (s, sr)
-        assert s["r_km"] == pytest.approx(sr["r_km"], rel=1e-13, abs=0)
+    assert sr["r_km"] == s["r_km"]
+    assert abs(s["accepted"] - sr["accepted"]) <= 1 and s["rejected"] == sr["rejected"], (s, sr)
     np.testing.assert_allclose(p, pr, rtol=p_rtol, atol=1e-13)
     np.testing.assert_allclose(psi, psir, rtol=0, atol=psi_atol)
-    np.testing.assert_allclose(ph, phr, rtol=1e-11, atol=1e-9)
+    # co-rotating phases reach ~1e2 rad near the neutrinosphere
+    np.testing.assert_allclose(ph, phr, rtol=1e-10, atol=1e-10)
     return p, pr, s
 
 
 @pytest.mark.parametrize("n,ne,na,prec", [
     (3, 37, 13, W.FP64), (2, 100, 0, W.FP64), (3, 200, 0, W.FP64), (2, 5, 7, W.FP64),
-    (3, 300, 3, W.FP64), (3, 37, 13, W.FP32_AMP), (2, 1, 1, W.FP64), (3, 1, 0, W.FP64),
+    (3, 300, 3, W.FP64), (3, 37, 13, W.FP32_AMP), (3, 37, 13, W.FP32_AMP_FP64_MATH),
+    (2, 1, 1, W.FP64), (3, 1, 0, W.FP64),
 ])
 def test_moments_of_random_states_match_the_oracle(n, ne, na, prec):
     w = W.multi_angle_3f(ne, na)
@@ -67,7 +75,7 @@ def test_moments_of_random_states_match_the_oracle(n, ne, na, prec):
     say(f"case: moments n={n} NE={ne} NA={na} prec={prec}")
     with nuosc.Run(w) as run:
         psi = W.random_states(n, run.nb, seed=100 + ne)
-        if prec == W.FP32_AMP:
+        if prec != W.FP64:
             psi = psi.astype(np.float32).astype(np.float64)
         phase = W.random_phases(n, run.na, seed=200 + na)
         run.set_state(psi, phase, 13.5)
@@ -79,9 +87,13 @@ def test_moments_of_random_states_match_the_oracle(n, ne, na, prec):
     ref = O.Run(w)
     ref.set_state(psi, phase, 13.5)
     k0, k1 = ref.moments()
-    scale = max(np.abs(k0).max(), 1e-300)
-    np.testing.assert_allclose(j0, k0, rtol=0, atol=1e-13 * scale)
-    np.testing.assert_allclose(j1, k1, rtol=0, atol=1e-13 * scale)
+    # Random states make the sums cancel: bound the rounding by the sum of the
+    # magnitudes of the terms, 2 sum_j w_j sum_k (|g_k| + |gbar_k|) (|psi| = 1).
+    _, g, gb, _ = ref.tables()
+    _, wj = ref.geometry(13.5)
+    scale = 2 * wj.sum() * (np.abs(g).sum() + np.abs(gb).sum())
+    np.testing.assert_allclose(j0, k0, rtol=0, atol=1e-14 * scale)
+    np.testing.assert_allclose(j1, k1, rtol=0, atol=1e-14 * scale)
 
 
 def test_single_angle_two_flavor_rk4_1e4_steps_from_50km():
@@ -136,32 +148,47 @@ def test_multi_angle_400x4000_fp64_window_at_full_size():
     _compare_runs(w, 2)
 
 
-def test_fp32_amplitudes_within_1e4_on_the_single_angle_run():
+@pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
+def test_fp32_amplitudes_on_the_single_angle_run(prec):
+    # FP32 amplitudes against the FP64 oracle over the whole 50 -> 250 km run.
+    # FP32 stage arithmetic puts a ~6e-8 relative error on every frequency, which
+    # accumulates over ~1e3 rad of vacuum phase in the lowest energy bins; with
+    # FP64 arithmetic only the storage rounding of the amplitudes remains.
+    # The FP32 forms renormalise every step; the reference is the same scheme in
+    # FP64 (oracle with renormalisation).  The unrenormalised FP64 run differs
+    # from it by RK4's own norm defect at this coarse step, reported alongside.
     w = W.single_angle_2f()
-    w.update(r_start_km=50.0, precision=W.FP32_AMP)
-    say("case: single-angle 2f RK4 FP32 50 -> 250 km")
+    w.update(r_start_km=50.0, precision=prec)
+    say(f"case: single-angle 2f RK4 50 -> 250 km precision {prec}")
     with nuosc.Run(w) as run:
         run.step(10000)
         p = run.probabilities()
-    ref = O.Run(dict(w, precision=W.FP64))
+    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
     ref.step_rk4(10000)
+    plain = O.Run(dict(w, precision=W.FP64))
+    plain.step_rk4(10000)
     err = np.abs(p - ref.probabilities())
-    say(f"fp32 single-angle: max {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e}")
+    scheme = np.abs(plain.probabilities() - ref.probabilities()).max()
+    say(f"fp32 single-angle precision {prec}: max {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e} "
+        f"(renormalisation vs none in FP64: {scheme:.3e})")
     assert err.max() <= 1e-4
 
 
-def test_fp32_amplitudes_within_1e4_on_a_multi_angle_window():
+@pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
+def test_fp32_amplitudes_within_1e4_on_a_multi_angle_window(prec):
     w = W.multi_angle_3f(64, 16)
-    w["precision"] = W.FP32_AMP
-    say("case: multi-angle FP32 window")
+    w["precision"] = prec
+    say(f"case: multi-angle window precision {prec}")
     with nuosc.Run(w) as run:
         run.step(300)
         p = run.probabilities()
         r = run.stats()["r_km"]
-    ref = O.Run(dict(w, precision=W.FP64))
+    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
     ref.evolve_dp54(r)
-    assert ref.stats()["r_km"] == pytest.approx(r, rel=1e-12)
-    assert np.abs(p - ref.probabilities()).max() <= 1e-4
+    assert ref.stats()["r_km"] == r
+    err = np.abs(p - ref.probabilities())
+    say(f"fp32 window precision {prec}: max {err.max():.3e}")
+    assert err.max() <= 1e-4
 
 
 def test_runs_are_bitwise_deterministic():
