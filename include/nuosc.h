@@ -142,6 +142,16 @@ nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted
  * is picked up by the next nuosc_step / nuosc_stats call. */
 nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts);
 
+/* Queue one launch of the current attempt: stage in 1..S, where S = 4 (RK4)
+ * or 7 (Dormand-Prince) and stage S forms the new state, reduces the step
+ * error and runs the controller.  A full attempt is stages 1..S in order;
+ * nuosc_enqueue_steps does exactly that.  For timing tools that bracket
+ * individual kernels with events.  NUOSC_E_INVALID for a stage out of range. */
+nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage);
+
+/* Number of launches S of one step attempt. */
+int32_t nuosc_num_stages(const nuosc_handle* h);
+
 /* Evolve until r = min(r_target, r_end) (the last step is clipped to land on
  * it), or until max_steps / max_wall_s is reached (NUOSC_E_LIMIT). */
 nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km);

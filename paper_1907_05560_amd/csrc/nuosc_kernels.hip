@@ -242,7 +242,6 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
     __shared__ StageMat<T, N> smat[NST > 0 ? NST : 1];
     __shared__ StageGeo<N> sgeo[kMaxStages];
     __shared__ double sred[2 * NM + 1][kBlock / 64];
-    __shared__ int s_last;
 
     // ---- per-trajectory prologue (FP64): stage radii, geometry, frame rates
     const int nprol = NST + 1;  // stages 0..NST-1 plus the output stage
@@ -464,15 +463,26 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         }
     }
 
-    // ---- last workgroup: deterministic finalisation
-    __threadfence();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(&rc.counter[0], 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// Finalisation of launch I: one workgroup adds the per-trajectory partials
+// of all trajectories in a fixed order into J_I (deterministic), and for the
+// final launch reduces the step error and runs the step controller.  Running
+// it as its own launch (instead of a last-workgroup handoff inside k_stage)
+// avoids a device-scope fence in every workgroup: on gfx950 such a fence
+// writes back and invalidates the XCD's L2.
+template <int N, typename TAB, int I>
+__global__ void __launch_bounds__(kBlock) k_finalize(const RunConst rc)
+{
+    constexpr int S = TAB::S;
+    constexpr bool FINAL = (I == S);
+    constexpr int NM = Shape<N>::NM;
+    constexpr bool MOMENTS = !FINAL || !TAB::fsal;
+    __shared__ double sred[2 * NM + 1][kBlock / 64];
+
+    const Control* ctl = rc.ctrl;
+    if (I > 0 && ctl->status != 0) return;
+    const double h = ctl->h;
 
     double* Jout = rc.jhist + (FINAL ? S : I) * 2 * NM;
     if constexpr (MOMENTS) {
@@ -482,7 +492,6 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         for (int jj = threadIdx.x; jj < rc.na; jj += kBlock)
 #pragma unroll
             for (int v = 0; v < 2 * NM; ++v) acc[v] += rc.partial[(size_t)v * rc.na + jj];
-        __syncthreads();
         block_sum<2 * NM>(acc, sred);
         if (threadIdx.x == 0)
             for (int v = 0; v < 2 * NM; ++v) Jout[v] = acc[v];
@@ -549,7 +558,6 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
             if (C.status == 0 && rc.max_steps > 0 && C.attempts >= rc.max_steps) C.status = -6;
         }
     }
-    if (threadIdx.x == 0) rc.counter[0] = 0u;
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -587,6 +595,22 @@ struct StageTable {
     static constexpr std::array<StageFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
+template <int N, typename TAB>
+struct FinTable {
+    template <int... Is>
+    static constexpr std::array<StageFn, kMaxStages> make(std::integer_sequence<int, Is...>)
+    {
+        return {{(Is <= TAB::S ? (StageFn)&k_finalize<N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+    }
+    static constexpr std::array<StageFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
+};
+
+StageFn pick_finalize(int n, int integrator, int stage)
+{
+    if (n == 2) return integrator == 0 ? FinTable<2, TabRK4>::fns[stage] : FinTable<2, TabDP54>::fns[stage];
+    return integrator == 0 ? FinTable<3, TabRK4>::fns[stage] : FinTable<3, TabDP54>::fns[stage];
+}
+
 template <typename TS, typename T, int N, bool MA>
 StageFn pick_tab(int integrator, int stage)
 {
@@ -618,8 +642,10 @@ hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s)
     case 2: fn = pick_n<float, double>(rc.n, rc.ma, rc.integrator, stage); break;    // FP32 amplitudes, FP64 math
     default: break;
     }
-    if (!fn) return hipErrorInvalidValue;
+    StageFn fin = pick_finalize(rc.n, rc.integrator, stage);
+    if (!fn || !fin) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(rc.na), dim3(kBlock), 0, s, rc);
+    hipLaunchKernelGGL(fin, dim3(1), dim3(kBlock), 0, s, rc);
     return hipGetLastError();
 }
 

@@ -422,6 +422,16 @@ nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts)
     return enqueue(h, n_attempts);
 }
 
+nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    if (stage < 1 || stage > h->S) return fail(h, NUOSC_E_INVALID, "stage out of range");
+    HIP_TRY(h, nuosc::launch_stage(h->rc, stage, h->stream));
+    return NUOSC_OK;
+}
+
+int32_t nuosc_num_stages(const nuosc_handle* h) { return h ? h->S : 0; }
+
 nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NONFINIT
 # Every function the C ABI exports (include/nuosc.h).
 EXPORTS = (
     "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
-    "nuosc_enqueue_steps", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
+    "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
     "nuosc_get_state", "nuosc_set_state", "nuosc_stats", "nuosc_num_beams",
     "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
 )
@@ -99,6 +99,10 @@ def lib() -> C.CDLL:
     L.nuosc_step.restype = C.c_int
     L.nuosc_enqueue_steps.argtypes = [C.c_void_p, C.c_int64]
     L.nuosc_enqueue_steps.restype = C.c_int
+    L.nuosc_enqueue_stage.argtypes = [C.c_void_p, C.c_int32]
+    L.nuosc_enqueue_stage.restype = C.c_int
+    L.nuosc_num_stages.argtypes = [C.c_void_p]
+    L.nuosc_num_stages.restype = C.c_int32
     L.nuosc_evolve.argtypes = [C.c_void_p, C.c_double]
     L.nuosc_evolve.restype = C.c_int
     L.nuosc_moments.argtypes = [C.c_void_p, _D, _D, _D]
@@ -172,13 +176,23 @@ class Run:
         self.na = int(lib().nuosc_num_traj(h))
 
     @classmethod
-    def with_torch(cls, w: Dict):
-        """Allocate the workspace with PyTorch and order work on torch's current stream."""
+    def with_torch(cls, w: Dict, stream=None):
+        """Allocate the workspace with PyTorch and order work on a torch stream.
+
+        `stream` is a ``torch.cuda.Stream``; by default torch's current stream,
+        or a new default-priority torch stream when the current one is the
+        legacy default stream (handle 0, which the C ABI reads as "none")."""
         import torch
 
+        if stream is None:
+            stream = torch.cuda.current_stream()
+            if stream.cuda_stream == 0:
+                stream = torch.cuda.Stream()
         nbytes = footprint_bytes(w)
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        return cls(w, stream=torch.cuda.current_stream().cuda_stream, workspace=ws)
+        run = cls(w, stream=stream.cuda_stream, workspace=ws)
+        run.torch_stream = stream
+        return run
 
     def _check(self, st: int) -> int:
         if st != OK:
@@ -212,6 +226,13 @@ class Run:
 
     def enqueue_steps(self, n_attempts: int):
         self._check(lib().nuosc_enqueue_steps(self.h, int(n_attempts)))
+
+    def enqueue_stage(self, stage: int):
+        self._check(lib().nuosc_enqueue_stage(self.h, int(stage)))
+
+    @property
+    def num_stages(self) -> int:
+        return int(lib().nuosc_num_stages(self.h))
 
     def evolve(self, r_target: float, check: bool = True) -> int:
         st = lib().nuosc_evolve(self.h, float(r_target))
