@@ -26,6 +26,19 @@ struct Control {
 // upper triangle (a < b, row-major) as (re, im) pairs: n*n doubles in total.
 template <int N> struct Herm { static constexpr int size = N * N; };
 
+// FP64 Hamiltonian pieces of one trajectory at one stage of the current
+// attempt, written by the launch that completes the stage and read by later
+// launches of the same attempt.  A, B: K~ = A + B / E of neutrinos, packed as
+// n real diagonal entries then the upper triangle (re, im).
+struct TrajStage {
+    double c, w;        // propagation cosine and angle weight at the stage radius
+    double G[3];        // d Phi / dr of the co-rotating frame
+    double phi[3];      // stage phase
+    double z[3][2];     // e^{i(phi_a - phi_b)}, upper pairs
+    double A[9];
+    double B[9];
+};
+
 // Everything a kernel needs about a run, passed by value.
 struct RunConst {
     int32_t n, ne, na, ma;       // flavors, energy bins, trajectories, multi-angle flag
@@ -43,8 +56,9 @@ struct RunConst {
     const double* g;             // [ne]  neutrino weights
     const double* gbar;          // [ne]  antineutrino weights
     double* jhist;               // [8][2][n*n] packed J0, J1 per stage
-    double* partial;             // [2*n*n][na] per-trajectory weighted sums
+    double* partial;             // [na][2*n*n] per-trajectory weighted sums
     double* errpart;             // [na]
+    TrajStage* tab;              // [kMaxStages][na]
     Control* ctrl;
     unsigned* counter;           // [2] last-block counters
 };

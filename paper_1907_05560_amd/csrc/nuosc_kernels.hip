@@ -60,29 +60,6 @@ struct TabDP54 {
                                     -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
 };
 
-// Runtime-indexed copies for the per-trajectory prologue (few lanes).
-struct TabConst {
-    double C[8];
-    double A[8][8];
-    double B[8];
-};
-template <typename TAB>
-constexpr TabConst make_tab()
-{
-    TabConst t{};
-    for (int i = 0; i < 8; ++i) {
-        t.C[i] = TAB::C[i];
-        t.B[i] = TAB::B[i];
-        for (int j = 0; j < 8; ++j) t.A[i][j] = TAB::A[i][j];
-    }
-    return t;
-}
-__constant__ TabConst c_tab[2] = {make_tab<TabRK4>(), make_tab<TabDP54>()};
-
-template <typename TAB> struct TabIndex;
-template <> struct TabIndex<TabRK4> { static constexpr int v = 0; };
-template <> struct TabIndex<TabDP54> { static constexpr int v = 1; };
-
 // ------------------------------------------------------------------ helpers
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -91,6 +68,15 @@ __device__ __forceinline__ void static_for(F&& f)
         f(std::integral_constant<int, B>{});
         static_for<B + 1, E>(f);
     }
+}
+
+// Empty asm that takes v as a register operand: the computation of v must be
+// complete here, which bounds how far the scheduler spreads one stage's loads
+// and arithmetic into the next (register pressure).  Emits no instruction.
+template <typename T>
+__device__ __forceinline__ void pin(T& v)
+{
+    asm volatile("" : "+v"(v));
 }
 
 template <int N> struct Shape {
@@ -178,13 +164,6 @@ __device__ __forceinline__ void collective(const RunConst& rc, const double* J, 
     }
 }
 
-// FP64 per-trajectory data of one stage, built by one lane.
-template <int N> struct StageGeo {
-    double r, c, w;
-    double G[N];      // d Phi / dr of the co-rotating frame
-    double phi[N];    // stage phase
-};
-
 template <typename T> __device__ __forceinline__ T* psi_ptr(const RunConst& rc, int buf)
 {
     return reinterpret_cast<T*>(rc.psi[buf]);
@@ -203,9 +182,10 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Sum NV doubles over the workgroup in a fixed order; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double* v, double (*lds)[kBlock / 64])
+// Sum NV doubles over a workgroup of NW waves in a fixed order (butterfly in
+// each wave, then waves in index order); result valid in thread 0.
+template <int NV, int NW>
+__device__ __forceinline__ void block_sum(double* v, double (*lds)[NW])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -216,115 +196,167 @@ __device__ __forceinline__ void block_sum(double* v, double (*lds)[kBlock / 64])
     if (threadIdx.x == 0)
         for (int i = 0; i < NV; ++i) {
             double s = lds[i][0];
-            for (int w = 1; w < kBlock / 64; ++w) s += lds[i][w];
+            for (int w = 1; w < NW; ++w) s += lds[i][w];
             v[i] = s;
         }
 }
 
+// Radius of stage l of the current attempt (l == S: the new state).
+template <typename TAB>
+__device__ __forceinline__ double stage_radius(const RunConst& rc, const Control* ctl, double r, double h, int l)
+{
+    if (l < TAB::S) return r + TAB::C[l] * h;
+    return (rc.integrator == 0) ? rc.r_start + (double)(ctl->istep + 1) * rc.h_fixed : r + h;
+}
+
 // ------------------------------------------------------------------ stage kernel
-// TS: type of the amplitudes in HBM; T: arithmetic type of the stage update.
+// One wavefront per trajectory j.  TS: amplitude type in HBM; T: arithmetic
+// type of the stage update.  Launch I (1 <= I <= S) needs the Hamiltonian
+// pieces of stages 0..I-1: those of stages < I-1 were built by earlier
+// launches of this attempt and are read from rc.tab; stage I-1 is completed
+// here from J_{I-1} (its geometry and phase were set by launch I-1); the
+// output stage I gets its geometry and phase here.
 template <typename TS, typename T, int N, bool MA, typename TAB, int I>
-__global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
+__global__ void __launch_bounds__(64) k_stage(const RunConst rc)
 {
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
-    constexpr int NST = FINAL ? S : I;          // stages whose derivative is needed
     constexpr int NU = Shape<N>::NU, NM = Shape<N>::NM;
-    constexpr bool MOMENTS = !FINAL || !TAB::fsal;  // final launch of RK4 also forms J of y_{n+1}
-    constexpr int TABI = TabIndex<TAB>::v;
+    constexpr bool MOMENTS = !FINAL || !TAB::fsal;  // the last RK4 launch also forms J of y_{n+1}
 
     const Control* ctl = rc.ctrl;
     if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
     const int cur = ctl->cur;
     const double r = ctl->r, h = ctl->h;
     const int j = blockIdx.x;
+    const int lane = threadIdx.x;
 
-    __shared__ StageMat<T, N> smat[NST > 0 ? NST : 1];
-    __shared__ StageGeo<N> sgeo[kMaxStages];
-    __shared__ double sred[2 * NM + 1][kBlock / 64];
+    __shared__ StageMat<T, N> smat[I > 0 ? I : 1];
+    __shared__ double sG[kMaxStages][N];
 
-    // ---- per-trajectory prologue (FP64): stage radii, geometry, frame rates
-    const int nprol = NST + 1;  // stages 0..NST-1 plus the output stage
-    if ((int)threadIdx.x < nprol) {
-        const int l = threadIdx.x;
-        StageGeo<N>& g = sgeo[l];
-        double rl;
-        if (l < NST) rl = r + c_tab[TABI].C[l] * h;
-        else if (FINAL) rl = (rc.integrator == 0) ? rc.r_start + (double)(ctl->istep + 1) * rc.h_fixed : r + h;
-        else rl = r + c_tab[TABI].C[I] * h;
-        g.r = rl;
-        traj_geometry(rc, j, rl, g.c, g.w);
-        if (l < NST && rc.frame == 0) {
-            double Cd[N], Cu[NU > 0 ? NU : 1][2];
-            collective<N>(rc, rc.jhist + l * 2 * NM, g.c, Cd, Cu);
-            const double lam = matter(rc, rl);
-            for (int a = 0; a < N; ++a) g.G[a] = (lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + Cd[a]) / g.c;
-        } else {
-            for (int a = 0; a < N; ++a) g.G[a] = 0.0;
+    // ---- stored Hamiltonian pieces of stages 0..I-2 -> LDS (both species)
+    if constexpr (I >= 2) {
+        constexpr int PER = 2 * NM;  // A then B, packed
+        for (int idx = lane; idx < (I - 1) * PER; idx += 64) {
+            const int l = idx / PER, q = idx - l * PER;
+            const TrajStage& e = rc.tab[(size_t)l * rc.na + j];
+            const int m = q < NM ? 0 : 1;       // 0: A, 1: B
+            const int x = q - m * NM;
+            const double v = m == 0 ? e.A[x] : e.B[x];
+            SpeciesMat<T, N>& nu = smat[l].sp[0];
+            SpeciesMat<T, N>& nb = smat[l].sp[1];
+            if (x < N) {
+                if (m == 0) { nu.ad[x] = (T)v; nb.ad[x] = (T)(-v); }
+                else { nu.bd[x] = (T)v; nb.bd[x] = (T)v; }
+            } else {
+                const int u = (x - N) >> 1, ri = (x - N) & 1;
+                // nubar: A -> -conj(A), B -> conj(B)
+                if (m == 0) { nu.au[u][ri] = (T)v; nb.au[u][ri] = (T)(ri ? v : -v); }
+                else { nu.bu[u][ri] = (T)v; nb.bu[u][ri] = (T)(ri ? -v : v); }
+            }
         }
     }
-    __syncthreads();
-    if ((int)threadIdx.x < nprol) {
-        const int l = threadIdx.x;
-        StageGeo<N>& g = sgeo[l];
+
+    // ---- lane 0: complete stage I-1, then geometry and phase of stage I (FP64)
+    double zo[NU > 0 ? NU : 1][2], co = 1.0, wo = 0.0, pho[N];
+    if (lane == 0) {
         const double* ph0 = rc.phase[cur] + (size_t)j * N;
-        for (int a = 0; a < N; ++a) {
-            double acc = 0.0;
-            if (l < NST || !FINAL) {
-                const int row = (l < NST) ? l : I;
-                for (int m = 0; m < row; ++m) acc += c_tab[TABI].A[row][m] * sgeo[m].G[a];
+        double (*G)[N] = sG;
+        for (int l = 0; l + 1 < I; ++l)
+            for (int a = 0; a < N; ++a) G[l][a] = rc.tab[(size_t)l * rc.na + j].G[a];
+        if constexpr (I >= 1) {
+            constexpr int l = I - 1;
+            TrajStage& e = rc.tab[(size_t)l * rc.na + j];
+            const double rl = stage_radius<TAB>(rc, ctl, r, h, l);
+            double c, w, phl[N], zl[NU > 0 ? NU : 1][2];
+            if (l == 0) {
+                traj_geometry(rc, j, rl, c, w);
+                for (int a = 0; a < N; ++a) phl[a] = ph0[a];
+                for (int a = 0; a < N; ++a)
+                    for (int b = a + 1; b < N; ++b) {
+                        const int u = Shape<N>::up(a, b);
+                        sincos(phl[a] - phl[b], &zl[u][1], &zl[u][0]);
+                    }
+                e.c = c; e.w = w;
+                for (int a = 0; a < N; ++a) e.phi[a] = phl[a];
+                for (int u = 0; u < NU; ++u) { e.z[u][0] = zl[u][0]; e.z[u][1] = zl[u][1]; }
             } else {
-                for (int m = 0; m < S; ++m) acc += c_tab[TABI].B[m] * sgeo[m].G[a];
+                c = e.c;
+                for (int u = 0; u < NU; ++u) { zl[u][0] = e.z[u][0]; zl[u][1] = e.z[u][1]; }
             }
-            g.phi[a] = ph0[a] + h * acc;
-        }
-        if (l < NST) {
             // Hamiltonian pieces of stage l in the co-rotating frame:
-            //   nu:    A_ab = e^{i(Phi_a-Phi_b)} C_ab / c,  B_ab = e^{i(Phi_a-Phi_b)} V_ab / c
-            //          A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab),  B_aa = V_aa / c
-            //   nubar: A -> -conj(A), B -> conj(B)   (eq 3.4 map, Phibar = -Phi)
+            //   A_ab = e^{i(Phi_a-Phi_b)} C_ab / c,  B_ab = e^{i(Phi_a-Phi_b)} V_ab / c   (a < b)
+            //   A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab),  B_aa = V_aa / c
             double Cd[N], Cu[NU > 0 ? NU : 1][2];
-            collective<N>(rc, rc.jhist + l * 2 * NM, g.c, Cd, Cu);
-            const double lam = matter(rc, g.r);
-            const double ic = 1.0 / g.c;
+            collective<N>(rc, rc.jhist + l * 2 * NM, c, Cd, Cu);
+            const double lam = matter(rc, rl);
+            const double ic = 1.0 / c;
             SpeciesMat<T, N>& nu = smat[l].sp[0];
             SpeciesMat<T, N>& nb = smat[l].sp[1];
             for (int a = 0; a < N; ++a) {
-                const double vd = rc.vac[a][a][0] * ic;
-                const double ad = (rc.frame == 0) ? 0.0 : (lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + Cd[a]) * ic;
-                nu.ad[a] = (T)ad;
-                nb.ad[a] = (T)(-ad);
-                nu.bd[a] = nb.bd[a] = (T)vd;
+                const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + Cd[a];
+                const double gd = (rc.frame == 0) ? hd * ic : 0.0;
+                G[l][a] = gd;
+                e.G[a] = gd;
+                const double ad = (rc.frame == 0) ? 0.0 : hd * ic;
+                const double bd = rc.vac[a][a][0] * ic;
+                e.A[a] = ad;
+                e.B[a] = bd;
+                nu.ad[a] = (T)ad; nb.ad[a] = (T)(-ad);
+                nu.bd[a] = (T)bd; nb.bd[a] = (T)bd;
             }
-            for (int a = 0; a < N; ++a)
-                for (int b = a + 1; b < N; ++b) {
-                    const int u = Shape<N>::up(a, b);
-                    double sn, cs;
-                    sincos(g.phi[a] - g.phi[b], &sn, &cs);
-                    const double cr = Cu[u][0] * ic, ci = Cu[u][1] * ic;
-                    const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
-                    const double Ar = cs * cr - sn * ci, Ai = cs * ci + sn * cr;
-                    const double Br = cs * vr - sn * vi, Bi = cs * vi + sn * vr;
-                    nu.au[u][0] = (T)Ar;  nu.au[u][1] = (T)Ai;
-                    nu.bu[u][0] = (T)Br;  nu.bu[u][1] = (T)Bi;
-                    nb.au[u][0] = (T)(-Ar); nb.au[u][1] = (T)Ai;
-                    nb.bu[u][0] = (T)Br;  nb.bu[u][1] = (T)(-Bi);
-                }
+            for (int u = 0; u < NU; ++u) {
+                const double cs = zl[u][0], sn = zl[u][1];
+                int a = 0, b = 1;
+                for (int aa = 0; aa < N; ++aa)
+                    for (int bb = aa + 1; bb < N; ++bb)
+                        if (Shape<N>::up(aa, bb) == u) { a = aa; b = bb; }
+                const double cr = Cu[u][0] * ic, ci = Cu[u][1] * ic;
+                const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
+                const double Ar = cs * cr - sn * ci, Ai = cs * ci + sn * cr;
+                const double Br = cs * vr - sn * vi, Bi = cs * vi + sn * vr;
+                e.A[N + 2 * u] = Ar; e.A[N + 2 * u + 1] = Ai;
+                e.B[N + 2 * u] = Br; e.B[N + 2 * u + 1] = Bi;
+                nu.au[u][0] = (T)Ar;  nu.au[u][1] = (T)Ai;
+                nu.bu[u][0] = (T)Br;  nu.bu[u][1] = (T)Bi;
+                nb.au[u][0] = (T)(-Ar); nb.au[u][1] = (T)Ai;
+                nb.bu[u][0] = (T)Br;  nb.bu[u][1] = (T)(-Bi);
+            }
+        }
+        // output stage (or new state): radius, geometry, phase, rotation
+        const double ro = stage_radius<TAB>(rc, ctl, r, h, I);
+        traj_geometry(rc, j, ro, co, wo);
+        for (int a = 0; a < N; ++a) {
+            double acc = 0.0;
+            static_for<0, I>([&](auto Mc) {
+                constexpr int m = decltype(Mc)::value;
+                constexpr double coef = FINAL ? TAB::B[m] : TAB::A[I < S ? I : 0][m];
+                if constexpr (coef != 0.0) acc += coef * G[m][a];
+            });
+            pho[a] = ph0[a] + h * acc;
+        }
+        for (int a = 0; a < N; ++a)
+            for (int b = a + 1; b < N; ++b) {
+                const int u = Shape<N>::up(a, b);
+                sincos(pho[a] - pho[b], &zo[u][1], &zo[u][0]);
+            }
+        if constexpr (!FINAL && I >= 1) {
+            TrajStage& e = rc.tab[(size_t)I * rc.na + j];
+            e.c = co; e.w = wo;
+            for (int a = 0; a < N; ++a) e.phi[a] = pho[a];
+            for (int u = 0; u < NU; ++u) { e.z[u][0] = zo[u][0]; e.z[u][1] = zo[u][1]; }
+        }
+        if constexpr (FINAL) {
+            double* ph1 = rc.phase[cur ^ 1] + (size_t)j * N;  // kept only if the attempt is accepted
+            for (int a = 0; a < N; ++a) ph1[a] = pho[a];
         }
     }
     __syncthreads();
 
-    // ---- per-beam work
-    T hA[NST > 0 ? NST + 1 : 1][NST > 0 ? NST : 1];
-    static_for<0, NST + 1>([&](auto Lc) {
-        constexpr int l = decltype(Lc)::value;
-        static_for<0, (l < NST ? l : NST)>([&](auto Mc) {
-            constexpr int m = decltype(Mc)::value;
-            if constexpr (l < NST) hA[l][m] = (T)(h * TAB::A[l][m]);
-            else if constexpr (FINAL) hA[l][m] = (T)(h * TAB::B[m]);
-            else hA[l][m] = (T)(h * TAB::A[I][m]);
-        });
-    });
+    // ---- per-beam work: lanes over the 2*NE beams of trajectory j
+    // Stage states are y + h * (sum_m a_lm k_m): the tableau coefficients are
+    // compile-time constants (scalar operands), only h is a runtime value.
+    const T hT = (T)h;
 
     const TS* __restrict__ src = psi_ptr<TS>(rc, cur);
     TS* __restrict__ dst = psi_ptr<TS>(rc, cur ^ 1);
@@ -334,7 +366,11 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
     for (int i = 0; i < NM; ++i) macc[i] = 0.0;
     double emax = 0.0;
 
-    for (int t = threadIdx.x; t < 2 * rc.ne; t += kBlock) {
+#pragma unroll 1
+    for (int t = lane; t < 2 * rc.ne; t += 64) {
+        // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
+        // LDS each iteration instead of keeping both species' copies in VGPRs.
+        asm volatile("" ::: "memory");
         const int s = (t >= rc.ne) ? 1 : 0;
         const int k = t - s * rc.ne;
         const int64_t b = ((int64_t)s * rc.na + j) * rc.ne + k;
@@ -343,34 +379,38 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         for (int q = 0; q < 2 * N; ++q) y[q] = (T)src[q * ld + b];
         const T inv_e = (T)rc.inv_e[k];
 
-        T kk[NST > 0 ? NST : 1][2 * N];
-        static_for<0, NST>([&](auto Lc) {
+        T kk[I > 0 ? I : 1][2 * N];
+        static_for<0, I>([&](auto Lc) {
             constexpr int l = decltype(Lc)::value;
             T Y[2 * N];
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) Y[q] = y[q];
-            static_for<0, l>([&](auto Mc) {
-                constexpr int m = decltype(Mc)::value;
-                if constexpr (TAB::A[l][m] != 0.0) {
-#pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) Y[q] = fma(hA[l][m], kk[m][q], Y[q]);
-                }
-            });
+            for (int q = 0; q < 2 * N; ++q) {
+                T acc = 0;
+                static_for<0, l>([&](auto Mc) {
+                    constexpr int m = decltype(Mc)::value;
+                    if constexpr (TAB::A[l][m] != 0.0) acc = fma((T)TAB::A[l][m], kk[m][q], acc);
+                });
+                Y[q] = (l == 0) ? y[q] : fma(hT, acc, y[q]);
+            }
+            // keep only this stage's matrix live: no LDS reads hoisted across stages
+            asm volatile("" ::: "memory");
             eval_k<T, N>(smat[l].sp[s], inv_e, Y, kk[l]);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
         });
 
         // output state: Y_I (stage) or y_{n+1} (final)
         T Y[2 * N];
 #pragma unroll
-        for (int q = 0; q < 2 * N; ++q) Y[q] = y[q];
-        static_for<0, NST>([&](auto Mc) {
-            constexpr int m = decltype(Mc)::value;
-            constexpr double coef = FINAL ? TAB::B[m] : TAB::A[I < S ? I : 0][m];
-            if constexpr (coef != 0.0) {
-#pragma unroll
-                for (int q = 0; q < 2 * N; ++q) Y[q] = fma(hA[NST][m], kk[m][q], Y[q]);
-            }
-        });
+        for (int q = 0; q < 2 * N; ++q) {
+            T acc = 0;
+            static_for<0, I>([&](auto Mc) {
+                constexpr int m = decltype(Mc)::value;
+                constexpr double coef = FINAL ? TAB::B[m] : TAB::A[I < S ? I : 0][m];
+                if constexpr (coef != 0.0) acc = fma((T)coef, kk[m][q], acc);
+            });
+            Y[q] = (I == 0) ? y[q] : fma(hT, acc, y[q]);
+        }
         // FP32 amplitudes are renormalised whenever a new state is formed, and
         // the moments of the new state are those of its stored FP32 values.
         if constexpr (std::is_same<TS, float>::value && (FINAL || (TAB::fsal && I == S - 1))) {
@@ -424,45 +464,32 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
         }
     }
 
-    // ---- workgroup reduction and per-trajectory output
+    // ---- wave reduction and per-trajectory output (lane 0)
     if constexpr (MOMENTS) {
-        block_sum<NM>(macc, sred);
-        if (threadIdx.x == 0) {
-            const StageGeo<N>& g = sgeo[NST];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) macc[i] = wave_sum(macc[i]);
+        if (lane == 0) {
             // lab frame: S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa
             double Sl[NM];
             for (int a = 0; a < N; ++a) Sl[a] = 2.0 * macc[a];
-            for (int a = 0; a < N; ++a)
-                for (int b = a + 1; b < N; ++b) {
-                    const int u = Shape<N>::up(a, b);
-                    double sn, cs;
-                    sincos(g.phi[a] - g.phi[b], &sn, &cs);
-                    const double xr = macc[N + 2 * u], xi = macc[N + 2 * u + 1];
-                    Sl[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
-                    Sl[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
-                }
-            const double w0 = g.w, w1 = MA ? g.w * g.c : 0.0;
+            for (int u = 0; u < NU; ++u) {
+                const double cs = zo[u][0], sn = zo[u][1];
+                const double xr = macc[N + 2 * u], xi = macc[N + 2 * u + 1];
+                Sl[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
+                Sl[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
+            }
+            const double w0 = wo, w1 = MA ? wo * co : 0.0;
+            double* out = rc.partial + (size_t)j * 2 * NM;
             for (int v = 0; v < NM; ++v) {
-                rc.partial[(size_t)v * rc.na + j] = w0 * Sl[v];
-                rc.partial[(size_t)(NM + v) * rc.na + j] = w1 * Sl[v];
+                out[v] = w0 * Sl[v];
+                out[NM + v] = w1 * Sl[v];
             }
         }
     }
     if constexpr (FINAL) {
-        __syncthreads();  // sred may still be read by the moment reduction
-        double e = wave_max(emax);
-        if ((threadIdx.x & 63) == 0) sred[0][threadIdx.x >> 6] = e;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double m = sred[0][0];
-            for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, sred[0][w]);
-            rc.errpart[j] = m;
-            // new phases of this trajectory (kept only if the attempt is accepted)
-            double* ph1 = rc.phase[cur ^ 1] + (size_t)j * N;
-            for (int a = 0; a < N; ++a) ph1[a] = sgeo[NST].phi[a];
-        }
+        const double e = wave_max(emax);
+        if (lane == 0) rc.errpart[j] = e;
     }
-
 }
 
 // Finalisation of launch I: one workgroup adds the per-trajectory partials
@@ -471,43 +498,52 @@ __global__ void __launch_bounds__(kBlock) k_stage(const RunConst rc)
 // it as its own launch (instead of a last-workgroup handoff inside k_stage)
 // avoids a device-scope fence in every workgroup: on gfx950 such a fence
 // writes back and invalidates the XCD's L2.
+constexpr int kFinBlock = 1024;
+
 template <int N, typename TAB, int I>
-__global__ void __launch_bounds__(kBlock) k_finalize(const RunConst rc)
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
 {
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
     constexpr int NM = Shape<N>::NM;
+    constexpr int NV = 2 * NM;
+    constexpr int NW = kFinBlock / 64;
     constexpr bool MOMENTS = !FINAL || !TAB::fsal;
-    __shared__ double sred[2 * NM + 1][kBlock / 64];
+    __shared__ double sred[NV + 1][NW];
 
     const Control* ctl = rc.ctrl;
     if (I > 0 && ctl->status != 0) return;
     const double h = ctl->h;
+    // contiguous trajectory range of this thread, summed in ascending order
+    const int per = (rc.na + kFinBlock - 1) / kFinBlock;
+    const int j0 = min(rc.na, (int)threadIdx.x * per), j1 = min(rc.na, j0 + per);
 
-    double* Jout = rc.jhist + (FINAL ? S : I) * 2 * NM;
+    double* Jout = rc.jhist + (FINAL ? S : I) * NV;
     if constexpr (MOMENTS) {
-        double acc[2 * NM];
+        double acc[NV];
 #pragma unroll
-        for (int v = 0; v < 2 * NM; ++v) acc[v] = 0.0;
-        for (int jj = threadIdx.x; jj < rc.na; jj += kBlock)
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        for (int jj = j0; jj < j1; ++jj) {
+            const double* src = rc.partial + (size_t)jj * NV;
 #pragma unroll
-            for (int v = 0; v < 2 * NM; ++v) acc[v] += rc.partial[(size_t)v * rc.na + jj];
-        block_sum<2 * NM>(acc, sred);
+            for (int v = 0; v < NV; ++v) acc[v] += src[v];
+        }
+        block_sum<NV, NW>(acc, sred);
         if (threadIdx.x == 0)
-            for (int v = 0; v < 2 * NM; ++v) Jout[v] = acc[v];
+            for (int v = 0; v < NV; ++v) Jout[v] = acc[v];
     }
     if constexpr (FINAL) {
         double m = 0.0;
-        for (int jj = threadIdx.x; jj < rc.na; jj += kBlock) m = fmax(m, rc.errpart[jj]);
+        for (int jj = j0; jj < j1; ++jj) m = fmax(m, rc.errpart[jj]);
         m = wave_max(m);
         __syncthreads();
         if ((threadIdx.x & 63) == 0) sred[0][threadIdx.x >> 6] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, sred[0][w]);
+            for (int w = 1; w < NW; ++w) m = fmax(m, sred[0][w]);
             Control& C = *rc.ctrl;
             C.attempts += 1;
-            const double* Jnext = rc.jhist + (TAB::fsal ? (S - 1) : S) * 2 * NM;
+            const double* Jnext = rc.jhist + (TAB::fsal ? (S - 1) : S) * NV;
             if constexpr (!TAB::embedded) {
                 // fixed step: always accepted
                 if (!(m <= 1.0e300)) { C.status = -4; }
@@ -517,7 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const RunConst rc)
                     C.cur ^= 1;
                     C.r = rc.r_start + (double)C.istep * rc.h_fixed;
                     C.h = rc.h_fixed;
-                    for (int v = 0; v < 2 * NM; ++v) rc.jhist[v] = Jnext[v];
+                    for (int v = 0; v < NV; ++v) rc.jhist[v] = Jnext[v];
                     if (C.istep >= rc.n_fixed || C.r >= C.r_end) C.status = 1;
                 }
             } else {
@@ -533,7 +569,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const RunConst rc)
                         C.r = rn;
                         C.nacc += 1;
                         C.cur ^= 1;
-                        for (int v = 0; v < 2 * NM; ++v) rc.jhist[v] = Jnext[v];
+                        for (int v = 0; v < NV; ++v) rc.jhist[v] = Jnext[v];
                         fac = (err == 0.0) ? f_hi : rc.safety * pow(err, -0.2);
                         fac = fmin(fmax(fac, f_lo), f_hi);
                         if (C.last_rejected && fac > 1.0) fac = 1.0;
@@ -644,8 +680,8 @@ hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s)
     }
     StageFn fin = pick_finalize(rc.n, rc.integrator, stage);
     if (!fn || !fin) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(rc.na), dim3(kBlock), 0, s, rc);
-    hipLaunchKernelGGL(fin, dim3(1), dim3(kBlock), 0, s, rc);
+    hipLaunchKernelGGL(fn, dim3(rc.na), dim3(64), 0, s, rc);
+    hipLaunchKernelGGL(fin, dim3(1), dim3(kFinBlock), 0, s, rc);
     return hipGetLastError();
 }
 

@@ -165,7 +165,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], inv_e, g, gbar, jhist, partial, errpart, ctrl, counter, prob, total;
+    size_t psi[2], phase[2], inv_e, g, gbar, jhist, partial, errpart, tab, ctrl, counter, prob, total;
     int64_t nb, nb_pad;
     int na;
 };
@@ -225,6 +225,7 @@ Layout make_layout(const nuosc_params& p)
     L.jhist = take((size_t)nuosc::kMaxStages * 2 * n * n * 8);
     L.partial = take((size_t)2 * n * n * L.na * 8);
     L.errpart = take((size_t)L.na * 8);
+    L.tab = take((size_t)nuosc::kMaxStages * L.na * sizeof(nuosc::TrajStage));
     L.ctrl = take(sizeof(Control));
     L.counter = take(2 * sizeof(unsigned));
     L.prob = take((size_t)L.nb * 8);
@@ -385,6 +386,7 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
+    rc.tab = (nuosc::TrajStage*)(base + L.tab);
     rc.ctrl = (Control*)(base + L.ctrl);
     rc.counter = (unsigned*)(base + L.counter);
     h->prob = (double*)(base + L.prob);
