@@ -155,6 +155,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-attempts", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32,fp32math64,fp64",
+                    help="precision forms to run (the first is the headline value)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this path runs on one GPU "
@@ -166,20 +168,24 @@ def main() -> int:
     from paper_1907_05560_amd import nuosc, workloads as W
 
     torch.cuda.init()
+    names = {"fp32": W.FP32_AMP, "fp32math64": W.FP32_AMP_FP64_MATH, "fp64": W.FP64}
+    order = [names[f] for f in args.forms.split(",")]
     forms = {}
     runs = {}
-    for prec in (W.FP32_AMP, W.FP32_AMP_FP64_MATH, W.FP64):
+    for prec in order:
         print(f"bench: precision {prec}: {args.warmup} warmup + {args.steps} timed attempts", file=sys.stderr, flush=True)
         run, form = run_form(nuosc, W, torch, prec, args.steps, args.warmup)
         forms[prec] = form
         runs[prec] = run
         print(f"bench: precision {prec}: {form['ms_per_step']:.3f} ms/step, {form['value']:.3e} beam-steps/s, "
               f"stages {[round(x * 1e3, 1) for x in form['stage_ms']]} us", file=sys.stderr, flush=True)
-    err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
+    err = None
+    if W.FP32_AMP in runs and W.FP64 in runs:
+        err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
     for r in runs.values():
         r.close()
 
-    head = forms[W.FP32_AMP]
+    head = forms[order[0]]
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -191,7 +197,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {W.FP32_AMP: "f32", W.FP32_AMP_FP64_MATH: "f32-storage/f64-math", W.FP64: "f64"}[order[0]],
         "data": "synthetic",
         "config": {
             "workload": "three-flavor multi-angle bulb model, 400 energies x 4000 angles x 2 species "
@@ -201,11 +207,8 @@ def main() -> int:
         },
         "roofline": roofline(head),
         "accepted_per_attempt": head["accepted"] / head["attempts"],
-        "fp32_amp_fp64_math": {"value": forms[W.FP32_AMP_FP64_MATH]["value"],
-                               "ms_per_step": forms[W.FP32_AMP_FP64_MATH]["ms_per_step"],
-                               "roofline": roofline(forms[W.FP32_AMP_FP64_MATH])},
-        "fp64": {"value": forms[W.FP64]["value"], "ms_per_step": forms[W.FP64]["ms_per_step"],
-                 "roofline": roofline(forms[W.FP64])},
+        "forms": {f: {"value": forms[names[f]]["value"], "ms_per_step": forms[names[f]]["ms_per_step"],
+                      "roofline": roofline(forms[names[f]])} for f in args.forms.split(",")},
         "fp32_vs_fp64_error": err,
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
     }
