@@ -193,13 +193,21 @@ __device__ __forceinline__ void block_sum(double* v, double (*lds)[NW])
     if (lane == 0)
         for (int i = 0; i < NV; ++i) lds[i][wave] = v[i];
     __syncthreads();
+    // value i is combined by thread i (waves in index order), then gathered
+    if ((int)threadIdx.x < NV) {
+        const int i = threadIdx.x;
+        double s = lds[i][0];
+        for (int w = 1; w < NW; ++w) s += lds[i][w];
+        lds[i][0] = s;
+    }
+    __syncthreads();
     if (threadIdx.x == 0)
-        for (int i = 0; i < NV; ++i) {
-            double s = lds[i][0];
-            for (int w = 1; w < NW; ++w) s += lds[i][w];
-            v[i] = s;
-        }
+        for (int i = 0; i < NV; ++i) v[i] = lds[i][0];
 }
+
+// Trajectories (wavefronts) per stage workgroup: their weighted sums are added
+// in wave order into one partial, so the finalise launch reads na / 4 partials.
+constexpr int kTrajPerBlock = 4;
 
 // Radius of stage l of the current attempt (l == S: the new state).
 template <typename TAB>
@@ -217,7 +225,7 @@ __device__ __forceinline__ double stage_radius(const RunConst& rc, const Control
 // here from J_{I-1} (its geometry and phase were set by launch I-1); the
 // output stage I gets its geometry and phase here.
 template <typename TS, typename T, int N, bool MA, typename TAB, int I>
-__global__ void __launch_bounds__(64) k_stage(const RunConst rc)
+__global__ void __launch_bounds__(64 * kTrajPerBlock) k_stage(const RunConst rc)
 {
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
@@ -228,40 +236,68 @@ __global__ void __launch_bounds__(64) k_stage(const RunConst rc)
     if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
     const int cur = ctl->cur;
     const double r = ctl->r, h = ctl->h;
-    const int j = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kTrajPerBlock + wave;
+    const bool active = j < rc.na;
 
-    __shared__ StageMat<T, N> smat[I > 0 ? I : 1];
-    __shared__ double sG[kMaxStages][N];
+    __shared__ StageMat<T, N> smat_all[kTrajPerBlock][I > 0 ? I : 1];
+    __shared__ double sG_all[kTrajPerBlock][kMaxStages][N];
+    __shared__ double spart[kTrajPerBlock][2 * NM + 1];
+    StageMat<T, N>* smat = smat_all[wave];
+
+    // ---- amplitudes stream through a two-deep register pipeline: the loads of
+    //      the next two beams of this lane are in flight while one is computed
+    //      (the first two are issued before the prologue).
+    const TS* __restrict__ src = psi_ptr<TS>(rc, cur);
+    TS* __restrict__ dst = psi_ptr<TS>(rc, cur ^ 1);
+    const int64_t ld = rc.nb_pad;
+    const int nbt = active ? 2 * rc.ne : 0;  // beams of this trajectory
+    auto beam_index = [&](int t) {
+        const int s = (t >= rc.ne) ? 1 : 0;
+        return ((int64_t)s * rc.na + j) * rc.ne + (t - s * rc.ne);
+    };
+    auto fetch = [&](int t, TS* v) {
+        if (t < nbt) {
+            const int64_t b = beam_index(t);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) v[q] = src[q * ld + b];
+        }
+    };
+    TS ynext0[2 * N], ynext1[2 * N];
+    fetch(lane, ynext0);
+    fetch(lane + 64, ynext1);
 
     // ---- stored Hamiltonian pieces of stages 0..I-2 -> LDS (both species)
     if constexpr (I >= 2) {
-        constexpr int PER = 2 * NM;  // A then B, packed
-        for (int idx = lane; idx < (I - 1) * PER; idx += 64) {
-            const int l = idx / PER, q = idx - l * PER;
-            const TrajStage& e = rc.tab[(size_t)l * rc.na + j];
-            const int m = q < NM ? 0 : 1;       // 0: A, 1: B
-            const int x = q - m * NM;
-            const double v = m == 0 ? e.A[x] : e.B[x];
-            SpeciesMat<T, N>& nu = smat[l].sp[0];
-            SpeciesMat<T, N>& nb = smat[l].sp[1];
-            if (x < N) {
-                if (m == 0) { nu.ad[x] = (T)v; nb.ad[x] = (T)(-v); }
-                else { nu.bd[x] = (T)v; nb.bd[x] = (T)v; }
-            } else {
-                const int u = (x - N) >> 1, ri = (x - N) & 1;
-                // nubar: A -> -conj(A), B -> conj(B)
-                if (m == 0) { nu.au[u][ri] = (T)v; nb.au[u][ri] = (T)(ri ? v : -v); }
-                else { nu.bu[u][ri] = (T)v; nb.bu[u][ri] = (T)(ri ? -v : v); }
+        if (active) {
+            constexpr int PER = 2 * NM;  // A then B, packed
+            for (int idx = lane; idx < (I - 1) * PER; idx += 64) {
+                const int l = idx / PER, q = idx - l * PER;
+                const TrajStage& e = rc.tab[(size_t)l * rc.na + j];
+                const int m = q < NM ? 0 : 1;       // 0: A, 1: B
+                const int x = q - m * NM;
+                const double v = m == 0 ? e.A[x] : e.B[x];
+                SpeciesMat<T, N>& nu = smat[l].sp[0];
+                SpeciesMat<T, N>& nb = smat[l].sp[1];
+                if (x < N) {
+                    if (m == 0) { nu.ad[x] = (T)v; nb.ad[x] = (T)(-v); }
+                    else { nu.bd[x] = (T)v; nb.bd[x] = (T)v; }
+                } else {
+                    const int u = (x - N) >> 1, ri = (x - N) & 1;
+                    // nubar: A -> -conj(A), B -> conj(B)
+                    if (m == 0) { nu.au[u][ri] = (T)v; nb.au[u][ri] = (T)(ri ? v : -v); }
+                    else { nu.bu[u][ri] = (T)v; nb.bu[u][ri] = (T)(ri ? -v : v); }
+                }
             }
         }
     }
 
     // ---- lane 0: complete stage I-1, then geometry and phase of stage I (FP64)
     double zo[NU > 0 ? NU : 1][2], co = 1.0, wo = 0.0, pho[N];
-    if (lane == 0) {
+    if (active && lane == 0) {
         const double* ph0 = rc.phase[cur] + (size_t)j * N;
-        double (*G)[N] = sG;
+        double (*G)[N] = sG_all[wave];
         for (int l = 0; l + 1 < I; ++l)
             for (int a = 0; a < N; ++a) G[l][a] = rc.tab[(size_t)l * rc.na + j].G[a];
         if constexpr (I >= 1) {
@@ -358,25 +394,26 @@ __global__ void __launch_bounds__(64) k_stage(const RunConst rc)
     // compile-time constants (scalar operands), only h is a runtime value.
     const T hT = (T)h;
 
-    const TS* __restrict__ src = psi_ptr<TS>(rc, cur);
-    TS* __restrict__ dst = psi_ptr<TS>(rc, cur ^ 1);
-    const int64_t ld = rc.nb_pad;
     double macc[NM];
 #pragma unroll
     for (int i = 0; i < NM; ++i) macc[i] = 0.0;
     double emax = 0.0;
 
 #pragma unroll 1
-    for (int t = lane; t < 2 * rc.ne; t += 64) {
+    for (int t = lane; t < nbt; t += 64) {
+        const int s = (t >= rc.ne) ? 1 : 0;
+        const int k = t - s * rc.ne;
+        const int64_t b = beam_index(t);
+        T y[2 * N];
+#pragma unroll
+        for (int q = 0; q < 2 * N; ++q) {
+            y[q] = (T)ynext0[q];
+            ynext0[q] = ynext1[q];
+        }
+        fetch(t + 128, ynext1);
         // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
         // LDS each iteration instead of keeping both species' copies in VGPRs.
         asm volatile("" ::: "memory");
-        const int s = (t >= rc.ne) ? 1 : 0;
-        const int k = t - s * rc.ne;
-        const int64_t b = ((int64_t)s * rc.na + j) * rc.ne + k;
-        T y[2 * N];
-#pragma unroll
-        for (int q = 0; q < 2 * N; ++q) y[q] = (T)src[q * ld + b];
         const T inv_e = (T)rc.inv_e[k];
 
         T kk[I > 0 ? I : 1][2 * N];
@@ -464,11 +501,15 @@ __global__ void __launch_bounds__(64) k_stage(const RunConst rc)
         }
     }
 
-    // ---- wave reduction and per-trajectory output (lane 0)
+    // ---- wave reduction, per-trajectory weighting, then the block's trajectories
+    //      in wave order (fixed) into one partial per block
     if constexpr (MOMENTS) {
 #pragma unroll
         for (int i = 0; i < NM; ++i) macc[i] = wave_sum(macc[i]);
         if (lane == 0) {
+            for (int v = 0; v < 2 * NM; ++v) spart[wave][v] = 0.0;
+        }
+        if (active && lane == 0) {
             // lab frame: S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa
             double Sl[NM];
             for (int a = 0; a < N; ++a) Sl[a] = 2.0 * macc[a];
@@ -479,16 +520,26 @@ __global__ void __launch_bounds__(64) k_stage(const RunConst rc)
                 Sl[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
             }
             const double w0 = wo, w1 = MA ? wo * co : 0.0;
-            double* out = rc.partial + (size_t)j * 2 * NM;
             for (int v = 0; v < NM; ++v) {
-                out[v] = w0 * Sl[v];
-                out[NM + v] = w1 * Sl[v];
+                spart[wave][v] = w0 * Sl[v];
+                spart[wave][NM + v] = w1 * Sl[v];
             }
         }
     }
     if constexpr (FINAL) {
         const double e = wave_max(emax);
-        if (lane == 0) rc.errpart[j] = e;
+        if (lane == 0) spart[wave][2 * NM] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NM + 1) {
+        const int v = threadIdx.x;
+        const bool is_err = (v == 2 * NM);
+        if ((MOMENTS && !is_err) || (FINAL && is_err)) {
+            double acc = spart[0][v];
+            for (int w = 1; w < kTrajPerBlock; ++w) acc = is_err ? fmax(acc, spart[w][v]) : acc + spart[w][v];
+            if (is_err) rc.errpart[blockIdx.x] = acc;
+            else rc.partial[(size_t)blockIdx.x * 2 * NM + v] = acc;
+        }
     }
 }
 
@@ -514,9 +565,10 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
     const Control* ctl = rc.ctrl;
     if (I > 0 && ctl->status != 0) return;
     const double h = ctl->h;
-    // contiguous trajectory range of this thread, summed in ascending order
-    const int per = (rc.na + kFinBlock - 1) / kFinBlock;
-    const int j0 = min(rc.na, (int)threadIdx.x * per), j1 = min(rc.na, j0 + per);
+    // one partial per stage block; contiguous ranges summed in ascending order
+    const int nparts = (rc.na + kTrajPerBlock - 1) / kTrajPerBlock;
+    const int per = (nparts + kFinBlock - 1) / kFinBlock;
+    const int j0 = min(nparts, (int)threadIdx.x * per), j1 = min(nparts, j0 + per);
 
     double* Jout = rc.jhist + (FINAL ? S : I) * NV;
     if constexpr (MOMENTS) {
@@ -680,7 +732,7 @@ hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s)
     }
     StageFn fin = pick_finalize(rc.n, rc.integrator, stage);
     if (!fn || !fin) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(rc.na), dim3(64), 0, s, rc);
+    hipLaunchKernelGGL(fn, dim3((rc.na + kTrajPerBlock - 1) / kTrajPerBlock), dim3(64 * kTrajPerBlock), 0, s, rc);
     hipLaunchKernelGGL(fin, dim3(1), dim3(kFinBlock), 0, s, rc);
     return hipGetLastError();
 }
