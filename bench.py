@@ -19,7 +19,6 @@ GPU (the angle-sharded multi-GPU design is described, not built).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,13 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "beam-steps/s at 1 GPU (FP32-amp vs FP64) @1e-4 prob error; p50/p99 latency"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-KERNEL_SRC = os.path.join(ROOT, "paper_1907_05560_amd", "csrc", "nuosc_kernels.hip")
+# Vector ALU peaks (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz = 78.6
+# TFLOP/s for FP64 and for unpacked FP32; packed FP32 doubles the FP32 figure).
+PEAK_FP32_TFS = 157.3
+PEAK_FP64_TFS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-
-
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def run_form(nuosc, W, torch, precision, steps, warmup):
@@ -78,36 +75,94 @@ def run_form(nuosc, W, torch, precision, steps, warmup):
     return run, out
 
 
+# Nonzero counts of the tableau rows (stage inputs 1..S-1, then the solution
+# weights) and of the error weights, for the flop model below.
+_NNZ = {
+    "rk4": dict(S=4, fsal=False, rows=[1, 1, 1], sol=4, err=0),
+    "dp54": dict(S=7, fsal=True, rows=[1, 2, 3, 4, 5, 5], sol=5, err=6),
+}
+
+
+def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
+    """Flops per beam of stage launch `stage` (FMA = 2) in the recompute design.
+
+    One derivative k = -i (A + B/E) y: n^2 FMAs to form the Hermitian matrix,
+    2n multiplies for its diagonal and n(n-1) complex multiply-adds (4 FMAs) for
+    the off-diagonals.  Launch I evaluates k_0..k_{I-1}, forms the inputs of
+    stages 1..I (2n reals x (nonzeros + 1) FMAs each), the moments of its output
+    state (n diagonal terms of 5 flops, n(n-1)/2 off-diagonal pairs of 10), and
+    in the final launch the embedded error and the FP32 renormalisation."""
+    t = _NNZ[integrator]
+    S = t["S"]
+    f_eval = 2 * n * n + 2 * n + 8 * n * (n - 1)
+    flops = stage * f_eval
+    last_row = min(stage, S - 1)
+    for l in range(1, last_row + 1):
+        nnz = t["rows"][l - 1]
+        flops += 2 * n * (nnz + 1) * 2
+    final = stage == S
+    if final and not t["fsal"]:
+        flops += 2 * n * (t["sol"] + 1) * 2
+    if not final or not t["fsal"]:
+        flops += 5 * n + 10 * n * (n - 1) // 2
+    if final and t["err"]:
+        flops += 2 * n * (t["err"] * 2 + 1)
+    if fp32_storage and (final or (t["fsal"] and stage == S - 1)):
+        flops += 6 * n + 2
+    return flops
+
+
 def roofline(form):
-    """HBM roofline of the dominant kernel: algorithmic bytes per launch / its
-    mean duration.  Stage launches read y_n once (NB x S bytes, S = 2n
-    amplitude reals); the final launch also writes y_{n+1}."""
+    """Roofline of the dominant kernel (the slowest stage launch).
+
+    HBM view: algorithmic bytes per launch (stage launches read y_n once, N_b x
+    2n amplitude reals; the final launch also writes y_{n+1}) / the launch's
+    mean duration.  ALU view: stage_flops x N_b / duration against the vector
+    peak of the arithmetic type.  The reported bound is the view with the
+    larger fraction of its peak; the other view is kept alongside."""
     S = len(form["stage_ms"])
     dom = max(range(S), key=lambda i: form["stage_ms"][i])
+    stage = dom + 1
     state_bytes = 2 * form["n"] * form["amp_bytes"] * form["beams"]
-    alg_bytes = state_bytes * (2 if dom == S - 1 else 1)
+    alg_bytes = state_bytes * (2 if stage == S else 1)
     dur_s = form["stage_ms"][dom] / 1e3
-    achieved = alg_bytes / dur_s / 1e9
+    gbs = alg_bytes / dur_s / 1e9
+    fp32_math = form["precision"] == 1
+    flops = stage_flops(form["n"], "dp54" if S == 7 else "rk4", stage, form["amp_bytes"] == 4) * form["beams"]
+    tfs = flops / dur_s / 1e12
+    peak_alu = PEAK_FP32_TFS if fp32_math else PEAK_FP64_TFS
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
+            from paper_1907_05560_amd.profile_summary import kernel_source_hash
+
             t = json.load(open(TRAFFIC_FILE))
-            key = f"stage{dom + 1}_prec{form['precision']}"
+            key = f"stage{stage}_prec{form['precision']}"
             if t.get("kernel_source_sha256_16") == kernel_source_hash() and key in t.get("bytes_per_launch", {}):
                 traffic = t["bytes_per_launch"][key]
         except (OSError, ValueError):
             traffic = None
-    return {
-        "bound": "hbm",
-        "kernel": f"k_stage stage {dom + 1}/{S}",
-        "achieved": round(achieved, 1),
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
+    hbm = {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+           "alg_bytes_per_launch": alg_bytes}
+    alu = {"achieved": round(tfs, 2), "peak": peak_alu, "unit": "TFLOP/s", "frac": round(tfs / peak_alu, 4),
+           "alg_flops_per_launch": flops, "frac_of_unpacked_peak": round(tfs / PEAK_FP64_TFS, 4)}
+    use_alu = alu["frac"] > hbm["frac"]
+    head = alu if use_alu else hbm
+    out = {
+        "bound": "alu" if use_alu else "hbm",
+        "kernel": f"k_stage stage {stage}/{S}",
+        "achieved": head["achieved"],
+        "peak": head["peak"],
+        "unit": head["unit"],
+        "frac": head["frac"],
         "traffic": traffic,
-        "alg_bytes_per_launch": alg_bytes,
         "mean_launch_us": round(dur_s * 1e6, 2),
+        "hbm": hbm,
+        "alu": alu,
     }
+    if traffic is not None:
+        out["traffic_gbs"] = round(traffic / dur_s / 1e9, 1)
+    return out
 
 
 def cpu_baseline(W, attempts):
@@ -157,6 +212,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32,fp32math64,fp64",
                     help="precision forms to run (the first is the headline value)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a device buffer of this size (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this path runs on one GPU "
@@ -168,6 +225,13 @@ def main() -> int:
     from paper_1907_05560_amd import nuosc, workloads as W
 
     torch.cuda.init()
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib * 2 ** 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     names = {"fp32": W.FP32_AMP, "fp32math64": W.FP32_AMP_FP64_MATH, "fp64": W.FP64}
     order = [names[f] for f in args.forms.split(",")]
     forms = {}

@@ -1,0 +1,179 @@
+"""Summaries of rocprofv3 output for the stage kernels (text for profiles/).
+
+Two inputs, both written by ``rocprofv3`` runs of ``bench.py``:
+
+* a kernel-trace run (``--kernel-trace --stats``): its ``*_kernel_trace.csv``
+  gives the duration of every dispatch;
+* two counter runs (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``) of a bench
+  invocation that also copies a buffer of known size
+  (``bench.py --copy-calibration-mib M``).  The HBM counters are scaled by
+  the ratio between the bytes that copy moves (M MiB read and M MiB written)
+  and what the same counter reports for it, so the stage-kernel figures are
+  in bytes that a plain copy would count as moved.
+
+Dispatches made after a run has reached its end radius (the attempts a host
+loop enqueues past the end) return at once; a dispatch is counted as such, and
+left out of the means, when its duration (or counter value) is below a quarter
+of the largest one of the same kernel.
+
+Usage::
+
+    python -m paper_1907_05560_amd.profile_summary trace <kernel_trace.csv> --command "..." > profiles/x.md
+    python -m paper_1907_05560_amd.profile_summary traffic --fetch <csv> --write <csv> \
+        --copy-mib M --command-fetch "..." --command-write "..." \
+        --json profiles/traffic.json > profiles/y.md
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(_HERE, "csrc", "nuosc_kernels.hip")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """k_stage<float, float, 3, true, TabDP54, 7> -> 'k_stage<float,float,3,MA,DP54,7>'."""
+    n = name.replace("nuosc::(anonymous namespace)::", "").replace("void ", "")
+    n = re.sub(r"\(nuosc::RunConst.*\)$", "", n)
+    n = n.replace("TabDP54", "DP54").replace("TabRK4", "RK4").replace(" ", "")
+    return n
+
+
+def stage_key(name: str):
+    """(stage, precision) of a k_stage instantiation, or None."""
+    m = re.search(r"k_stage<(\w+),(\w+),(\d),(\w+),\w+,(\d)>", short_name(name))
+    if not m:
+        return None
+    ts, t, _, _, stage = m.groups()
+    prec = 0 if ts == "double" else (1 if t == "float" else 2)
+    return int(stage), prec
+
+
+def _full(values):
+    """Values of full dispatches (at least a quarter of the largest)."""
+    if not values:
+        return []
+    top = max(values)
+    return [v for v in values if v >= 0.25 * top]
+
+
+def trace_summary(trace_csv: str, command: str) -> str:
+    per = collections.defaultdict(list)
+    regs = {}
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"]
+        per[name].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        regs[name] = (r["VGPR_Count"], r["Accum_VGPR_Count"], r["SGPR_Count"], r["LDS_Block_Size"],
+                      r["Workgroup_Size_X"], r["Grid_Size_X"])
+    total = sum(sum(v) for v in per.values())
+    out = ["# Kernel trace summary", "", "Command:", "", "```", command, "```", "",
+           "Means are over full dispatches; `early` counts dispatches that returned at once because the "
+           "run had already reached its end radius.", "",
+           "| kernel | full | early | mean us | min us | max us | share % | VGPR | AGPR | SGPR | LDS B | WG | grid |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name in sorted(per, key=lambda n: -sum(per[n])):
+        v = per[name]
+        f = _full(v)
+        vg, ag, sg, lds, wg, grid = regs[name]
+        out.append(f"| `{short_name(name)}` | {len(f)} | {len(v) - len(f)} | {sum(f) / len(f):.2f} | "
+                   f"{min(f):.2f} | {max(f):.2f} | {100 * sum(v) / total:.2f} | {vg} | {ag} | {sg} | {lds} | "
+                   f"{wg} | {grid} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter_means(path: str, counter: str):
+    """Mean counter value (KiB as reported) per kernel name; copy kernel: per-dispatch values."""
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, copy_mib: float, cmd_f: str, cmd_w: str):
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    copy_bytes = copy_mib * 2 ** 20
+    # the calibration copy is the largest copy dispatch of the run
+    cf = max(fetch.get(COPY_KERNEL, [0.0]))
+    cw = max(write.get(COPY_KERNEL, [0.0]))
+    if cf <= 0 or cw <= 0:
+        raise SystemExit("calibration copy kernel not found in the counter runs")
+    scale_f = copy_bytes / (cf * 1024.0)
+    scale_w = copy_bytes / (cw * 1024.0)
+    per_launch = {}
+    lines = ["# HBM traffic of the stage kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+             "Commands:", "", "```", cmd_f, cmd_w, "```", "",
+             f"Calibration: a device-to-device copy of {copy_mib:g} MiB ({COPY_KERNEL}) reads "
+             f"{cf:.0f} KiB by FETCH_SIZE and writes {cw:.0f} KiB by WRITE_SIZE, so FETCH_SIZE is scaled by "
+             f"{scale_f:.3f} and WRITE_SIZE by {scale_w:.3f}.", "",
+             f"Kernel source sha256[:16]: `{kernel_source_hash()}`", "",
+             "| kernel | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | read MB (scaled) | write MB (scaled) | total MB |",
+             "|---|---|---|---|---|---|---|"]
+    for name in sorted(set(fetch) | set(write), key=lambda n: (stage_key(n) or (99, 9), n)):
+        if name == COPY_KERNEL:
+            continue
+        f = fetch.get(name, [])
+        w = write.get(name, [])
+        if not f or not w:
+            continue
+        f, w = _full(f), _full(w)
+        fm, wm = sum(f) / len(f), sum(w) / len(w)
+        rb, wb = fm * 1024 * scale_f, wm * 1024 * scale_w
+        lines.append(f"| `{short_name(name)}` | {len(f)} | {fm:.0f} | {wm:.0f} | {rb / 1e6:.2f} | "
+                     f"{wb / 1e6:.2f} | {(rb + wb) / 1e6:.2f} |")
+        k = stage_key(name)
+        if k:
+            per_launch[f"stage{k[0]}_prec{k[1]}"] = round(rb + wb)
+    doc = {
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "copy_calibration_mib": copy_mib,
+        "fetch_scale": scale_f,
+        "write_scale": scale_w,
+        "bytes_per_launch": per_launch,
+    }
+    return "\n".join(lines) + "\n", doc
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("trace_csv")
+    t.add_argument("--command", required=True)
+    f = sub.add_parser("traffic")
+    f.add_argument("--fetch", required=True)
+    f.add_argument("--write", required=True)
+    f.add_argument("--copy-mib", type=float, required=True)
+    f.add_argument("--command-fetch", required=True)
+    f.add_argument("--command-write", required=True)
+    f.add_argument("--json", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        sys.stdout.write(trace_summary(a.trace_csv, a.command))
+    else:
+        text, doc = traffic_summary(a.fetch, a.write, a.copy_mib, a.command_fetch, a.command_write)
+        with open(a.json, "w") as fh:
+            json.dump(doc, fh, indent=1)
+            fh.write("\n")
+        sys.stdout.write(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
