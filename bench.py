@@ -37,29 +37,32 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def run_form(nuosc, W, torch, precision, steps, warmup):
-    """Time `steps` attempts of one precision form; per-stage HIP events on the
-    run's own stream give the kernel durations."""
+    """Time `steps` attempts of one precision form on the run's own stream.
+
+    Two passes over the same number of attempts: the first is timed as a
+    whole (HIP events around it) and gives the throughput; in the second the
+    library records events around every beam kernel and finalise kernel,
+    which gives the per-kernel durations."""
     w = W.multi_angle_3f_large(precision)
     run = nuosc.Run.with_torch(w)
     stream = run.torch_stream
     S = run.num_stages
     run.step(warmup)
     s0 = run.stats()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(S + 1)] for _ in range(steps)]
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    for k in range(steps):
-        ev[k][0].record(stream)
-        for st in range(1, S + 1):
-            run.enqueue_stage(st)
-            ev[k][st].record(stream)
+    run.enqueue_steps(steps)
     t1.record(stream)
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
     s1 = run.stats()
-    stage_ms = [sum(ev[k][st - 1].elapsed_time(ev[k][st]) for k in range(steps)) / steps for st in range(1, S + 1)]
+    run.timing_enable(True)
+    run.enqueue_steps(steps)
+    beam, fin, cnt = run.timing_read()
+    run.timing_enable(False)
     accepted = s1["accepted"] - s0["accepted"]
+    n = [max(int(c), 1) for c in cnt]
     out = dict(
         precision=precision,
         beams=run.nb,
@@ -67,7 +70,8 @@ def run_form(nuosc, W, torch, precision, steps, warmup):
         accepted=accepted,
         ms_per_step=total_ms / steps,
         value=run.nb * accepted / (total_ms / 1e3),
-        stage_ms=stage_ms,
+        stage_ms=[beam[st] / n[st] for st in range(1, S + 1)],
+        fin_ms=[fin[st] / n[st] for st in range(1, S + 1)],
         r_km=s1["r_km"],
         amp_bytes=4 if precision != W.FP64 else 8,
         n=run.n,
@@ -107,7 +111,7 @@ def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
         flops += 5 * n + 10 * n * (n - 1) // 2
     if final and t["err"]:
         flops += 2 * n * (t["err"] * 2 + 1)
-    if fp32_storage and (final or (t["fsal"] and stage == S - 1)):
+    if fp32_storage and stage == (S - 1 if t["fsal"] else S):
         flops += 6 * n + 2
     return flops
 
@@ -115,16 +119,18 @@ def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
 def roofline(form):
     """Roofline of the dominant kernel (the slowest stage launch).
 
-    HBM view: algorithmic bytes per launch (stage launches read y_n once, N_b x
-    2n amplitude reals; the final launch also writes y_{n+1}) / the launch's
-    mean duration.  ALU view: stage_flops x N_b / duration against the vector
+    HBM view: algorithmic bytes per launch (every beam launch reads y_n once,
+    N_b x 2n amplitude reals; the launch that forms y_{n+1} -- the last one,
+    or the one before it for a first-same-as-last pair -- also writes it) /
+    the launch's mean duration.  ALU view: stage_flops x N_b / duration against the vector
     peak of the arithmetic type.  The reported bound is the view with the
     larger fraction of its peak; the other view is kept alongside."""
     S = len(form["stage_ms"])
     dom = max(range(S), key=lambda i: form["stage_ms"][i])
     stage = dom + 1
     state_bytes = 2 * form["n"] * form["amp_bytes"] * form["beams"]
-    alg_bytes = state_bytes * (2 if stage == S else 1)
+    write_stage = S - 1 if S == 7 else S
+    alg_bytes = state_bytes * (2 if stage == write_stage else 1)
     dur_s = form["stage_ms"][dom] / 1e3
     gbs = alg_bytes / dur_s / 1e9
     fp32_math = form["precision"] == 1
@@ -242,7 +248,8 @@ def main() -> int:
         forms[prec] = form
         runs[prec] = run
         print(f"bench: precision {prec}: {form['ms_per_step']:.3f} ms/step, {form['value']:.3e} beam-steps/s, "
-              f"stages {[round(x * 1e3, 1) for x in form['stage_ms']]} us", file=sys.stderr, flush=True)
+              f"beam kernels {[round(x * 1e3, 1) for x in form['stage_ms']]} us, "
+              f"finalise {[round(x * 1e3, 1) for x in form['fin_ms']]} us", file=sys.stderr, flush=True)
     err = None
     if W.FP32_AMP in runs and W.FP64 in runs:
         err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
@@ -275,6 +282,7 @@ def main() -> int:
                       "roofline": roofline(forms[names[f]])} for f in args.forms.split(",")},
         "fp32_vs_fp64_error": err,
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
+        "finalize_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
     }
     if not args.no_cpu_baseline:
         print(f"bench: cpu baseline ({args.cpu_attempts} oracle attempts)", file=sys.stderr, flush=True)

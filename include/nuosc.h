@@ -152,6 +152,19 @@ nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage);
 /* Number of launches S of one step attempt. */
 int32_t nuosc_num_stages(const nuosc_handle* h);
 
+/* Kernel timing for measurement tools.  While enabled, every stage launch
+ * records HIP events on the handle's stream before its beam kernel, between
+ * the beam kernel and its finalise kernel, and after the finalise kernel.
+ * nuosc_timing_read waits for the stream, adds the elapsed times of all
+ * launches recorded since the last read into per-stage sums and writes them:
+ * beam_ms and fin_ms (milliseconds, nuosc_num_stages(h) + 1 entries each,
+ * index = stage, 0 being the moment launch of create / set_state / moments)
+ * and count (launches per stage, same length); each pointer nullable.  The
+ * sums are cleared by the read.  Enabling or disabling clears them too.
+ * Timing adds three event records per launch and changes no result. */
+nuosc_status nuosc_timing_enable(nuosc_handle* h, int32_t on);
+nuosc_status nuosc_timing_read(nuosc_handle* h, double* beam_ms, double* fin_ms, int64_t* count);
+
 /* Evolve until r = min(r_target, r_end) (the last step is clipped to land on
  * it), or until max_steps / max_wall_s is reached (NUOSC_E_LIMIT). */
 nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km);

@@ -7,8 +7,13 @@
 
 namespace nuosc {
 
-// Device control block of one run.  Kernels read r, h and cur at entry; only
-// the last workgroup of the final stage kernel of a step writes it.
+// Device control block of one run.  Two copies live on the device: ctrl[1] is
+// the state between attempts (the host reads and writes it; the stage-0
+// kernels and the first stage kernel of an attempt read it), ctrl[0] the copy
+// the rest of an attempt reads.  The first stage kernel of an attempt copies
+// ctrl[1] into ctrl[0]; the finalise kernel of the last stage writes the
+// updated block into ctrl[1].  No kernel reads a copy that a workgroup of the
+// same launch writes.
 struct Control {
     double r;          // radius of the current accepted state y_n
     double h;          // step of the next attempt (clipped to r_end)
@@ -23,52 +28,70 @@ struct Control {
 };
 
 // Packed Hermitian n x n matrix: n real diagonal entries followed by the
-// upper triangle (a < b, row-major) as (re, im) pairs: n*n doubles in total.
-template <int N> struct Herm { static constexpr int size = N * N; };
+// upper triangle (a < b, row-major) as (re, im) pairs, n*n reals in total.
+template <int N> struct Shape {
+    static constexpr int NU = N * (N - 1) / 2;  // upper off-diagonal entries
+    static constexpr int NM = N * N;            // reals of a packed Hermitian matrix
+    __host__ __device__ static constexpr int up(int a, int b) { return a * N - a * (a + 1) / 2 + (b - a - 1); }
+};
 
-// FP64 Hamiltonian pieces of one trajectory at one stage of the current
-// attempt, written by the launch that completes the stage and read by later
-// launches of the same attempt.  A, B: K~ = A + B / E of neutrinos, packed as
-// n real diagonal entries then the upper triangle (re, im).
-struct TrajStage {
-    double c, w;        // propagation cosine and angle weight at the stage radius
-    double G[3];        // d Phi / dr of the co-rotating frame
-    double phi[3];      // stage phase
-    double z[3][2];     // e^{i(phi_a - phi_b)}, upper pairs
-    double A[9];
-    double B[9];
+// Stage matrix of one trajectory in the co-rotating frame, K = A + B u with
+// u = +1/E for neutrinos and u = -1/E for antineutrinos (whose amplitudes are
+// held complex-conjugated on the device).  Packed Hermitian, A then B, in the
+// arithmetic type T of the stage kernels.  Written by the finalise kernel
+// that completes the stage, read by the stage kernels of the same attempt.
+template <typename T, int N> struct alignas(16) StageMat {
+    T a[Shape<N>::NM];
+    T b[Shape<N>::NM];
+};
+constexpr size_t kStageMatBytes = sizeof(StageMat<double, 3>);
+
+// FP64 geometry and frame data of one trajectory at one stage radius.
+struct TrajGeo {
+    double c, w, wc, ic;  // cos(theta), angle weight w, w*c (0 single angle), 1/c
+    double G[3];          // d Phi / dr of the co-rotating frame at this stage
+    double z[3][2];       // e^{i(Phi_a - Phi_b)}, upper pairs
 };
 
 // Everything a kernel needs about a run, passed by value.
 struct RunConst {
     int32_t n, ne, na, ma;       // flavors, energy bins, trajectories, multi-angle flag
     int64_t nb, nb_pad;          // beams, padded stride of one component array
-    int32_t frame, precision, integrator, pad0;
+    int32_t frame, precision, integrator, nblk;  // nblk: stage workgroups (partials)
     double r_nu, mu0, lambda0, lambda_rref, lambda_power;
     double rtol, safety, dr_max;
     double r_start, h_fixed;
     int64_t n_fixed, max_steps;
     double vac[3][3][2];         // H_vac(E) = vac * (1/E), traceless, complex
     // device buffers
-    void* psi[2];                // state buffers: [2n][nb_pad] of T
+    void* psi[2];                // state buffers: [2n][nb_pad] of the storage type
     double* phase[2];            // [na][n]
-    const double* inv_e;         // [ne]
-    const double* g;             // [ne]  neutrino weights
-    const double* gbar;          // [ne]  antineutrino weights
-    double* jhist;               // [8][2][n*n] packed J0, J1 per stage
-    double* partial;             // [na][2*n*n] per-trajectory weighted sums
-    double* errpart;             // [na]
-    TrajStage* tab;              // [kMaxStages][na]
-    Control* ctrl;
-    unsigned* counter;           // [2] last-block counters
+    const double* uinv64;        // [2 ne] signed 1/E per beam slot of a trajectory
+    const float* uinv32;         // [2 ne] the same in FP32
+    const double* wgt;           // [2 ne] g (neutrino slots), -gbar (antineutrino slots)
+    double* jhist;               // [kMaxStages + 1][2 n n] packed J0, J1 per stage
+    double* partial;             // [2 n n][nblk] per-workgroup weighted sums (value-major)
+    double* errpart;             // [nblk]
+    void* mat;                   // [kMaxStages][na] StageMat<T, n>
+    TrajGeo* geo;                // [kMaxStages + 1][na]
+    Control* ctrl;               // [2]
 };
 
-constexpr int kBlock = 256;
 constexpr int kMaxStages = 8;
+constexpr int kFinBlock = 256;     // threads per finalise workgroup
 
-// Launch the kernel that forms stage `stage` of the current attempt (stage 0 =
-// moments of the current state; stage == S = final: new state, error, control).
-hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s);
+// Trajectories per beam workgroup (one partial density sum each): 16 for the
+// FP32-arithmetic form, 8 for the FP64-arithmetic forms.
+inline int traj_per_block(int precision) { return precision == 1 ? 16 : 8; }
+
+// One stage of the current attempt: the stage kernel (stage 0 = moments of
+// the current state; stage == S = final launch) followed by its finalise
+// kernel.  ev, if not null, receives three events: before the stage kernel,
+// between the two kernels, after the finalise kernel.
+hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
+// Geometry and frame factors of stage 0 for the current state (before a
+// stage-0 launch).
+hipError_t launch_prepare(const RunConst& rc, hipStream_t s);
 hipError_t launch_probabilities(const RunConst& rc, double* p_dev, hipStream_t s);
 hipError_t launch_init_state(const RunConst& rc, hipStream_t s);
 int num_stages(int integrator);

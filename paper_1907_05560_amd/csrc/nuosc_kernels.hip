@@ -1,22 +1,33 @@
 // gfx950 kernels of the bulb-model flavor evolution.
 //
 // One step attempt of an explicit Runge-Kutta tableau with S stages runs as S
-// launches of k_stage<..., I> for I = 1..S.  Launch I:
-//   * per trajectory j (one workgroup): rebuilds, in FP64, the per-trajectory
-//     Hamiltonian pieces of stages 0..I-1 from the broadcast moments J_0..J_{I-1}
-//     (geometry eq 3.14-3.15, matter eq 3.7, self-interaction eq 3.13/3.16,
-//     co-rotating phases) and stores them in LDS as K~ = A + B / E;
-//   * per beam (one lane): reads y_n once, recomputes k_0..k_{I-1}, forms the
-//     stage state Y_I (or the new state for I = S) and accumulates its
-//     contribution to the per-trajectory density sum in FP64;
-//   * the workgroup reduces its sum (wave shuffles, then LDS, fixed order),
-//     rotates it to the lab frame, weights it by w_j and w_j c_j and writes
-//     it; the last workgroup to finish adds all trajectories in a fixed order
-//     into J_I (deterministic), or for I = S reduces the step error and runs
-//     the step controller.
-// Only y_n is read from HBM per launch and only y_{n+1} is written (in the
-// final launch): every stage derivative is recomputed from y_n and the small
-// J history instead of being stored.
+// pairs of launches, I = 1..S:
+//   * k_stage<I> (the beam kernel; one wavefront per emission-angle
+//     trajectory j, lanes over its 2 N_E beams): reads y_n once, recomputes
+//     k_0..k_{I-1} from y_n and the stage matrices K_l = A_l + B_l u, forms
+//     the input of stage I (the new state for the last stage-forming launch,
+//     written back in the storage type), accumulates its weighted density sum
+//     in FP64 and reduces it per workgroup; the final launch of an embedded
+//     pair instead forms the step error h sum_i e_i k_i and its maximum.
+//   * k_finalize<I> (one lane per trajectory): every workgroup adds the
+//     workgroup partials of k_stage<I> in one fixed order, so all of them hold
+//     the same J_I (deterministic), then builds the per-trajectory tables the
+//     next beam launch needs: stage I is completed from J_I (collective
+//     Hamiltonian eq 3.13 / 3.16, matter term, frame rate G_I, matrix A_I),
+//     and stage I+1 gets its geometry (eq 3.14-3.15), co-rotating phase,
+//     rotation factors and vacuum matrix B_{I+1}.  After the final launch it
+//     reduces the step error, runs the step controller and prepares stages 0
+//     and 1 of the next attempt.
+// Only y_n is read from HBM per beam launch and only y_{n+1} is written (by
+// the launch that forms it): every stage derivative is recomputed from y_n and
+// the small per-trajectory tables instead of being stored.
+//
+// Antineutrino amplitudes are held complex-conjugated on the device.  With
+// phi = conj(psibar), the antineutrino equation in the co-rotating frame reads
+// d phi / dr = -i (A - B / E) phi with the neutrino's A and B, so one matrix
+// per trajectory and stage serves both species (u = +1/E or -1/E per beam),
+// and the density sum takes the same form g psi psi^dagger for both species
+// with weight g or -gbar.
 #include "nuosc_internal.hpp"
 
 #include <math.h>
@@ -36,7 +47,7 @@ struct TabRK4 {
     static constexpr double C[8] = {0.0, 0.5, 0.5, 1.0};
     static constexpr double A[8][8] = {{0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}};
     static constexpr double B[8] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    static constexpr double E[8] = {0};
+    [[maybe_unused]] static constexpr double E[8] = {0};
 };
 
 // Dormand-Prince RK5(4)7M: the last stage is the new state (first same as
@@ -60,6 +71,13 @@ struct TabDP54 {
                                     -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
 };
 
+// Coefficient of k_m in the state formed for stage l (l == S: the new state).
+template <typename TAB>
+__host__ __device__ constexpr double coef(int l, int m)
+{
+    return l < TAB::S ? TAB::A[l][m] : TAB::B[m];
+}
+
 // ------------------------------------------------------------------ helpers
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -79,31 +97,29 @@ __device__ __forceinline__ void pin(T& v)
     asm volatile("" : "+v"(v));
 }
 
-template <int N> struct Shape {
-    static constexpr int NU = N * (N - 1) / 2;  // upper off-diagonal entries
-    static constexpr int NM = N * N;            // reals of a packed Hermitian matrix
-    __host__ __device__ static constexpr int up(int a, int b) { return a * N - a * (a + 1) / 2 + (b - a - 1); }
-};
+// Element i of an array at a wave-uniform base: a 32-bit byte offset from a
+// 64-bit base, which maps onto the scalar-base + vector-offset addressing of
+// global loads and stores (every array indexed this way is below 4 GiB).
+template <typename T>
+__device__ __forceinline__ T* elem(T* base, uint32_t i)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
 
-// K~ = A + B / E of one species on one trajectory at one stage.
-template <typename T, int N> struct SpeciesMat {
-    T ad[N], bd[N];
-    T au[Shape<N>::NU][2], bu[Shape<N>::NU][2];
-};
-template <typename T, int N> struct StageMat { SpeciesMat<T, N> sp[2]; };
-
-// k = -i K~ y for one beam.  y, k: [2N] as (re, im) per component.
+// k = -i K y for one beam with K = A + B u (packed Hermitian).  y, k: [2N] as
+// (re, im) per component.
 template <typename T, int N>
-__device__ __forceinline__ void eval_k(const SpeciesMat<T, N>& M, T inv_e, const T* y, T* k)
+__device__ __forceinline__ void eval_k(const T* A, const T* B, T u, const T* y, T* k)
 {
     constexpr int NU = Shape<N>::NU;
     T kd[N], ku[NU][2];
 #pragma unroll
-    for (int a = 0; a < N; ++a) kd[a] = fma(M.bd[a], inv_e, M.ad[a]);
+    for (int a = 0; a < N; ++a) kd[a] = fma(B[a], u, A[a]);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        ku[u][0] = fma(M.bu[u][0], inv_e, M.au[u][0]);
-        ku[u][1] = fma(M.bu[u][1], inv_e, M.au[u][1]);
+    for (int q = 0; q < NU; ++q) {
+        ku[q][0] = fma(B[N + 2 * q], u, A[N + 2 * q]);
+        ku[q][1] = fma(B[N + 2 * q + 1], u, A[N + 2 * q + 1]);
     }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
@@ -122,12 +138,352 @@ __device__ __forceinline__ void eval_k(const SpeciesMat<T, N>& M, T inv_e, const
     }
 }
 
-// Geometry of trajectory j at radius r (eq 3.14-3.15; single angle: c = 1,
-// w = D(r/R) of eq 3.17).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ const T* uinv_table(const RunConst& rc);
+template <> __device__ __forceinline__ const float* uinv_table<float>(const RunConst& rc) { return rc.uinv32; }
+template <> __device__ __forceinline__ const double* uinv_table<double>(const RunConst& rc) { return rc.uinv64; }
+
+// ------------------------------------------------------------------ beam kernel
+// Launch shape of the beam kernels: one wavefront per trajectory.  FP32
+// arithmetic: 16 trajectories per workgroup (at most 128 VGPRs, so every
+// wavefront of the grid is resident at once) and three beams of each lane in
+// flight; FP64 arithmetic (about twice the registers): 8 trajectories per
+// workgroup and two beams in flight.
+template <typename T> struct BeamShape {
+    static constexpr bool fp64 = std::is_same<T, double>::value;
+    static constexpr int traj = fp64 ? 8 : 16;
+    static constexpr int waves_per_traj = 1;
+    static constexpr int slots = fp64 ? 2 : 3;
+    static constexpr int block = 64 * traj * waves_per_traj;
+};
+
+// BeamShape<T>::traj trajectories per workgroup, BeamShape<T>::waves_per_traj
+// wavefronts per trajectory.  TS: amplitude type in HBM; T: arithmetic type
+// of the stage update (the density sums are FP64 in every form).
+template <typename TS, typename T, int N, typename TAB, int I>
+__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc)
+{
+    constexpr int kTrajPerBlock = BeamShape<T>::traj;
+    constexpr int kWavesPerTraj = BeamShape<T>::waves_per_traj;
+    constexpr int NSLOT = BeamShape<T>::slots;
+    constexpr int S = TAB::S;
+    constexpr bool FINAL = (I == S);
+    constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU;
+    constexpr bool ERROR = FINAL && TAB::embedded;
+    constexpr bool FSAL_FINAL = FINAL && TAB::fsal;      // derivatives and error only
+    constexpr bool MOMENTS = !FSAL_FINAL;                // density sum of the formed state
+    constexpr bool NEWSTATE = TAB::fsal ? (I == S - 1) : FINAL;
+    constexpr int NK = I;                                // derivatives k_0..k_{I-1}
+    constexpr int NWAVE = kTrajPerBlock * kWavesPerTraj;
+    constexpr uint32_t STRIDE = 64 * kWavesPerTraj;      // beam-slot stride of one lane
+    using Mat = StageMat<T, N>;
+
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int jt = wave / kWavesPerTraj, sub = wave - jt * kWavesPerTraj;
+    const int j = blockIdx.x * kTrajPerBlock + jt;
+    const bool active = j < rc.na;
+
+    __shared__ Mat smat[kTrajPerBlock][NK > 0 ? NK : 1];
+    __shared__ double swave[NWAVE][NM + 1];
+    __shared__ double spart[kTrajPerBlock][2 * NM];
+
+    // ---- stage matrices of k_0..k_{I-1} (raw dwords, by the waves of the
+    //      trajectory): loaded before the control block is read, so that both
+    //      latencies overlap; stored to LDS after the first beams' loads are issued
+    constexpr int MPER = sizeof(Mat) / 4;
+    constexpr int MREG = (NK * MPER + (int)STRIDE - 1) / (int)STRIDE;
+    uint32_t mreg[MREG > 0 ? MREG : 1];
+    if constexpr (NK > 0) {
+        const uint32_t* msrc = reinterpret_cast<const uint32_t*>(rc.mat);
+#pragma unroll
+        for (int i = 0; i < MREG; ++i) {
+            const int x = sub * 64 + lane + i * (int)STRIDE;
+            if (active && x < NK * MPER) {
+                const int l = x / MPER, q = x - l * MPER;
+                mreg[i] = msrc[((size_t)l * rc.na + j) * MPER + q];
+            }
+        }
+    }
+
+    // the first launch of an attempt takes the control block between attempts
+    if (I == 1 && blockIdx.x == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
+    const Control* ctl = rc.ctrl + (I <= 1 ? 1 : 0);
+    if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
+    const int cur = ctl->cur;
+    const double h = ctl->h;
+
+    // ---- per-beam work over the 2 N_E beam slots of trajectory j
+    // slot t < N_E: neutrino of energy bin t; t >= N_E: antineutrino of bin t - N_E
+    const uint32_t ne = (uint32_t)rc.ne;
+    const uint32_t nbt = active ? 2u * ne : 0u;
+    const uint32_t base0 = (uint32_t)j * ne;
+    const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
+    const TS* __restrict__ src = reinterpret_cast<const TS*>(rc.psi[cur]);
+    TS* __restrict__ dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
+    const size_t ld = (size_t)rc.nb_pad;
+    const T* __restrict__ uinv = uinv_table<T>(rc);
+    const T hT = (T)h;
+    const Mat* mats = smat[jt];
+
+    double macc[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) macc[i] = 0.0;
+    T emax = 0;
+    bool bad = false;
+
+    auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
+    auto fetch = [&](uint32_t t, TS* yv, T& uv, double& wv) __attribute__((always_inline)) {
+        if (t < nbt) {
+            const uint32_t off = offset(t);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(src + q * ld, off);
+            uv = *elem(uinv, t);
+            if constexpr (MOMENTS) wv = *elem(rc.wgt, t);
+        }
+    };
+    auto process = [&](uint32_t t, const TS* yv, T u, double wt) __attribute__((always_inline)) {
+        T y[2 * N];
+#pragma unroll
+        for (int q = 0; q < 2 * N; ++q) y[q] = (T)yv[q];
+        // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
+        // LDS for every beam instead of holding all of them in registers.
+        asm volatile("" ::: "memory");
+
+        T kk[NK > 0 ? NK : 1][2 * N];
+        static_for<0, NK>([&](auto Lc) {
+            constexpr int l = decltype(Lc)::value;
+            T Y[2 * N];
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                if constexpr (l == 0) {
+                    Y[q] = y[q];
+                } else {
+                    T acc = 0;
+                    bool first = true;
+                    static_for<0, l>([&](auto Mc) {
+                        constexpr int m = decltype(Mc)::value;
+                        if constexpr (TAB::A[l][m] != 0.0) {
+                            acc = first ? (T)TAB::A[l][m] * kk[m][q] : fma((T)TAB::A[l][m], kk[m][q], acc);
+                            first = false;
+                        }
+                    });
+                    Y[q] = fma(hT, acc, y[q]);
+                }
+            }
+            // keep only this stage's matrix live: no LDS reads hoisted across stages
+            asm volatile("" ::: "memory");
+            eval_k<T, N>(mats[l].a, mats[l].b, u, Y, kk[l]);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
+        });
+
+        if constexpr (ERROR) {
+            // h sum_m e_m k_m per real component (the last derivative is that
+            // of the new state, first same as last)
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                T d = 0;
+                bool first = true;
+                static_for<0, S>([&](auto Mc) {
+                    constexpr int m = decltype(Mc)::value;
+                    if constexpr (TAB::E[m] != 0.0) {
+                        d = first ? (T)TAB::E[m] * kk[m][q] : fma((T)TAB::E[m], kk[m][q], d);
+                        first = false;
+                    }
+                });
+                const T e = fabs(hT * d);
+                bad |= !isfinite(e);
+                emax = fmax(emax, e);
+            }
+        }
+
+        if constexpr (MOMENTS) {
+            // the state this launch forms: Y_I, or y_{n+1} for the last launch of
+            // a tableau without first-same-as-last (y_n itself for I == 0)
+            T Yo[2 * N];
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                if constexpr (I == 0) {
+                    Yo[q] = y[q];
+                } else {
+                    T acc = 0;
+                    bool first = true;
+                    static_for<0, NK>([&](auto Mc) {
+                        constexpr int m = decltype(Mc)::value;
+                        if constexpr (coef<TAB>(I, m) != 0.0) {
+                            acc = first ? (T)coef<TAB>(I, m) * kk[m][q] : fma((T)coef<TAB>(I, m), kk[m][q], acc);
+                            first = false;
+                        }
+                    });
+                    Yo[q] = fma(hT, acc, y[q]);
+                }
+            }
+            if constexpr (NEWSTATE) {
+                // FP32 amplitudes are renormalised whenever a new state is
+                // formed; the moments are those of the stored values.
+                if constexpr (std::is_same<TS, float>::value) {
+                    T nn = 0;
+#pragma unroll
+                    for (int q = 0; q < 2 * N; ++q) nn = fma(Yo[q], Yo[q], nn);
+                    const T sc = T(1) / sqrt(nn);
+#pragma unroll
+                    for (int q = 0; q < 2 * N; ++q) Yo[q] = (T)(TS)(Yo[q] * sc);
+                }
+                const uint32_t off = offset(t);
+#pragma unroll
+                for (int q = 0; q < 2 * N; ++q) *elem(dst + q * ld, off) = (TS)Yo[q];
+                if constexpr (!TAB::embedded) {
+#pragma unroll
+                    for (int q = 0; q < 2 * N; ++q) bad |= !isfinite(Yo[q]);
+                }
+            }
+            // weighted density sum in the rotated frame: wt psi_a conj(psi_b)
+            double z[2 * N], wz[2 * N];
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                z[q] = (double)Yo[q];
+                wz[q] = wt * z[q];
+            }
+#pragma unroll
+            for (int a = 0; a < N; ++a) macc[a] = fma(wz[2 * a], z[2 * a], fma(wz[2 * a + 1], z[2 * a + 1], macc[a]));
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = a + 1; b < N; ++b) {
+                    const int q = Shape<N>::up(a, b);
+                    macc[N + 2 * q] = fma(wz[2 * a], z[2 * b], fma(wz[2 * a + 1], z[2 * b + 1], macc[N + 2 * q]));
+                    macc[N + 2 * q + 1] = fma(wz[2 * a + 1], z[2 * b], fma(-wz[2 * a], z[2 * b + 1], macc[N + 2 * q + 1]));
+                }
+        }
+    };
+
+    // NSLOT-slot load pipeline: the next beams of the other slots are in
+    // flight while one is computed (no register copies: the loop is unrolled
+    // by NSLOT and every slot keeps its registers)
+    {
+        TS ys[NSLOT][2 * N];
+        T us[NSLOT];
+        double ws[NSLOT];
+        const uint32_t t0 = (uint32_t)(sub * 64 + lane);
+        static_for<0, NSLOT>([&](auto Sc) {
+            constexpr int sl = decltype(Sc)::value;
+            us[sl] = 0;
+            ws[sl] = 0.0;
+            fetch(t0 + sl * STRIDE, ys[sl], us[sl], ws[sl]);
+        });
+        if constexpr (NK > 0) {
+            uint32_t* mdst = reinterpret_cast<uint32_t*>(&smat[jt][0]);
+#pragma unroll
+            for (int i = 0; i < MREG; ++i) {
+                const int x = sub * 64 + lane + i * (int)STRIDE;
+                if (active && x < NK * MPER) mdst[x] = mreg[i];
+            }
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (uint32_t t = t0; t < nbt; t += NSLOT * STRIDE) {
+            static_for<0, NSLOT>([&](auto Sc) {
+                constexpr int sl = decltype(Sc)::value;
+                const uint32_t ts = t + sl * STRIDE;
+                if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], ws[sl]);
+                fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], ws[sl]);
+            });
+        }
+    }
+
+    // ---- per-wave sums; per trajectory: waves added in order, rotated to the
+    //      lab frame and weighted; then the block's trajectories in order
+    if constexpr (MOMENTS) {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) macc[i] = wave_sum(macc[i]);
+        if (lane == 0)
+            for (int i = 0; i < NM; ++i) swave[wave][i] = macc[i];
+    }
+    if constexpr (FINAL) {
+        double e = bad ? (double)INFINITY : (double)emax;
+        e = wave_max(e);
+        if (lane == 0) swave[wave][NM] = active ? e : 0.0;
+    }
+    __syncthreads();
+    if constexpr (MOMENTS) {
+        if (threadIdx.x < kTrajPerBlock) {
+            const int tj = threadIdx.x;
+            const int jj = blockIdx.x * kTrajPerBlock + tj;
+            double Sl[NM];
+            double w0 = 0.0, w1 = 0.0;
+            if (jj < rc.na) {
+                double m[NM];
+#pragma unroll
+                for (int v = 0; v < NM; ++v) {
+                    m[v] = swave[tj * kWavesPerTraj][v];
+                    for (int w = 1; w < kWavesPerTraj; ++w) m[v] += swave[tj * kWavesPerTraj + w][v];
+                }
+                // S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa
+                const TrajGeo& g = rc.geo[(size_t)I * rc.na + jj];
+#pragma unroll
+                for (int a = 0; a < N; ++a) Sl[a] = 2.0 * m[a];
+#pragma unroll
+                for (int q = 0; q < NU; ++q) {
+                    const double cs = g.z[q][0], sn = g.z[q][1];
+                    const double xr = m[N + 2 * q], xi = m[N + 2 * q + 1];
+                    Sl[N + 2 * q] = 2.0 * (cs * xr + sn * xi);
+                    Sl[N + 2 * q + 1] = 2.0 * (cs * xi - sn * xr);
+                }
+                w0 = g.w;
+                w1 = g.wc;
+            } else {
+#pragma unroll
+                for (int v = 0; v < NM; ++v) Sl[v] = 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < NM; ++v) {
+                spart[tj][v] = w0 * Sl[v];
+                spart[tj][NM + v] = w1 * Sl[v];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * NM) {
+            const int v = threadIdx.x;
+            double acc = spart[0][v];
+            for (int w = 1; w < kTrajPerBlock; ++w) acc += spart[w][v];
+            rc.partial[(size_t)v * rc.nblk + blockIdx.x] = acc;
+        }
+    }
+    if constexpr (FINAL) {
+        if (threadIdx.x == 0) {
+            double e = swave[0][NM];
+            for (int w = 1; w < NWAVE; ++w) e = fmax(e, swave[w][NM]);
+            rc.errpart[blockIdx.x] = e;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ per-trajectory tables
+// Stage radius l of the attempt described by C (l == S: the new state).
+template <typename TAB>
+__device__ __forceinline__ double stage_radius(const RunConst& rc, const Control& C, int l)
+{
+    if (l < TAB::S) return C.r + TAB::C[l] * C.h;
+    return (rc.integrator == 0) ? rc.r_start + (double)(C.istep + 1) * rc.h_fixed : C.r + C.h;
+}
+
+// Geometry of trajectory j at radius r (eq 3.14-3.15, with 1 - (R/r)^2 formed
+// as (r - R)(r + R) / r^2; single angle: c = 1, w = D(r/R) of eq 3.17).
 __device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double r, double& c, double& w)
 {
-    // 1 - (R/r)^2 as (r - R)(r + R) / r^2: exact subtraction near the
-    // neutrinosphere, where 1 - (R/r)^2 (1 - u^2) would cancel for small u.
     const double x = (rc.r_nu / r) * (rc.r_nu / r);
     const double y = (r - rc.r_nu) * (r + rc.r_nu) / (r * r);
     if (rc.ma) {
@@ -142,510 +498,343 @@ __device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double 
     }
 }
 
-__device__ __forceinline__ double matter(const RunConst& rc, double r)
+// Geometry (c, w at the stage radius) and frame factors of stage l of
+// trajectory j with co-rotating phase ph[] (written to geo[l]; returned for an
+// immediate completion of the same stage).
+template <int N>
+struct StageFrame {
+    double c, ic;
+    double z[Shape<N>::NU > 0 ? Shape<N>::NU : 1][2];
+};
+
+template <int N>
+__device__ StageFrame<N> prepare_stage(const RunConst& rc, int j, int l, double c, double w, const double* ph)
 {
-    return rc.lambda0 * pow(rc.lambda_rref / r, rc.lambda_power);
+    StageFrame<N> f;
+    TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
+    f.c = c;
+    f.ic = 1.0 / c;
+    g.c = c;
+    g.w = w;
+    g.wc = rc.ma ? w * c : 0.0;
+    g.ic = f.ic;
+    for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; ++b) {
+            const int q = Shape<N>::up(a, b);
+            double sn, cs;
+            sincos(ph[a] - ph[b], &sn, &cs);
+            f.z[q][0] = cs;
+            f.z[q][1] = sn;
+            g.z[q][0] = cs;
+            g.z[q][1] = sn;
+        }
+    return f;
 }
 
-// mu0 * traceless(J0 - c J1) from packed moments J (J0 then J1).
-template <int N>
-__device__ __forceinline__ void collective(const RunConst& rc, const double* J, double c, double* Cd, double (*Cu)[2])
+// Completes stage l of trajectory j from J_l (J0 then J1, packed) and the
+// matter potential lam at the stage radius:
+//   C = mu0 traceless(J0 - c J1)                       (eq 3.13; single angle: J1 = 0)
+//   G = diag(H_m + C) / c in the co-rotating frame, 0 in the lab frame
+//   A_ab = e^{i(Phi_a - Phi_b)} C_ab / c (a < b), A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab)
+//   B_ab = e^{i(Phi_a - Phi_b)} V_ab / c,  B_aa = V_aa / c  (H_vac = V / E)
+// G is written to geo[l] and returned in G[].
+template <typename T, int N>
+__device__ void complete_stage(const RunConst& rc, int j, int l, const StageFrame<N>& f, double lam,
+                               const double* J, double* G)
 {
-    constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU;
-    double tr = 0.0;
+    constexpr int NM = Shape<N>::NM;
+    TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
+    StageMat<T, N>& M = reinterpret_cast<StageMat<T, N>*>(rc.mat)[(size_t)l * rc.na + j];
+    const double c = f.c, ic = f.ic;
+    double Cd[N], tr = 0.0;
     for (int a = 0; a < N; ++a) {
         Cd[a] = J[a] - c * J[NM + a];
         tr += Cd[a];
     }
-    for (int a = 0; a < N; ++a) Cd[a] = rc.mu0 * (Cd[a] - tr / N);
-    for (int u = 0; u < NU; ++u) {
-        Cu[u][0] = rc.mu0 * (J[N + 2 * u] - c * J[NM + N + 2 * u]);
-        Cu[u][1] = rc.mu0 * (J[N + 2 * u + 1] - c * J[NM + N + 2 * u + 1]);
+    for (int a = 0; a < N; ++a) {
+        const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
+        const double gd = (rc.frame == 0) ? hd * ic : 0.0;
+        G[a] = gd;
+        g.G[a] = gd;
+        M.a[a] = (T)((rc.frame == 0) ? 0.0 : hd * ic);
+        M.b[a] = (T)(rc.vac[a][a][0] * ic);
     }
+    for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; ++b) {
+            const int q = Shape<N>::up(a, b);
+            const double cs = f.z[q][0], sn = f.z[q][1];
+            const double cr = rc.mu0 * (J[N + 2 * q] - c * J[NM + N + 2 * q]) * ic;
+            const double ci = rc.mu0 * (J[N + 2 * q + 1] - c * J[NM + N + 2 * q + 1]) * ic;
+            const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
+            M.a[N + 2 * q] = (T)(cs * cr - sn * ci);
+            M.a[N + 2 * q + 1] = (T)(cs * ci + sn * cr);
+            M.b[N + 2 * q] = (T)(cs * vr - sn * vi);
+            M.b[N + 2 * q + 1] = (T)(cs * vi + sn * vr);
+        }
 }
 
-template <typename T> __device__ __forceinline__ T* psi_ptr(const RunConst& rc, int buf)
+__device__ __forceinline__ double matter(const RunConst& rc, double r)
 {
-    return reinterpret_cast<T*>(rc.psi[buf]);
+    const double x = rc.lambda_rref / r, p = rc.lambda_power;
+    if (p == 3.0) return rc.lambda0 * (x * x * x);  // the bulb profile, without pow
+    return rc.lambda0 * pow(x, p);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Sum NV doubles over a workgroup of NW waves in a fixed order (butterfly in
-// each wave, then waves in index order); result valid in thread 0.
-template <int NV, int NW>
-__device__ __forceinline__ void block_sum(double* v, double (*lds)[NW])
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0)
-        for (int i = 0; i < NV; ++i) lds[i][wave] = v[i];
-    __syncthreads();
-    // value i is combined by thread i (waves in index order), then gathered
-    if ((int)threadIdx.x < NV) {
-        const int i = threadIdx.x;
-        double s = lds[i][0];
-        for (int w = 1; w < NW; ++w) s += lds[i][w];
-        lds[i][0] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int i = 0; i < NV; ++i) v[i] = lds[i][0];
-}
-
-// Trajectories (wavefronts) per stage workgroup: their weighted sums are added
-// in wave order into one partial, so the finalise launch reads na / 4 partials.
-constexpr int kTrajPerBlock = 4;
-
-// Radius of stage l of the current attempt (l == S: the new state).
+// Step controller (readings J, K of the oracle's header; fixed-step RK4 always
+// accepts a finite step).  Returns whether the attempt is accepted.
 template <typename TAB>
-__device__ __forceinline__ double stage_radius(const RunConst& rc, const Control* ctl, double r, double h, int l)
+__device__ bool control_step(const RunConst& rc, Control& C, double m)
 {
-    if (l < TAB::S) return r + TAB::C[l] * h;
-    return (rc.integrator == 0) ? rc.r_start + (double)(ctl->istep + 1) * rc.h_fixed : r + h;
-}
-
-// ------------------------------------------------------------------ stage kernel
-// One wavefront per trajectory j.  TS: amplitude type in HBM; T: arithmetic
-// type of the stage update.  Launch I (1 <= I <= S) needs the Hamiltonian
-// pieces of stages 0..I-1: those of stages < I-1 were built by earlier
-// launches of this attempt and are read from rc.tab; stage I-1 is completed
-// here from J_{I-1} (its geometry and phase were set by launch I-1); the
-// output stage I gets its geometry and phase here.
-template <typename TS, typename T, int N, bool MA, typename TAB, int I>
-__global__ void __launch_bounds__(64 * kTrajPerBlock) k_stage(const RunConst rc)
-{
-    constexpr int S = TAB::S;
-    constexpr bool FINAL = (I == S);
-    constexpr int NU = Shape<N>::NU, NM = Shape<N>::NM;
-    constexpr bool MOMENTS = !FINAL || !TAB::fsal;  // the last RK4 launch also forms J of y_{n+1}
-
-    const Control* ctl = rc.ctrl;
-    if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
-    const int cur = ctl->cur;
-    const double r = ctl->r, h = ctl->h;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * kTrajPerBlock + wave;
-    const bool active = j < rc.na;
-
-    __shared__ StageMat<T, N> smat_all[kTrajPerBlock][I > 0 ? I : 1];
-    __shared__ double sG_all[kTrajPerBlock][kMaxStages][N];
-    __shared__ double spart[kTrajPerBlock][2 * NM + 1];
-    StageMat<T, N>* smat = smat_all[wave];
-
-    // ---- amplitudes stream through a two-deep register pipeline: the loads of
-    //      the next two beams of this lane are in flight while one is computed
-    //      (the first two are issued before the prologue).
-    const TS* __restrict__ src = psi_ptr<TS>(rc, cur);
-    TS* __restrict__ dst = psi_ptr<TS>(rc, cur ^ 1);
-    const int64_t ld = rc.nb_pad;
-    const int nbt = active ? 2 * rc.ne : 0;  // beams of this trajectory
-    auto beam_index = [&](int t) {
-        const int s = (t >= rc.ne) ? 1 : 0;
-        return ((int64_t)s * rc.na + j) * rc.ne + (t - s * rc.ne);
-    };
-    auto fetch = [&](int t, TS* v) {
-        if (t < nbt) {
-            const int64_t b = beam_index(t);
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) v[q] = src[q * ld + b];
+    C.attempts += 1;
+    bool accepted = false;
+    const double h = C.h;
+    if constexpr (!TAB::embedded) {
+        if (!(m <= 1.0e300)) {
+            C.status = -4;
+        } else {
+            accepted = true;
+            C.istep += 1;
+            C.nacc += 1;
+            C.cur ^= 1;
+            C.r = rc.r_start + (double)C.istep * rc.h_fixed;
+            C.h = rc.h_fixed;
+            if (C.istep >= rc.n_fixed || C.r >= C.r_end) C.status = 1;
         }
-    };
-    TS ynext0[2 * N], ynext1[2 * N];
-    fetch(lane, ynext0);
-    fetch(lane + 64, ynext1);
-
-    // ---- stored Hamiltonian pieces of stages 0..I-2 -> LDS (both species)
-    if constexpr (I >= 2) {
-        if (active) {
-            constexpr int PER = 2 * NM;  // A then B, packed
-            for (int idx = lane; idx < (I - 1) * PER; idx += 64) {
-                const int l = idx / PER, q = idx - l * PER;
-                const TrajStage& e = rc.tab[(size_t)l * rc.na + j];
-                const int m = q < NM ? 0 : 1;       // 0: A, 1: B
-                const int x = q - m * NM;
-                const double v = m == 0 ? e.A[x] : e.B[x];
-                SpeciesMat<T, N>& nu = smat[l].sp[0];
-                SpeciesMat<T, N>& nb = smat[l].sp[1];
-                if (x < N) {
-                    if (m == 0) { nu.ad[x] = (T)v; nb.ad[x] = (T)(-v); }
-                    else { nu.bd[x] = (T)v; nb.bd[x] = (T)v; }
-                } else {
-                    const int u = (x - N) >> 1, ri = (x - N) & 1;
-                    // nubar: A -> -conj(A), B -> conj(B)
-                    if (m == 0) { nu.au[u][ri] = (T)v; nb.au[u][ri] = (T)(ri ? v : -v); }
-                    else { nu.bu[u][ri] = (T)v; nb.bu[u][ri] = (T)(ri ? -v : v); }
-                }
-            }
-        }
-    }
-
-    // ---- lane 0: complete stage I-1, then geometry and phase of stage I (FP64)
-    double zo[NU > 0 ? NU : 1][2], co = 1.0, wo = 0.0, pho[N];
-    if (active && lane == 0) {
-        const double* ph0 = rc.phase[cur] + (size_t)j * N;
-        double (*G)[N] = sG_all[wave];
-        for (int l = 0; l + 1 < I; ++l)
-            for (int a = 0; a < N; ++a) G[l][a] = rc.tab[(size_t)l * rc.na + j].G[a];
-        if constexpr (I >= 1) {
-            constexpr int l = I - 1;
-            TrajStage& e = rc.tab[(size_t)l * rc.na + j];
-            const double rl = stage_radius<TAB>(rc, ctl, r, h, l);
-            double c, w, phl[N], zl[NU > 0 ? NU : 1][2];
-            if (l == 0) {
-                traj_geometry(rc, j, rl, c, w);
-                for (int a = 0; a < N; ++a) phl[a] = ph0[a];
-                for (int a = 0; a < N; ++a)
-                    for (int b = a + 1; b < N; ++b) {
-                        const int u = Shape<N>::up(a, b);
-                        sincos(phl[a] - phl[b], &zl[u][1], &zl[u][0]);
-                    }
-                e.c = c; e.w = w;
-                for (int a = 0; a < N; ++a) e.phi[a] = phl[a];
-                for (int u = 0; u < NU; ++u) { e.z[u][0] = zl[u][0]; e.z[u][1] = zl[u][1]; }
+    } else {
+        const double err = m / rc.rtol;
+        C.err = err;
+        if (!(err <= 1.0e300)) {
+            C.status = -4;
+        } else {
+            const double f_lo = 0.2, f_hi = 5.0;
+            double fac, rn = C.r;
+            if (err <= 1.0) {
+                accepted = true;
+                rn = C.r + h;
+                C.r = rn;
+                C.nacc += 1;
+                C.cur ^= 1;
+                fac = (err == 0.0) ? f_hi : rc.safety * pow(err, -0.2);
+                fac = fmin(fmax(fac, f_lo), f_hi);
+                if (C.last_rejected && fac > 1.0) fac = 1.0;
+                C.last_rejected = 0;
             } else {
-                c = e.c;
-                for (int u = 0; u < NU; ++u) { zl[u][0] = e.z[u][0]; zl[u][1] = e.z[u][1]; }
+                C.nrej += 1;
+                fac = fmax(rc.safety * pow(err, -0.2), f_lo);
+                C.last_rejected = 1;
             }
-            // Hamiltonian pieces of stage l in the co-rotating frame:
-            //   A_ab = e^{i(Phi_a-Phi_b)} C_ab / c,  B_ab = e^{i(Phi_a-Phi_b)} V_ab / c   (a < b)
-            //   A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab),  B_aa = V_aa / c
-            double Cd[N], Cu[NU > 0 ? NU : 1][2];
-            collective<N>(rc, rc.jhist + l * 2 * NM, c, Cd, Cu);
-            const double lam = matter(rc, rl);
-            const double ic = 1.0 / c;
-            SpeciesMat<T, N>& nu = smat[l].sp[0];
-            SpeciesMat<T, N>& nb = smat[l].sp[1];
-            for (int a = 0; a < N; ++a) {
-                const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + Cd[a];
-                const double gd = (rc.frame == 0) ? hd * ic : 0.0;
-                G[l][a] = gd;
-                e.G[a] = gd;
-                const double ad = (rc.frame == 0) ? 0.0 : hd * ic;
-                const double bd = rc.vac[a][a][0] * ic;
-                e.A[a] = ad;
-                e.B[a] = bd;
-                nu.ad[a] = (T)ad; nb.ad[a] = (T)(-ad);
-                nu.bd[a] = (T)bd; nb.bd[a] = (T)bd;
+            double hn = fmin(h * fac, rc.dr_max);
+            C.h_prop = hn;
+            if (rn >= C.r_end) {
+                C.status = 1;
+            } else if (hn < 1e-14 * rn) {
+                C.status = -5;
+            } else {
+                if (rn + hn > C.r_end) hn = C.r_end - rn;
             }
-            for (int u = 0; u < NU; ++u) {
-                const double cs = zl[u][0], sn = zl[u][1];
-                int a = 0, b = 1;
-                for (int aa = 0; aa < N; ++aa)
-                    for (int bb = aa + 1; bb < N; ++bb)
-                        if (Shape<N>::up(aa, bb) == u) { a = aa; b = bb; }
-                const double cr = Cu[u][0] * ic, ci = Cu[u][1] * ic;
-                const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
-                const double Ar = cs * cr - sn * ci, Ai = cs * ci + sn * cr;
-                const double Br = cs * vr - sn * vi, Bi = cs * vi + sn * vr;
-                e.A[N + 2 * u] = Ar; e.A[N + 2 * u + 1] = Ai;
-                e.B[N + 2 * u] = Br; e.B[N + 2 * u + 1] = Bi;
-                nu.au[u][0] = (T)Ar;  nu.au[u][1] = (T)Ai;
-                nu.bu[u][0] = (T)Br;  nu.bu[u][1] = (T)Bi;
-                nb.au[u][0] = (T)(-Ar); nb.au[u][1] = (T)Ai;
-                nb.bu[u][0] = (T)Br;  nb.bu[u][1] = (T)(-Bi);
-            }
-        }
-        // output stage (or new state): radius, geometry, phase, rotation
-        const double ro = stage_radius<TAB>(rc, ctl, r, h, I);
-        traj_geometry(rc, j, ro, co, wo);
-        for (int a = 0; a < N; ++a) {
-            double acc = 0.0;
-            static_for<0, I>([&](auto Mc) {
-                constexpr int m = decltype(Mc)::value;
-                constexpr double coef = FINAL ? TAB::B[m] : TAB::A[I < S ? I : 0][m];
-                if constexpr (coef != 0.0) acc += coef * G[m][a];
-            });
-            pho[a] = ph0[a] + h * acc;
-        }
-        for (int a = 0; a < N; ++a)
-            for (int b = a + 1; b < N; ++b) {
-                const int u = Shape<N>::up(a, b);
-                sincos(pho[a] - pho[b], &zo[u][1], &zo[u][0]);
-            }
-        if constexpr (!FINAL && I >= 1) {
-            TrajStage& e = rc.tab[(size_t)I * rc.na + j];
-            e.c = co; e.w = wo;
-            for (int a = 0; a < N; ++a) e.phi[a] = pho[a];
-            for (int u = 0; u < NU; ++u) { e.z[u][0] = zo[u][0]; e.z[u][1] = zo[u][1]; }
-        }
-        if constexpr (FINAL) {
-            double* ph1 = rc.phase[cur ^ 1] + (size_t)j * N;  // kept only if the attempt is accepted
-            for (int a = 0; a < N; ++a) ph1[a] = pho[a];
+            C.h = hn;
         }
     }
-    __syncthreads();
+    if (C.status == 0 && rc.max_steps > 0 && C.attempts >= rc.max_steps) C.status = -6;
+    return accepted;
+}
 
-    // ---- per-beam work: lanes over the 2*NE beams of trajectory j
-    // Stage states are y + h * (sum_m a_lm k_m): the tableau coefficients are
-    // compile-time constants (scalar operands), only h is a runtime value.
-    const T hT = (T)h;
-
-    double macc[NM];
+// Partials of the stage workgroups, value-major: thread i adds partials i,
+// i + kFinBlock, ..., four at a time with all loads of a group issued
+// together; the per-thread sums are reduced through LDS in a fixed order
+// (8 chunks of 32 threads per value, then the 8 chunk sums).  Every workgroup
+// running this gets the same bits.
+template <int NV>
+__device__ __forceinline__ void load_partials(const RunConst& rc, int p0, double (&x)[4][NV])
+{
+    const int nblk = rc.nblk;
 #pragma unroll
-    for (int i = 0; i < NM; ++i) macc[i] = 0.0;
-    double emax = 0.0;
-
-#pragma unroll 1
-    for (int t = lane; t < nbt; t += 64) {
-        const int s = (t >= rc.ne) ? 1 : 0;
-        const int k = t - s * rc.ne;
-        const int64_t b = beam_index(t);
-        T y[2 * N];
+    for (int i = 0; i < 4; ++i) {
+        const int p = p0 + i * kFinBlock;
 #pragma unroll
-        for (int q = 0; q < 2 * N; ++q) {
-            y[q] = (T)ynext0[q];
-            ynext0[q] = ynext1[q];
-        }
-        fetch(t + 128, ynext1);
-        // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
-        // LDS each iteration instead of keeping both species' copies in VGPRs.
-        asm volatile("" ::: "memory");
-        const T inv_e = (T)rc.inv_e[k];
-
-        T kk[I > 0 ? I : 1][2 * N];
-        static_for<0, I>([&](auto Lc) {
-            constexpr int l = decltype(Lc)::value;
-            T Y[2 * N];
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                T acc = 0;
-                static_for<0, l>([&](auto Mc) {
-                    constexpr int m = decltype(Mc)::value;
-                    if constexpr (TAB::A[l][m] != 0.0) acc = fma((T)TAB::A[l][m], kk[m][q], acc);
-                });
-                Y[q] = (l == 0) ? y[q] : fma(hT, acc, y[q]);
-            }
-            // keep only this stage's matrix live: no LDS reads hoisted across stages
-            asm volatile("" ::: "memory");
-            eval_k<T, N>(smat[l].sp[s], inv_e, Y, kk[l]);
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
-        });
-
-        // output state: Y_I (stage) or y_{n+1} (final)
-        T Y[2 * N];
-#pragma unroll
-        for (int q = 0; q < 2 * N; ++q) {
-            T acc = 0;
-            static_for<0, I>([&](auto Mc) {
-                constexpr int m = decltype(Mc)::value;
-                constexpr double coef = FINAL ? TAB::B[m] : TAB::A[I < S ? I : 0][m];
-                if constexpr (coef != 0.0) acc = fma((T)coef, kk[m][q], acc);
-            });
-            Y[q] = (I == 0) ? y[q] : fma(hT, acc, y[q]);
-        }
-        // FP32 amplitudes are renormalised whenever a new state is formed, and
-        // the moments of the new state are those of its stored FP32 values.
-        if constexpr (std::is_same<TS, float>::value && (FINAL || (TAB::fsal && I == S - 1))) {
-            T nn = 0;
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) nn = fma(Y[q], Y[q], nn);
-            const T sc = T(1) / sqrt(nn);
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) Y[q] = (T)(TS)(Y[q] * sc);
-        }
-        if constexpr (FINAL) {
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) dst[q * ld + b] = (TS)Y[q];
-            bool bad = false;
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) bad |= !isfinite((double)Y[q]);
-            if constexpr (TAB::embedded) {
-#pragma unroll
-                for (int q = 0; q < 2 * N; ++q) {
-                    double d = 0.0;
-                    static_for<0, S>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        if constexpr (TAB::E[m] != 0.0) d = fma(TAB::E[m], (double)kk[m][q], d);
-                    });
-                    d = fabs(h * d);
-                    bad |= !isfinite(d);
-                    emax = fmax(emax, d);
-                }
-            }
-            if (bad) emax = INFINITY;
-        }
-        if constexpr (MOMENTS) {
-            // rotated-frame density sum: nu: +g psi_a conj(psi_b); nubar: -gbar conj(psi_a conj(psi_b))
-            const double wt = s ? -rc.gbar[k] : rc.g[k];
-            const double sg = s ? -1.0 : 1.0;
-            double z[2 * N];
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) z[q] = (double)Y[q];
-#pragma unroll
-            for (int a = 0; a < N; ++a) macc[a] = fma(wt, fma(z[2 * a], z[2 * a], z[2 * a + 1] * z[2 * a + 1]), macc[a]);
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int c2 = a + 1; c2 < N; ++c2) {
-                    const int u = Shape<N>::up(a, c2);
-                    const double re = fma(z[2 * a], z[2 * c2], z[2 * a + 1] * z[2 * c2 + 1]);
-                    const double im = fma(z[2 * a + 1], z[2 * c2], -z[2 * a] * z[2 * c2 + 1]);
-                    macc[N + 2 * u] = fma(wt, re, macc[N + 2 * u]);
-                    macc[N + 2 * u + 1] = fma(wt * sg, im, macc[N + 2 * u + 1]);
-                }
-        }
-    }
-
-    // ---- wave reduction, per-trajectory weighting, then the block's trajectories
-    //      in wave order (fixed) into one partial per block
-    if constexpr (MOMENTS) {
-#pragma unroll
-        for (int i = 0; i < NM; ++i) macc[i] = wave_sum(macc[i]);
-        if (lane == 0) {
-            for (int v = 0; v < 2 * NM; ++v) spart[wave][v] = 0.0;
-        }
-        if (active && lane == 0) {
-            // lab frame: S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa
-            double Sl[NM];
-            for (int a = 0; a < N; ++a) Sl[a] = 2.0 * macc[a];
-            for (int u = 0; u < NU; ++u) {
-                const double cs = zo[u][0], sn = zo[u][1];
-                const double xr = macc[N + 2 * u], xi = macc[N + 2 * u + 1];
-                Sl[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
-                Sl[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
-            }
-            const double w0 = wo, w1 = MA ? wo * co : 0.0;
-            for (int v = 0; v < NM; ++v) {
-                spart[wave][v] = w0 * Sl[v];
-                spart[wave][NM + v] = w1 * Sl[v];
-            }
-        }
-    }
-    if constexpr (FINAL) {
-        const double e = wave_max(emax);
-        if (lane == 0) spart[wave][2 * NM] = e;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * NM + 1) {
-        const int v = threadIdx.x;
-        const bool is_err = (v == 2 * NM);
-        if ((MOMENTS && !is_err) || (FINAL && is_err)) {
-            double acc = spart[0][v];
-            for (int w = 1; w < kTrajPerBlock; ++w) acc = is_err ? fmax(acc, spart[w][v]) : acc + spart[w][v];
-            if (is_err) rc.errpart[blockIdx.x] = acc;
-            else rc.partial[(size_t)blockIdx.x * 2 * NM + v] = acc;
-        }
+        for (int v = 0; v < NV; ++v) x[i][v] = (p < nblk) ? rc.partial[(size_t)v * nblk + p] : 0.0;
     }
 }
 
-// Finalisation of launch I: one workgroup adds the per-trajectory partials
-// of all trajectories in a fixed order into J_I (deterministic), and for the
-// final launch reduces the step error and runs the step controller.  Running
-// it as its own launch (instead of a last-workgroup handoff inside k_stage)
-// avoids a device-scope fence in every workgroup: on gfx950 such a fence
-// writes back and invalidates the XCD's L2.
-constexpr int kFinBlock = 1024;
+// x: the first group, loaded by load_partials(rc, threadIdx.x, x).
+template <int NV>
+__device__ void reduce_partials(const RunConst& rc, double (&x)[4][NV], double* out, double (*sred)[kFinBlock],
+                                double (*schunk)[8])
+{
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int p0 = threadIdx.x;;) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += x[i][v];
+        p0 += 4 * kFinBlock;
+        if (p0 >= rc.nblk) break;
+        load_partials<NV>(rc, p0, x);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sred[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int w = threadIdx.x; w < NV * 8; w += kFinBlock) {
+        const int v = w / 8, c = w - v * 8;
+        double sum = 0.0;
+        for (int i = 0; i < kFinBlock / 8; ++i) sum += sred[v][c * (kFinBlock / 8) + i];
+        schunk[v][c] = sum;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        const int v = threadIdx.x;
+        double sum = schunk[v][0];
+        for (int c = 1; c < 8; ++c) sum += schunk[v][c];
+        out[v] = sum;
+    }
+    __syncthreads();
+}
 
-template <int N, typename TAB, int I>
+// Finalise launch I (see the file header).  T: the stage kernels' arithmetic
+// type (of the stage matrices it writes).
+template <typename T, int N, typename TAB, int I>
 __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
 {
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
     constexpr int NM = Shape<N>::NM;
     constexpr int NV = 2 * NM;
-    constexpr int NW = kFinBlock / 64;
-    constexpr bool MOMENTS = !FINAL || !TAB::fsal;
-    __shared__ double sred[NV + 1][NW];
+    constexpr int NU = Shape<N>::NU > 0 ? Shape<N>::NU : 1;
+    constexpr bool MOMENTS = !(FINAL && TAB::fsal);
+    constexpr int NG = FINAL ? 1 : (I > 0 ? I : 1);  // stored frame rates G_0..G_{I-1}
+    __shared__ double sred[NV][kFinBlock];
+    __shared__ double schunk[NV][8];
+    __shared__ double sJ[NV];
+    __shared__ double serr[kFinBlock / 64];
+    __shared__ Control sC;
+    __shared__ int s_acc;
 
-    const Control* ctl = rc.ctrl;
-    if (I > 0 && ctl->status != 0) return;
-    const double h = ctl->h;
-    // one partial per stage block; contiguous ranges summed in ascending order
-    const int nparts = (rc.na + kTrajPerBlock - 1) / kTrajPerBlock;
-    const int per = (nparts + kFinBlock - 1) / kFinBlock;
-    const int j0 = min(nparts, (int)threadIdx.x * per), j1 = min(nparts, j0 + per);
-
-    double* Jout = rc.jhist + (FINAL ? S : I) * NV;
-    if constexpr (MOMENTS) {
-        double acc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        for (int jj = j0; jj < j1; ++jj) {
-            const double* src = rc.partial + (size_t)jj * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += src[v];
+    // ---- per-trajectory inputs and the partials, loaded first so that their
+    //      latencies overlap that of the control block
+    const int j = blockIdx.x * kFinBlock + threadIdx.x;
+    const bool own = j < rc.na;
+    double ph0[N], ph1[N], Gh[NG][N];
+    StageFrame<N> fI;
+    if (own) {
+        for (int a = 0; a < N; ++a) {
+            ph0[a] = rc.phase[0][(size_t)j * N + a];
+            ph1[a] = rc.phase[1][(size_t)j * N + a];
         }
-        block_sum<NV, NW>(acc, sred);
-        if (threadIdx.x == 0)
-            for (int v = 0; v < NV; ++v) Jout[v] = acc[v];
+        if constexpr (!FINAL) {
+            const TrajGeo& g = rc.geo[(size_t)I * rc.na + j];
+            fI.c = g.c;
+            fI.ic = g.ic;
+            for (int q = 0; q < NU; ++q) {
+                fI.z[q][0] = g.z[q][0];
+                fI.z[q][1] = g.z[q][1];
+            }
+            for (int m = 0; m < I; ++m)
+                for (int a = 0; a < N; ++a) Gh[m][a] = rc.geo[(size_t)m * rc.na + j].G[a];
+        }
     }
+
+    double xp[4][NV];
+    if constexpr (MOMENTS) load_partials<NV>(rc, threadIdx.x, xp);
+
+    const Control* ctl = rc.ctrl + (I == 0 ? 1 : 0);
+    if (I > 0 && ctl->status != 0) return;
+
+    // work that does not need J_I, done while the partials are in flight:
+    // matter potential at stage I and geometry at stage I + 1
+    double lamI = 0.0, cn = 1.0, wn = 0.0;
+    if constexpr (!FINAL) {
+        const Control& C0 = *ctl;
+        lamI = matter(rc, stage_radius<TAB>(rc, C0, I));
+        if (own) traj_geometry(rc, j, stage_radius<TAB>(rc, C0, I + 1), cn, wn);
+    }
+
+    if constexpr (MOMENTS) reduce_partials<NV>(rc, xp, sJ, sred, schunk);
+
+    Control C;
     if constexpr (FINAL) {
+        // global error maximum (order-independent), then the controller; every
+        // workgroup computes the same control block, workgroup 0 publishes it
         double m = 0.0;
-        for (int jj = j0; jj < j1; ++jj) m = fmax(m, rc.errpart[jj]);
+        for (int p = threadIdx.x; p < rc.nblk; p += kFinBlock) m = fmax(m, rc.errpart[p]);
         m = wave_max(m);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sred[0][threadIdx.x >> 6] = m;
+        if ((threadIdx.x & 63) == 0) serr[threadIdx.x >> 6] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 1; w < NW; ++w) m = fmax(m, sred[0][w]);
-            Control& C = *rc.ctrl;
-            C.attempts += 1;
-            const double* Jnext = rc.jhist + (TAB::fsal ? (S - 1) : S) * NV;
-            if constexpr (!TAB::embedded) {
-                // fixed step: always accepted
-                if (!(m <= 1.0e300)) { C.status = -4; }
-                else {
-                    C.istep += 1;
-                    C.nacc += 1;
-                    C.cur ^= 1;
-                    C.r = rc.r_start + (double)C.istep * rc.h_fixed;
-                    C.h = rc.h_fixed;
-                    for (int v = 0; v < NV; ++v) rc.jhist[v] = Jnext[v];
-                    if (C.istep >= rc.n_fixed || C.r >= C.r_end) C.status = 1;
-                }
+            for (int w = 1; w < kFinBlock / 64; ++w) m = fmax(m, serr[w]);
+            Control c = *ctl;
+            s_acc = control_step<TAB>(rc, c, m) ? 1 : 0;
+            sC = c;
+            if (blockIdx.x == 0) rc.ctrl[1] = c;
+        }
+        __syncthreads();
+        // J_0 of the next attempt: the accepted state's moments (J of the
+        // state formed by the last stage-forming launch), else unchanged
+        if ((int)threadIdx.x < NV) {
+            const int v = threadIdx.x;
+            if (s_acc) {
+                if constexpr (TAB::fsal) sJ[v] = rc.jhist[(size_t)(S - 1) * NV + v];
+                if (blockIdx.x == 0) rc.jhist[v] = sJ[v];
             } else {
-                const double err = m / rc.rtol;
-                C.err = err;
-                if (!(err <= 1.0e300)) {
-                    C.status = -4;
-                } else {
-                    const double f_lo = 0.2, f_hi = 5.0;
-                    double fac, rn = C.r;
-                    if (err <= 1.0) {
-                        rn = C.r + h;
-                        C.r = rn;
-                        C.nacc += 1;
-                        C.cur ^= 1;
-                        for (int v = 0; v < NV; ++v) rc.jhist[v] = Jnext[v];
-                        fac = (err == 0.0) ? f_hi : rc.safety * pow(err, -0.2);
-                        fac = fmin(fmax(fac, f_lo), f_hi);
-                        if (C.last_rejected && fac > 1.0) fac = 1.0;
-                        C.last_rejected = 0;
-                    } else {
-                        C.nrej += 1;
-                        fac = fmax(rc.safety * pow(err, -0.2), f_lo);
-                        C.last_rejected = 1;
-                    }
-                    double hn = fmin(h * fac, rc.dr_max);
-                    C.h_prop = hn;
-                    if (rn >= C.r_end) {
-                        C.status = 1;
-                    } else if (hn < 1e-14 * rn) {
-                        C.status = -5;
-                    } else {
-                        if (rn + hn > C.r_end) hn = C.r_end - rn;
-                    }
-                    C.h = hn;
-                }
+                sJ[v] = rc.jhist[v];
             }
-            if (C.status == 0 && rc.max_steps > 0 && C.attempts >= rc.max_steps) C.status = -6;
+        }
+        __syncthreads();
+        C = sC;
+        if (C.status != 0) return;
+    } else {
+        C = *ctl;
+        if (blockIdx.x == 0 && (int)threadIdx.x < NV) rc.jhist[(size_t)I * NV + threadIdx.x] = sJ[threadIdx.x];
+    }
+    if (!own) return;
+
+    double J[NV];
+    for (int v = 0; v < NV; ++v) J[v] = sJ[v];
+    const double* phn = C.cur ? ph1 : ph0;  // Phi_n of the attempt the tables are for
+    double G[N];
+    if constexpr (FINAL) {
+        // next attempt: stage 0 at the new radius, completed with its J_0; stage 1
+        double c0, w0, c1, w1;
+        traj_geometry(rc, j, stage_radius<TAB>(rc, C, 0), c0, w0);
+        traj_geometry(rc, j, stage_radius<TAB>(rc, C, 1), c1, w1);
+        const StageFrame<N> f0 = prepare_stage<N>(rc, j, 0, c0, w0, phn);
+        complete_stage<T, N>(rc, j, 0, f0, matter(rc, stage_radius<TAB>(rc, C, 0)), J, G);
+        double ph[N];
+        for (int a = 0; a < N; ++a) ph[a] = phn[a] + C.h * (TAB::A[1][0] * G[a]);
+        prepare_stage<N>(rc, j, 1, c1, w1, ph);
+    } else {
+        complete_stage<T, N>(rc, j, I, fI, lamI, J, G);
+        // phase of stage I+1: Phi_n + h sum_{m <= I} coef(I+1, m) G_m
+        constexpr int L = I + 1;
+        double ph[N];
+        for (int a = 0; a < N; ++a) {
+            double acc = 0.0;
+            static_for<0, L>([&](auto Mc) {
+                constexpr int m = decltype(Mc)::value;
+                if constexpr (coef<TAB>(L, m) != 0.0) acc += coef<TAB>(L, m) * (m == I ? G[a] : Gh[m < NG ? m : 0][a]);
+            });
+            ph[a] = phn[a] + C.h * acc;
+        }
+        prepare_stage<N>(rc, j, L, cn, wn, ph);
+        if (L == S) {
+            double* out = rc.phase[C.cur ^ 1] + (size_t)j * N;  // kept only if the attempt is accepted
+            for (int a = 0; a < N; ++a) out[a] = ph[a];
         }
     }
+}
+
+// Stage-0 geometry and frame factors of the current state.
+template <int N, typename TAB>
+__global__ void __launch_bounds__(kFinBlock) k_prepare(const RunConst rc)
+{
+    const int j = blockIdx.x * kFinBlock + threadIdx.x;
+    if (j >= rc.na) return;
+    const Control C = rc.ctrl[1];
+    double ph[N], c, w;
+    for (int a = 0; a < N; ++a) ph[a] = rc.phase[C.cur][(size_t)j * N + a];
+    traj_geometry(rc, j, stage_radius<TAB>(rc, C, 0), c, w);
+    prepare_stage<N>(rc, j, 0, c, w, ph);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -654,7 +843,7 @@ __global__ void k_probabilities(const RunConst rc, double* __restrict__ p)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= rc.nb) return;
-    const T* src = psi_ptr<T>(rc, rc.ctrl->cur);
+    const T* src = reinterpret_cast<const T*>(rc.psi[rc.ctrl[1].cur]);
     const double re = (double)src[0 * rc.nb_pad + b], im = (double)src[1 * rc.nb_pad + b];
     p[b] = re * re + im * im;
 }
@@ -664,76 +853,97 @@ __global__ void k_init(const RunConst rc)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b < rc.nb_pad) {
-        T* dst = psi_ptr<T>(rc, rc.ctrl->cur);
+        T* dst = reinterpret_cast<T*>(rc.psi[rc.ctrl[1].cur]);
         for (int q = 0; q < 2 * N; ++q) dst[q * rc.nb_pad + b] = (q == 0 && b < rc.nb) ? T(1) : T(0);
     }
-    if (b < (int64_t)rc.na * N) rc.phase[rc.ctrl->cur][b] = 0.0;
+    if (b < (int64_t)rc.na * N) rc.phase[rc.ctrl[1].cur][b] = 0.0;
 }
 
 // ------------------------------------------------------------------ dispatch
-using StageFn = void (*)(const RunConst);
+using KernFn = void (*)(const RunConst);
 
-template <typename TS, typename T, int N, bool MA, typename TAB>
+template <typename TS, typename T, int N, typename TAB>
 struct StageTable {
     template <int... Is>
-    static constexpr std::array<StageFn, kMaxStages> make(std::integer_sequence<int, Is...>)
+    static constexpr std::array<KernFn, kMaxStages> make(std::integer_sequence<int, Is...>)
     {
-        return {{(Is <= TAB::S ? (StageFn)&k_stage<TS, T, N, MA, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+        return {{(Is <= TAB::S ? (KernFn)&k_stage<TS, T, N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
     }
-    static constexpr std::array<StageFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
+    static constexpr std::array<KernFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
-template <int N, typename TAB>
+template <typename T, int N, typename TAB>
 struct FinTable {
     template <int... Is>
-    static constexpr std::array<StageFn, kMaxStages> make(std::integer_sequence<int, Is...>)
+    static constexpr std::array<KernFn, kMaxStages> make(std::integer_sequence<int, Is...>)
     {
-        return {{(Is <= TAB::S ? (StageFn)&k_finalize<N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+        return {{(Is <= TAB::S ? (KernFn)&k_finalize<T, N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
     }
-    static constexpr std::array<StageFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
+    static constexpr std::array<KernFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
-StageFn pick_finalize(int n, int integrator, int stage)
+template <typename TS, typename T, int N>
+void pick(int integrator, int stage, KernFn& k, KernFn& f)
 {
-    if (n == 2) return integrator == 0 ? FinTable<2, TabRK4>::fns[stage] : FinTable<2, TabDP54>::fns[stage];
-    return integrator == 0 ? FinTable<3, TabRK4>::fns[stage] : FinTable<3, TabDP54>::fns[stage];
+    if (integrator == 0) {
+        k = StageTable<TS, T, N, TabRK4>::fns[stage];
+        f = FinTable<T, N, TabRK4>::fns[stage];
+    } else {
+        k = StageTable<TS, T, N, TabDP54>::fns[stage];
+        f = FinTable<T, N, TabDP54>::fns[stage];
+    }
 }
 
-template <typename TS, typename T, int N, bool MA>
-StageFn pick_tab(int integrator, int stage)
-{
-    return integrator == 0 ? StageTable<TS, T, N, MA, TabRK4>::fns[stage]
-                           : StageTable<TS, T, N, MA, TabDP54>::fns[stage];
-}
-template <typename TS, typename T, int N>
-StageFn pick_ma(int ma, int integrator, int stage)
-{
-    return ma ? pick_tab<TS, T, N, true>(integrator, stage) : pick_tab<TS, T, N, false>(integrator, stage);
-}
 template <typename TS, typename T>
-StageFn pick_n(int n, int ma, int integrator, int stage)
+void pick_n(int n, int integrator, int stage, KernFn& k, KernFn& f)
 {
-    return n == 2 ? pick_ma<TS, T, 2>(ma, integrator, stage) : pick_ma<TS, T, 3>(ma, integrator, stage);
+    if (n == 2) pick<TS, T, 2>(integrator, stage, k, f);
+    else pick<TS, T, 3>(integrator, stage, k, f);
 }
+
+unsigned fin_grid(const RunConst& rc) { return (unsigned)((rc.na + kFinBlock - 1) / kFinBlock); }
 
 }  // namespace
 
 int num_stages(int integrator) { return integrator == 0 ? TabRK4::S : TabDP54::S; }
 
-hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s)
+hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s, hipEvent_t* ev)
 {
     if (stage < 0 || stage > num_stages(rc.integrator)) return hipErrorInvalidValue;
-    StageFn fn = nullptr;
+    KernFn k = nullptr, f = nullptr;
+    const unsigned block = rc.precision == 1 ? BeamShape<float>::block : BeamShape<double>::block;
+    if ((rc.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(rc.precision))
+        return hipErrorInvalidValue;
     switch (rc.precision) {
-    case 0: fn = pick_n<double, double>(rc.n, rc.ma, rc.integrator, stage); break;   // FP64
-    case 1: fn = pick_n<float, float>(rc.n, rc.ma, rc.integrator, stage); break;     // FP32 amplitudes
-    case 2: fn = pick_n<float, double>(rc.n, rc.ma, rc.integrator, stage); break;    // FP32 amplitudes, FP64 math
+    case 0: pick_n<double, double>(rc.n, rc.integrator, stage, k, f); break;  // FP64
+    case 1: pick_n<float, float>(rc.n, rc.integrator, stage, k, f); break;    // FP32 amplitudes
+    case 2: pick_n<float, double>(rc.n, rc.integrator, stage, k, f); break;   // FP32 amplitudes, FP64 math
     default: break;
     }
-    StageFn fin = pick_finalize(rc.n, rc.integrator, stage);
-    if (!fn || !fin) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3((rc.na + kTrajPerBlock - 1) / kTrajPerBlock), dim3(64 * kTrajPerBlock), 0, s, rc);
-    hipLaunchKernelGGL(fin, dim3(1), dim3(kFinBlock), 0, s, rc);
+    if (!k || !f) return hipErrorInvalidValue;
+    if (ev) {
+        hipError_t e = hipEventRecord(ev[0], s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)rc.nblk), dim3(block), 0, s, rc);
+    if (ev) {
+        hipError_t e = hipEventRecord(ev[1], s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(f, dim3(fin_grid(rc)), dim3(kFinBlock), 0, s, rc);
+    if (ev) {
+        hipError_t e = hipEventRecord(ev[2], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const RunConst& rc, hipStream_t s)
+{
+    KernFn k;
+    if (rc.n == 2) k = rc.integrator == 0 ? (KernFn)&k_prepare<2, TabRK4> : (KernFn)&k_prepare<2, TabDP54>;
+    else k = rc.integrator == 0 ? (KernFn)&k_prepare<3, TabRK4> : (KernFn)&k_prepare<3, TabDP54>;
+    hipLaunchKernelGGL(k, dim3(fin_grid(rc)), dim3(kFinBlock), 0, s, rc);
     return hipGetLastError();
 }
 

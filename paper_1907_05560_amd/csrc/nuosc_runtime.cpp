@@ -32,6 +32,15 @@ struct nuosc_handle {
     double* prob = nullptr;  // device [nb]
     Control hctl{};
     std::string err;
+    // kernel timing: a pool of event triples, the stage of each used triple,
+    // and per-stage sums of the harvested durations
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_stage;
+    size_t ev_used = 0;
+    double t_beam[nuosc::kMaxStages + 1] = {};
+    double t_fin[nuosc::kMaxStages + 1] = {};
+    int64_t t_count[nuosc::kMaxStages + 1] = {};
 };
 
 namespace {
@@ -99,8 +108,13 @@ double fermi_integral(int k, double eta)
     return total;
 }
 
+// Per-slot tables of one trajectory's 2 NE beam slots (slot k: neutrino of
+// bin k; slot NE + k: antineutrino of bin k, whose amplitudes the device holds
+// conjugated): signed inverse energy u and density weight.
 struct Tables {
     std::vector<double> inv_e, g, gbar;
+    std::vector<double> uinv64, wgt;
+    std::vector<float> uinv32;
     double vac[3][3][2];
 };
 
@@ -110,6 +124,9 @@ bool build_tables(const nuosc_params& p, Tables& t)
     t.inv_e.resize(ne);
     t.g.resize(ne);
     t.gbar.resize(ne);
+    t.uinv64.resize(2 * ne);
+    t.uinv32.resize(2 * ne);
+    t.wgt.resize(2 * ne);
     double temp[4], f2[4], nrel[4];
     for (int s = 0; s < 4; ++s) {
         f2[s] = fermi_integral(2, p.eta[s]);
@@ -158,6 +175,13 @@ bool build_tables(const nuosc_params& p, Tables& t)
                 t.vac[a][b][1] = v.imag();
             }
     }
+    for (int k = 0; k < ne; ++k) {
+        t.uinv64[k] = t.inv_e[k];
+        t.uinv64[ne + k] = -t.inv_e[k];
+        t.wgt[k] = t.g[k];
+        t.wgt[ne + k] = -t.gbar[k];
+    }
+    for (int i = 0; i < 2 * ne; ++i) t.uinv32[i] = (float)t.uinv64[i];
     for (int k = 0; k < ne; ++k)
         if (!std::isfinite(t.g[k]) || !std::isfinite(t.gbar[k])) return false;
     return true;
@@ -165,9 +189,9 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], inv_e, g, gbar, jhist, partial, errpart, tab, ctrl, counter, prob, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, mat, geo, ctrl, prob, total;
     int64_t nb, nb_pad;
-    int na;
+    int na, nblk;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -199,7 +223,10 @@ const char* validate(const nuosc_params* p)
     if (p->frame != NUOSC_FRAME_COROTATING && p->frame != NUOSC_FRAME_LAB) return "unknown frame";
     if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
     const int64_t na = std::max(p->n_angle, 1);
-    if (2 * (int64_t)p->n_energy * na > ((int64_t)1 << 31)) return "too many beams";
+    // each amplitude component array is addressed with 32-bit byte offsets
+    const int64_t tsz = p->precision == NUOSC_FP64 ? 8 : 4;
+    if ((2 * (int64_t)p->n_energy * na + 64) * tsz >= ((int64_t)1 << 32))
+        return "too many beams (one amplitude component must stay below 4 GiB)";
     return nullptr;
 }
 
@@ -217,17 +244,19 @@ Layout make_layout(const nuosc_params& p)
         off = align_up(off + bytes, 256);
         return at;
     };
+    const int tpb = nuosc::traj_per_block(p.precision);
+    L.nblk = (L.na + tpb - 1) / tpb;
     for (int b = 0; b < 2; ++b) L.psi[b] = take(2 * n * (size_t)L.nb_pad * tsz);
     for (int b = 0; b < 2; ++b) L.phase[b] = take((size_t)L.na * n * 8);
-    L.inv_e = take((size_t)p.n_energy * 8);
-    L.g = take((size_t)p.n_energy * 8);
-    L.gbar = take((size_t)p.n_energy * 8);
-    L.jhist = take((size_t)nuosc::kMaxStages * 2 * n * n * 8);
-    L.partial = take((size_t)2 * n * n * L.na * 8);
-    L.errpart = take((size_t)L.na * 8);
-    L.tab = take((size_t)nuosc::kMaxStages * L.na * sizeof(nuosc::TrajStage));
-    L.ctrl = take(sizeof(Control));
-    L.counter = take(2 * sizeof(unsigned));
+    L.uinv64 = take((size_t)2 * p.n_energy * 8);
+    L.uinv32 = take((size_t)2 * p.n_energy * 4);
+    L.wgt = take((size_t)2 * p.n_energy * 8);
+    L.jhist = take((size_t)(nuosc::kMaxStages + 1) * 2 * n * n * 8);
+    L.partial = take((size_t)2 * n * n * L.nblk * 8);
+    L.errpart = take((size_t)L.nblk * 8);
+    L.mat = take((size_t)nuosc::kMaxStages * L.na * nuosc::kStageMatBytes);
+    L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
+    L.ctrl = take(2 * sizeof(Control));
     L.prob = take((size_t)L.nb * 8);
     L.total = off;
     return L;
@@ -251,18 +280,75 @@ nuosc_status hip_fail(nuosc_handle* h, hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail((h), e_, #call);   \
     } while (0)
 
+// Host state <-> device state: the device holds antineutrino amplitudes
+// (beams NE*NA .. NB-1) complex-conjugated; psi is [2n][nb] (re/im rows).
+void conjugate_antineutrinos(const RunConst& rc, double* psi)
+{
+    const int64_t half = rc.nb / 2;
+    for (int a = 0; a < rc.n; ++a) {
+        double* im = psi + (size_t)(2 * a + 1) * rc.nb;
+        for (int64_t b = half; b < rc.nb; ++b) im[b] = -im[b];
+    }
+}
+
+// The control block between attempts is ctrl[1]; the host writes both copies.
 nuosc_status read_control(nuosc_handle* h)
 {
-    HIP_TRY(h, hipMemcpyAsync(&h->hctl, h->rc.ctrl, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&h->hctl, h->rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return NUOSC_OK;
 }
 
 nuosc_status write_control(nuosc_handle* h)
 {
-    HIP_TRY(h, hipMemcpyAsync(h->rc.ctrl, &h->hctl, sizeof(Control), hipMemcpyHostToDevice, h->stream));
+    Control two[2] = {h->hctl, h->hctl};
+    HIP_TRY(h, hipMemcpyAsync(h->rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return NUOSC_OK;
+}
+
+// Harvest every recorded event triple into the per-stage sums.
+nuosc_status harvest_timing(nuosc_handle* h)
+{
+    if (h->ev_used == 0) return NUOSC_OK;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < h->ev_used; ++i) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&a, h->ev[3 * i], h->ev[3 * i + 1]));
+        HIP_TRY(h, hipEventElapsedTime(&b, h->ev[3 * i + 1], h->ev[3 * i + 2]));
+        const int st = h->ev_stage[i];
+        h->t_beam[st] += a;
+        h->t_fin[st] += b;
+        h->t_count[st] += 1;
+    }
+    h->ev_used = 0;
+    return NUOSC_OK;
+}
+
+// One stage launch (beam kernel + finalise kernel), timed when enabled.
+nuosc_status stage(nuosc_handle* h, int st)
+{
+    hipEvent_t* ev = nullptr;
+    if (h->timing) {
+        if (h->ev_used * 3 == h->ev.size()) {
+            nuosc_status s = harvest_timing(h);
+            if (s != NUOSC_OK) return s;
+        }
+        ev = &h->ev[3 * h->ev_used];
+        h->ev_stage[h->ev_used] = st;
+        h->ev_used += 1;
+    }
+    HIP_TRY(h, nuosc::launch_stage(h->rc, st, h->stream, ev));
+    return NUOSC_OK;
+}
+
+// Moments of the current state and the tables of stages 0 and 1 of the next
+// attempt, for the control block on the device (after create, set_state, or
+// a host change of the step).
+nuosc_status restart(nuosc_handle* h)
+{
+    HIP_TRY(h, nuosc::launch_prepare(h->rc, h->stream));
+    return stage(h, 0);
 }
 
 nuosc_status status_of(nuosc_handle* h)
@@ -280,7 +366,10 @@ nuosc_status status_of(nuosc_handle* h)
 nuosc_status enqueue(nuosc_handle* h, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i)
-        for (int st = 1; st <= h->S; ++st) HIP_TRY(h, nuosc::launch_stage(h->rc, st, h->stream));
+        for (int st = 1; st <= h->S; ++st) {
+            nuosc_status s = stage(h, st);
+            if (s != NUOSC_OK) return s;
+        }
     return NUOSC_OK;
 }
 
@@ -360,6 +449,7 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
     rc.ma = p->n_angle > 0;
     rc.nb = L.nb;
     rc.nb_pad = L.nb_pad;
+    rc.nblk = L.nblk;
     rc.frame = p->frame;
     rc.precision = p->precision;
     rc.integrator = p->integrator;
@@ -380,15 +470,15 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
         rc.psi[b] = base + L.psi[b];
         rc.phase[b] = (double*)(base + L.phase[b]);
     }
-    rc.inv_e = (const double*)(base + L.inv_e);
-    rc.g = (const double*)(base + L.g);
-    rc.gbar = (const double*)(base + L.gbar);
+    rc.uinv64 = (const double*)(base + L.uinv64);
+    rc.uinv32 = (const float*)(base + L.uinv32);
+    rc.wgt = (const double*)(base + L.wgt);
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
-    rc.tab = (nuosc::TrajStage*)(base + L.tab);
+    rc.mat = (void*)(base + L.mat);
+    rc.geo = (nuosc::TrajGeo*)(base + L.geo);
     rc.ctrl = (Control*)(base + L.ctrl);
-    rc.counter = (unsigned*)(base + L.counter);
     h->prob = (double*)(base + L.prob);
 
     Control& c = h->hctl;
@@ -403,13 +493,14 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
     }
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    chk(hipMemcpyAsync((void*)rc.inv_e, tab.inv_e.data(), tab.inv_e.size() * 8, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemcpyAsync((void*)rc.g, tab.g.data(), tab.g.size() * 8, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemcpyAsync((void*)rc.gbar, tab.gbar.data(), tab.gbar.size() * 8, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemsetAsync(rc.jhist, 0, (size_t)nuosc::kMaxStages * 2 * rc.n * rc.n * 8, h->stream));
-    chk(hipMemsetAsync(rc.counter, 0, 2 * sizeof(unsigned), h->stream));
-    chk(hipMemcpyAsync(rc.ctrl, &c, sizeof(Control), hipMemcpyHostToDevice, h->stream));
+    const Control two[2] = {c, c};
+    chk(hipMemcpyAsync((void*)rc.uinv64, tab.uinv64.data(), tab.uinv64.size() * 8, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemcpyAsync((void*)rc.uinv32, tab.uinv32.data(), tab.uinv32.size() * 4, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemcpyAsync((void*)rc.wgt, tab.wgt.data(), tab.wgt.size() * 8, hipMemcpyHostToDevice, h->stream));
+    chk(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * 2 * rc.n * rc.n * 8, h->stream));
+    chk(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, h->stream));
     if (e == hipSuccess) e = nuosc::launch_init_state(rc, h->stream);
+    if (e == hipSuccess) e = nuosc::launch_prepare(rc, h->stream);
     if (e == hipSuccess) e = nuosc::launch_stage(rc, 0, h->stream);  // J of the initial state
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return bail(NUOSC_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
@@ -428,7 +519,40 @@ nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
     if (stage < 1 || stage > h->S) return fail(h, NUOSC_E_INVALID, "stage out of range");
-    HIP_TRY(h, nuosc::launch_stage(h->rc, stage, h->stream));
+    return ::stage(h, stage);
+}
+
+nuosc_status nuosc_timing_enable(nuosc_handle* h, int32_t on)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (on && h->ev.empty()) {
+        const size_t triples = 512;
+        h->ev.resize(3 * triples, nullptr);
+        h->ev_stage.resize(triples, 0);
+        for (auto& x : h->ev) HIP_TRY(h, hipEventCreate(&x));
+    }
+    h->timing = on != 0;
+    h->ev_used = 0;
+    for (int i = 0; i <= nuosc::kMaxStages; ++i) {
+        h->t_beam[i] = h->t_fin[i] = 0.0;
+        h->t_count[i] = 0;
+    }
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_timing_read(nuosc_handle* h, double* beam_ms, double* fin_ms, int64_t* count)
+{
+    if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
+    nuosc_status st = harvest_timing(h);
+    if (st != NUOSC_OK) return st;
+    for (int i = 0; i <= h->S; ++i) {
+        if (beam_ms) beam_ms[i] = h->t_beam[i];
+        if (fin_ms) fin_ms[i] = h->t_fin[i];
+        if (count) count[i] = h->t_count[i];
+        h->t_beam[i] = h->t_fin[i] = 0.0;
+        h->t_count[i] = 0;
+    }
     return NUOSC_OK;
 }
 
@@ -463,6 +587,8 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
     if (h->p.integrator == NUOSC_RK_DP54) h->hctl.h = std::min(h->hctl.h_prop, target - h->hctl.r);
     st = write_control(h);
     if (st != NUOSC_OK) return st;
+    st = restart(h);  // stage tables for the (possibly clipped) step
+    if (st != NUOSC_OK) return st;
     const auto t0 = std::chrono::steady_clock::now();
     int64_t batch = 8;
     for (;;) {
@@ -483,7 +609,8 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
 nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    HIP_TRY(h, nuosc::launch_stage(h->rc, 0, h->stream));
+    nuosc_status st0 = restart(h);
+    if (st0 != NUOSC_OK) return st0;
     const int n = h->rc.n, nm = n * n;
     std::vector<double> J(2 * nm);
     HIP_TRY(h, hipMemcpyAsync(J.data(), h->rc.jhist, J.size() * 8, hipMemcpyDeviceToHost, h->stream));
@@ -532,6 +659,7 @@ nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase)
         if (rc.precision == NUOSC_FP64) {
             HIP_TRY(h, hipMemcpy2DAsync(psi, rc.nb * 8, rc.psi[cur], rc.nb_pad * 8, rc.nb * 8, rows,
                                         hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
         } else {
             std::vector<float> tmp(rows * rc.nb);
             HIP_TRY(h, hipMemcpy2DAsync(tmp.data(), rc.nb * 4, rc.psi[cur], rc.nb_pad * 4, rc.nb * 4, rows,
@@ -539,6 +667,7 @@ nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase)
             HIP_TRY(h, hipStreamSynchronize(h->stream));
             for (size_t i = 0; i < tmp.size(); ++i) psi[i] = tmp[i];
         }
+        conjugate_antineutrinos(rc, psi);
     }
     if (phase)
         HIP_TRY(h, hipMemcpyAsync(phase, rc.phase[cur], (size_t)rc.na * rc.n * 8, hipMemcpyDeviceToHost, h->stream));
@@ -555,13 +684,15 @@ nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* p
     const RunConst& rc = h->rc;
     const int cur = h->hctl.cur;
     const size_t rows = 2 * (size_t)rc.n;
+    std::vector<double> dev(psi, psi + rows * rc.nb);
+    conjugate_antineutrinos(rc, dev.data());
     if (rc.precision == NUOSC_FP64) {
-        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 8, psi, rc.nb * 8, rc.nb * 8, rows,
+        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 8, dev.data(), rc.nb * 8, rc.nb * 8, rows,
                                     hipMemcpyHostToDevice, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
     } else {
         std::vector<float> tmp(rows * rc.nb);
-        for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)psi[i];
+        for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)dev[i];
         HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 4, tmp.data(), rc.nb * 4, rc.nb * 4, rows,
                                     hipMemcpyHostToDevice, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -588,10 +719,9 @@ nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* p
     }
     st = write_control(h);
     if (st != NUOSC_OK) return st;
-    if (c.status == 0) {
-        HIP_TRY(h, nuosc::launch_stage(rc, 0, h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
-    }
+    st = restart(h);
+    if (st != NUOSC_OK) return st;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return NUOSC_OK;
 }
 
@@ -616,6 +746,8 @@ void nuosc_destroy(nuosc_handle* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto& x : h->ev)
+        if (x) (void)hipEventDestroy(x);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NONFINIT
 # Every function the C ABI exports (include/nuosc.h).
 EXPORTS = (
     "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
-    "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
+    "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_timing_enable",
+    "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
     "nuosc_get_state", "nuosc_set_state", "nuosc_stats", "nuosc_num_beams",
     "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
 )
@@ -103,6 +104,10 @@ def lib() -> C.CDLL:
     L.nuosc_enqueue_stage.restype = C.c_int
     L.nuosc_num_stages.argtypes = [C.c_void_p]
     L.nuosc_num_stages.restype = C.c_int32
+    L.nuosc_timing_enable.argtypes = [C.c_void_p, C.c_int32]
+    L.nuosc_timing_enable.restype = C.c_int
+    L.nuosc_timing_read.argtypes = [C.c_void_p, _D, _D, _I64]
+    L.nuosc_timing_read.restype = C.c_int
     L.nuosc_evolve.argtypes = [C.c_void_p, C.c_double]
     L.nuosc_evolve.restype = C.c_int
     L.nuosc_moments.argtypes = [C.c_void_p, _D, _D, _D]
@@ -233,6 +238,20 @@ class Run:
     @property
     def num_stages(self) -> int:
         return int(lib().nuosc_num_stages(self.h))
+
+    # kernel timing (HIP events recorded by the library on the run's stream)
+    def timing_enable(self, on: bool = True):
+        self._check(lib().nuosc_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self):
+        """Summed beam-kernel and finalise-kernel milliseconds and launch counts
+        per stage (index 0 = the moment launch) since the last read."""
+        n = self.num_stages + 1
+        beam = np.zeros(n)
+        fin = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int64)
+        self._check(lib().nuosc_timing_read(self.h, _ptr(beam), _ptr(fin), cnt.ctypes.data_as(_I64)))
+        return beam, fin, cnt
 
     def evolve(self, r_target: float, check: bool = True) -> int:
         st = lib().nuosc_evolve(self.h, float(r_target))
