@@ -204,6 +204,65 @@ const char* nuosc_last_error(const nuosc_handle* h);
 /* Release the handle and everything it owns.  NULL-safe. */
 void nuosc_destroy(nuosc_handle* h);
 
+/* ---------------------------------------------------------------- batches
+ * Continuous batching of independent runs (the serving pattern): runs with
+ * different grids, spectra, luminosities and mixing parameters are admitted
+ * into slots while others are being stepped, keep their state resident in
+ * device memory, and are advanced together -- every launch of a batch step
+ * covers all active runs, each workgroup belonging to exactly one run, so a
+ * run's result is bitwise the same alone and in any mix.  All runs of a batch
+ * share n_flavors, precision and integrator.  Device memory for the runs
+ * comes from one arena; admission fails with NUOSC_E_BUSY when no slot is
+ * free or the arena has no gap of nuosc_footprint_bytes(p) bytes. */
+typedef struct nuosc_batch nuosc_batch;
+
+/* Create a batch of at most max_slots runs (1..1024).
+ *   hbm_budget_bytes  size of the device arena the runs are placed in
+ *   hip_stream        stream to order all work on, borrowed; NULL => own stream
+ *   device_arena      optional caller-owned device memory of hbm_budget_bytes
+ *                     (kept alive until nuosc_batch_destroy); NULL => allocated
+ * NUOSC_E_INVALID for bad arguments, NUOSC_E_NOMEM when the arena cannot be
+ * allocated.  On failure *out is NULL. */
+nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t precision, int32_t integrator,
+                                size_t hbm_budget_bytes, void* hip_stream, void* device_arena,
+                                nuosc_batch** out);
+
+/* Admit a run in its initial state; *slot receives its slot.  NUOSC_E_BUSY:
+ * no free slot or no arena gap large enough (nothing changes); NUOSC_E_INVALID:
+ * invalid parameters, or n_flavors / precision / integrator differ from the
+ * batch's.  Synchronises the stream. */
+nuosc_status nuosc_batch_admit(nuosc_batch* b, const nuosc_params* p, int32_t* slot);
+
+/* Make n_attempts step attempts of every admitted run that is still running
+ * (the launch sequence of one batch step is captured once per set of active
+ * runs as a HIP graph and replayed).  *n_finished (nullable) receives the
+ * number of admitted runs that have stopped (reached r_end, or stopped on an
+ * error or limit).  Synchronises the stream. */
+nuosc_status nuosc_batch_step(nuosc_batch* b, int64_t n_attempts, int32_t* n_finished);
+
+/* State of the run in a slot (each pointer nullable): accepted and rejected
+ * steps, radius, and its status (NUOSC_OK while running or after reaching
+ * r_end, which *done reports as 1; else the error it stopped on). */
+nuosc_status nuosc_batch_query(nuosc_batch* b, int32_t slot, int64_t* accepted, int64_t* rejected,
+                               double* r_km, int32_t* done, int32_t* run_status);
+
+/* Number of beams of the run in a slot (0 for a free slot). */
+int64_t nuosc_batch_num_beams(const nuosc_batch* b, int32_t slot);
+
+/* Remove the run in a slot, first writing its survival probabilities to
+ * p_out (host, NB doubles; nullable), and free its memory and slot. */
+nuosc_status nuosc_batch_retire(nuosc_batch* b, int32_t slot, double* p_out);
+
+/* Number of occupied slots. */
+int32_t nuosc_batch_occupied(const nuosc_batch* b);
+
+/* Message of the last failure on b (or of the last failed batch create when
+ * b is NULL). */
+const char* nuosc_batch_last_error(const nuosc_batch* b);
+
+/* Release the batch, its runs and everything it owns.  NULL-safe. */
+void nuosc_batch_destroy(nuosc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

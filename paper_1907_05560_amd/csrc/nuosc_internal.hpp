@@ -84,16 +84,38 @@ constexpr int kFinBlock = 256;     // threads per finalise workgroup
 // FP32-arithmetic form, 8 for the FP64-arithmetic forms.
 inline int traj_per_block(int precision) { return precision == 1 ? 16 : 8; }
 
-// One stage of the current attempt: the stage kernel (stage 0 = moments of
-// the current state; stage == S = final launch) followed by its finalise
-// kernel.  ev, if not null, receives three events: before the stage kernel,
-// between the two kernels, after the finalise kernel.
-hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
+// The runs one launch covers.  Run i of the launch is runs[slot[i]] and owns
+// the workgroups [first[i], first[i + 1]); a workgroup never spans two runs,
+// so every run computes exactly what it would alone.  All runs of a launch
+// share the flavor count, precision and integrator (template parameters).
+constexpr int kMaxRuns = 64;
+struct LaunchSet {
+    const RunConst* runs;          // device array of run constants
+    int32_t count;
+    int32_t pad;
+    int32_t slot[kMaxRuns];
+    int32_t first[kMaxRuns + 1];
+};
+
+// Host view of the runs a launch covers: rc[i] is a host copy of the constants
+// stored at runs_dev[slot[i]].
+struct RunList {
+    const RunConst* runs_dev;
+    int count;
+    const int* slot;
+    const RunConst* const* rc;
+};
+
+// One stage of the current attempt of every listed run: the beam kernel
+// (stage 0 = moments of the current state; stage == S = final launch)
+// followed by its finalise kernel.  ev, if not null, receives three events:
+// before the beam kernel, between the two kernels, after the finalise kernel.
+hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
 // Geometry and frame factors of stage 0 for the current state (before a
 // stage-0 launch).
-hipError_t launch_prepare(const RunConst& rc, hipStream_t s);
-hipError_t launch_probabilities(const RunConst& rc, double* p_dev, hipStream_t s);
-hipError_t launch_init_state(const RunConst& rc, hipStream_t s);
+hipError_t launch_prepare(const RunList& runs, hipStream_t s);
+hipError_t launch_probabilities(const RunList& runs, double* p_dev, hipStream_t s);  // first run only
+hipError_t launch_init_state(const RunList& runs, hipStream_t s);
 int num_stages(int integrator);
 
 }  // namespace nuosc

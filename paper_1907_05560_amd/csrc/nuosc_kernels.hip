@@ -151,6 +151,21 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Run of workgroup blockIdx.x in launch set ls (binary search over the
+// cumulative offsets; wave-uniform) and the workgroup's index within the run.
+__device__ __forceinline__ int run_of_block(const LaunchSet& ls, int& blk)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = ls.count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ls.first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    blk = b - ls.first[lo];
+    return ls.slot[lo];
+}
+
 template <typename T> __device__ __forceinline__ const T* uinv_table(const RunConst& rc);
 template <> __device__ __forceinline__ const float* uinv_table<float>(const RunConst& rc) { return rc.uinv32; }
 template <> __device__ __forceinline__ const double* uinv_table<double>(const RunConst& rc) { return rc.uinv64; }
@@ -173,8 +188,10 @@ template <typename T> struct BeamShape {
 // wavefronts per trajectory.  TS: amplitude type in HBM; T: arithmetic type
 // of the stage update (the density sums are FP64 in every form).
 template <typename TS, typename T, int N, typename TAB, int I>
-__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc)
+__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet ls)
 {
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     constexpr int kTrajPerBlock = BeamShape<T>::traj;
     constexpr int kWavesPerTraj = BeamShape<T>::waves_per_traj;
     constexpr int NSLOT = BeamShape<T>::slots;
@@ -193,7 +210,7 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int jt = wave / kWavesPerTraj, sub = wave - jt * kWavesPerTraj;
-    const int j = blockIdx.x * kTrajPerBlock + jt;
+    const int j = blk * kTrajPerBlock + jt;
     const bool active = j < rc.na;
 
     __shared__ Mat smat[kTrajPerBlock][NK > 0 ? NK : 1];
@@ -219,7 +236,7 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
     }
 
     // the first launch of an attempt takes the control block between attempts
-    if (I == 1 && blockIdx.x == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
+    if (I == 1 && blk == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
     const Control* ctl = rc.ctrl + (I <= 1 ? 1 : 0);
     if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
     const int cur = ctl->cur;
@@ -235,6 +252,7 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
     TS* __restrict__ dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
     const size_t ld = (size_t)rc.nb_pad;
     const T* __restrict__ uinv = uinv_table<T>(rc);
+    const double* __restrict__ wgtp = rc.wgt;
     const T hT = (T)h;
     const Mat* mats = smat[jt];
 
@@ -251,7 +269,7 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(src + q * ld, off);
             uv = *elem(uinv, t);
-            if constexpr (MOMENTS) wv = *elem(rc.wgt, t);
+            if constexpr (MOMENTS) wv = *elem(wgtp, t);
         }
     };
     auto process = [&](uint32_t t, const TS* yv, T u, double wt) __attribute__((always_inline)) {
@@ -421,7 +439,7 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
     if constexpr (MOMENTS) {
         if (threadIdx.x < kTrajPerBlock) {
             const int tj = threadIdx.x;
-            const int jj = blockIdx.x * kTrajPerBlock + tj;
+            const int jj = blk * kTrajPerBlock + tj;
             double Sl[NM];
             double w0 = 0.0, w1 = 0.0;
             if (jj < rc.na) {
@@ -459,14 +477,14 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const RunConst rc
             const int v = threadIdx.x;
             double acc = spart[0][v];
             for (int w = 1; w < kTrajPerBlock; ++w) acc += spart[w][v];
-            rc.partial[(size_t)v * rc.nblk + blockIdx.x] = acc;
+            rc.partial[(size_t)v * rc.nblk + blk] = acc;
         }
     }
     if constexpr (FINAL) {
         if (threadIdx.x == 0) {
             double e = swave[0][NM];
             for (int w = 1; w < NWAVE; ++w) e = fmax(e, swave[w][NM]);
-            rc.errpart[blockIdx.x] = e;
+            rc.errpart[blk] = e;
         }
     }
 }
@@ -695,8 +713,10 @@ __device__ void reduce_partials(const RunConst& rc, double (&x)[4][NV], double* 
 // Finalise launch I (see the file header).  T: the stage kernels' arithmetic
 // type (of the stage matrices it writes).
 template <typename T, int N, typename TAB, int I>
-__global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const LaunchSet ls)
 {
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
     constexpr int NM = Shape<N>::NM;
@@ -713,7 +733,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
 
     // ---- per-trajectory inputs and the partials, loaded first so that their
     //      latencies overlap that of the control block
-    const int j = blockIdx.x * kFinBlock + threadIdx.x;
+    const int j = blk * kFinBlock + threadIdx.x;
     const bool own = j < rc.na;
     double ph0[N], ph1[N], Gh[NG][N];
     StageFrame<N> fI;
@@ -766,7 +786,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
             Control c = *ctl;
             s_acc = control_step<TAB>(rc, c, m) ? 1 : 0;
             sC = c;
-            if (blockIdx.x == 0) rc.ctrl[1] = c;
+            if (blk == 0) rc.ctrl[1] = c;
         }
         __syncthreads();
         // J_0 of the next attempt: the accepted state's moments (J of the
@@ -775,7 +795,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
             const int v = threadIdx.x;
             if (s_acc) {
                 if constexpr (TAB::fsal) sJ[v] = rc.jhist[(size_t)(S - 1) * NV + v];
-                if (blockIdx.x == 0) rc.jhist[v] = sJ[v];
+                if (blk == 0) rc.jhist[v] = sJ[v];
             } else {
                 sJ[v] = rc.jhist[v];
             }
@@ -785,7 +805,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
         if (C.status != 0) return;
     } else {
         C = *ctl;
-        if (blockIdx.x == 0 && (int)threadIdx.x < NV) rc.jhist[(size_t)I * NV + threadIdx.x] = sJ[threadIdx.x];
+        if (blk == 0 && (int)threadIdx.x < NV) rc.jhist[(size_t)I * NV + threadIdx.x] = sJ[threadIdx.x];
     }
     if (!own) return;
 
@@ -826,9 +846,11 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const RunConst rc)
 
 // Stage-0 geometry and frame factors of the current state.
 template <int N, typename TAB>
-__global__ void __launch_bounds__(kFinBlock) k_prepare(const RunConst rc)
+__global__ void __launch_bounds__(kFinBlock) k_prepare(const LaunchSet ls)
 {
-    const int j = blockIdx.x * kFinBlock + threadIdx.x;
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    const int j = blk * kFinBlock + threadIdx.x;
     if (j >= rc.na) return;
     const Control C = rc.ctrl[1];
     double ph[N], c, w;
@@ -839,9 +861,11 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(const RunConst rc)
 
 // ------------------------------------------------------------------ small kernels
 template <typename T, int N>
-__global__ void k_probabilities(const RunConst rc, double* __restrict__ p)
+__global__ void k_probabilities(const LaunchSet ls, double* __restrict__ p)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    const int64_t b = (int64_t)blk * blockDim.x + threadIdx.x;
     if (b >= rc.nb) return;
     const T* src = reinterpret_cast<const T*>(rc.psi[rc.ctrl[1].cur]);
     const double re = (double)src[0 * rc.nb_pad + b], im = (double)src[1 * rc.nb_pad + b];
@@ -849,9 +873,11 @@ __global__ void k_probabilities(const RunConst rc, double* __restrict__ p)
 }
 
 template <typename T, int N>
-__global__ void k_init(const RunConst rc)
+__global__ void k_init(const LaunchSet ls)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    const int64_t b = (int64_t)blk * blockDim.x + threadIdx.x;
     if (b < rc.nb_pad) {
         T* dst = reinterpret_cast<T*>(rc.psi[rc.ctrl[1].cur]);
         for (int q = 0; q < 2 * N; ++q) dst[q * rc.nb_pad + b] = (q == 0 && b < rc.nb) ? T(1) : T(0);
@@ -860,7 +886,7 @@ __global__ void k_init(const RunConst rc)
 }
 
 // ------------------------------------------------------------------ dispatch
-using KernFn = void (*)(const RunConst);
+using KernFn = void (*)(const LaunchSet);
 
 template <typename TS, typename T, int N, typename TAB>
 struct StageTable {
@@ -901,23 +927,58 @@ void pick_n(int n, int integrator, int stage, KernFn& k, KernFn& f)
     else pick<TS, T, 3>(integrator, stage, k, f);
 }
 
-unsigned fin_grid(const RunConst& rc) { return (unsigned)((rc.na + kFinBlock - 1) / kFinBlock); }
+// Launches fn over the listed runs, at most kMaxRuns runs per launch, with
+// blocks(rc) workgroups per run; launches nothing for an empty list.
+template <typename Blocks, typename Launch>
+hipError_t for_launch_sets(const RunList& runs, Blocks blocks, Launch launch)
+{
+    for (int i0 = 0; i0 < runs.count; i0 += kMaxRuns) {
+        LaunchSet ls{};
+        ls.runs = runs.runs_dev;
+        ls.count = runs.count - i0 < kMaxRuns ? runs.count - i0 : kMaxRuns;
+        ls.first[0] = 0;
+        for (int i = 0; i < ls.count; ++i) {
+            ls.slot[i] = runs.slot[i0 + i];
+            const long long nb = blocks(*runs.rc[i0 + i]);
+            if (nb < 1 || (long long)ls.first[i] + nb > 0x7fffffffLL) return hipErrorInvalidValue;
+            ls.first[i + 1] = ls.first[i] + (int)nb;
+        }
+        hipError_t e = launch(ls, (unsigned)ls.first[ls.count]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+long long fin_blocks(const RunConst& rc) { return (rc.na + kFinBlock - 1) / kFinBlock; }
+
+bool same_kind(const RunList& runs)
+{
+    for (int i = 1; i < runs.count; ++i) {
+        const RunConst& a = *runs.rc[0];
+        const RunConst& b = *runs.rc[i];
+        if (a.n != b.n || a.precision != b.precision || a.integrator != b.integrator) return false;
+    }
+    return true;
+}
 
 }  // namespace
 
 int num_stages(int integrator) { return integrator == 0 ? TabRK4::S : TabDP54::S; }
 
-hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s, hipEvent_t* ev)
+hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev)
 {
-    if (stage < 0 || stage > num_stages(rc.integrator)) return hipErrorInvalidValue;
+    if (runs.count < 1) return hipSuccess;
+    if (!same_kind(runs)) return hipErrorInvalidValue;
+    const RunConst& r0 = *runs.rc[0];
+    if (stage < 0 || stage > num_stages(r0.integrator)) return hipErrorInvalidValue;
     KernFn k = nullptr, f = nullptr;
-    const unsigned block = rc.precision == 1 ? BeamShape<float>::block : BeamShape<double>::block;
-    if ((rc.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(rc.precision))
+    const unsigned block = r0.precision == 1 ? BeamShape<float>::block : BeamShape<double>::block;
+    if ((r0.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(r0.precision))
         return hipErrorInvalidValue;
-    switch (rc.precision) {
-    case 0: pick_n<double, double>(rc.n, rc.integrator, stage, k, f); break;  // FP64
-    case 1: pick_n<float, float>(rc.n, rc.integrator, stage, k, f); break;    // FP32 amplitudes
-    case 2: pick_n<float, double>(rc.n, rc.integrator, stage, k, f); break;   // FP32 amplitudes, FP64 math
+    switch (r0.precision) {
+    case 0: pick_n<double, double>(r0.n, r0.integrator, stage, k, f); break;  // FP64
+    case 1: pick_n<float, float>(r0.n, r0.integrator, stage, k, f); break;    // FP32 amplitudes
+    case 2: pick_n<float, double>(r0.n, r0.integrator, stage, k, f); break;   // FP32 amplitudes, FP64 math
     default: break;
     }
     if (!k || !f) return hipErrorInvalidValue;
@@ -925,53 +986,74 @@ hipError_t launch_stage(const RunConst& rc, int stage, hipStream_t s, hipEvent_t
         hipError_t e = hipEventRecord(ev[0], s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)rc.nblk), dim3(block), 0, s, rc);
+    hipError_t e = for_launch_sets(runs, [](const RunConst& rc) { return (long long)rc.nblk; },
+                                   [&](const LaunchSet& ls, unsigned grid) {
+                                       hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, ls);
+                                       return hipGetLastError();
+                                   });
+    if (e != hipSuccess) return e;
     if (ev) {
-        hipError_t e = hipEventRecord(ev[1], s);
+        e = hipEventRecord(ev[1], s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(f, dim3(fin_grid(rc)), dim3(kFinBlock), 0, s, rc);
+    e = for_launch_sets(runs, fin_blocks, [&](const LaunchSet& ls, unsigned grid) {
+        hipLaunchKernelGGL(f, dim3(grid), dim3(kFinBlock), 0, s, ls);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     if (ev) {
-        hipError_t e = hipEventRecord(ev[2], s);
+        e = hipEventRecord(ev[2], s);
         if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
-hipError_t launch_prepare(const RunConst& rc, hipStream_t s)
+hipError_t launch_prepare(const RunList& runs, hipStream_t s)
 {
+    if (runs.count < 1) return hipSuccess;
+    if (!same_kind(runs)) return hipErrorInvalidValue;
+    const RunConst& r0 = *runs.rc[0];
     KernFn k;
-    if (rc.n == 2) k = rc.integrator == 0 ? (KernFn)&k_prepare<2, TabRK4> : (KernFn)&k_prepare<2, TabDP54>;
-    else k = rc.integrator == 0 ? (KernFn)&k_prepare<3, TabRK4> : (KernFn)&k_prepare<3, TabDP54>;
-    hipLaunchKernelGGL(k, dim3(fin_grid(rc)), dim3(kFinBlock), 0, s, rc);
-    return hipGetLastError();
+    if (r0.n == 2) k = r0.integrator == 0 ? (KernFn)&k_prepare<2, TabRK4> : (KernFn)&k_prepare<2, TabDP54>;
+    else k = r0.integrator == 0 ? (KernFn)&k_prepare<3, TabRK4> : (KernFn)&k_prepare<3, TabDP54>;
+    return for_launch_sets(runs, fin_blocks, [&](const LaunchSet& ls, unsigned grid) {
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kFinBlock), 0, s, ls);
+        return hipGetLastError();
+    });
 }
 
-hipError_t launch_probabilities(const RunConst& rc, double* p, hipStream_t s)
+hipError_t launch_probabilities(const RunList& runs, double* p, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((rc.nb + 255) / 256);
-    if (rc.precision == 0) {
-        if (rc.n == 2) hipLaunchKernelGGL((k_probabilities<double, 2>), dim3(grid), dim3(256), 0, s, rc, p);
-        else hipLaunchKernelGGL((k_probabilities<double, 3>), dim3(grid), dim3(256), 0, s, rc, p);
-    } else {
-        if (rc.n == 2) hipLaunchKernelGGL((k_probabilities<float, 2>), dim3(grid), dim3(256), 0, s, rc, p);
-        else hipLaunchKernelGGL((k_probabilities<float, 3>), dim3(grid), dim3(256), 0, s, rc, p);
-    }
-    return hipGetLastError();
+    if (runs.count < 1) return hipSuccess;
+    const RunList one{runs.runs_dev, 1, runs.slot, runs.rc};
+    const RunConst& r0 = *runs.rc[0];
+    using PFn = void (*)(const LaunchSet, double*);
+    PFn k;
+    if (r0.precision == 0) k = r0.n == 2 ? (PFn)&k_probabilities<double, 2> : (PFn)&k_probabilities<double, 3>;
+    else k = r0.n == 2 ? (PFn)&k_probabilities<float, 2> : (PFn)&k_probabilities<float, 3>;
+    return for_launch_sets(one, [](const RunConst& rc) { return (long long)((rc.nb + 255) / 256); },
+                           [&](const LaunchSet& ls, unsigned grid) {
+                               hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, ls, p);
+                               return hipGetLastError();
+                           });
 }
 
-hipError_t launch_init_state(const RunConst& rc, hipStream_t s)
+hipError_t launch_init_state(const RunList& runs, hipStream_t s)
 {
-    int64_t work = rc.nb_pad > (int64_t)rc.na * rc.n ? rc.nb_pad : (int64_t)rc.na * rc.n;
-    const unsigned grid = (unsigned)((work + 255) / 256);
-    if (rc.precision == 0) {
-        if (rc.n == 2) hipLaunchKernelGGL((k_init<double, 2>), dim3(grid), dim3(256), 0, s, rc);
-        else hipLaunchKernelGGL((k_init<double, 3>), dim3(grid), dim3(256), 0, s, rc);
-    } else {
-        if (rc.n == 2) hipLaunchKernelGGL((k_init<float, 2>), dim3(grid), dim3(256), 0, s, rc);
-        else hipLaunchKernelGGL((k_init<float, 3>), dim3(grid), dim3(256), 0, s, rc);
-    }
-    return hipGetLastError();
+    if (runs.count < 1) return hipSuccess;
+    if (!same_kind(runs)) return hipErrorInvalidValue;
+    const RunConst& r0 = *runs.rc[0];
+    KernFn k;
+    if (r0.precision == 0) k = r0.n == 2 ? (KernFn)&k_init<double, 2> : (KernFn)&k_init<double, 3>;
+    else k = r0.n == 2 ? (KernFn)&k_init<float, 2> : (KernFn)&k_init<float, 3>;
+    auto blocks = [](const RunConst& rc) {
+        const long long work = rc.nb_pad > (long long)rc.na * rc.n ? rc.nb_pad : (long long)rc.na * rc.n;
+        return (work + 255) / 256;
+    };
+    return for_launch_sets(runs, blocks, [&](const LaunchSet& ls, unsigned grid) {
+        hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, ls);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace nuosc

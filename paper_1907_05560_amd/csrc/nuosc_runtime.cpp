@@ -1,10 +1,14 @@
 // Host runtime and C ABI of libnuosc (see include/nuosc.h).
 //
 // The runtime validates a parameter set, builds the per-energy tables in FP64
-// (spectra eq 4.1-4.2, vacuum Hamiltonian eq 3.5-3.6), lays the run out in one
-// device allocation, and drives the stage kernels on the run's stream.  The
-// step controller runs on the device, so stepping needs no host round trip;
-// the host reads the control block only when a call returns.
+// (spectra eq 4.1-4.2, vacuum Hamiltonian eq 3.5-3.6), lays each run out in
+// one device region, and drives the kernels on a stream.  The step controller
+// runs on the device, so stepping needs no host round trip; the host reads a
+// run's control block only when a call returns.
+//
+// A run (RunState) is served either by a handle of its own (nuosc_create) or
+// as one slot of a batch (nuosc_batch_create), whose runs share every launch
+// and whose device memory comes from one arena with a first-fit allocator.
 #include "../../include/nuosc.h"
 #include "nuosc_internal.hpp"
 
@@ -13,35 +17,13 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
 using nuosc::Control;
 using nuosc::RunConst;
-
-struct nuosc_handle {
-    nuosc_params p{};
-    RunConst rc{};
-    int S = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    void* ws = nullptr;
-    bool own_ws = false;
-    size_t ws_bytes = 0;
-    double* prob = nullptr;  // device [nb]
-    Control hctl{};
-    std::string err;
-    // kernel timing: a pool of event triples, the stage of each used triple,
-    // and per-stage sums of the harvested durations
-    bool timing = false;
-    std::vector<hipEvent_t> ev;
-    std::vector<int> ev_stage;
-    size_t ev_used = 0;
-    double t_beam[nuosc::kMaxStages + 1] = {};
-    double t_fin[nuosc::kMaxStages + 1] = {};
-    int64_t t_count[nuosc::kMaxStages + 1] = {};
-};
 
 namespace {
 
@@ -189,7 +171,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, mat, geo, ctrl, prob, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, mat, geo, ctrl, prob, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk;
 };
@@ -258,27 +240,169 @@ Layout make_layout(const nuosc_params& p)
     L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
     L.ctrl = take(2 * sizeof(Control));
     L.prob = take((size_t)L.nb * 8);
+    L.rconst = take(sizeof(RunConst));
     L.total = off;
     return L;
 }
 
-nuosc_status fail(nuosc_handle* h, nuosc_status st, const std::string& msg)
-{
-    if (h) h->err = msg;
-    else g_create_error = msg;
-    return st;
-}
+// ---------------------------------------------------------------- one run
+// Host bookkeeping of one run and where its device data lives.
+struct RunState {
+    nuosc_params p{};
+    RunConst rc{};               // host copy of the device constants
+    Layout L{};
+    int S = 0;
+    char* base = nullptr;        // device region of the run (L.total bytes)
+    RunConst* runs_dev = nullptr;  // device array the launches index
+    int slot = 0;                // index of this run in runs_dev
+    double* prob = nullptr;      // device [nb]
+    Control hctl{};              // host copy of ctrl[1]
+};
 
-nuosc_status hip_fail(nuosc_handle* h, hipError_t e, const char* what)
-{
-    return fail(h, NUOSC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
+// A launch list holding one run.
+struct OneRun {
+    int slot;
+    const RunConst* rcp;
+    nuosc::RunList list;
+    explicit OneRun(const RunState& r) : slot(r.slot), rcp(&r.rc), list{r.runs_dev, 1, &slot, &rcp} {}
+};
 
-#define HIP_TRY(h, call)                                          \
-    do {                                                          \
-        hipError_t e_ = (call);                                   \
-        if (e_ != hipSuccess) return hip_fail((h), e_, #call);   \
+std::string hip_msg(hipError_t e, const char* what) { return std::string(what) + ": " + hipGetErrorString(e); }
+
+#define HIP_CHECK(call, msg_out)                       \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) {                        \
+            (msg_out) = hip_msg(e_, #call);            \
+            return NUOSC_E_DEVICE;                     \
+        }                                              \
     } while (0)
+
+// The control block between attempts is ctrl[1]; the host writes both copies.
+nuosc_status read_control(RunState& r, hipStream_t s, std::string& err)
+{
+    HIP_CHECK(hipMemcpyAsync(&r.hctl, r.rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost, s), err);
+    HIP_CHECK(hipStreamSynchronize(s), err);
+    return NUOSC_OK;
+}
+
+nuosc_status write_control(RunState& r, hipStream_t s, std::string& err)
+{
+    const Control two[2] = {r.hctl, r.hctl};
+    HIP_CHECK(hipMemcpyAsync(r.rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipStreamSynchronize(s), err);
+    return NUOSC_OK;
+}
+
+nuosc_status status_of(const Control& c, std::string& err)
+{
+    switch (c.status) {
+    case 0:
+    case 1: return NUOSC_OK;
+    case -4: err = "step error is not finite"; return NUOSC_E_NONFINITE;
+    case -5: err = "adaptive step fell below 1e-14 r"; return NUOSC_E_STEP_UNDERFLOW;
+    case -6: err = "max_steps reached"; return NUOSC_E_LIMIT;
+    default: err = "corrupt control block"; return NUOSC_E_DEVICE;
+    }
+}
+
+// Moments of the current state and the tables of stages 0 and 1 of the next
+// attempt, for the control block on the device (after initialisation, a new
+// state, or a host change of the step).
+nuosc_status restart(RunState& r, hipStream_t s, std::string& err)
+{
+    OneRun one(r);
+    HIP_CHECK(nuosc::launch_prepare(one.list, s), err);
+    HIP_CHECK(nuosc::launch_stage(one.list, 0, s), err);
+    return NUOSC_OK;
+}
+
+// Lays run r out at device address base (nuosc_footprint_bytes(p) bytes),
+// uploads its tables, constants and control block (its constants go to
+// runs_dev[slot]) and puts it in its initial state.  Synchronises s.
+nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* runs_dev, int slot, hipStream_t s,
+                      std::string& err)
+{
+    if (const char* why = validate(p)) {
+        err = why;
+        return NUOSC_E_INVALID;
+    }
+    Tables tab;
+    if (!build_tables(*p, tab)) {
+        err = "spectral tables are not finite";
+        return NUOSC_E_INVALID;
+    }
+    r.p = *p;
+    r.L = make_layout(*p);
+    r.S = nuosc::num_stages(p->integrator);
+    r.base = base;
+    r.runs_dev = runs_dev;
+    r.slot = slot;
+    const Layout& L = r.L;
+    RunConst& rc = r.rc;
+    rc = RunConst{};
+    rc.n = p->n_flavors;
+    rc.ne = p->n_energy;
+    rc.na = L.na;
+    rc.ma = p->n_angle > 0;
+    rc.nb = L.nb;
+    rc.nb_pad = L.nb_pad;
+    rc.nblk = L.nblk;
+    rc.frame = p->frame;
+    rc.precision = p->precision;
+    rc.integrator = p->integrator;
+    rc.r_nu = p->r_nu_km;
+    rc.mu0 = p->mu0_km;
+    rc.lambda0 = p->lambda0_km;
+    rc.lambda_rref = p->lambda_rref_km;
+    rc.lambda_power = p->lambda_power;
+    rc.rtol = p->rtol;
+    rc.safety = p->safety;
+    rc.dr_max = p->dr_max_km;
+    rc.r_start = p->r_start_km;
+    rc.n_fixed = p->n_fixed_steps;
+    rc.h_fixed = p->integrator == NUOSC_RK4_FIXED ? (p->r_end_km - p->r_start_km) / (double)p->n_fixed_steps : 0.0;
+    rc.max_steps = p->max_steps;
+    std::memcpy(rc.vac, tab.vac, sizeof(rc.vac));
+    for (int b = 0; b < 2; ++b) {
+        rc.psi[b] = base + L.psi[b];
+        rc.phase[b] = (double*)(base + L.phase[b]);
+    }
+    rc.uinv64 = (const double*)(base + L.uinv64);
+    rc.uinv32 = (const float*)(base + L.uinv32);
+    rc.wgt = (const double*)(base + L.wgt);
+    rc.jhist = (double*)(base + L.jhist);
+    rc.partial = (double*)(base + L.partial);
+    rc.errpart = (double*)(base + L.errpart);
+    rc.mat = (void*)(base + L.mat);
+    rc.geo = (nuosc::TrajGeo*)(base + L.geo);
+    rc.ctrl = (Control*)(base + L.ctrl);
+    r.prob = (double*)(base + L.prob);
+
+    Control& c = r.hctl;
+    std::memset(&c, 0, sizeof(c));
+    c.r = p->r_start_km;
+    c.r_end = p->r_end_km;
+    if (p->integrator == NUOSC_RK4_FIXED) {
+        c.h = c.h_prop = rc.h_fixed;
+    } else {
+        c.h_prop = std::min(p->dr_init_km, p->dr_max_km);
+        c.h = std::min(c.h_prop, p->r_end_km - p->r_start_km);
+    }
+    const Control two[2] = {c, c};
+    HIP_CHECK(hipMemcpyAsync((void*)rc.uinv64, tab.uinv64.data(), tab.uinv64.size() * 8, hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemcpyAsync((void*)rc.uinv32, tab.uinv32.data(), tab.uinv32.size() * 4, hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemcpyAsync((void*)rc.wgt, tab.wgt.data(), tab.wgt.size() * 8, hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * 2 * rc.n * rc.n * 8, s), err);
+    HIP_CHECK(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemcpyAsync(runs_dev + slot, &rc, sizeof(RunConst), hipMemcpyHostToDevice, s), err);
+    OneRun one(r);
+    HIP_CHECK(nuosc::launch_init_state(one.list, s), err);
+    nuosc_status st = restart(r, s, err);
+    if (st != NUOSC_OK) return st;
+    HIP_CHECK(hipStreamSynchronize(s), err);
+    return NUOSC_OK;
+}
 
 // Host state <-> device state: the device holds antineutrino amplitudes
 // (beams NE*NA .. NB-1) complex-conjugated; psi is [2n][nb] (re/im rows).
@@ -291,31 +415,62 @@ void conjugate_antineutrinos(const RunConst& rc, double* psi)
     }
 }
 
-// The control block between attempts is ctrl[1]; the host writes both copies.
-nuosc_status read_control(nuosc_handle* h)
+nuosc_status probabilities_of(RunState& r, double* p_out, hipStream_t s, std::string& err)
 {
-    HIP_TRY(h, hipMemcpyAsync(&h->hctl, h->rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    OneRun one(r);
+    HIP_CHECK(nuosc::launch_probabilities(one.list, r.prob, s), err);
+    HIP_CHECK(hipMemcpyAsync(p_out, r.prob, (size_t)r.rc.nb * 8, hipMemcpyDeviceToHost, s), err);
+    HIP_CHECK(hipStreamSynchronize(s), err);
     return NUOSC_OK;
 }
 
-nuosc_status write_control(nuosc_handle* h)
+}  // namespace
+
+// ---------------------------------------------------------------- handles
+struct nuosc_handle {
+    RunState run;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* ws = nullptr;
+    bool own_ws = false;
+    size_t ws_bytes = 0;
+    std::string err;
+    // kernel timing: a pool of event triples, the stage of each used triple,
+    // and per-stage sums of the harvested durations
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_stage;
+    size_t ev_used = 0;
+    double t_beam[nuosc::kMaxStages + 1] = {};
+    double t_fin[nuosc::kMaxStages + 1] = {};
+    int64_t t_count[nuosc::kMaxStages + 1] = {};
+};
+
+namespace {
+
+nuosc_status fail(nuosc_handle* h, nuosc_status st, const std::string& msg)
 {
-    Control two[2] = {h->hctl, h->hctl};
-    HIP_TRY(h, hipMemcpyAsync(h->rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    return NUOSC_OK;
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+nuosc_status checked(nuosc_handle* h, nuosc_status st, const std::string& msg)
+{
+    if (st != NUOSC_OK) h->err = msg;
+    return st;
 }
 
 // Harvest every recorded event triple into the per-stage sums.
 nuosc_status harvest_timing(nuosc_handle* h)
 {
     if (h->ev_used == 0) return NUOSC_OK;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::string& err = h->err;
+    HIP_CHECK(hipStreamSynchronize(h->stream), err);
     for (size_t i = 0; i < h->ev_used; ++i) {
         float a = 0.f, b = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&a, h->ev[3 * i], h->ev[3 * i + 1]));
-        HIP_TRY(h, hipEventElapsedTime(&b, h->ev[3 * i + 1], h->ev[3 * i + 2]));
+        HIP_CHECK(hipEventElapsedTime(&a, h->ev[3 * i], h->ev[3 * i + 1]), err);
+        HIP_CHECK(hipEventElapsedTime(&b, h->ev[3 * i + 1], h->ev[3 * i + 2]), err);
         const int st = h->ev_stage[i];
         h->t_beam[st] += a;
         h->t_fin[st] += b;
@@ -325,7 +480,7 @@ nuosc_status harvest_timing(nuosc_handle* h)
     return NUOSC_OK;
 }
 
-// One stage launch (beam kernel + finalise kernel), timed when enabled.
+// One stage launch of the handle's run, timed when enabled.
 nuosc_status stage(nuosc_handle* h, int st)
 {
     hipEvent_t* ev = nullptr;
@@ -338,40 +493,24 @@ nuosc_status stage(nuosc_handle* h, int st)
         h->ev_stage[h->ev_used] = st;
         h->ev_used += 1;
     }
-    HIP_TRY(h, nuosc::launch_stage(h->rc, st, h->stream, ev));
+    OneRun one(h->run);
+    HIP_CHECK(nuosc::launch_stage(one.list, st, h->stream, ev), h->err);
     return NUOSC_OK;
-}
-
-// Moments of the current state and the tables of stages 0 and 1 of the next
-// attempt, for the control block on the device (after create, set_state, or
-// a host change of the step).
-nuosc_status restart(nuosc_handle* h)
-{
-    HIP_TRY(h, nuosc::launch_prepare(h->rc, h->stream));
-    return stage(h, 0);
-}
-
-nuosc_status status_of(nuosc_handle* h)
-{
-    switch (h->hctl.status) {
-    case 0:
-    case 1: return NUOSC_OK;
-    case -4: return fail(h, NUOSC_E_NONFINITE, "step error is not finite");
-    case -5: return fail(h, NUOSC_E_STEP_UNDERFLOW, "adaptive step fell below 1e-14 r");
-    case -6: return fail(h, NUOSC_E_LIMIT, "max_steps reached");
-    default: return fail(h, NUOSC_E_DEVICE, "corrupt control block");
-    }
 }
 
 nuosc_status enqueue(nuosc_handle* h, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i)
-        for (int st = 1; st <= h->S; ++st) {
+        for (int st = 1; st <= h->run.S; ++st) {
             nuosc_status s = stage(h, st);
             if (s != NUOSC_OK) return s;
         }
     return NUOSC_OK;
 }
+
+nuosc_status hread(nuosc_handle* h) { return read_control(h->run, h->stream, h->err); }
+nuosc_status hwrite(nuosc_handle* h) { return write_control(h->run, h->stream, h->err); }
+nuosc_status hstatus(nuosc_handle* h) { return checked(h, status_of(h->run.hctl, h->err), h->err); }
 
 }  // namespace
 
@@ -410,16 +549,12 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
     if (!out) return fail(nullptr, NUOSC_E_INVALID, "out is NULL");
     *out = nullptr;
     if (const char* why = validate(p)) return fail(nullptr, NUOSC_E_INVALID, why);
-    Tables tab;
-    if (!build_tables(*p, tab)) return fail(nullptr, NUOSC_E_INVALID, "spectral tables are not finite");
     const Layout L = make_layout(*p);
     if (device_workspace && workspace_bytes < L.total)
         return fail(nullptr, NUOSC_E_INVALID, "workspace smaller than nuosc_footprint_bytes");
 
     nuosc_handle* h = new (std::nothrow) nuosc_handle();
     if (!h) return fail(nullptr, NUOSC_E_NOMEM, "host allocation failed");
-    h->p = *p;
-    h->S = nuosc::num_stages(p->integrator);
     auto bail = [&](nuosc_status st, const std::string& msg) {
         g_create_error = msg;
         nuosc_destroy(h);
@@ -429,7 +564,7 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
         h->stream = (hipStream_t)hip_stream;
     } else {
         hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return bail(NUOSC_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return bail(NUOSC_E_DEVICE, hip_msg(e, "hipStreamCreate"));
         h->own_stream = true;
     }
     if (device_workspace) {
@@ -437,73 +572,14 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
         h->ws_bytes = workspace_bytes;
     } else {
         hipError_t e = hipMalloc(&h->ws, L.total);
-        if (e != hipSuccess) return bail(NUOSC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return bail(NUOSC_E_NOMEM, hip_msg(e, "hipMalloc"));
         h->own_ws = true;
         h->ws_bytes = L.total;
     }
     char* base = (char*)h->ws;
-    RunConst& rc = h->rc;
-    rc.n = p->n_flavors;
-    rc.ne = p->n_energy;
-    rc.na = L.na;
-    rc.ma = p->n_angle > 0;
-    rc.nb = L.nb;
-    rc.nb_pad = L.nb_pad;
-    rc.nblk = L.nblk;
-    rc.frame = p->frame;
-    rc.precision = p->precision;
-    rc.integrator = p->integrator;
-    rc.r_nu = p->r_nu_km;
-    rc.mu0 = p->mu0_km;
-    rc.lambda0 = p->lambda0_km;
-    rc.lambda_rref = p->lambda_rref_km;
-    rc.lambda_power = p->lambda_power;
-    rc.rtol = p->rtol;
-    rc.safety = p->safety;
-    rc.dr_max = p->dr_max_km;
-    rc.r_start = p->r_start_km;
-    rc.n_fixed = p->n_fixed_steps;
-    rc.h_fixed = p->integrator == NUOSC_RK4_FIXED ? (p->r_end_km - p->r_start_km) / (double)p->n_fixed_steps : 0.0;
-    rc.max_steps = p->max_steps;
-    std::memcpy(rc.vac, tab.vac, sizeof(rc.vac));
-    for (int b = 0; b < 2; ++b) {
-        rc.psi[b] = base + L.psi[b];
-        rc.phase[b] = (double*)(base + L.phase[b]);
-    }
-    rc.uinv64 = (const double*)(base + L.uinv64);
-    rc.uinv32 = (const float*)(base + L.uinv32);
-    rc.wgt = (const double*)(base + L.wgt);
-    rc.jhist = (double*)(base + L.jhist);
-    rc.partial = (double*)(base + L.partial);
-    rc.errpart = (double*)(base + L.errpart);
-    rc.mat = (void*)(base + L.mat);
-    rc.geo = (nuosc::TrajGeo*)(base + L.geo);
-    rc.ctrl = (Control*)(base + L.ctrl);
-    h->prob = (double*)(base + L.prob);
-
-    Control& c = h->hctl;
-    std::memset(&c, 0, sizeof(c));
-    c.r = p->r_start_km;
-    c.r_end = p->r_end_km;
-    if (p->integrator == NUOSC_RK4_FIXED) {
-        c.h = c.h_prop = rc.h_fixed;
-    } else {
-        c.h_prop = std::min(p->dr_init_km, p->dr_max_km);
-        c.h = std::min(c.h_prop, p->r_end_km - p->r_start_km);
-    }
-    hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    const Control two[2] = {c, c};
-    chk(hipMemcpyAsync((void*)rc.uinv64, tab.uinv64.data(), tab.uinv64.size() * 8, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemcpyAsync((void*)rc.uinv32, tab.uinv32.data(), tab.uinv32.size() * 4, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemcpyAsync((void*)rc.wgt, tab.wgt.data(), tab.wgt.size() * 8, hipMemcpyHostToDevice, h->stream));
-    chk(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * 2 * rc.n * rc.n * 8, h->stream));
-    chk(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, h->stream));
-    if (e == hipSuccess) e = nuosc::launch_init_state(rc, h->stream);
-    if (e == hipSuccess) e = nuosc::launch_prepare(rc, h->stream);
-    if (e == hipSuccess) e = nuosc::launch_stage(rc, 0, h->stream);  // J of the initial state
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return bail(NUOSC_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    std::string err;
+    nuosc_status st = init_run(h->run, p, base, (RunConst*)(base + L.rconst), 0, h->stream, err);
+    if (st != NUOSC_OK) return bail(st, "initialisation: " + err);
     *out = h;
     return NUOSC_OK;
 }
@@ -518,19 +594,19 @@ nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts)
 nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    if (stage < 1 || stage > h->S) return fail(h, NUOSC_E_INVALID, "stage out of range");
+    if (stage < 1 || stage > h->run.S) return fail(h, NUOSC_E_INVALID, "stage out of range");
     return ::stage(h, stage);
 }
 
 nuosc_status nuosc_timing_enable(nuosc_handle* h, int32_t on)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     if (on && h->ev.empty()) {
         const size_t triples = 512;
         h->ev.resize(3 * triples, nullptr);
         h->ev_stage.resize(triples, 0);
-        for (auto& x : h->ev) HIP_TRY(h, hipEventCreate(&x));
+        for (auto& x : h->ev) HIP_CHECK(hipEventCreate(&x), h->err);
     }
     h->timing = on != 0;
     h->ev_used = 0;
@@ -546,7 +622,7 @@ nuosc_status nuosc_timing_read(nuosc_handle* h, double* beam_ms, double* fin_ms,
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
     nuosc_status st = harvest_timing(h);
     if (st != NUOSC_OK) return st;
-    for (int i = 0; i <= h->S; ++i) {
+    for (int i = 0; i <= h->run.S; ++i) {
         if (beam_ms) beam_ms[i] = h->t_beam[i];
         if (fin_ms) fin_ms[i] = h->t_fin[i];
         if (count) count[i] = h->t_count[i];
@@ -556,65 +632,66 @@ nuosc_status nuosc_timing_read(nuosc_handle* h, double* beam_ms, double* fin_ms,
     return NUOSC_OK;
 }
 
-int32_t nuosc_num_stages(const nuosc_handle* h) { return h ? h->S : 0; }
+int32_t nuosc_num_stages(const nuosc_handle* h) { return h ? h->run.S : 0; }
 
 nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
     if (n_attempts < 0) return fail(h, NUOSC_E_INVALID, "n_attempts must be >= 0");
-    nuosc_status st = read_control(h);
+    nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
-    const int64_t before = h->hctl.nacc;
+    const int64_t before = h->run.hctl.nacc;
     st = enqueue(h, n_attempts);
     if (st != NUOSC_OK) return st;
-    st = read_control(h);
+    st = hread(h);
     if (st != NUOSC_OK) return st;
-    if (n_accepted) *n_accepted = h->hctl.nacc - before;
-    return status_of(h);
+    if (n_accepted) *n_accepted = h->run.hctl.nacc - before;
+    return hstatus(h);
 }
 
 nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    nuosc_status st = read_control(h);
+    nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
-    if (h->hctl.status < 0) return status_of(h);
-    const double target = std::min(r_target_km, h->p.r_end_km);
-    if (h->hctl.r >= target) return NUOSC_OK;
+    Control& c = h->run.hctl;
+    if (c.status < 0) return hstatus(h);
+    const double target = std::min(r_target_km, h->run.p.r_end_km);
+    if (c.r >= target) return NUOSC_OK;
     // resume towards the new target
-    h->hctl.r_end = target;
-    h->hctl.status = 0;
-    if (h->p.integrator == NUOSC_RK_DP54) h->hctl.h = std::min(h->hctl.h_prop, target - h->hctl.r);
-    st = write_control(h);
+    c.r_end = target;
+    c.status = 0;
+    if (h->run.p.integrator == NUOSC_RK_DP54) c.h = std::min(c.h_prop, target - c.r);
+    st = hwrite(h);
     if (st != NUOSC_OK) return st;
-    st = restart(h);  // stage tables for the (possibly clipped) step
+    st = checked(h, restart(h->run, h->stream, h->err), h->err);  // stage tables for the (possibly clipped) step
     if (st != NUOSC_OK) return st;
     const auto t0 = std::chrono::steady_clock::now();
     int64_t batch = 8;
     for (;;) {
         st = enqueue(h, batch);
         if (st != NUOSC_OK) return st;
-        st = read_control(h);
+        st = hread(h);
         if (st != NUOSC_OK) return st;
-        if (h->hctl.status != 0) break;
-        if (h->p.max_wall_s > 0) {
+        if (c.status != 0) break;
+        if (h->run.p.max_wall_s > 0) {
             const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (el > h->p.max_wall_s) return fail(h, NUOSC_E_LIMIT, "max_wall_s reached");
+            if (el > h->run.p.max_wall_s) return fail(h, NUOSC_E_LIMIT, "max_wall_s reached");
         }
         batch = std::min<int64_t>(batch * 2, 2048);
     }
-    return status_of(h);
+    return hstatus(h);
 }
 
 nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    nuosc_status st0 = restart(h);
-    if (st0 != NUOSC_OK) return st0;
-    const int n = h->rc.n, nm = n * n;
+    nuosc_status st = checked(h, restart(h->run, h->stream, h->err), h->err);
+    if (st != NUOSC_OK) return st;
+    const int n = h->run.rc.n, nm = n * n;
     std::vector<double> J(2 * nm);
-    HIP_TRY(h, hipMemcpyAsync(J.data(), h->rc.jhist, J.size() * 8, hipMemcpyDeviceToHost, h->stream));
-    nuosc_status st = read_control(h);
+    HIP_CHECK(hipMemcpyAsync(J.data(), h->run.rc.jhist, J.size() * 8, hipMemcpyDeviceToHost, h->stream), h->err);
+    st = hread(h);
     if (st != NUOSC_OK) return st;
     for (int m = 0; m < 2; ++m) {
         double* out = m == 0 ? j0 : j1;
@@ -634,111 +711,111 @@ nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km
                 out[(b * n + a) * 2 + 1] = -im;
             }
     }
-    if (r_km) *r_km = h->hctl.r;
+    if (r_km) *r_km = h->run.hctl.r;
     return NUOSC_OK;
 }
 
 nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out)
 {
     if (!h || !p_out) return fail(h, NUOSC_E_INVALID, "NULL argument");
-    HIP_TRY(h, nuosc::launch_probabilities(h->rc, h->prob, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(p_out, h->prob, (size_t)h->rc.nb * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    return NUOSC_OK;
+    return checked(h, probabilities_of(h->run, p_out, h->stream, h->err), h->err);
 }
 
 nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    nuosc_status st = read_control(h);
+    nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
-    const RunConst& rc = h->rc;
-    const int cur = h->hctl.cur;
+    const RunConst& rc = h->run.rc;
+    const int cur = h->run.hctl.cur;
     const size_t rows = 2 * (size_t)rc.n;
     if (psi) {
         if (rc.precision == NUOSC_FP64) {
-            HIP_TRY(h, hipMemcpy2DAsync(psi, rc.nb * 8, rc.psi[cur], rc.nb_pad * 8, rc.nb * 8, rows,
-                                        hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            HIP_CHECK(hipMemcpy2DAsync(psi, rc.nb * 8, rc.psi[cur], rc.nb_pad * 8, rc.nb * 8, rows,
+                                       hipMemcpyDeviceToHost, h->stream), h->err);
+            HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
         } else {
             std::vector<float> tmp(rows * rc.nb);
-            HIP_TRY(h, hipMemcpy2DAsync(tmp.data(), rc.nb * 4, rc.psi[cur], rc.nb_pad * 4, rc.nb * 4, rows,
-                                        hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            HIP_CHECK(hipMemcpy2DAsync(tmp.data(), rc.nb * 4, rc.psi[cur], rc.nb_pad * 4, rc.nb * 4, rows,
+                                       hipMemcpyDeviceToHost, h->stream), h->err);
+            HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
             for (size_t i = 0; i < tmp.size(); ++i) psi[i] = tmp[i];
         }
         conjugate_antineutrinos(rc, psi);
     }
     if (phase)
-        HIP_TRY(h, hipMemcpyAsync(phase, rc.phase[cur], (size_t)rc.na * rc.n * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_CHECK(hipMemcpyAsync(phase, rc.phase[cur], (size_t)rc.na * rc.n * 8, hipMemcpyDeviceToHost, h->stream),
+                  h->err);
+    HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     return NUOSC_OK;
 }
 
 nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* phase, double r_km, double dr_km)
 {
     if (!h || !psi) return fail(h, NUOSC_E_INVALID, "NULL argument");
-    if (!(r_km >= h->p.r_nu_km) || !(r_km <= h->p.r_end_km)) return fail(h, NUOSC_E_INVALID, "radius out of range");
-    nuosc_status st = read_control(h);
+    const nuosc_params& P = h->run.p;
+    if (!(r_km >= P.r_nu_km) || !(r_km <= P.r_end_km)) return fail(h, NUOSC_E_INVALID, "radius out of range");
+    nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
-    const RunConst& rc = h->rc;
-    const int cur = h->hctl.cur;
+    const RunConst& rc = h->run.rc;
+    const int cur = h->run.hctl.cur;
     const size_t rows = 2 * (size_t)rc.n;
     std::vector<double> dev(psi, psi + rows * rc.nb);
     conjugate_antineutrinos(rc, dev.data());
     if (rc.precision == NUOSC_FP64) {
-        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 8, dev.data(), rc.nb * 8, rc.nb * 8, rows,
-                                    hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_CHECK(hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 8, dev.data(), rc.nb * 8, rc.nb * 8, rows,
+                                   hipMemcpyHostToDevice, h->stream), h->err);
+        HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     } else {
         std::vector<float> tmp(rows * rc.nb);
         for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)dev[i];
-        HIP_TRY(h, hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 4, tmp.data(), rc.nb * 4, rc.nb * 4, rows,
-                                    hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_CHECK(hipMemcpy2DAsync(rc.psi[cur], rc.nb_pad * 4, tmp.data(), rc.nb * 4, rc.nb * 4, rows,
+                                   hipMemcpyHostToDevice, h->stream), h->err);
+        HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     }
     std::vector<double> ph((size_t)rc.na * rc.n, 0.0);
     if (phase) std::memcpy(ph.data(), phase, ph.size() * 8);
-    HIP_TRY(h, hipMemcpyAsync(rc.phase[cur], ph.data(), ph.size() * 8, hipMemcpyHostToDevice, h->stream));
-    Control& c = h->hctl;
+    HIP_CHECK(hipMemcpyAsync(rc.phase[cur], ph.data(), ph.size() * 8, hipMemcpyHostToDevice, h->stream), h->err);
+    Control& c = h->run.hctl;
     c.nacc = c.nrej = c.attempts = 0;
     c.status = 0;
     c.last_rejected = 0;
-    c.r_end = h->p.r_end_km;
-    if (h->p.integrator == NUOSC_RK4_FIXED) {
+    c.r_end = P.r_end_km;
+    if (P.integrator == NUOSC_RK4_FIXED) {
         c.istep = (int64_t)std::llround((r_km - rc.r_start) / rc.h_fixed);
         c.r = rc.r_start + (double)c.istep * rc.h_fixed;
         c.h = c.h_prop = rc.h_fixed;
         if (c.istep >= rc.n_fixed) c.status = 1;
     } else {
         c.r = r_km;
-        const double d = dr_km > 0 ? dr_km : h->p.dr_init_km;
-        c.h_prop = std::min(d, h->p.dr_max_km);
-        c.h = std::min(c.h_prop, h->p.r_end_km - r_km);
-        if (c.r >= h->p.r_end_km) c.status = 1;
+        const double d = dr_km > 0 ? dr_km : P.dr_init_km;
+        c.h_prop = std::min(d, P.dr_max_km);
+        c.h = std::min(c.h_prop, P.r_end_km - r_km);
+        if (c.r >= P.r_end_km) c.status = 1;
     }
-    st = write_control(h);
+    st = hwrite(h);
     if (st != NUOSC_OK) return st;
-    st = restart(h);
+    st = checked(h, restart(h->run, h->stream, h->err), h->err);
     if (st != NUOSC_OK) return st;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     return NUOSC_OK;
 }
 
 nuosc_status nuosc_stats(nuosc_handle* h, int64_t* accepted, int64_t* rejected, double* r_km, double* dr_km)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
-    nuosc_status st = read_control(h);
+    nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
-    if (accepted) *accepted = h->hctl.nacc;
-    if (rejected) *rejected = h->hctl.nrej;
-    if (r_km) *r_km = h->hctl.r;
-    if (dr_km) *dr_km = h->hctl.h_prop;
-    return status_of(h);
+    const Control& c = h->run.hctl;
+    if (accepted) *accepted = c.nacc;
+    if (rejected) *rejected = c.nrej;
+    if (r_km) *r_km = c.r;
+    if (dr_km) *dr_km = c.h_prop;
+    return hstatus(h);
 }
 
-int64_t nuosc_num_beams(const nuosc_handle* h) { return h ? h->rc.nb : 0; }
-int32_t nuosc_num_traj(const nuosc_handle* h) { return h ? h->rc.na : 0; }
+int64_t nuosc_num_beams(const nuosc_handle* h) { return h ? h->run.rc.nb : 0; }
+int32_t nuosc_num_traj(const nuosc_handle* h) { return h ? h->run.rc.na : 0; }
 
 const char* nuosc_last_error(const nuosc_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -751,6 +828,294 @@ void nuosc_destroy(nuosc_handle* h)
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+struct nuosc_batch {
+    int32_t max_slots = 0, n = 0, precision = 0, integrator = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    bool own_arena = false;
+    size_t runs_bytes = 0;                 // device RunConst array at the arena's front
+    RunConst* runs_dev = nullptr;
+    std::map<size_t, size_t> free_blocks;  // arena offset -> bytes, disjoint, coalesced
+    std::vector<RunState> runs;
+    std::vector<char> used;
+    std::vector<size_t> off, bytes;        // arena block of each slot
+    // the captured launch sequence of a batch step for one set of active runs
+    hipGraphExec_t graph = nullptr;
+    std::vector<int> graph_slots;
+    int64_t graph_attempts = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+nuosc_status bfail(nuosc_batch* b, nuosc_status st, const std::string& msg)
+{
+    if (b) b->err = msg;
+    else g_batch_create_error = msg;
+    return st;
+}
+
+// First fit over the free blocks (offsets and sizes multiples of 256).
+bool arena_alloc(nuosc_batch* b, size_t need, size_t& at)
+{
+    need = align_up(need, 256);
+    for (auto it = b->free_blocks.begin(); it != b->free_blocks.end(); ++it) {
+        if (it->second < need) continue;
+        at = it->first;
+        const size_t rest = it->second - need;
+        b->free_blocks.erase(it);
+        if (rest) b->free_blocks[at + need] = rest;
+        return true;
+    }
+    return false;
+}
+
+void arena_free(nuosc_batch* b, size_t at, size_t bytes)
+{
+    bytes = align_up(bytes, 256);
+    auto it = b->free_blocks.emplace(at, bytes).first;
+    auto next = std::next(it);
+    if (next != b->free_blocks.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        b->free_blocks.erase(next);
+    }
+    if (it != b->free_blocks.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            b->free_blocks.erase(it);
+        }
+    }
+}
+
+void drop_graph(nuosc_batch* b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_slots.clear();
+    b->graph_attempts = 0;
+}
+
+// n attempts of every listed run, launched directly on the stream.
+hipError_t launch_attempts(nuosc_batch* b, const nuosc::RunList& list, int64_t n)
+{
+    const int S = nuosc::num_stages(b->integrator);
+    for (int64_t i = 0; i < n; ++i)
+        for (int st = 1; st <= S; ++st) {
+            hipError_t e = nuosc::launch_stage(list, st, b->stream);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+// Replays (capturing first if the active set or the count changed) the graph
+// of n attempts of the listed runs.
+nuosc_status graph_attempts(nuosc_batch* b, const std::vector<int>& slots, const nuosc::RunList& list, int64_t n)
+{
+    if (!b->graph || b->graph_slots != slots || b->graph_attempts != n) {
+        drop_graph(b);
+        HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), b->err);
+        hipError_t e = launch_attempts(b, list, n);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            b->err = hip_msg(e != hipSuccess ? e : e2, "capture of the batch step");
+            return NUOSC_E_DEVICE;
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->err = hip_msg(e, "hipGraphInstantiate");
+            return NUOSC_E_DEVICE;
+        }
+        b->graph = x;
+        b->graph_slots = slots;
+        b->graph_attempts = n;
+    }
+    HIP_CHECK(hipGraphLaunch(b->graph, b->stream), b->err);
+    return NUOSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t precision, int32_t integrator,
+                                size_t hbm_budget_bytes, void* hip_stream, void* device_arena, nuosc_batch** out)
+{
+    if (!out) return bfail(nullptr, NUOSC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 1024) return bfail(nullptr, NUOSC_E_INVALID, "max_slots must be in 1..1024");
+    if (n_flavors != 2 && n_flavors != 3) return bfail(nullptr, NUOSC_E_INVALID, "n_flavors must be 2 or 3");
+    if (precision != NUOSC_FP64 && precision != NUOSC_FP32_AMP && precision != NUOSC_FP32_AMP_FP64_MATH)
+        return bfail(nullptr, NUOSC_E_INVALID, "unknown precision");
+    if (integrator != NUOSC_RK4_FIXED && integrator != NUOSC_RK_DP54)
+        return bfail(nullptr, NUOSC_E_INVALID, "unknown integrator");
+    const size_t runs_bytes = align_up((size_t)max_slots * sizeof(RunConst), 256);
+    if (hbm_budget_bytes < runs_bytes + 256) return bfail(nullptr, NUOSC_E_INVALID, "hbm budget too small");
+    nuosc_batch* b = new (std::nothrow) nuosc_batch();
+    if (!b) return bfail(nullptr, NUOSC_E_NOMEM, "host allocation failed");
+    auto bail = [&](nuosc_status st, const std::string& msg) {
+        g_batch_create_error = msg;
+        nuosc_batch_destroy(b);
+        return st;
+    };
+    b->max_slots = max_slots;
+    b->n = n_flavors;
+    b->precision = precision;
+    b->integrator = integrator;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(NUOSC_E_DEVICE, hip_msg(e, "hipStreamCreate"));
+        b->own_stream = true;
+    }
+    if (device_arena) {
+        b->arena = (char*)device_arena;
+    } else {
+        hipError_t e = hipMalloc((void**)&b->arena, hbm_budget_bytes);
+        if (e != hipSuccess) return bail(NUOSC_E_NOMEM, hip_msg(e, "hipMalloc of the arena"));
+        b->own_arena = true;
+    }
+    b->arena_bytes = hbm_budget_bytes;
+    b->runs_bytes = runs_bytes;
+    b->runs_dev = (RunConst*)b->arena;
+    const size_t usable = (hbm_budget_bytes - runs_bytes) / 256 * 256;
+    if (usable) b->free_blocks[runs_bytes] = usable;
+    b->runs.resize(max_slots);
+    b->used.assign(max_slots, 0);
+    b->off.assign(max_slots, 0);
+    b->bytes.assign(max_slots, 0);
+    *out = b;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_batch_admit(nuosc_batch* b, const nuosc_params* p, int32_t* slot)
+{
+    if (!b || !slot) return bfail(b, NUOSC_E_INVALID, "NULL argument");
+    if (const char* why = validate(p)) return bfail(b, NUOSC_E_INVALID, why);
+    if (p->n_flavors != b->n || p->precision != b->precision || p->integrator != b->integrator)
+        return bfail(b, NUOSC_E_INVALID, "n_flavors, precision and integrator must match the batch");
+    int free_slot = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!b->used[i]) {
+            free_slot = i;
+            break;
+        }
+    if (free_slot < 0) return bfail(b, NUOSC_E_BUSY, "no free slot");
+    const size_t need = make_layout(*p).total;
+    size_t at = 0;
+    if (!arena_alloc(b, need, at)) return bfail(b, NUOSC_E_BUSY, "no arena gap for the run's footprint");
+    RunState& r = b->runs[free_slot];
+    r = RunState{};
+    nuosc_status st = init_run(r, p, b->arena + at, b->runs_dev, free_slot, b->stream, b->err);
+    if (st != NUOSC_OK) {
+        arena_free(b, at, need);
+        return st;
+    }
+    b->used[free_slot] = 1;
+    b->off[free_slot] = at;
+    b->bytes[free_slot] = need;
+    drop_graph(b);
+    *slot = free_slot;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_batch_step(nuosc_batch* b, int64_t n_attempts, int32_t* n_finished)
+{
+    if (!b) return bfail(nullptr, NUOSC_E_INVALID, "batch is NULL");
+    if (n_attempts < 0) return bfail(b, NUOSC_E_INVALID, "n_attempts must be >= 0");
+    std::vector<int> slots;
+    std::vector<const RunConst*> rcs;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->used[i] && b->runs[i].hctl.status == 0) {
+            slots.push_back(i);
+            rcs.push_back(&b->runs[i].rc);
+        }
+    if (!slots.empty() && n_attempts > 0) {
+        const nuosc::RunList list{b->runs_dev, (int)slots.size(), slots.data(), rcs.data()};
+        nuosc_status st = graph_attempts(b, slots, list, n_attempts);
+        if (st != NUOSC_OK) return st;
+        for (int i : slots)
+            HIP_CHECK(hipMemcpyAsync(&b->runs[i].hctl, b->runs[i].rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost,
+                                     b->stream), b->err);
+        HIP_CHECK(hipStreamSynchronize(b->stream), b->err);
+    }
+    int32_t fin = 0;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->used[i] && b->runs[i].hctl.status != 0) ++fin;
+    if (n_finished) *n_finished = fin;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_batch_query(nuosc_batch* b, int32_t slot, int64_t* accepted, int64_t* rejected, double* r_km,
+                               int32_t* done, int32_t* run_status)
+{
+    if (!b) return bfail(nullptr, NUOSC_E_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= b->max_slots || !b->used[slot]) return bfail(b, NUOSC_E_INVALID, "slot is not occupied");
+    const Control& c = b->runs[slot].hctl;
+    if (accepted) *accepted = c.nacc;
+    if (rejected) *rejected = c.nrej;
+    if (r_km) *r_km = c.r;
+    if (done) *done = c.status != 0 ? 1 : 0;
+    std::string why;
+    const nuosc_status st = status_of(c, why);
+    if (run_status) *run_status = st;
+    return NUOSC_OK;
+}
+
+int64_t nuosc_batch_num_beams(const nuosc_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->used[slot]) return 0;
+    return b->runs[slot].rc.nb;
+}
+
+nuosc_status nuosc_batch_retire(nuosc_batch* b, int32_t slot, double* p_out)
+{
+    if (!b) return bfail(nullptr, NUOSC_E_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= b->max_slots || !b->used[slot]) return bfail(b, NUOSC_E_INVALID, "slot is not occupied");
+    if (p_out) {
+        nuosc_status st = probabilities_of(b->runs[slot], p_out, b->stream, b->err);
+        if (st != NUOSC_OK) return st;
+    }
+    HIP_CHECK(hipStreamSynchronize(b->stream), b->err);
+    arena_free(b, b->off[slot], b->bytes[slot]);
+    b->used[slot] = 0;
+    b->runs[slot] = RunState{};
+    drop_graph(b);
+    return NUOSC_OK;
+}
+
+int32_t nuosc_batch_occupied(const nuosc_batch* b)
+{
+    if (!b) return 0;
+    int32_t k = 0;
+    for (char u : b->used) k += u ? 1 : 0;
+    return k;
+}
+
+const char* nuosc_batch_last_error(const nuosc_batch* b) { return b ? b->err.c_str() : g_batch_create_error.c_str(); }
+
+void nuosc_batch_destroy(nuosc_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->own_arena && b->arena) (void)hipFree(b->arena);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
 }
 
 }  // extern "C"

@@ -30,6 +30,9 @@ EXPORTS = (
     "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
     "nuosc_get_state", "nuosc_set_state", "nuosc_stats", "nuosc_num_beams",
     "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
+    "nuosc_batch_create", "nuosc_batch_admit", "nuosc_batch_step", "nuosc_batch_query",
+    "nuosc_batch_num_beams", "nuosc_batch_retire", "nuosc_batch_occupied", "nuosc_batch_last_error",
+    "nuosc_batch_destroy",
 )
 
 
@@ -128,6 +131,26 @@ def lib() -> C.CDLL:
     L.nuosc_last_error.restype = C.c_char_p
     L.nuosc_destroy.argtypes = [C.c_void_p]
     L.nuosc_destroy.restype = None
+    L.nuosc_batch_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_size_t, C.c_void_p,
+                                     C.c_void_p, C.POINTER(C.c_void_p)]
+    L.nuosc_batch_create.restype = C.c_int
+    L.nuosc_batch_admit.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_int32)]
+    L.nuosc_batch_admit.restype = C.c_int
+    L.nuosc_batch_step.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]
+    L.nuosc_batch_step.restype = C.c_int
+    L.nuosc_batch_query.argtypes = [C.c_void_p, C.c_int32, _I64, _I64, _D, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]
+    L.nuosc_batch_query.restype = C.c_int
+    L.nuosc_batch_num_beams.argtypes = [C.c_void_p, C.c_int32]
+    L.nuosc_batch_num_beams.restype = C.c_int64
+    L.nuosc_batch_retire.argtypes = [C.c_void_p, C.c_int32, _D]
+    L.nuosc_batch_retire.restype = C.c_int
+    L.nuosc_batch_occupied.argtypes = [C.c_void_p]
+    L.nuosc_batch_occupied.restype = C.c_int32
+    L.nuosc_batch_last_error.argtypes = [C.c_void_p]
+    L.nuosc_batch_last_error.restype = C.c_char_p
+    L.nuosc_batch_destroy.argtypes = [C.c_void_p]
+    L.nuosc_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -298,3 +321,98 @@ class Run:
         r, dr = C.c_double(), C.c_double()
         st = lib().nuosc_stats(self.h, C.byref(a), C.byref(rj), C.byref(r), C.byref(dr))
         return dict(accepted=a.value, rejected=rj.value, r_km=r.value, dr_km=dr.value, status=st)
+
+
+class Batch:
+    """A batch of independent runs stepped together (``nuosc_batch``).
+
+    All runs share n_flavors, precision and integrator.  ``admit`` returns the
+    slot, or None when the batch is full or its arena has no room (the
+    request stays with the caller).  stream / arena: optional HIP stream
+    handle and caller-owned device memory (e.g. a torch uint8 tensor of
+    ``hbm_budget`` bytes, kept alive by this object)."""
+
+    def __init__(self, max_slots: int, n_flavors: int, precision: int, integrator: int, hbm_budget: int,
+                 stream: Optional[int] = None, arena=None):
+        self._arena = arena
+        h = C.c_void_p()
+        st = lib().nuosc_batch_create(int(max_slots), int(n_flavors), int(precision), int(integrator),
+                                      int(hbm_budget), stream, arena.data_ptr() if arena is not None else None,
+                                      C.byref(h))
+        if st != OK:
+            raise NuoscError(st, lib().nuosc_batch_last_error(None).decode())
+        self.h = h
+        self.max_slots = int(max_slots)
+
+    @classmethod
+    def with_torch(cls, max_slots: int, n_flavors: int, precision: int, integrator: int, hbm_budget: int,
+                   stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+            if stream.cuda_stream == 0:
+                stream = torch.cuda.Stream()
+        arena = torch.empty(int(hbm_budget), dtype=torch.uint8, device="cuda")
+        b = cls(max_slots, n_flavors, precision, integrator, hbm_budget, stream=stream.cuda_stream, arena=arena)
+        b.torch_stream = stream
+        return b
+
+    def _check(self, st: int) -> int:
+        if st != OK:
+            raise NuoscError(st, lib().nuosc_batch_last_error(self.h).decode())
+        return st
+
+    def admit(self, w: Dict) -> Optional[int]:
+        slot = C.c_int32(-1)
+        st = lib().nuosc_batch_admit(self.h, C.byref(params_from(w)), C.byref(slot))
+        if st == E_BUSY:
+            return None
+        self._check(st)
+        return int(slot.value)
+
+    def step(self, n_attempts: int) -> int:
+        fin = C.c_int32(0)
+        self._check(lib().nuosc_batch_step(self.h, int(n_attempts), C.byref(fin)))
+        return int(fin.value)
+
+    def query(self, slot: int) -> Dict:
+        a, rj = C.c_int64(), C.c_int64()
+        r = C.c_double()
+        done, st = C.c_int32(), C.c_int32()
+        self._check(lib().nuosc_batch_query(self.h, int(slot), C.byref(a), C.byref(rj), C.byref(r), C.byref(done),
+                                            C.byref(st)))
+        return dict(accepted=a.value, rejected=rj.value, r_km=r.value, done=bool(done.value), status=st.value)
+
+    def num_beams(self, slot: int) -> int:
+        return int(lib().nuosc_batch_num_beams(self.h, int(slot)))
+
+    def retire(self, slot: int, probabilities: bool = True) -> Optional[np.ndarray]:
+        p = None
+        if probabilities:
+            p = np.empty(self.num_beams(slot))
+            self._check(lib().nuosc_batch_retire(self.h, int(slot), _ptr(p)))
+        else:
+            self._check(lib().nuosc_batch_retire(self.h, int(slot), None))
+        return p
+
+    @property
+    def occupied(self) -> int:
+        return int(lib().nuosc_batch_occupied(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nuosc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -67,3 +67,24 @@ def test_invalid_parameters_are_rejected_without_a_device(bad):
     with pytest.raises(nuosc.NuoscError) as e:
         nuosc.Run(w)
     assert e.value.status == nuosc.E_INVALID
+
+
+@pytest.mark.parametrize("args", [
+    (0, 3, W.FP32_AMP, W.RK_DP54, 1 << 20),      # no slots
+    (2000, 3, W.FP32_AMP, W.RK_DP54, 1 << 30),   # too many slots
+    (4, 4, W.FP32_AMP, W.RK_DP54, 1 << 20),      # flavors
+    (4, 3, 9, W.RK_DP54, 1 << 20),               # precision
+    (4, 3, W.FP64, 5, 1 << 20),                  # integrator
+    (64, 3, W.FP64, W.RK_DP54, 1024),            # budget below the run-constant table
+])
+def test_invalid_batches_are_rejected_without_a_device(args):
+    with pytest.raises(nuosc.NuoscError) as e:
+        nuosc.Batch(*args)
+    assert e.value.status == nuosc.E_INVALID
+
+
+def test_footprint_of_a_serving_mix_is_what_admission_checks():
+    ws = W.serving_requests(duration_s=2.0)
+    assert len(ws) > 10
+    sizes = [nuosc.footprint_bytes(w) for w in ws]
+    assert all(s > 2 * 6 * W.n_beams(w) * 4 for s, w in zip(sizes, ws))

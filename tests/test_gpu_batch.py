@@ -1,0 +1,151 @@
+"""GPU tests of batched runs (continuous batching through the nuosc_batch ABI).
+
+A run's workgroups never span two runs and every reduction stays inside its
+run, so a run must give bitwise the same result alone (nuosc_create) and in
+any mix of other runs, whenever it was admitted.  The single-run path is
+itself checked against the oracle in test_gpu_parity.py; one batched run is
+also compared with the oracle directly here.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_05560_amd import nuosc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mix(precision, count=4, seed_shift=0):
+    """Seeded three-flavor runs with the physics draws of the batched workload
+    (luminosities, hierarchy, theta13) on small uneven grids; the last one is
+    single-angle."""
+    runs = W.batched_runs(count + seed_shift)[seed_shift:]
+    out = []
+    for k, w in enumerate(runs):
+        w = dict(w)
+        w.update(n_energy=9 + 7 * k, n_angle=(5 + 4 * k) if k < count - 1 else 0, precision=precision,
+                 r_start_km=12.0, dr_init_km=1e-4)
+        out.append(w)
+    return out
+
+
+def _alone(w, attempts):
+    with nuosc.Run(w) as r:
+        r.step(attempts)
+        return r.probabilities(), r.stats()
+
+
+def _budget(ws, extra=1 << 20):
+    return sum(nuosc.footprint_bytes(w) + 4096 for w in ws) + 1024 * 512 + extra
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_AMP, W.FP32_AMP_FP64_MATH])
+def test_runs_in_a_batch_match_the_same_runs_alone(precision):
+    ws = _mix(precision)
+    K = 12
+    say(f"case: batch of {len(ws)} prec={precision} attempts={K}")
+    alone = [_alone(w, K) for w in ws]
+    with nuosc.Batch(8, 3, precision, W.RK_DP54, _budget(ws)) as b:
+        slots = [b.admit(w) for w in ws]
+        assert None not in slots
+        b.step(K)
+        for w, s, (pa, sa) in zip(ws, slots, alone):
+            q = b.query(s)
+            assert q["accepted"] == sa["accepted"] and q["rejected"] == sa["rejected"]
+            assert q["r_km"] == sa["r_km"]
+            p = b.retire(s)
+            assert np.array_equal(p, pa), f"slot {s}: max diff {np.abs(p - pa).max()}"
+        assert b.occupied == 0
+
+
+def test_runs_admitted_while_others_step_match_their_solo_runs():
+    ws = _mix(W.FP32_AMP, count=5)
+    say("case: staggered admission, 5 runs")
+    with nuosc.Batch(3, 3, W.FP32_AMP, W.RK_DP54, _budget(ws[:3])) as b:
+        a = b.admit(ws[0])
+        c = b.admit(ws[1])
+        b.step(5)
+        d = b.admit(ws[2])
+        b.step(5)
+        assert b.admit(ws[3]) is None  # all three slots taken
+        pa = b.retire(a)
+        e = b.admit(ws[3])             # the freed slot and memory are reused
+        assert e is not None
+        b.step(4)
+        got = {0: pa, 1: b.retire(c), 2: b.retire(d), 3: b.retire(e)}
+    want = {0: _alone(ws[0], 10)[0], 1: _alone(ws[1], 14)[0], 2: _alone(ws[2], 9)[0], 3: _alone(ws[3], 4)[0]}
+    for k in got:
+        assert np.array_equal(got[k], want[k]), f"run {k}: max diff {np.abs(got[k] - want[k]).max()}"
+
+
+def test_admission_is_bounded_by_the_arena():
+    small, large = _mix(W.FP64, count=2)[0], dict(_mix(W.FP64, count=2)[0])
+    large.update(n_energy=60, n_angle=90)
+    fs, fl = nuosc.footprint_bytes(small), nuosc.footprint_bytes(large)
+    assert fl > 2 * fs + 16384
+    say(f"case: arena bound small={fs} large={fl}")
+    # the arena's front holds the run-constant table of the 4 slots (< 4 KiB)
+    budget = 4096 + fs + fl // 2
+    with nuosc.Batch(4, 3, W.FP64, W.RK_DP54, budget) as b:
+        s0 = b.admit(small)
+        assert s0 is not None
+        assert b.admit(large) is None          # does not fit next to the small run
+        b.retire(s0, probabilities=False)
+        assert b.admit(large) is None          # does not fit at all
+        assert b.admit(small) is not None
+
+
+def test_batch_rejects_runs_of_another_kind():
+    w = _mix(W.FP64, count=1)[0]
+    with nuosc.Batch(2, 3, W.FP64, W.RK_DP54, _budget([w])) as b:
+        other = dict(w, precision=W.FP32_AMP)
+        with pytest.raises(nuosc.NuoscError):
+            b.admit(other)
+        two = dict(w, n_flavors=2)
+        with pytest.raises(nuosc.NuoscError):
+            b.admit(two)
+
+
+def test_finished_runs_stop_and_are_counted():
+    ws = _mix(W.FP64, count=3)
+    ws[0] = dict(ws[0], r_end_km=ws[0]["r_start_km"] + 2e-4)
+    say("case: one run reaches its end radius")
+    with nuosc.Batch(4, 3, W.FP64, W.RK_DP54, _budget(ws)) as b:
+        slots = [b.admit(w) for w in ws]
+        fin = 0
+        for _ in range(40):
+            fin = b.step(10)
+            if fin:
+                break
+        assert fin == 1
+        q = b.query(slots[0])
+        assert q["done"] and q["status"] == nuosc.OK and q["r_km"] == ws[0]["r_end_km"]
+        before = b.query(slots[1])["accepted"]
+        assert b.step(3) == 1
+        assert b.query(slots[0])["accepted"] == q["accepted"]   # stopped runs do not move
+        assert b.query(slots[1])["accepted"] > before
+
+
+def test_a_batched_run_matches_the_oracle():
+    ws = _mix(W.FP64, count=3)
+    K = 10
+    with nuosc.Batch(4, 3, W.FP64, W.RK_DP54, _budget(ws)) as b:
+        slots = [b.admit(w) for w in ws]
+        b.step(K)
+        q = b.query(slots[1])
+        p = b.retire(slots[1])
+    # the oracle takes the same adaptive steps (to rounding) and clips its
+    # last one to land on the batched run's radius
+    ref = O.Run(ws[1])
+    ref.evolve_dp54(q["r_km"])
+    assert ref.stats()["r_km"] == q["r_km"]
+    assert abs(ref.stats()["accepted"] - q["accepted"]) <= 1
+    np.testing.assert_allclose(p, ref.probabilities(), rtol=1e-10, atol=1e-13)
