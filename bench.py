@@ -192,6 +192,34 @@ def cpu_baseline(W, attempts):
     }
 
 
+def batched(nuosc, W, torch, attempts):
+    """The 64-run batched workload: every run admitted into one batch and
+    advanced together; aggregate beam-steps/s over `attempts` attempts."""
+    from paper_1907_05560_amd import serving
+
+    return serving.run_batched(W.batched_runs(64), attempts, torch=torch)
+
+
+def served(nuosc, W, seconds, precision):
+    """The serving workload for `seconds` of Poisson arrivals: latency
+    percentiles, throughput, and a bitwise check of two completed requests
+    against the same runs alone."""
+    import numpy as np
+
+    from paper_1907_05560_amd import serving
+
+    reqs = W.serving_requests(duration_s=seconds, precision=precision)
+    out = serving.serve(reqs, max_slots=64, keep=2, wall_limit_s=max(120.0, 4 * seconds))
+    same = True
+    for i, p in out.pop("kept"):
+        w = dict(reqs[i])
+        with nuosc.Run(w) as run:
+            run.evolve(w["r_end_km"])
+            same = same and bool(np.array_equal(run.probabilities(), p))
+    out["mix_equals_alone"] = same
+    return out
+
+
 def subsample_error(nuosc, W, run32, run64):
     """FP32-form error against the FP64 form on the seeded 4096-beam subsample,
     at a common radius (the run that is behind evolves to the other's radius)."""
@@ -220,6 +248,10 @@ def main() -> int:
                     help="precision forms to run (the first is the headline value)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a device buffer of this size (for scaling HBM counters)")
+    ap.add_argument("--batched-attempts", type=int, default=50,
+                    help="attempts of the 64-run batched workload (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=20.0,
+                    help="seconds of Poisson arrivals in the serving runs (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this path runs on one GPU "
@@ -284,6 +316,18 @@ def main() -> int:
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
         "finalize_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
     }
+    if args.batched_attempts > 0:
+        print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)
+        line["batched"] = batched(nuosc, W, torch, args.batched_attempts)
+        print(f"bench: batched {line['batched']['value']:.3e} beam-steps/s", file=sys.stderr, flush=True)
+    if args.serving_seconds > 0:
+        line["serving"] = {}
+        for name, prec in (("fp32", W.FP32_AMP), ("fp64", W.FP64)):
+            print(f"bench: serving {name} ({args.serving_seconds:g} s of arrivals)", file=sys.stderr, flush=True)
+            sv = served(nuosc, W, args.serving_seconds, prec)
+            line["serving"][name] = sv
+            print(f"bench: serving {name}: {sv['completed']}/{sv['requests']} done, p50 {sv['p50_s']:.3f} s, "
+                  f"p99 {sv['p99_s']:.3f} s, {sv['value']:.3e} beam-steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print(f"bench: cpu baseline ({args.cpu_attempts} oracle attempts)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(W, args.cpu_attempts)

@@ -234,8 +234,8 @@ nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t pr
 nuosc_status nuosc_batch_admit(nuosc_batch* b, const nuosc_params* p, int32_t* slot);
 
 /* Make n_attempts step attempts of every admitted run that is still running
- * (the launch sequence of one batch step is captured once per set of active
- * runs as a HIP graph and replayed).  *n_finished (nullable) receives the
+ * (when the same set of runs is stepped with the same count twice in a row,
+ * the launch sequence is captured as a HIP graph and replayed from then on).  *n_finished (nullable) receives the
  * number of admitted runs that have stopped (reached r_end, or stopped on an
  * error or limit).  Synchronises the stream. */
 nuosc_status nuosc_batch_step(nuosc_batch* b, int64_t n_attempts, int32_t* n_finished);

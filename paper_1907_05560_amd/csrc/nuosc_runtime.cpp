@@ -846,10 +846,13 @@ struct nuosc_batch {
     std::vector<RunState> runs;
     std::vector<char> used;
     std::vector<size_t> off, bytes;        // arena block of each slot
-    // the captured launch sequence of a batch step for one set of active runs
+    // the captured launch sequence of a batch step for one set of active runs;
+    // a set is captured only when it is stepped a second time in a row
     hipGraphExec_t graph = nullptr;
     std::vector<int> graph_slots;
     int64_t graph_attempts = 0;
+    std::vector<int> last_slots;
+    int64_t last_attempts = 0;
     std::string err;
 };
 
@@ -1046,8 +1049,15 @@ nuosc_status nuosc_batch_step(nuosc_batch* b, int64_t n_attempts, int32_t* n_fin
         }
     if (!slots.empty() && n_attempts > 0) {
         const nuosc::RunList list{b->runs_dev, (int)slots.size(), slots.data(), rcs.data()};
-        nuosc_status st = graph_attempts(b, slots, list, n_attempts);
-        if (st != NUOSC_OK) return st;
+        const bool repeat = slots == b->last_slots && n_attempts == b->last_attempts;
+        b->last_slots = slots;
+        b->last_attempts = n_attempts;
+        if (repeat) {
+            nuosc_status st = graph_attempts(b, slots, list, n_attempts);
+            if (st != NUOSC_OK) return st;
+        } else {
+            HIP_CHECK(launch_attempts(b, list, n_attempts), b->err);
+        }
         for (int i : slots)
             HIP_CHECK(hipMemcpyAsync(&b->runs[i].hctl, b->runs[i].rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost,
                                      b->stream), b->err);

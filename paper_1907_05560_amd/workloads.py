@@ -22,7 +22,8 @@ not datasets):
 * ``multi_angle_3f_large``: 400 energies x 4000 angles (3.2M beams), FP32
   amplitudes with FP64 moments, step error and phases.
 * ``batched_runs``: 64 independent multi-angle runs with seeded uneven grids.
-* ``serving_requests``: a seeded Poisson arrival stream of such runs.
+* ``serving_requests``: a seeded Poisson arrival stream of such runs, each
+  evolved over a short radius window from the neutrinosphere.
 """
 
 from __future__ import annotations
@@ -148,8 +149,17 @@ def batched_runs(count: int = 64) -> List[Dict]:
 
 
 def serving_requests(rate_per_s: float = 20.0, duration_s: float = 120.0,
-                     large_fraction: float = 0.1) -> List[Dict]:
-    """Poisson arrivals; each request is a batched-runs draw, 10% large."""
+                     large_fraction: float = 0.1, window_km: float = 2e-6,
+                     precision: int = FP32_AMP) -> List[Dict]:
+    """Poisson arrivals; each request is a batched-runs draw, 10% large.
+
+    Each request evolves from the neutrinosphere over a radius window of
+    `window_km` (its r_end): near R the adaptive step of a multi-angle run is
+    about 5e-7 km x (20 / N_A) at rtol 1e-9 (nearly tangential trajectories
+    have 1 / cos(theta) up to 2 N_A), so a window of 2e-6 km takes tens of
+    steps for the smallest grids and several hundred for the 400 x 4000 ones.
+    The draws of every request (and so the sequence) do not depend on the
+    window or the precision."""
     rng = np.random.default_rng(SEED_BASE + 4)
     out = []
     t = 0.0
@@ -160,6 +170,8 @@ def serving_requests(rate_per_s: float = 20.0, duration_s: float = 120.0,
         large = bool(rng.random() < large_fraction)
         w = _draw_run(rng, large=large)
         w["arrival_s"] = t
+        w["r_end_km"] = w["r_start_km"] + window_km
+        w["precision"] = precision
         out.append(w)
     return out
 
