@@ -70,7 +70,8 @@ struct RunConst {
     const float* uinv32;         // [2 ne] the same in FP32
     const double* wgt;           // [2 ne] g (neutrino slots), -gbar (antineutrino slots)
     double* jhist;               // [kMaxStages + 1][2 n n] packed J0, J1 per stage
-    double* partial;             // [2 n n][nblk] per-workgroup weighted sums (value-major)
+    double* partial;             // [2][2 n n][nblk] per-workgroup weighted sums of the last two
+                                 // beam launches (launch I uses [I & 1]), value-major
     double* errpart;             // [nblk]
     void* mat;                   // [kMaxStages][na] StageMat<T, n>
     TrajGeo* geo;                // [kMaxStages + 1][na]
@@ -107,9 +108,10 @@ struct RunList {
 };
 
 // One stage of the current attempt of every listed run: the beam kernel
-// (stage 0 = moments of the current state; stage == S = final launch)
-// followed by its finalise kernel.  ev, if not null, receives three events:
-// before the beam kernel, between the two kernels, after the finalise kernel.
+// (stage 0 = moments of the current state; stage == S = final launch),
+// followed after stage 0 and stage S by the control kernel.  ev, if not null,
+// receives three events: before the beam kernel, after it, and after the
+// control kernel (if any).
 hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
 // Geometry and frame factors of stage 0 for the current state (before a
 // stage-0 launch).

@@ -234,7 +234,7 @@ Layout make_layout(const nuosc_params& p)
     L.uinv32 = take((size_t)2 * p.n_energy * 4);
     L.wgt = take((size_t)2 * p.n_energy * 8);
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * 2 * n * n * 8);
-    L.partial = take((size_t)2 * n * n * L.nblk * 8);
+    L.partial = take((size_t)2 * 2 * n * n * L.nblk * 8);  // two launches' partials (alternating)
     L.errpart = take((size_t)L.nblk * 8);
     L.mat = take((size_t)nuosc::kMaxStages * L.na * nuosc::kStageMatBytes);
     L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
