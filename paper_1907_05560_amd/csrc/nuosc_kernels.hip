@@ -497,7 +497,7 @@ template <typename T> struct BeamShape {
 // workgroup.  TS: amplitude type in HBM; T: arithmetic type of the stage
 // update (density sums are FP64 in every form).
 template <typename TS, typename T, int N, typename TAB, int I>
-__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet ls)
+__device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 {
     constexpr int kTrajPerBlock = BeamShape<T>::traj;
     constexpr int NSLOT = BeamShape<T>::slots;
@@ -513,8 +513,6 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet l
     constexpr uint32_t STRIDE = 64;                      // beam-slot stride of one lane
     using Mat = StageMat<T, N>;
 
-    int blk;
-    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int jt = wave;
@@ -874,13 +872,30 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet l
     }
 }
 
+// Beam launch over a launch set (any number of runs) and over one run whose
+// constants travel as the kernel argument (no table lookup before the first
+// loads).
+template <typename TS, typename T, int N, typename TAB, int I>
+__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet ls)
+{
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    stage_body<TS, T, N, TAB, I>(rc, blk);
+}
+
+template <typename TS, typename T, int N, typename TAB, int I>
+__global__ void __launch_bounds__(BeamShape<T>::block) k_stage_one(const RunConst rc)
+{
+    stage_body<TS, T, N, TAB, I>(rc, blockIdx.x);
+}
+
 // After the last beam launch of an attempt, one workgroup per run: the global
 // step-error maximum (order-independent), the controller, and J_0 of the next
 // attempt (J of the accepted state, else unchanged).  For a tableau without
 // first-same-as-last, J of the new state is summed from the last launch's
 // partials here.  Also used after a stage-0 launch (I == 0) to sum J_0.
 template <int N, typename TAB, int I>
-__global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
+__device__ __forceinline__ void control_body(const RunConst& rc)
 {
     constexpr int S = TAB::S;
     constexpr int NV = 2 * Shape<N>::NM;
@@ -888,8 +903,6 @@ __global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
     __shared__ double sred[NV][kFinBlock / NV];
     __shared__ double sJ[NV];
     __shared__ double serr[kFinBlock / 64];
-    int blk;
-    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     if constexpr (I == 0) {
         reduce_partials<NV, kFinBlock>(rc, 0, sJ, sred);
         if ((int)threadIdx.x < NV) rc.jhist[threadIdx.x] = sJ[threadIdx.x];
@@ -913,6 +926,20 @@ __global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
             rc.ctrl[1] = c;
         }
     }
+}
+
+template <int N, typename TAB, int I>
+__global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
+{
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    control_body<N, TAB, I>(rc);
+}
+
+template <int N, typename TAB, int I>
+__global__ void __launch_bounds__(kFinBlock) k_control_one(const RunConst rc)
+{
+    control_body<N, TAB, I>(rc);
 }
 
 // Stage-0 frame of the current state (before a stage-0 launch).
@@ -968,33 +995,50 @@ struct StageTable {
     static constexpr std::array<KernFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
-// The control kernel that follows beam launch `stage` (after stage 0 and
-// after the last stage), or nullptr.
-template <int N, typename TAB>
-KernFn control_for(int stage)
-{
-    if (stage == 0) return (KernFn)&k_control<N, TAB, 0>;
-    if (stage == TAB::S) return (KernFn)&k_control<N, TAB, TAB::S>;
-    return nullptr;
-}
+using OneFn = void (*)(const RunConst);
 
-template <typename TS, typename T, int N>
-void pick(int integrator, int stage, KernFn& k, KernFn& f)
+template <typename TS, typename T, int N, typename TAB>
+struct StageOneTable {
+    template <int... Is>
+    static constexpr std::array<OneFn, kMaxStages> make(std::integer_sequence<int, Is...>)
+    {
+        return {{(Is <= TAB::S ? (OneFn)&k_stage_one<TS, T, N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+    }
+    static constexpr std::array<OneFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
+};
+
+// The kernels of beam launch `stage`: over launch sets (k, f) and over one
+// run (k1, f1); f, f1: the control kernel that follows stage 0 and the last
+// stage, else nullptr.
+struct StageKernels {
+    KernFn k = nullptr, f = nullptr;
+    OneFn k1 = nullptr, f1 = nullptr;
+};
+
+template <typename TS, typename T, int N, typename TAB>
+void pick_tab(int stage, StageKernels& K)
 {
-    if (integrator == 0) {
-        k = StageTable<TS, T, N, TabRK4>::fns[stage];
-        f = control_for<N, TabRK4>(stage);
-    } else {
-        k = StageTable<TS, T, N, TabDP54>::fns[stage];
-        f = control_for<N, TabDP54>(stage);
+    K.k = StageTable<TS, T, N, TAB>::fns[stage];
+    K.k1 = StageOneTable<TS, T, N, TAB>::fns[stage];
+    if (stage == 0) {
+        K.f = (KernFn)&k_control<N, TAB, 0>;
+        K.f1 = (OneFn)&k_control_one<N, TAB, 0>;
+    } else if (stage == TAB::S) {
+        K.f = (KernFn)&k_control<N, TAB, TAB::S>;
+        K.f1 = (OneFn)&k_control_one<N, TAB, TAB::S>;
     }
 }
 
 template <typename TS, typename T>
-void pick_n(int n, int integrator, int stage, KernFn& k, KernFn& f)
+void pick_n(int n, int integrator, int stage, StageKernels& K)
 {
-    if (n == 2) pick<TS, T, 2>(integrator, stage, k, f);
-    else pick<TS, T, 3>(integrator, stage, k, f);
+    if (n == 2) {
+        if (integrator == 0) pick_tab<TS, T, 2, TabRK4>(stage, K);
+        else pick_tab<TS, T, 2, TabDP54>(stage, K);
+    } else {
+        if (integrator == 0) pick_tab<TS, T, 3, TabRK4>(stage, K);
+        else pick_tab<TS, T, 3, TabDP54>(stage, K);
+    }
 }
 
 // Launches fn over the listed runs, at most kMaxRuns runs per launch, with
@@ -1041,34 +1085,45 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
     if (!same_kind(runs)) return hipErrorInvalidValue;
     const RunConst& r0 = *runs.rc[0];
     if (stage < 0 || stage > num_stages(r0.integrator)) return hipErrorInvalidValue;
-    KernFn k = nullptr, f = nullptr;
+    StageKernels K;
     const unsigned block = r0.precision == 1 ? BeamShape<float>::block : BeamShape<double>::block;
     if ((r0.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(r0.precision))
         return hipErrorInvalidValue;
     switch (r0.precision) {
-    case 0: pick_n<double, double>(r0.n, r0.integrator, stage, k, f); break;  // FP64
-    case 1: pick_n<float, float>(r0.n, r0.integrator, stage, k, f); break;    // FP32 amplitudes
-    case 2: pick_n<float, double>(r0.n, r0.integrator, stage, k, f); break;   // FP32 amplitudes, FP64 math
+    case 0: pick_n<double, double>(r0.n, r0.integrator, stage, K); break;  // FP64
+    case 1: pick_n<float, float>(r0.n, r0.integrator, stage, K); break;    // FP32 amplitudes
+    case 2: pick_n<float, double>(r0.n, r0.integrator, stage, K); break;   // FP32 amplitudes, FP64 math
     default: break;
     }
-    if (!k) return hipErrorInvalidValue;
+    if (!K.k || !K.k1) return hipErrorInvalidValue;
+    const bool one = runs.count == 1;
     if (ev) {
         hipError_t e = hipEventRecord(ev[0], s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = for_launch_sets(runs, [](const RunConst& rc) { return (long long)rc.nblk; },
-                                   [&](const LaunchSet& ls, unsigned grid) {
-                                       hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, ls);
-                                       return hipGetLastError();
-                                   });
+    hipError_t e = hipSuccess;
+    if (one) {
+        hipLaunchKernelGGL(K.k1, dim3((unsigned)r0.nblk), dim3(block), 0, s, r0);
+        e = hipGetLastError();
+    } else {
+        e = for_launch_sets(runs, [](const RunConst& rc) { return (long long)rc.nblk; },
+                            [&](const LaunchSet& ls, unsigned grid) {
+                                hipLaunchKernelGGL(K.k, dim3(grid), dim3(block), 0, s, ls);
+                                return hipGetLastError();
+                            });
+    }
     if (e != hipSuccess) return e;
     if (ev) {
         e = hipEventRecord(ev[1], s);
         if (e != hipSuccess) return e;
     }
-    if (f) {
+    if (K.f && one) {
+        hipLaunchKernelGGL(K.f1, dim3(1), dim3(kFinBlock), 0, s, r0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else if (K.f) {
         e = for_launch_sets(runs, [](const RunConst&) { return 1LL; }, [&](const LaunchSet& ls, unsigned grid) {
-            hipLaunchKernelGGL(f, dim3(grid), dim3(kFinBlock), 0, s, ls);
+            hipLaunchKernelGGL(K.f, dim3(grid), dim3(kFinBlock), 0, s, ls);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
