@@ -41,8 +41,9 @@ def run_form(nuosc, W, torch, precision, steps, warmup):
 
     Two passes over the same number of attempts: the first is timed as a
     whole (HIP events around it) and gives the throughput; in the second the
-    library records events around every beam kernel and finalise kernel,
-    which gives the per-kernel durations."""
+    library records events around every beam kernel and control kernel,
+    which gives the per-kernel durations (each including the few
+    microseconds an event record adds on the stream)."""
     w = W.multi_angle_3f_large(precision)
     run = nuosc.Run.with_torch(w)
     stream = run.torch_stream
@@ -95,10 +96,16 @@ def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
     the off-diagonals.  Launch I evaluates k_0..k_{I-1}, forms the inputs of
     stages 1..I (2n reals x (nonzeros + 1) FMAs each), the moments of its output
     state (n diagonal terms of 5 flops, n(n-1)/2 off-diagonal pairs of 10), and
-    in the final launch the embedded error and the FP32 renormalisation."""
+    the FP32 renormalisation of the new state, and the embedded error.  For a
+    first-same-as-last pair the error is split: the launch that forms y_{n+1}
+    also sums e_i k_i over i < S-1, and the final launch evaluates only
+    k_{S-1} = f(y_{n+1}) and adds h e_{S-1} k_{S-1}."""
     t = _NNZ[integrator]
     S = t["S"]
     f_eval = 2 * n * n + 2 * n + 8 * n * (n - 1)
+    split = t["fsal"] and t["err"] > 0
+    if split and stage == S:
+        return f_eval + 2 * n * 3
     flops = stage * f_eval
     last_row = min(stage, S - 1)
     for l in range(1, last_row + 1):
@@ -109,8 +116,10 @@ def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
         flops += 2 * n * (t["sol"] + 1) * 2
     if not final or not t["fsal"]:
         flops += 5 * n + 10 * n * (n - 1) // 2
-    if final and t["err"]:
+    if final and t["err"] and not split:
         flops += 2 * n * (t["err"] * 2 + 1)
+    if split and stage == S - 1:
+        flops += 2 * n * (2 * (t["err"] - 1) - 1)
     if fp32_storage and stage == (S - 1 if t["fsal"] else S):
         flops += 6 * n + 2
     return flops
@@ -121,7 +130,9 @@ def roofline(form):
 
     HBM view: algorithmic bytes per launch (every beam launch reads y_n once,
     N_b x 2n amplitude reals; the launch that forms y_{n+1} -- the last one,
-    or the one before it for a first-same-as-last pair -- also writes it) /
+    or the one before it for a first-same-as-last pair -- also writes it; in
+    the pair, that launch also writes the partial error sum, N_b x 2n reals of
+    the arithmetic type, and the final launch reads y_{n+1} and that sum) /
     the launch's mean duration.  ALU view: stage_flops x N_b / duration against the vector
     peak of the arithmetic type.  The reported bound is the view with the
     larger fraction of its peak; the other view is kept alongside."""
@@ -131,6 +142,8 @@ def roofline(form):
     state_bytes = 2 * form["n"] * form["amp_bytes"] * form["beams"]
     write_stage = S - 1 if S == 7 else S
     alg_bytes = state_bytes * (2 if stage == write_stage else 1)
+    if S == 7 and stage >= S - 1:
+        alg_bytes += 2 * form["n"] * (4 if form["precision"] == 1 else 8) * form["beams"]
     dur_s = form["stage_ms"][dom] / 1e3
     gbs = alg_bytes / dur_s / 1e9
     fp32_math = form["precision"] == 1
@@ -281,7 +294,7 @@ def main() -> int:
         runs[prec] = run
         print(f"bench: precision {prec}: {form['ms_per_step']:.3f} ms/step, {form['value']:.3e} beam-steps/s, "
               f"beam kernels {[round(x * 1e3, 1) for x in form['stage_ms']]} us, "
-              f"finalise {[round(x * 1e3, 1) for x in form['fin_ms']]} us", file=sys.stderr, flush=True)
+              f"control {[round(x * 1e3, 1) for x in form['fin_ms']]} us", file=sys.stderr, flush=True)
     err = None
     if W.FP32_AMP in runs and W.FP64 in runs:
         err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
@@ -314,7 +327,7 @@ def main() -> int:
                       "roofline": roofline(forms[names[f]])} for f in args.forms.split(",")},
         "fp32_vs_fp64_error": err,
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
-        "finalize_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
+        "control_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
     }
     if args.batched_attempts > 0:
         print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)

@@ -153,15 +153,18 @@ nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage);
 int32_t nuosc_num_stages(const nuosc_handle* h);
 
 /* Kernel timing for measurement tools.  While enabled, every stage launch
- * records HIP events on the handle's stream before its beam kernel, between
- * the beam kernel and its finalise kernel, and after the finalise kernel.
+ * records HIP events on the handle's stream before its beam kernel, after
+ * it, and after the control kernel that follows the beam kernel of stage 0
+ * and of the last stage (the second interval is empty for the other stages).
  * nuosc_timing_read waits for the stream, adds the elapsed times of all
  * launches recorded since the last read into per-stage sums and writes them:
  * beam_ms and fin_ms (milliseconds, nuosc_num_stages(h) + 1 entries each,
- * index = stage, 0 being the moment launch of create / set_state / moments)
- * and count (launches per stage, same length); each pointer nullable.  The
- * sums are cleared by the read.  Enabling or disabling clears them too.
- * Timing adds three event records per launch and changes no result. */
+ * index = stage, 0 being the moment launch of create / set_state / moments;
+ * fin_ms holds the second interval) and count (launches per stage, same
+ * length); each pointer nullable.  The sums are cleared by the read.
+ * Enabling or disabling clears them too.  Timing adds three event records
+ * per launch (a few microseconds each on the stream) and changes no
+ * result. */
 nuosc_status nuosc_timing_enable(nuosc_handle* h, int32_t on);
 nuosc_status nuosc_timing_read(nuosc_handle* h, double* beam_ms, double* fin_ms, int64_t* count);
 

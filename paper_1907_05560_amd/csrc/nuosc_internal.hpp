@@ -11,7 +11,7 @@ namespace nuosc {
 // the state between attempts (the host reads and writes it; the stage-0
 // kernels and the first stage kernel of an attempt read it), ctrl[0] the copy
 // the rest of an attempt reads.  The first stage kernel of an attempt copies
-// ctrl[1] into ctrl[0]; the finalise kernel of the last stage writes the
+// ctrl[1] into ctrl[0]; the control kernel after the last stage writes the
 // updated block into ctrl[1].  No kernel reads a copy that a workgroup of the
 // same launch writes.
 struct Control {
@@ -38,8 +38,8 @@ template <int N> struct Shape {
 // Stage matrix of one trajectory in the co-rotating frame, K = A + B u with
 // u = +1/E for neutrinos and u = -1/E for antineutrinos (whose amplitudes are
 // held complex-conjugated on the device).  Packed Hermitian, A then B, in the
-// arithmetic type T of the stage kernels.  Written by the finalise kernel
-// that completes the stage, read by the stage kernels of the same attempt.
+// arithmetic type T of the stage kernels.  Written by the beam launch that
+// completes the stage, read by the later beam launches of the same attempt.
 template <typename T, int N> struct alignas(16) StageMat {
     T a[Shape<N>::NM];
     T b[Shape<N>::NM];
@@ -73,13 +73,15 @@ struct RunConst {
     double* partial;             // [2][2 n n][nblk] per-workgroup weighted sums of the last two
                                  // beam launches (launch I uses [I & 1]), value-major
     double* errpart;             // [nblk]
+    void* errv;                  // [2n][nb_pad] of the arithmetic type: sum_{i<S-1} e_i k_i of
+                                 // an embedded first-same-as-last pair (else unused)
     void* mat;                   // [kMaxStages][na] StageMat<T, n>
     TrajGeo* geo;                // [kMaxStages + 1][na]
     Control* ctrl;               // [2]
 };
 
 constexpr int kMaxStages = 8;
-constexpr int kFinBlock = 256;     // threads per finalise workgroup
+constexpr int kFinBlock = 256;     // threads per control / prepare workgroup
 
 // Trajectories per beam workgroup (one partial density sum each): 16 for the
 // FP32-arithmetic form, 8 for the FP64-arithmetic forms.

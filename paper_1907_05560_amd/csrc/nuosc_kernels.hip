@@ -12,16 +12,20 @@
 //       beam loop: reads y_n once, recomputes k_0..k_{I-1} from y_n and the
 //         stage matrices, forms the input of stage I (the new state in the
 //         launch that forms it, written back in the storage type) and adds
-//         its weighted density matrix in FP64; the final launch of an
-//         embedded pair forms the step error h sum_i e_i k_i instead;
+//         its weighted density matrix in FP64.  Embedded pair with first
+//         same as last (k_{S-1} = f(y_{n+1})): launch S-1 also writes the
+//         partial error sum sum_{i<S-1} e_i k_i per beam, and launch S reads
+//         it with y_{n+1}, evaluates k_{S-1} only and forms the step error
+//         h sum_i e_i k_i;
 //       epilogue: prepares stage I (geometry eq 3.14-3.15, co-rotating phase,
 //         rotation factors) and adds the rotated, angle-weighted density sums
 //         of its trajectories into one partial per workgroup.
 //   * k_control (one workgroup per run): global error maximum, step
 //     controller, and J_0 of the next attempt.
 // Only y_n is read from HBM per beam launch and only y_{n+1} is written (by
-// the launch that forms it): every stage derivative is recomputed from y_n and
-// the small per-trajectory tables instead of being stored.
+// the launch that forms it, with the partial error sum): every stage
+// derivative is recomputed from y_n and the small per-trajectory tables
+// instead of being stored.
 //
 // Antineutrino amplitudes are held complex-conjugated on the device.  With
 // phi = conj(psibar), the antineutrino equation in the co-rotating frame reads
@@ -509,7 +513,13 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     constexpr bool FSAL_FINAL = FINAL && TAB::fsal;      // derivatives and error only
     constexpr bool MOMENTS = !FSAL_FINAL;                // density sum of the formed state
     constexpr bool NEWSTATE = TAB::fsal ? (I == S - 1) : FINAL;
-    constexpr int NK = I;                                // derivatives k_0..k_{I-1}
+    // Embedded pair with first-same-as-last: the launch that forms y_{n+1}
+    // also stores sum_{m<S-1} e_m k_m per beam component, and the final launch
+    // evaluates only k_{S-1} = f(y_{n+1}) and adds its term.
+    constexpr bool SPLIT = TAB::fsal && TAB::embedded;
+    constexpr bool ERRSTORE = SPLIT && I == S - 1;
+    constexpr bool ERRLAST = SPLIT && FINAL;
+    constexpr int NK = ERRLAST ? 1 : I;                  // derivatives evaluated per beam
     constexpr uint32_t STRIDE = 64;                      // beam-slot stride of one lane
     using Mat = StageMat<T, N>;
 
@@ -558,8 +568,9 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     const uint32_t nbt = active ? 2u * ne : 0u;
     const uint32_t base0 = (uint32_t)j * ne;
     const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
-    const TS* __restrict__ src = reinterpret_cast<const TS*>(rc.psi[cur]);
+    const TS* __restrict__ src = reinterpret_cast<const TS*>(rc.psi[ERRLAST ? cur ^ 1 : cur]);
     TS* __restrict__ dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
+    T* __restrict__ errv = reinterpret_cast<T*>(rc.errv);
     const size_t ld = (size_t)rc.nb_pad;
     const T* __restrict__ uinv = uinv_table<T>(rc);
     const double* __restrict__ wgtp = rc.wgt;
@@ -573,19 +584,37 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     bool bad = false;
 
     auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
-    auto fetch = [&](uint32_t t, TS* yv, T& uv, double& wv) __attribute__((always_inline)) {
+    auto fetch = [&](uint32_t t, TS* yv, T* dv, T& uv, double& wv) __attribute__((always_inline)) {
         if (t < nbt) {
             const uint32_t off = offset(t);
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(src + q * ld, off);
+            if constexpr (ERRLAST) {
+#pragma unroll
+                for (int q = 0; q < 2 * N; ++q) dv[q] = *elem(errv + q * ld, off);
+            }
             uv = *elem(uinv, t);
             if constexpr (MOMENTS) wv = *elem(wgtp, t);
         }
     };
-    auto process = [&](uint32_t t, const TS* yv, T u, double wt) __attribute__((always_inline)) {
+    auto process = [&](uint32_t t, const TS* yv, const T* dv, T u, double wt) __attribute__((always_inline)) {
         T y[2 * N];
 #pragma unroll
         for (int q = 0; q < 2 * N; ++q) y[q] = (T)yv[q];
+        if constexpr (ERRLAST) {
+            // y = y_{n+1}, dv = sum_{m<S-1} e_m k_m: the error h sum_m e_m k_m
+            T k[2 * N];
+            eval_k<T, N>(mats[0].a, mats[0].b, u, y, k);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                T d = dv[q];
+                if constexpr (TAB::E[S - 1] != 0.0) d = fma((T)TAB::E[S - 1], k[q], d);
+                const T e = fabs(hT * d);
+                bad |= !isfinite(e);
+                emax = fmax(emax, e);
+            }
+            return;
+        }
         // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
         // LDS for every beam instead of holding all of them in registers.
         asm volatile("" ::: "memory");
@@ -618,9 +647,26 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
         });
 
-        if constexpr (ERROR) {
-            // h sum_m e_m k_m per real component (the last derivative is that
-            // of the new state, first same as last)
+        if constexpr (ERRSTORE) {
+            // the error terms of k_0..k_{S-2}, summed in the order of the final sum
+            const uint32_t off = offset(t);
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                T d = 0;
+                bool first = true;
+                static_for<0, NK>([&](auto Mc) {
+                    constexpr int m = decltype(Mc)::value;
+                    if constexpr (TAB::E[m] != 0.0) {
+                        d = first ? (T)TAB::E[m] * kk[m][q] : fma((T)TAB::E[m], kk[m][q], d);
+                        first = false;
+                    }
+                });
+                *elem(errv + q * ld, off) = d;
+            }
+        }
+
+        if constexpr (ERROR && !SPLIT) {
+            // h sum_m e_m k_m per real component
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) {
                 T d = 0;
@@ -699,6 +745,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     };
 
     TS ys[NSLOT][2 * N];
+    T ds[NSLOT][ERRLAST ? 2 * N : 1];
     T us[NSLOT];
     double ws[NSLOT];
     const uint32_t t0 = (uint32_t)lane;
@@ -706,7 +753,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         constexpr int sl = decltype(Sc)::value;
         us[sl] = 0;
         ws[sl] = 0.0;
-        fetch(t0 + sl * STRIDE, ys[sl], us[sl], ws[sl]);
+        fetch(t0 + sl * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
     });
 
     // ---- per-trajectory inputs of the prologue (wave-uniform)
@@ -773,7 +820,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             }
             double GP[N];
             complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, GP,
-                                &smat[jt][I - 1], lane);
+                                &smat[jt][NK - 1], lane);
             if (lane == 0)
                 for (int a = 0; a < N; ++a) sG[jt][a] = GP[a];
         }
@@ -787,8 +834,8 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         static_for<0, NSLOT>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
             const uint32_t ts = t + sl * STRIDE;
-            if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], ws[sl]);
-            fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], ws[sl]);
+            if (sl == 0 || ts < nbt) process(ts, ys[sl], ds[sl], us[sl], ws[sl]);
+            fetch(ts + NSLOT * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
         });
     }
 

@@ -171,7 +171,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, mat, geo, ctrl, prob, rconst, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, mat, geo, ctrl, prob, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk;
 };
@@ -206,7 +206,8 @@ const char* validate(const nuosc_params* p)
     if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
     const int64_t na = std::max(p->n_angle, 1);
     // each amplitude component array is addressed with 32-bit byte offsets
-    const int64_t tsz = p->precision == NUOSC_FP64 ? 8 : 4;
+    // (and so is the per-beam error sum, held in the arithmetic type)
+    const int64_t tsz = p->precision == NUOSC_FP32_AMP ? 4 : 8;
     if ((2 * (int64_t)p->n_energy * na + 64) * tsz >= ((int64_t)1 << 32))
         return "too many beams (one amplitude component must stay below 4 GiB)";
     return nullptr;
@@ -236,6 +237,8 @@ Layout make_layout(const nuosc_params& p)
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * 2 * n * n * 8);
     L.partial = take((size_t)2 * 2 * n * n * L.nblk * 8);  // two launches' partials (alternating)
     L.errpart = take((size_t)L.nblk * 8);
+    const size_t asz = p.precision == NUOSC_FP32_AMP ? 4 : 8;
+    L.errv = take(p.integrator == NUOSC_RK_DP54 ? 2 * n * (size_t)L.nb_pad * asz : 0);
     L.mat = take((size_t)nuosc::kMaxStages * L.na * nuosc::kStageMatBytes);
     L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
     L.ctrl = take(2 * sizeof(Control));
@@ -374,6 +377,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
+    rc.errv = (void*)(base + L.errv);
     rc.mat = (void*)(base + L.mat);
     rc.geo = (nuosc::TrajGeo*)(base + L.geo);
     rc.ctrl = (Control*)(base + L.ctrl);
