@@ -49,7 +49,8 @@ constexpr size_t kStageMatBytes = sizeof(StageMat<double, 3>);
 // FP64 geometry and frame data of one trajectory at one stage radius.
 struct TrajGeo {
     double c, w, wc, ic;  // cos(theta), angle weight w, w*c (0 single angle), 1/c
-    double G[3];          // d Phi / dr of the co-rotating frame at this stage
+    double P[3];          // phase sum sum_{m < l} coef(l, m) G_m of stage l, G_m = d Phi / dr of
+                          // the co-rotating frame at stage m (accumulated by the beam launches)
     double z[3][2];       // e^{i(Phi_a - Phi_b)}, upper pairs
 };
 

@@ -93,6 +93,18 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
+// coef(l, M) for a runtime stage l in (M, LAST], else 0.
+template <typename TAB, int M, int LAST>
+__device__ __forceinline__ double coef_of_column(int l)
+{
+    double r = 0.0;
+    static_for<M + 1, LAST + 1>([&](auto Lc) {
+        constexpr int ll = decltype(Lc)::value;
+        if (l == ll) r = coef<TAB>(ll, M);
+    });
+    return r;
+}
+
 // Empty asm that takes v as a register operand: the computation of v must be
 // complete here, which bounds how far the scheduler spreads one stage's loads
 // and arithmetic into the next (register pressure).  Emits no instruction.
@@ -112,10 +124,36 @@ __device__ __forceinline__ T* elem(T* base, uint32_t i)
     return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
 }
 
-// k = -i K y for one beam with K = A + B u (packed Hermitian).  y, k: [2N] as
-// (re, im) per component.
+// Global-memory views of the beam arrays.  uniform_global(p) takes a
+// wave-uniform pointer into a scalar register as a global-address-space
+// pointer: loads and stores through it become global (not flat) operations
+// with a scalar base and a 32-bit vector offset, and one such base per
+// amplitude component keeps the per-component address arithmetic out of the
+// vector ALU.
+template <typename T> using global = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ global<T>* uniform_global(T* p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return reinterpret_cast<global<T>*>(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ global<T>* elem(global<T>* base, uint32_t i)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<global<T>*>(reinterpret_cast<global<B>*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
+
+// K y for one beam with K = A + B u (packed Hermitian).  y, ky: [2N] as (re,
+// im) per component.  The derivative is k = -i K y: Re k_a = Im (K y)_a and
+// Im k_a = -Re (K y)_a.  The kernels keep K y and fold -i into the Runge-Kutta
+// coefficients (c k[q] = ksign(q) c ky[q ^ 1]), which saves the negations.
 template <typename T, int N>
-__device__ __forceinline__ void eval_k(const T* A, const T* B, T u, const T* y, T* k)
+__device__ __forceinline__ void eval_ky(const T* A, const T* B, T u, const T* y, T* k)
 {
     constexpr int NU = Shape<N>::NU;
     T kd[N], ku[NU][2];
@@ -138,10 +176,12 @@ __device__ __forceinline__ void eval_k(const T* A, const T* B, T u, const T* y, 
             p = fma(kr, y[2 * b], fma(-ki, y[2 * b + 1], p));
             q = fma(kr, y[2 * b + 1], fma(ki, y[2 * b], q));
         }
-        k[2 * a] = q;       // -i (p + i q) = q - i p
-        k[2 * a + 1] = -p;
+        k[2 * a] = p;
+        k[2 * a + 1] = q;
     }
 }
+
+__host__ __device__ constexpr double ksign(int q) { return (q & 1) ? -1.0 : 1.0; }
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -330,8 +370,6 @@ __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, 
             M->a[x] = (T)av[x];
             M->b[x] = (T)bv[x];
         }
-        TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
-        for (int a = 0; a < N; ++a) g.G[a] = G[a];
     }
 }
 
@@ -532,8 +570,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     __shared__ Mat smat[kTrajPerBlock][NK > 0 ? NK : 1];
     __shared__ double swave[kTrajPerBlock][NV + 1];
     __shared__ double sJ[NV];
-    __shared__ double sG[kTrajPerBlock][N];   // G_{I-1} of each trajectory (prologue -> epilogue)
-    __shared__ double sGeo[kTrajPerBlock][2]; // c, w of stage I (prologue -> epilogue)
+    __shared__ double sF[kTrajPerBlock][2 + 2 * (NU > 0 ? NU : 1)];  // w, wc, z of stage I (-> epilogue)
 
     // ---- stage matrices of k_0..k_{I-2} (raw dwords, by the trajectory's
     //      wavefront): loaded before the control block is read so that both
@@ -554,6 +591,33 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         }
     }
 
+    // ---- prologue inputs that do not depend on the control block (in flight
+    //      while it is read): launch I-1's partial density sums, the frame of
+    //      stage I-1, and the phase sums of stages I, I+1, ... (lane k: stage
+    //      I + k) that the earlier launches of this attempt accumulated
+    constexpr int LASTPREP = TAB::fsal ? S - 1 : S;      // last launch that prepares a stage frame
+    PartialRegs<NV, kTrajPerBlock> xp;
+    if constexpr (I >= 2) load_partials_waves<NV, kTrajPerBlock>(rc, I - 1, xp);
+    double cP = 1.0, icP = 1.0, zP[NU > 0 ? NU : 1][2];
+    double psum[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) psum[a] = 0.0;
+    if (active) {
+        if constexpr (I >= 2) {
+            const TrajGeo& g = rc.geo[(size_t)(I - 1) * rc.na + j];
+            cP = g.c;
+            icP = g.ic;
+            for (int q = 0; q < NU; ++q) {
+                zP[q][0] = g.z[q][0];
+                zP[q][1] = g.z[q][1];
+            }
+            if constexpr (MOMENTS) {
+                if (I + lane <= LASTPREP)
+                    for (int a = 0; a < N; ++a) psum[a] = rc.geo[(size_t)(I + lane) * rc.na + j].P[a];
+            }
+        }
+    }
+
     // the first launch of an attempt takes the control block between attempts
     if (I == 1 && blk == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
     const Control* ctl = rc.ctrl + (I <= 1 ? 1 : 0);
@@ -568,12 +632,23 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     const uint32_t nbt = active ? 2u * ne : 0u;
     const uint32_t base0 = (uint32_t)j * ne;
     const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
-    const TS* __restrict__ src = reinterpret_cast<const TS*>(rc.psi[ERRLAST ? cur ^ 1 : cur]);
-    TS* __restrict__ dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
-    T* __restrict__ errv = reinterpret_cast<T*>(rc.errv);
+    const TS* src = reinterpret_cast<const TS*>(rc.psi[ERRLAST ? cur ^ 1 : cur]);
+    TS* dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
+    T* errv = reinterpret_cast<T*>(rc.errv);
     const size_t ld = (size_t)rc.nb_pad;
-    const T* __restrict__ uinv = uinv_table<T>(rc);
-    const double* __restrict__ wgtp = rc.wgt;
+    global<const T>* __restrict__ uinv = uniform_global(uinv_table<T>(rc));
+    global<const double>* __restrict__ wgtp = uniform_global(rc.wgt);
+    // per-component bases: state read (y_n, or y_{n+1} for the final launch of
+    // a split error), state written, partial error sums
+    global<const TS>* __restrict__ srcq[2 * N];
+    global<TS>* __restrict__ dstq[2 * N];
+    global<T>* __restrict__ errq[2 * N];
+#pragma unroll
+    for (int q = 0; q < 2 * N; ++q) {
+        srcq[q] = uniform_global(src + q * ld);
+        dstq[q] = uniform_global(dst + q * ld);
+        errq[q] = uniform_global(errv + q * ld);
+    }
     const T hT = (T)h;
     const Mat* mats = smat[jt];
 
@@ -588,10 +663,10 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         if (t < nbt) {
             const uint32_t off = offset(t);
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(src + q * ld, off);
+            for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(srcq[q], off);
             if constexpr (ERRLAST) {
 #pragma unroll
-                for (int q = 0; q < 2 * N; ++q) dv[q] = *elem(errv + q * ld, off);
+                for (int q = 0; q < 2 * N; ++q) dv[q] = *elem(errq[q], off);
             }
             uv = *elem(uinv, t);
             if constexpr (MOMENTS) wv = *elem(wgtp, t);
@@ -604,11 +679,11 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         if constexpr (ERRLAST) {
             // y = y_{n+1}, dv = sum_{m<S-1} e_m k_m: the error h sum_m e_m k_m
             T k[2 * N];
-            eval_k<T, N>(mats[0].a, mats[0].b, u, y, k);
+            eval_ky<T, N>(mats[0].a, mats[0].b, u, y, k);
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) {
                 T d = dv[q];
-                if constexpr (TAB::E[S - 1] != 0.0) d = fma((T)TAB::E[S - 1], k[q], d);
+                if constexpr (TAB::E[S - 1] != 0.0) d = fma((T)(ksign(q) * TAB::E[S - 1]), k[q ^ 1], d);
                 const T e = fabs(hT * d);
                 bad |= !isfinite(e);
                 emax = fmax(emax, e);
@@ -633,7 +708,8 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                     static_for<0, l>([&](auto Mc) {
                         constexpr int m = decltype(Mc)::value;
                         if constexpr (TAB::A[l][m] != 0.0) {
-                            acc = first ? (T)TAB::A[l][m] * kk[m][q] : fma((T)TAB::A[l][m], kk[m][q], acc);
+                            constexpr double a_lm = TAB::A[l][m];
+                            acc = first ? (T)(ksign(q) * a_lm) * kk[m][q ^ 1] : fma((T)(ksign(q) * a_lm), kk[m][q ^ 1], acc);
                             first = false;
                         }
                     });
@@ -642,7 +718,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             }
             // keep only this stage's matrix live: no LDS reads hoisted across stages
             asm volatile("" ::: "memory");
-            eval_k<T, N>(mats[l].a, mats[l].b, u, Y, kk[l]);
+            eval_ky<T, N>(mats[l].a, mats[l].b, u, Y, kk[l]);
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
         });
@@ -657,11 +733,11 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 static_for<0, NK>([&](auto Mc) {
                     constexpr int m = decltype(Mc)::value;
                     if constexpr (TAB::E[m] != 0.0) {
-                        d = first ? (T)TAB::E[m] * kk[m][q] : fma((T)TAB::E[m], kk[m][q], d);
+                        d = first ? (T)(ksign(q) * TAB::E[m]) * kk[m][q ^ 1] : fma((T)(ksign(q) * TAB::E[m]), kk[m][q ^ 1], d);
                         first = false;
                     }
                 });
-                *elem(errv + q * ld, off) = d;
+                *elem(errq[q], off) = d;
             }
         }
 
@@ -674,7 +750,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 static_for<0, S>([&](auto Mc) {
                     constexpr int m = decltype(Mc)::value;
                     if constexpr (TAB::E[m] != 0.0) {
-                        d = first ? (T)TAB::E[m] * kk[m][q] : fma((T)TAB::E[m], kk[m][q], d);
+                        d = first ? (T)(ksign(q) * TAB::E[m]) * kk[m][q ^ 1] : fma((T)(ksign(q) * TAB::E[m]), kk[m][q ^ 1], d);
                         first = false;
                     }
                 });
@@ -698,7 +774,8 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                     static_for<0, NK>([&](auto Mc) {
                         constexpr int m = decltype(Mc)::value;
                         if constexpr (coef<TAB>(I, m) != 0.0) {
-                            acc = first ? (T)coef<TAB>(I, m) * kk[m][q] : fma((T)coef<TAB>(I, m), kk[m][q], acc);
+                            constexpr double c_im = coef<TAB>(I, m);
+                            acc = first ? (T)(ksign(q) * c_im) * kk[m][q ^ 1] : fma((T)(ksign(q) * c_im), kk[m][q ^ 1], acc);
                             first = false;
                         }
                     });
@@ -718,7 +795,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 }
                 const uint32_t off = offset(t);
 #pragma unroll
-                for (int q = 0; q < 2 * N; ++q) *elem(dst + q * ld, off) = (TS)Yo[q];
+                for (int q = 0; q < 2 * N; ++q) *elem(dstq[q], off) = (TS)Yo[q];
                 if constexpr (!TAB::embedded) {
 #pragma unroll
                     for (int q = 0; q < 2 * N; ++q) bad |= !isfinite(Yo[q]);
@@ -744,49 +821,36 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         }
     };
 
+    // ---- phase of the accepted state and geometry of stage I (wave-uniform)
+    double phn[N];
+    double cN = 1.0, wN = 0.0;
+    if (active) {
+        if constexpr (MOMENTS && I > 0) {
+            for (int a = 0; a < N; ++a) phn[a] = rc.phase[cur][(size_t)j * N + a];
+            traj_geometry(rc, j, stage_radius<TAB>(rc, C, I), cN, wN);
+        }
+    }
+
+    // ---- the first beam of every slot: in flight from here on (no stage to
+    //      complete), else (register pressure) from the stage completion on
+    //      (the final launch of a split error) or from its end on, overlapping
+    //      the frame preparation
+    constexpr int FETCH_AT = NK == 0 ? 0 : (ERRLAST ? 1 : 2);
     TS ys[NSLOT][2 * N];
     T ds[NSLOT][ERRLAST ? 2 * N : 1];
     T us[NSLOT];
     double ws[NSLOT];
     const uint32_t t0 = (uint32_t)lane;
-    static_for<0, NSLOT>([&](auto Sc) {
-        constexpr int sl = decltype(Sc)::value;
-        us[sl] = 0;
-        ws[sl] = 0.0;
-        fetch(t0 + sl * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
-    });
+    auto fetch_first = [&]() __attribute__((always_inline)) {
+        static_for<0, NSLOT>([&](auto Sc) {
+            constexpr int sl = decltype(Sc)::value;
+            us[sl] = 0;
+            ws[sl] = 0.0;
+            fetch(t0 + sl * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
+        });
+    };
+    if constexpr (FETCH_AT == 0) fetch_first();
 
-    // ---- per-trajectory inputs of the prologue (wave-uniform)
-    double phn[N];
-    double cP = 1.0, icP = 1.0, zP[NU > 0 ? NU : 1][2];
-    if (active) {
-        if constexpr (I == 1)
-            for (int a = 0; a < N; ++a) phn[a] = rc.phase[cur][(size_t)j * N + a];
-        if constexpr (I >= 2) {
-            const TrajGeo& g = rc.geo[(size_t)(I - 1) * rc.na + j];
-            cP = g.c;
-            icP = g.ic;
-            for (int q = 0; q < NU; ++q) {
-                zP[q][0] = g.z[q][0];
-                zP[q][1] = g.z[q][1];
-            }
-        }
-    }
-
-    // the first partials of launch I-1 in flight, then the geometry of stage
-    // I (which does not need J) while they arrive
-    PartialRegs<NV, kTrajPerBlock> xp;
-    if constexpr (I >= 2) load_partials_waves<NV, kTrajPerBlock>(rc, I - 1, xp);
-    if constexpr (MOMENTS && I > 0) {
-        if (active) {
-            double cN, wN;
-            traj_geometry(rc, j, stage_radius<TAB>(rc, C, I), cN, wN);
-            if (lane == 0) {
-                sGeo[jt][0] = cN;
-                sGeo[jt][1] = wN;
-            }
-        }
-    }
 
     // ---- J_{I-1}: the previous launch's partials (launch 1: J_0 of the state)
     if constexpr (NK > 0) {
@@ -805,6 +869,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             if (active && x < NKS * MPER) mdst[x] = mreg[i];
         }
         if (active) {
+            if constexpr (FETCH_AT == 1) fetch_first();
             double J[NV];
             for (int v = 0; v < NV; ++v) J[v] = sJ[v];
             if constexpr (I == 1) {
@@ -821,10 +886,38 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             double GP[N];
             complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, GP,
                                 &smat[jt][NK - 1], lane);
-            if (lane == 0)
-                for (int a = 0; a < N; ++a) sG[jt][a] = GP[a];
+            if constexpr (FETCH_AT == 2) fetch_first();
+            if constexpr (MOMENTS) {
+                // phase sums sum_{m < l} coef(l, m) G_m: lane k adds the term of
+                // G_{I-1} to that of stage l = I + k and passes it on to launch l
+                const int l = I + lane;
+                const double cf = coef_of_column<TAB, I - 1, LASTPREP>(l);
+                if (cf != 0.0)
+                    for (int a = 0; a < N; ++a) psum[a] += cf * GP[a];
+                if (lane >= 1 && l <= LASTPREP)
+                    for (int a = 0; a < N; ++a) rc.geo[(size_t)l * rc.na + j].P[a] = psum[a];
+                // stage I prepared now, its frame kept for the epilogue: phase
+                // Phi_n + h sum_{m < I} coef(I, m) G_m, rotation factors, geometry
+                double ph[N];
+                for (int a = 0; a < N; ++a) ph[a] = phn[a] + h * __shfl(psum[a], 0, 64);
+                const Frame<N> f = prepare_wave<N>(rc, j, I, cN, wN, ph, lane);
+                if (lane == 0) {
+                    if (I == LASTPREP)  // the new state's phase; kept only if the attempt is accepted
+                        for (int a = 0; a < N; ++a) rc.phase[cur ^ 1][(size_t)j * N + a] = ph[a];
+                    sF[jt][0] = f.w;
+                    sF[jt][1] = f.wc;
+                    for (int q = 0; q < NU; ++q) {
+                        sF[jt][2 + 2 * q] = f.z[q][0];
+                        sF[jt][3 + 2 * q] = f.z[q][1];
+                    }
+                }
+            }
         }
-        __syncthreads();
+        // the stage matrices in LDS are this wavefront's own: a wavefront-level
+        // barrier orders its LDS writes before the beam loop reads them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     // ---- beam loop: NSLOT-slot load pipeline, the next beams of the other
@@ -860,23 +953,12 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                     f.z[q][1] = g.z[q][1];
                 }
             } else {
-                // phase of stage I: Phi_n + h sum_{m < I} coef(I, m) G_m (G_{I-1}
-                // from this launch's prologue, the earlier ones from geo)
-                double ph[N];
-                for (int a = 0; a < N; ++a) {
-                    double acc = 0.0;
-                    static_for<0, I>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        if constexpr (coef<TAB>(I, m) != 0.0)
-                            acc += coef<TAB>(I, m) * (m == I - 1 ? sG[jt][a] : rc.geo[(size_t)m * rc.na + j].G[a]);
-                    });
-                    ph[a] = rc.phase[cur][(size_t)j * N + a] + h * acc;
-                }
-                f = prepare_wave<N>(rc, j, I, sGeo[jt][0], sGeo[jt][1], ph, lane);
-                if (I == S || (TAB::fsal && I == S - 1)) {
-                    // the new state's phase; kept only if the attempt is accepted
-                    if (lane == 0)
-                        for (int a = 0; a < N; ++a) rc.phase[cur ^ 1][(size_t)j * N + a] = ph[a];
+                // frame of stage I prepared in the prologue
+                f.w = sF[jt][0];
+                f.wc = sF[jt][1];
+                for (int q = 0; q < NU; ++q) {
+                    f.z[q][0] = sF[jt][2 + 2 * q];
+                    f.z[q][1] = sF[jt][3 + 2 * q];
                 }
             }
             // S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa, weighted by w and w c
