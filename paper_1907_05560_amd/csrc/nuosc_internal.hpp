@@ -37,8 +37,9 @@ template <int N> struct Shape {
 
 // Stage matrix of one trajectory in the co-rotating frame, K = A + B u with
 // u = +1/E for neutrinos and u = -1/E for antineutrinos (whose amplitudes are
-// held complex-conjugated on the device).  Packed Hermitian, A then B, in the
-// arithmetic type T of the stage kernels.  Written by the beam launch that
+// held complex-conjugated on the device).  Packed Hermitian, h A then h B (the
+// attempt's step size folded in), in the arithmetic type T of the stage
+// kernels.  Written by the beam launch that
 // completes the stage, read by the later beam launches of the same attempt.
 template <typename T, int N> struct alignas(16) StageMat {
     T a[Shape<N>::NM];

@@ -8,7 +8,7 @@
 //         in one fixed order (all workgroups get the same J_{I-1}; launch 1
 //         takes J_0 of the accepted state) and completes stage I-1 of its own
 //         trajectories: collective Hamiltonian (eq 3.13 / 3.16), matter term,
-//         frame rate G, stage matrices K_{I-1} = A + B u;
+//         frame rate G, stage matrices h K_{I-1} = h (A + B u);
 //       beam loop: reads y_n once, recomputes k_0..k_{I-1} from y_n and the
 //         stage matrices, forms the input of stage I (the new state in the
 //         launch that forms it, written back in the storage type) and adds
@@ -331,11 +331,12 @@ __device__ void prepare_thread(const RunConst& rc, int j, int l, double rl, cons
 //   G = diag(H_m + C) / c in the co-rotating frame, 0 in the lab frame
 //   A_ab = e^{i(Phi_a - Phi_b)} C_ab / c (a < b), A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab)
 //   B_ab = e^{i(Phi_a - Phi_b)} V_ab / c,  B_aa = V_aa / c  (H_vac = V / E)
-// Lane 0 stores A, B in mat[l] and in M (LDS), and G in geo[l].
+// Lane 0 stores h A and h B (the step size folded in: the beam kernels form
+// h k = -i h K y directly) in mat[l] and in M (LDS); G is returned.
 template <typename T, int N>
 __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, const double ic,
-                              const double (*z)[2], double lam, const double* J, double* G, StageMat<T, N>* M,
-                              int lane)
+                              const double (*z)[2], double lam, const double* J, double h, double* G,
+                              StageMat<T, N>* M, int lane)
 {
     constexpr int NM = Shape<N>::NM;
     double Cd[N], tr = 0.0;
@@ -365,10 +366,11 @@ __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, 
     if (lane == 0) {
         StageMat<T, N>& Mh = reinterpret_cast<StageMat<T, N>*>(rc.mat)[(size_t)l * rc.na + j];
         for (int x = 0; x < NM; ++x) {
-            Mh.a[x] = (T)av[x];
-            Mh.b[x] = (T)bv[x];
-            M->a[x] = (T)av[x];
-            M->b[x] = (T)bv[x];
+            const T ha = (T)(h * av[x]), hb = (T)(h * bv[x]);
+            Mh.a[x] = ha;
+            Mh.b[x] = hb;
+            M->a[x] = ha;
+            M->b[x] = hb;
         }
     }
 }
@@ -649,7 +651,6 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         dstq[q] = uniform_global(dst + q * ld);
         errq[q] = uniform_global(errv + q * ld);
     }
-    const T hT = (T)h;
     const Mat* mats = smat[jt];
 
     double macc[NM];
@@ -684,7 +685,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             for (int q = 0; q < 2 * N; ++q) {
                 T d = dv[q];
                 if constexpr (TAB::E[S - 1] != 0.0) d = fma((T)(ksign(q) * TAB::E[S - 1]), k[q ^ 1], d);
-                const T e = fabs(hT * d);
+                const T e = fabs(d);
                 bad |= !isfinite(e);
                 emax = fmax(emax, e);
             }
@@ -700,21 +701,16 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             T Y[2 * N];
 #pragma unroll
             for (int q = 0; q < 2 * N; ++q) {
-                if constexpr (l == 0) {
-                    Y[q] = y[q];
-                } else {
-                    T acc = 0;
-                    bool first = true;
-                    static_for<0, l>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        if constexpr (TAB::A[l][m] != 0.0) {
-                            constexpr double a_lm = TAB::A[l][m];
-                            acc = first ? (T)(ksign(q) * a_lm) * kk[m][q ^ 1] : fma((T)(ksign(q) * a_lm), kk[m][q ^ 1], acc);
-                            first = false;
-                        }
-                    });
-                    Y[q] = fma(hT, acc, y[q]);
-                }
+                // Y_l = y_n + sum_m a_lm (h k_m), added onto y_n term by term
+                T acc = y[q];
+                static_for<0, l>([&](auto Mc) {
+                    constexpr int m = decltype(Mc)::value;
+                    if constexpr (TAB::A[l][m] != 0.0) {
+                        constexpr double a_lm = TAB::A[l][m];
+                        acc = fma((T)(ksign(q) * a_lm), kk[m][q ^ 1], acc);
+                    }
+                });
+                Y[q] = acc;
             }
             // keep only this stage's matrix live: no LDS reads hoisted across stages
             asm volatile("" ::: "memory");
@@ -754,7 +750,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                         first = false;
                     }
                 });
-                const T e = fabs(hT * d);
+                const T e = fabs(d);
                 bad |= !isfinite(e);
                 emax = fmax(emax, e);
             }
@@ -768,7 +764,8 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             for (int q = 0; q < 2 * N; ++q) {
                 if constexpr (I == 0) {
                     Yo[q] = y[q];
-                } else {
+                } else if constexpr (NEWSTATE) {
+                    // y_{n+1}: the increment summed first, then added to y_n once
                     T acc = 0;
                     bool first = true;
                     static_for<0, NK>([&](auto Mc) {
@@ -779,7 +776,19 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                             first = false;
                         }
                     });
-                    Yo[q] = fma(hT, acc, y[q]);
+                    Yo[q] = y[q] + acc;
+                } else {
+                    // a stage input: the same operations as its recomputation
+                    // in the later launches
+                    T acc = y[q];
+                    static_for<0, NK>([&](auto Mc) {
+                        constexpr int m = decltype(Mc)::value;
+                        if constexpr (coef<TAB>(I, m) != 0.0) {
+                            constexpr double c_im = coef<TAB>(I, m);
+                            acc = fma((T)(ksign(q) * c_im), kk[m][q ^ 1], acc);
+                        }
+                    });
+                    Yo[q] = acc;
                 }
             }
             if constexpr (NEWSTATE) {
@@ -884,7 +893,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 }
             }
             double GP[N];
-            complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, GP,
+            complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, h, GP,
                                 &smat[jt][NK - 1], lane);
             if constexpr (FETCH_AT == 2) fetch_first();
             if constexpr (MOMENTS) {
