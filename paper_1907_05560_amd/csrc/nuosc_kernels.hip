@@ -105,6 +105,22 @@ __device__ __forceinline__ double coef_of_column(int l)
     return r;
 }
 
+// Lane k < NV stores v[k] to dst[k]: NV values that every lane of the
+// wavefront holds, written with one store instruction instead of NV.
+template <int NV, typename D>
+__device__ __forceinline__ void lane_scatter(D* dst, const double (&v)[NV], int lane)
+{
+    if (lane < NV) {
+        double x = v[0];
+#pragma unroll
+        for (int k = 1; k < NV; ++k) {
+            x = (lane == k) ? v[k] : x;
+            asm volatile("" : "+v"(x));  // a select chain, not a table in scratch memory
+        }
+        dst[lane] = (D)x;
+    }
+}
+
 // Empty asm that takes v as a register operand: the computation of v must be
 // complete here, which bounds how far the scheduler spreads one stage's loads
 // and arithmetic into the next (register pressure).  Emits no instruction.
@@ -288,17 +304,15 @@ __device__ Frame<N> prepare_wave(const RunConst& rc, int j, int l, double c, dou
         f.z[q][0] = __shfl(cs, q, 64);
         f.z[q][1] = __shfl(sn, q, 64);
     }
-    if (lane == 0) {
-        TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
-        g.c = f.c;
-        g.w = f.w;
-        g.wc = f.wc;
-        g.ic = f.ic;
-        for (int q = 0; q < NU; ++q) {
-            g.z[q][0] = f.z[q][0];
-            g.z[q][1] = f.z[q][1];
-        }
+    TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
+    const double head[4] = {f.c, f.w, f.wc, f.ic};
+    double zz[2 * (NU > 0 ? NU : 1)];
+    for (int q = 0; q < NU; ++q) {
+        zz[2 * q] = f.z[q][0];
+        zz[2 * q + 1] = f.z[q][1];
     }
+    lane_scatter(&g.c, head, lane);    // c, w, wc, ic are contiguous
+    if constexpr (NU > 0) lane_scatter(&g.z[0][0], zz, lane);
     return f;
 }
 
@@ -331,7 +345,7 @@ __device__ void prepare_thread(const RunConst& rc, int j, int l, double rl, cons
 //   G = diag(H_m + C) / c in the co-rotating frame, 0 in the lab frame
 //   A_ab = e^{i(Phi_a - Phi_b)} C_ab / c (a < b), A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab)
 //   B_ab = e^{i(Phi_a - Phi_b)} V_ab / c,  B_aa = V_aa / c  (H_vac = V / E)
-// Lane 0 stores h A and h B (the step size folded in: the beam kernels form
+// Stores h A and h B (the step size folded in: the beam kernels form
 // h k = -i h K y directly) in mat[l] and in M (LDS); G is returned.
 template <typename T, int N>
 __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, const double ic,
@@ -363,16 +377,14 @@ __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, 
             bv[N + 2 * q] = cs * vr - sn * vi;
             bv[N + 2 * q + 1] = cs * vi + sn * vr;
         }
-    if (lane == 0) {
-        StageMat<T, N>& Mh = reinterpret_cast<StageMat<T, N>*>(rc.mat)[(size_t)l * rc.na + j];
-        for (int x = 0; x < NM; ++x) {
-            const T ha = (T)(h * av[x]), hb = (T)(h * bv[x]);
-            Mh.a[x] = ha;
-            Mh.b[x] = hb;
-            M->a[x] = ha;
-            M->b[x] = hb;
-        }
+    double hab[2 * NM];
+    for (int x = 0; x < NM; ++x) {
+        hab[x] = h * av[x];
+        hab[NM + x] = h * bv[x];
     }
+    StageMat<T, N>& Mh = reinterpret_cast<StageMat<T, N>*>(rc.mat)[(size_t)l * rc.na + j];
+    lane_scatter(Mh.a, hab, lane);   // a and b are contiguous
+    lane_scatter(M->a, hab, lane);
 }
 
 // Step controller (readings J, K of the oracle's header; fixed-step RK4 always
@@ -574,9 +586,22 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     __shared__ double sJ[NV];
     __shared__ double sF[kTrajPerBlock][2 + 2 * (NU > 0 ? NU : 1)];  // w, wc, z of stage I (-> epilogue)
 
+    // ---- the control block first (the longest dependent chain starts here);
+    //      ctrl[1] holds it between attempts, ctrl[0] during one
+    // (relaxed atomic loads: issued here rather than sunk to their first use)
+    Control C{};
+    {
+        Control* vc = rc.ctrl + (I <= 1 ? 1 : 0);
+        C.r = __hip_atomic_load(&vc->r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.h = __hip_atomic_load(&vc->h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.istep = __hip_atomic_load(&vc->istep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
     // ---- stage matrices of k_0..k_{I-2} (raw dwords, by the trajectory's
-    //      wavefront): loaded before the control block is read so that both
-    //      latencies overlap; stored to LDS after the first beams' loads
+    //      wavefront), in flight while the control block arrives; stored to
+    //      LDS after the stage completion
     constexpr int MPER = sizeof(Mat) / 4;
     constexpr int NKS = NK > 1 ? NK - 1 : 0;             // stored matrices
     constexpr int MREG = (NKS * MPER + (int)STRIDE - 1) / (int)STRIDE;
@@ -622,9 +647,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 
     // the first launch of an attempt takes the control block between attempts
     if (I == 1 && blk == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
-    const Control* ctl = rc.ctrl + (I <= 1 ? 1 : 0);
-    if (I > 0 && ctl->status != 0) return;  // run finished: attempts are no-ops
-    const Control C = *ctl;
+    if (I > 0 && C.status != 0) return;  // run finished: attempts are no-ops
     const int cur = C.cur;
     const double h = C.h;
 
@@ -910,16 +933,16 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 double ph[N];
                 for (int a = 0; a < N; ++a) ph[a] = phn[a] + h * __shfl(psum[a], 0, 64);
                 const Frame<N> f = prepare_wave<N>(rc, j, I, cN, wN, ph, lane);
-                if (lane == 0) {
-                    if (I == LASTPREP)  // the new state's phase; kept only if the attempt is accepted
-                        for (int a = 0; a < N; ++a) rc.phase[cur ^ 1][(size_t)j * N + a] = ph[a];
-                    sF[jt][0] = f.w;
-                    sF[jt][1] = f.wc;
-                    for (int q = 0; q < NU; ++q) {
-                        sF[jt][2 + 2 * q] = f.z[q][0];
-                        sF[jt][3 + 2 * q] = f.z[q][1];
-                    }
+                if (I == LASTPREP)  // the new state's phase; kept only if the attempt is accepted
+                    lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
+                double fw[2 + 2 * (NU > 0 ? NU : 1)];
+                fw[0] = f.w;
+                fw[1] = f.wc;
+                for (int q = 0; q < NU; ++q) {
+                    fw[2 + 2 * q] = f.z[q][0];
+                    fw[3 + 2 * q] = f.z[q][1];
                 }
+                lane_scatter(sF[jt], fw, lane);
             }
         }
         // the stage matrices in LDS are this wavefront's own: a wavefront-level
