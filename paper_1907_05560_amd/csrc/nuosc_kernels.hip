@@ -863,11 +863,10 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         }
     }
 
-    // ---- the first beam of every slot: in flight from here on (no stage to
-    //      complete), else (register pressure) from the stage completion on
-    //      (the final launch of a split error) or from its end on, overlapping
-    //      the frame preparation
-    constexpr int FETCH_AT = NK == 0 ? 0 : (ERRLAST ? 1 : 2);
+    // ---- the first beam of every slot: in flight from here on (no stage
+    //      frame to prepare), else (register pressure) from the end of the
+    //      stage completion on, overlapping the frame preparation
+    constexpr bool EARLY_FETCH = !(MOMENTS && I > 0);
     TS ys[NSLOT][2 * N];
     T ds[NSLOT][ERRLAST ? 2 * N : 1];
     T us[NSLOT];
@@ -881,7 +880,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             fetch(t0 + sl * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
         });
     };
-    if constexpr (FETCH_AT == 0) fetch_first();
+    if constexpr (EARLY_FETCH) fetch_first();
 
 
     // ---- J_{I-1}: the previous launch's partials (launch 1: J_0 of the state)
@@ -901,7 +900,6 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             if (active && x < NKS * MPER) mdst[x] = mreg[i];
         }
         if (active) {
-            if constexpr (FETCH_AT == 1) fetch_first();
             double J[NV];
             for (int v = 0; v < NV; ++v) J[v] = sJ[v];
             if constexpr (I == 1) {
@@ -918,7 +916,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             double GP[N];
             complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, h, GP,
                                 &smat[jt][NK - 1], lane);
-            if constexpr (FETCH_AT == 2) fetch_first();
+            if constexpr (!EARLY_FETCH) fetch_first();
             if constexpr (MOMENTS) {
                 // phase sums sum_{m < l} coef(l, m) G_m: lane k adds the term of
                 // G_{I-1} to that of stage l = I + k and passes it on to launch l
