@@ -46,19 +46,20 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    """k_stage<float, float, 3, true, TabDP54, 7> -> 'k_stage<float,float,3,MA,DP54,7>'."""
+    """'void nuosc::(anonymous namespace)::k_stage_one<float, float, 3, ...TabDP54, 7>(nuosc::RunConst)'
+    -> 'k_stage_one<float,float,3,DP54,7>'."""
     n = name.replace("nuosc::(anonymous namespace)::", "").replace("void ", "")
-    n = re.sub(r"\(nuosc::RunConst.*\)$", "", n)
+    n = re.sub(r"\(nuosc::(RunConst|LaunchSet).*\)$", "", n)
     n = n.replace("TabDP54", "DP54").replace("TabRK4", "RK4").replace(" ", "")
     return n
 
 
 def stage_key(name: str):
-    """(stage, precision) of a k_stage instantiation, or None."""
-    m = re.search(r"k_stage<(\w+),(\w+),(\d),(\w+),\w+,(\d)>", short_name(name))
+    """(stage, precision) of a beam-kernel instantiation (one run or a launch set), or None."""
+    m = re.search(r"k_stage(?:_one)?<(\w+),(\w+),(\d),\w+,(\d)>", short_name(name))
     if not m:
         return None
-    ts, t, _, _, stage = m.groups()
+    ts, t, _, stage = m.groups()
     prec = 0 if ts == "double" else (1 if t == "float" else 2)
     return int(stage), prec
 

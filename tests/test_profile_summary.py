@@ -1,0 +1,51 @@
+"""Host logic of the rocprofv3 summary tool (no GPU): kernel-name parsing and
+the copy-calibrated traffic figures."""
+
+import csv
+
+import pytest
+
+from paper_1907_05560_amd import profile_summary as PS
+
+NS = "nuosc::(anonymous namespace)::"
+
+
+def _name(kernel, ts, t, tab, stage, arg):
+    return f"void {NS}{kernel}<{ts}, {t}, 3, {NS}{tab}, {stage}>(nuosc::{arg})"
+
+
+@pytest.mark.parametrize("kernel,arg", [("k_stage_one", "RunConst"), ("k_stage", "LaunchSet")])
+@pytest.mark.parametrize("ts,t,prec", [("double", "double", 0), ("float", "float", 1), ("float", "double", 2)])
+def test_stage_key_reads_stage_and_precision(kernel, arg, ts, t, prec):
+    n = _name(kernel, ts, t, "TabDP54", 6, arg)
+    assert PS.stage_key(n) == (6, prec)
+    assert PS.short_name(n) == f"{kernel}<{ts},{t},3,DP54,6>"
+
+
+def test_other_kernels_have_no_stage_key():
+    assert PS.stage_key(f"void {NS}k_control_one<3, {NS}TabDP54, 7>(nuosc::RunConst)") is None
+    assert PS.stage_key(PS.COPY_KERNEL) is None
+
+
+def _write(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_traffic_is_scaled_by_the_calibration_copy(tmp_path):
+    k6 = _name("k_stage_one", "float", "float", "TabDP54", 6, "RunConst")
+    mib = 64
+    # the copy reads 2 x its size by FETCH_SIZE and writes 1 x by WRITE_SIZE
+    f_rows = [(PS.COPY_KERNEL, 2 * mib * 1024), (k6, 1000.0), (k6, 1000.0), (k6, 10.0)]  # last: early exit
+    w_rows = [(PS.COPY_KERNEL, mib * 1024), (k6, 500.0), (k6, 500.0), (k6, 5.0)]
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write(fp, "FETCH_SIZE", f_rows)
+    _write(wp, "WRITE_SIZE", w_rows)
+    text, doc = PS.traffic_summary(str(fp), str(wp), mib, "cmd f", "cmd w")
+    assert doc["fetch_scale"] == pytest.approx(0.5)
+    assert doc["write_scale"] == pytest.approx(1.0)
+    assert doc["bytes_per_launch"]["stage6_prec1"] == round(1000 * 1024 * 0.5 + 500 * 1024)
+    assert "k_stage_one<float,float,3,DP54,6>" in text
