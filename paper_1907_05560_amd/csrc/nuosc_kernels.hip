@@ -533,15 +533,31 @@ __device__ void finish_partials_waves(const RunConst& rc, int st, const PartialR
 
 // ------------------------------------------------------------------ beam kernel
 // Launch shape of the beam kernels: one wavefront per trajectory.  FP32
-// arithmetic: 16 trajectories per workgroup (at most 128 VGPRs, so every
-// wavefront of the grid is resident at once) and three beams of each lane in
-// flight; FP64 arithmetic (about twice the registers): 8 trajectories per
-// workgroup and two beams in flight.
+// arithmetic: 16 trajectories per workgroup, three beams of each lane in
+// flight, at most 128 VGPRs, so every wavefront of a 4000-trajectory grid is
+// resident at once.  FP64 arithmetic: 8 trajectories per workgroup.
 template <typename T> struct BeamShape {
     static constexpr bool fp64 = std::is_same<T, double>::value;
     static constexpr int traj = fp64 ? 8 : 16;
-    static constexpr int slots = fp64 ? 2 : 3;
     static constexpr int block = 64 * traj;
+};
+
+// Beams in flight per lane and the wavefronts per SIMD the register
+// allocation must allow, per launch.  FP32 arithmetic: three beams, four
+// wavefronts.  FP64 arithmetic needs about twice the registers per beam;
+// with two beams in flight the middle launches exceed 128 VGPRs and their
+// grid runs in two rounds.  Measured on the 3.2M-beam grid, these launches
+// are faster with one beam in flight and four wavefronts per SIMD (the
+// compiler spills a few registers of the prologue), the others with two
+// beams: stages 2-4 (FP64 storage; also its final launch of a split error)
+// and 3-5 (FP32 storage).
+template <typename TS, typename T, typename TAB, int I> struct BeamPlan {
+    static constexpr bool fp64 = BeamShape<T>::fp64;
+    static constexpr bool split_final = TAB::fsal && TAB::embedded && I == TAB::S;
+    static constexpr bool narrow =
+        fp64 && (std::is_same<TS, double>::value ? ((I >= 2 && I <= 4) || split_final) : (I >= 3 && I <= 5));
+    static constexpr int slots = fp64 ? (narrow ? 1 : 2) : 3;
+    static constexpr int waves_per_eu = (!fp64 || narrow) ? 4 : 1;
 };
 
 // Beam launch I of the attempt (the file header describes the whole step).
@@ -556,7 +572,6 @@ template <typename TS, typename T, int N, typename TAB, int I>
 __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 {
     constexpr int kTrajPerBlock = BeamShape<T>::traj;
-    constexpr int NSLOT = BeamShape<T>::slots;
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
     constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU;
@@ -571,6 +586,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     constexpr bool SPLIT = TAB::fsal && TAB::embedded;
     constexpr bool ERRSTORE = SPLIT && I == S - 1;
     constexpr bool ERRLAST = SPLIT && FINAL;
+    constexpr int NSLOT = BeamPlan<TS, T, TAB, I>::slots;
     constexpr int NK = ERRLAST ? 1 : I;                  // derivatives evaluated per beam
     constexpr uint32_t STRIDE = 64;                      // beam-slot stride of one lane
     using Mat = StageMat<T, N>;
@@ -1035,7 +1051,8 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 // constants travel as the kernel argument (no table lookup before the first
 // loads).
 template <typename TS, typename T, int N, typename TAB, int I>
-__global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet ls)
+__global__ void __launch_bounds__(BeamShape<T>::block)
+__attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
@@ -1043,7 +1060,8 @@ __global__ void __launch_bounds__(BeamShape<T>::block) k_stage(const LaunchSet l
 }
 
 template <typename TS, typename T, int N, typename TAB, int I>
-__global__ void __launch_bounds__(BeamShape<T>::block) k_stage_one(const RunConst rc)
+__global__ void __launch_bounds__(BeamShape<T>::block)
+__attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage_one(const RunConst rc)
 {
     stage_body<TS, T, N, TAB, I>(rc, blockIdx.x);
 }
