@@ -520,11 +520,23 @@ __device__ void finish_partials_waves(const RunConst& rc, int st, const PartialR
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
         if (v >= NV) continue;
+        // partials 256..511 (launches with more than 256 workgroups): all four
+        // loads issued before the first add, then any further ones in turn
+        double t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int p = lane + 256 + 64 * k;
+            t[k] = p < nblk ? src[(size_t)v * nblk + p] : 0.0;
+        }
         double acc = r.x[i][0];
         acc += r.x[i][1];
         acc += r.x[i][2];
         acc += r.x[i][3];
-        for (int p = lane + 256; p < nblk; p += 64) acc += src[(size_t)v * nblk + p];
+        acc += t[0];
+        acc += t[1];
+        acc += t[2];
+        acc += t[3];
+        for (int p = lane + 512; p < nblk; p += 64) acc += src[(size_t)v * nblk + p];
         acc = wave_sum(acc);
         if (lane == 0) out[v] = acc;
     }
