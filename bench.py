@@ -205,6 +205,28 @@ def cpu_baseline(W, attempts):
     }
 
 
+def energy_average_timing(run, torch, amp_bytes, reps=50):
+    """The energy-averaged output (k_energy_average) on the run's current state:
+    mean duration of `reps` launches queued back to back on the run's stream
+    (device output), against the HBM roofline of its algorithmic bytes (the
+    state read once, the per-bin flux table, the output)."""
+    out = torch.empty(2 * run.na * run.n, dtype=torch.float64, device="cuda")
+    stream = run.torch_stream
+    run.enqueue_energy_average(out.data_ptr())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run.enqueue_energy_average(out.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = run.nb * 2 * run.n * amp_bytes + (run.nb // run.na) * 8 + 2 * run.na * run.n * 8
+    gbs = nbytes / us / 1e3
+    return {"us": round(us, 2), "alg_bytes": nbytes, "achieved_gbs": round(gbs, 1),
+            "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def batched(nuosc, W, torch, attempts):
     """The 64-run batched workload: every run admitted into one batch and
     advanced together; aggregate beam-steps/s over `attempts` attempts."""
@@ -298,6 +320,10 @@ def main() -> int:
     err = None
     if W.FP32_AMP in runs and W.FP64 in runs:
         err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
+    averages = {}
+    for prec, r in runs.items():
+        averages[{W.FP32_AMP: "fp32", W.FP32_AMP_FP64_MATH: "fp32math64", W.FP64: "fp64"}[prec]] = \
+            energy_average_timing(r, torch, 4 if prec != W.FP64 else 8)
     for r in runs.values():
         r.close()
 
@@ -328,6 +354,7 @@ def main() -> int:
         "fp32_vs_fp64_error": err,
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
         "control_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
+        "energy_average": averages,
     }
     if args.batched_attempts > 0:
         print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)

@@ -192,6 +192,47 @@ nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase);
 nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* phase,
                              double r_km, double dr_km);
 
+/* Energy-averaged flavor content of every trajectory: the paper's second
+ * dump mode (Section 4.2.5, the average flavor state over the energy bins of
+ * one trajectory), computed on the device from the current state:
+ *   out[s][j][a] = sum_k f_sk |psi_{s,j,k,a}|^2 / sum_k f_sk
+ * for species s (0 neutrino, 1 antineutrino), trajectory j < NA and flavor
+ * a < n, with f_sk the number flux of the species' birth flavor (nu_e or
+ * nubar_e, eq 4.1-4.2) in energy bin k; the plain mean over bins if it sums
+ * to zero.  out: host, 2*NA*n doubles, written before the call returns. */
+nuosc_status nuosc_energy_average(nuosc_handle* h, double* out);
+
+/* The same average queued on the handle's stream into device memory
+ * out_device (2*NA*n doubles, owned by the caller), without waiting: for
+ * callers that keep the result on the device and for timing. */
+nuosc_status nuosc_enqueue_energy_average(nuosc_handle* h, double* out_device);
+
+/* Snapshots: the paper's first dump mode and resume (Section 4.2.5).  A
+ * snapshot file holds this header, then the state in the host layout above
+ * (psi: n*2*NB doubles, phase: NA*n doubles), then a 64-bit FNV-1a hash of
+ * all preceding bytes; integers and doubles are little-endian as in memory:
+ *   "NUOSCSN1" (8 bytes), nuosc_snapshot_header (72 bytes), payload, hash.
+ * nuosc_snapshot_write stores the current state, radius, next step, step
+ * counters and the controller's rejection flag.  nuosc_snapshot_read restores them into a run with the same
+ * flavors, energy and angle grid and frame (as nuosc_set_state, then the
+ * counters and the flag); the precision may differ (FP32 runs round the amplitudes).
+ * nuosc_snapshot_info reads and checks a file's header and hash without a
+ * handle.  A missing, truncated or corrupted file, or a grid mismatch, gives
+ * NUOSC_E_INVALID and leaves the run unchanged. */
+typedef struct {
+    int32_t n_flavors, n_energy, n_angle;   /* as in nuosc_params */
+    int32_t precision, integrator, frame;
+    int32_t last_rejected;                  /* the last attempt was rejected (no step growth next) */
+    int32_t reserved;                       /* 0 */
+    int64_t n_beams;                        /* NB */
+    double  r_km, dr_km;                    /* radius of the state, next step */
+    int64_t accepted, rejected;             /* step counters */
+} nuosc_snapshot_header;
+
+nuosc_status nuosc_snapshot_write(nuosc_handle* h, const char* path);
+nuosc_status nuosc_snapshot_read(nuosc_handle* h, const char* path);
+nuosc_status nuosc_snapshot_info(const char* path, nuosc_snapshot_header* info);
+
 /* Step statistics (each pointer nullable). */
 nuosc_status nuosc_stats(nuosc_handle* h, int64_t* accepted, int64_t* rejected,
                          double* r_km, double* dr_km);

@@ -688,6 +688,39 @@ void or_probabilities(const or_run* R, double* p)
     }
 }
 
+/* Energy-averaged flavor content of every trajectory: the second dump mode
+ * of Section 4.2.5 (the flavor state of one trajectory averaged over its
+ * energy bins).  Reading O: each bin counts with the number flux of the
+ * beam's birth flavor in it (nu_e for neutrino beams, nubar_e for
+ * antineutrino beams; spectra eq 4.1-4.2 with the luminosities of reading C),
+ * and a species whose flux is zero gets the plain mean over bins:
+ *   out[s][j][a] = sum_k f_sk |psi_{s,j,k,a}|^2 / sum_k f_sk. */
+void or_energy_average(const or_run* R, double* out)
+{
+    const or_params* p = &R->p;
+    const double de = (p->e_max_mev - p->e_min_mev) / (double)R->ne;
+    for (int s = 0; s < 2; ++s) {
+        /* species s = 0: nu_e (index 0 of the luminosities), s = 1: nubar_e */
+        const double f2 = or_fermi_integral(2, p->eta[s]);
+        const double temp = p->mean_e_mev[s] * f2 / or_fermi_integral(3, p->eta[s]);
+        const double nrel = (p->lum_erg_s[s] / LREF_ERG_S) * (EREF_MEV / p->mean_e_mev[s]);
+        for (int j = 0; j < R->na; ++j)
+            for (int a = 0; a < R->n; ++a) {
+                double num = 0.0, den = 0.0, plain = 0.0;
+                for (int k = 0; k < R->ne; ++k) {
+                    const double e = p->e_min_mev + ((double)k + 0.5) * de;
+                    const double f = de * nrel * spectrum(e, temp, p->eta[s], f2);
+                    const cplx z = amp(R, R->y, ((int64_t)s * R->na + j) * R->ne + k, a);
+                    const double prob = z.re * z.re + z.im * z.im;
+                    num += f * prob;
+                    den += f;
+                    plain += prob;
+                }
+                out[((size_t)s * R->na + j) * R->n + a] = den != 0.0 ? num / den : plain / (double)R->ne;
+            }
+    }
+}
+
 void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr)
 {
     if (accepted) *accepted = R->nacc;

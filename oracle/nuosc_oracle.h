@@ -71,6 +71,8 @@ int  or_step_dp54(or_run* R, int64_t nattempts);        /* adaptive attempts */
 int  or_evolve_dp54(or_run* R, double r_target, int64_t max_attempts);
 
 void or_probabilities(const or_run* R, double* p);      /* |psi_1|^2 per beam */
+/* energy-averaged flavor content [2 species][na][n] (reading O) */
+void or_energy_average(const or_run* R, double* out);
 void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr);
 
 /* Tables and pieces, exposed for the tests. */

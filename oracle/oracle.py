@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
         L.or_evolve_dp54.restype = C.c_int
         L.or_evolve_dp54.argtypes = [C.c_void_p, C.c_double, C.c_int64]
         L.or_probabilities.argtypes = [C.c_void_p, _P]
+        L.or_energy_average.argtypes = [C.c_void_p, _P]
         L.or_stats.argtypes = [C.c_void_p, _I64P, _I64P, _P, _P]
         L.or_fermi_integral.restype = C.c_double
         L.or_fermi_integral.argtypes = [C.c_int, C.c_double]
@@ -239,6 +240,11 @@ class Run:
         p = np.empty(self.nb)
         lib().or_probabilities(self.h, _ptr(p))
         return p
+
+    def energy_average(self) -> np.ndarray:
+        out = np.empty((2, self.na, self.n))
+        lib().or_energy_average(self.h, _ptr(out))
+        return out
 
     def stats(self):
         a = C.c_int64()

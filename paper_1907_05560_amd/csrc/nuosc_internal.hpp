@@ -71,6 +71,7 @@ struct RunConst {
     const double* uinv64;        // [2 ne] signed 1/E per beam slot of a trajectory
     const float* uinv32;         // [2 ne] the same in FP32
     const double* wgt;           // [2 ne] g (neutrino slots), -gbar (antineutrino slots)
+    const double* flux;          // [2 ne] number flux of the slot's birth flavor in its energy bin
     double* jhist;               // [kMaxStages + 1][2 n n] packed J0, J1 per stage
     double* partial;             // [2][2 n n][nblk] per-workgroup weighted sums of the last two
                                  // beam launches (launch I uses [I & 1]), value-major
@@ -122,6 +123,8 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
 hipError_t launch_prepare(const RunList& runs, hipStream_t s);
 hipError_t launch_probabilities(const RunList& runs, double* p_dev, hipStream_t s);  // first run only
 hipError_t launch_init_state(const RunList& runs, hipStream_t s);
+// Energy-averaged flavor content [2][na][n] of the first listed run.
+hipError_t launch_energy_average(const RunList& runs, double* out_dev, hipStream_t s);
 int num_stages(int integrator);
 
 }  // namespace nuosc

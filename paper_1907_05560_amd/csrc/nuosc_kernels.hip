@@ -1158,6 +1158,92 @@ __global__ void k_probabilities(const LaunchSet ls, double* __restrict__ p)
     p[b] = re * re + im * im;
 }
 
+// Energy-averaged flavor content of every trajectory (the paper's second
+// dump mode, Section 4.2.5): for species s and trajectory j,
+//   out[s][j][a] = sum_k f_sk |psi_{s,j,k,a}|^2 / sum_k f_sk,
+// f_sk the number flux of the species' birth flavor (nu_e, nubar_e) in
+// energy bin k (eq 4.1-4.2); the plain mean over bins if it sums to zero.
+// |psi_a|^2 is the same in the co-rotating frame and for the conjugated
+// antineutrino amplitudes held on the device.  One wavefront per trajectory,
+// lanes over its beam slots; FP64 sums.  It reads the state once.
+constexpr int kAvgTraj = 4;  // trajectories (wavefronts) per workgroup
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * kAvgTraj) k_energy_average(const LaunchSet ls, double* __restrict__ out)
+{
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    const int lane = threadIdx.x & 63;
+    const int j = blk * kAvgTraj + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (j >= rc.na) return;
+    const uint32_t ne = (uint32_t)rc.ne;
+    const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
+    const uint32_t base0 = (uint32_t)j * ne;
+    const T* src = reinterpret_cast<const T*>(rc.psi[rc.ctrl[1].cur]);
+    global<const T>* __restrict__ q0 = uniform_global(src);
+    const size_t ld = (size_t)rc.nb_pad;
+    // weighted sums, weight sums, plain sums and bin counts per species
+    double num[2][N], pm[2][N], den[2], cnt[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        den[s] = cnt[s] = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) num[s][a] = pm[s][a] = 0.0;
+    }
+    // four beams of each lane per round: all their loads issued first
+    constexpr int U = 4;
+    for (uint32_t t0 = lane; t0 < 2u * ne; t0 += 64 * U) {
+        T y[U][2 * N];
+        double g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t t = t0 + 64 * u;
+            const uint32_t off = t + base0 + (t >= ne ? delta : 0u);
+            g[u] = 0.0;
+            if (t < 2u * ne) {
+                g[u] = rc.flux[t];
+#pragma unroll
+                for (int q = 0; q < 2 * N; ++q) y[u][q] = *elem(q0 + q * ld, off);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t t = t0 + 64 * u;
+            if (t >= 2u * ne) break;
+            const bool nub = t >= ne;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const double re = (double)y[u][2 * a], im = (double)y[u][2 * a + 1];
+                const double v = re * re + im * im;
+                num[0][a] += nub ? 0.0 : g[u] * v;
+                num[1][a] += nub ? g[u] * v : 0.0;
+                pm[0][a] += nub ? 0.0 : v;
+                pm[1][a] += nub ? v : 0.0;
+            }
+            den[0] += nub ? 0.0 : g[u];
+            den[1] += nub ? g[u] : 0.0;
+            cnt[0] += nub ? 0.0 : 1.0;
+            cnt[1] += nub ? 1.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        den[s] = wave_sum(den[s]);
+        cnt[s] = wave_sum(cnt[s]);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            num[s][a] = wave_sum(num[s][a]);
+            pm[s][a] = wave_sum(pm[s][a]);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+                out[((size_t)s * rc.na + j) * N + a] = den[s] != 0.0 ? num[s][a] / den[s] : pm[s][a] / cnt[s];
+    }
+}
+
 template <typename T, int N>
 __global__ void k_init(const LaunchSet ls)
 {
@@ -1350,6 +1436,22 @@ hipError_t launch_probabilities(const RunList& runs, double* p, hipStream_t s)
     return for_launch_sets(one, [](const RunConst& rc) { return (long long)((rc.nb + 255) / 256); },
                            [&](const LaunchSet& ls, unsigned grid) {
                                hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, ls, p);
+                               return hipGetLastError();
+                           });
+}
+
+hipError_t launch_energy_average(const RunList& runs, double* out, hipStream_t s)
+{
+    if (runs.count < 1) return hipSuccess;
+    const RunList one{runs.runs_dev, 1, runs.slot, runs.rc};
+    const RunConst& r0 = *runs.rc[0];
+    using AFn = void (*)(const LaunchSet, double*);
+    AFn k;
+    if (r0.precision == 0) k = r0.n == 2 ? (AFn)&k_energy_average<double, 2> : (AFn)&k_energy_average<double, 3>;
+    else k = r0.n == 2 ? (AFn)&k_energy_average<float, 2> : (AFn)&k_energy_average<float, 3>;
+    return for_launch_sets(one, [](const RunConst& rc) { return (long long)((rc.na + kAvgTraj - 1) / kAvgTraj); },
+                           [&](const LaunchSet& ls, unsigned grid) {
+                               hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kAvgTraj), 0, s, ls, out);
                                return hipGetLastError();
                            });
 }

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -96,6 +97,7 @@ double fermi_integral(int k, double eta)
 struct Tables {
     std::vector<double> inv_e, g, gbar;
     std::vector<double> uinv64, wgt;
+    std::vector<double> flux;   // number flux of the slot's birth flavor (nu_e or nubar_e) in its bin
     std::vector<float> uinv32;
     double vac[3][3][2];
 };
@@ -109,6 +111,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
     t.uinv64.resize(2 * ne);
     t.uinv32.resize(2 * ne);
     t.wgt.resize(2 * ne);
+    t.flux.resize(2 * ne);
     double temp[4], f2[4], nrel[4];
     for (int s = 0; s < 4; ++s) {
         f2[s] = fermi_integral(2, p.eta[s]);
@@ -126,6 +129,8 @@ bool build_tables(const nuosc_params& p, Tables& t)
         // to (n_e - n_x) rho_e up to the identity, which a traceless H drops.
         t.g[k] = de * (nrel[0] * spectrum(0, e) - nrel[2] * spectrum(2, e));
         t.gbar[k] = de * (nrel[1] * spectrum(1, e) - nrel[3] * spectrum(3, e));
+        t.flux[k] = de * nrel[0] * spectrum(0, e);
+        t.flux[ne + k] = de * nrel[1] * spectrum(1, e);
     }
     // Vacuum Hamiltonian H_vac(E) = vac / E, traceless, in km^-1 (E in MeV).
     const double kappa = 1.0 / (2.0e6 * kHbarcEvKm);
@@ -165,13 +170,15 @@ bool build_tables(const nuosc_params& p, Tables& t)
     }
     for (int i = 0; i < 2 * ne; ++i) t.uinv32[i] = (float)t.uinv64[i];
     for (int k = 0; k < ne; ++k)
-        if (!std::isfinite(t.g[k]) || !std::isfinite(t.gbar[k])) return false;
+        if (!std::isfinite(t.g[k]) || !std::isfinite(t.gbar[k]) || !std::isfinite(t.flux[k]) ||
+            !std::isfinite(t.flux[ne + k]))
+            return false;
     return true;
 }
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, mat, geo, ctrl, prob, rconst, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, flux, mat, geo, ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk;
 };
@@ -234,6 +241,7 @@ Layout make_layout(const nuosc_params& p)
     L.uinv64 = take((size_t)2 * p.n_energy * 8);
     L.uinv32 = take((size_t)2 * p.n_energy * 4);
     L.wgt = take((size_t)2 * p.n_energy * 8);
+    L.flux = take((size_t)2 * p.n_energy * 8);
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * 2 * n * n * 8);
     L.partial = take((size_t)2 * 2 * n * n * L.nblk * 8);  // two launches' partials (alternating)
     L.errpart = take((size_t)L.nblk * 8);
@@ -243,6 +251,7 @@ Layout make_layout(const nuosc_params& p)
     L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
     L.ctrl = take(2 * sizeof(Control));
     L.prob = take((size_t)L.nb * 8);
+    L.eavg = take((size_t)2 * L.na * n * 8);
     L.rconst = take(sizeof(RunConst));
     L.total = off;
     return L;
@@ -259,6 +268,7 @@ struct RunState {
     RunConst* runs_dev = nullptr;  // device array the launches index
     int slot = 0;                // index of this run in runs_dev
     double* prob = nullptr;      // device [nb]
+    double* eavg = nullptr;      // device [2][na][n]
     Control hctl{};              // host copy of ctrl[1]
 };
 
@@ -374,6 +384,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.uinv64 = (const double*)(base + L.uinv64);
     rc.uinv32 = (const float*)(base + L.uinv32);
     rc.wgt = (const double*)(base + L.wgt);
+    rc.flux = (const double*)(base + L.flux);
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
@@ -382,6 +393,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.geo = (nuosc::TrajGeo*)(base + L.geo);
     rc.ctrl = (Control*)(base + L.ctrl);
     r.prob = (double*)(base + L.prob);
+    r.eavg = (double*)(base + L.eavg);
 
     Control& c = r.hctl;
     std::memset(&c, 0, sizeof(c));
@@ -397,6 +409,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     HIP_CHECK(hipMemcpyAsync((void*)rc.uinv64, tab.uinv64.data(), tab.uinv64.size() * 8, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync((void*)rc.uinv32, tab.uinv32.data(), tab.uinv32.size() * 4, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync((void*)rc.wgt, tab.wgt.data(), tab.wgt.size() * 8, hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemcpyAsync((void*)rc.flux, tab.flux.data(), tab.flux.size() * 8, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * 2 * rc.n * rc.n * 8, s), err);
     HIP_CHECK(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync(runs_dev + slot, &rc, sizeof(RunConst), hipMemcpyHostToDevice, s), err);
@@ -725,6 +738,26 @@ nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out)
     return checked(h, probabilities_of(h->run, p_out, h->stream, h->err), h->err);
 }
 
+nuosc_status nuosc_energy_average(nuosc_handle* h, double* out)
+{
+    if (!h || !out) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    RunState& r = h->run;
+    OneRun one(r);
+    HIP_CHECK(nuosc::launch_energy_average(one.list, r.eavg, h->stream), h->err);
+    HIP_CHECK(hipMemcpyAsync(out, r.eavg, (size_t)2 * r.rc.na * r.rc.n * 8, hipMemcpyDeviceToHost, h->stream),
+              h->err);
+    HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_enqueue_energy_average(nuosc_handle* h, double* out_device)
+{
+    if (!h || !out_device) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    OneRun one(h->run);
+    HIP_CHECK(nuosc::launch_energy_average(one.list, out_device, h->stream), h->err);
+    return NUOSC_OK;
+}
+
 nuosc_status nuosc_get_state(nuosc_handle* h, double* psi, double* phase)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
@@ -803,6 +836,150 @@ nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* p
     if (st != NUOSC_OK) return st;
     HIP_CHECK(hipStreamSynchronize(h->stream), h->err);
     return NUOSC_OK;
+}
+
+// ---------------------------------------------------------------- snapshots
+// File layout (little-endian): the 8-byte tag, the header below, psi
+// [n][2][nb] and phase [na][n] as FP64 in the host state layout, then a
+// 64-bit FNV-1a hash of everything before it.
+namespace {
+constexpr char kSnapTag[8] = {'N', 'U', 'O', 'S', 'C', 'S', 'N', '1'};
+
+uint64_t fnv1a(const void* data, size_t bytes, uint64_t h)
+{
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+constexpr uint64_t kFnvBasis = 14695981039346656037ull;
+
+bool read_exact(std::FILE* f, void* dst, size_t bytes, uint64_t& hash)
+{
+    if (std::fread(dst, 1, bytes, f) != bytes) return false;
+    hash = fnv1a(dst, bytes, hash);
+    return true;
+}
+
+// Reads and checks the tag and header; on success the file is positioned at
+// psi and hash covers everything read.
+const char* read_snapshot_header(std::FILE* f, nuosc_snapshot_header& info, uint64_t& hash)
+{
+    char tag[8];
+    hash = kFnvBasis;
+    if (!read_exact(f, tag, sizeof(tag), hash) || std::memcmp(tag, kSnapTag, sizeof(tag)) != 0)
+        return "not a snapshot file";
+    if (!read_exact(f, &info, sizeof(info), hash)) return "truncated snapshot header";
+    if ((info.n_flavors != 2 && info.n_flavors != 3) || info.n_energy < 1 || info.n_angle < 0 ||
+        info.n_beams != 2 * (int64_t)info.n_energy * std::max(info.n_angle, 1) || info.n_beams > ((int64_t)1 << 40) ||
+        (info.last_rejected != 0 && info.last_rejected != 1) || info.reserved != 0)
+        return "inconsistent snapshot header";
+    return nullptr;
+}
+}  // namespace
+
+nuosc_status nuosc_snapshot_info(const char* path, nuosc_snapshot_header* info)
+{
+    if (!path || !info) return fail(nullptr, NUOSC_E_INVALID, "NULL argument");
+    std::FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(nullptr, NUOSC_E_INVALID, std::string("cannot open ") + path);
+    uint64_t hash;
+    nuosc_snapshot_header hdr{};
+    const char* e = read_snapshot_header(f, hdr, hash);
+    if (!e) {
+        // payload and hash
+        const int64_t na = std::max(hdr.n_angle, 1);
+        const size_t values = (size_t)hdr.n_flavors * 2 * hdr.n_beams + (size_t)na * hdr.n_flavors;
+        std::vector<double> buf(1 << 16);
+        size_t left = values;
+        while (left && !e) {
+            const size_t k = std::min(left, buf.size());
+            if (!read_exact(f, buf.data(), k * 8, hash)) e = "truncated snapshot payload";
+            left -= k;
+        }
+        uint64_t stored = 0;
+        if (!e && std::fread(&stored, 8, 1, f) != 1) e = "truncated snapshot payload";
+        if (!e && stored != hash) e = "snapshot checksum mismatch";
+    }
+    std::fclose(f);
+    if (e) return fail(nullptr, NUOSC_E_INVALID, e);
+    *info = hdr;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_snapshot_write(nuosc_handle* h, const char* path)
+{
+    if (!h || !path) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    const RunConst& rc = h->run.rc;
+    const nuosc_params& P = h->run.p;
+    std::vector<double> psi((size_t)rc.n * 2 * rc.nb), phase((size_t)rc.na * rc.n);
+    nuosc_status st = nuosc_get_state(h, psi.data(), phase.data());
+    if (st != NUOSC_OK) return st;
+    const Control& c = h->run.hctl;
+    nuosc_snapshot_header info{};
+    info.n_flavors = rc.n;
+    info.n_energy = rc.ne;
+    info.n_angle = P.n_angle;
+    info.precision = rc.precision;
+    info.integrator = rc.integrator;
+    info.frame = rc.frame;
+    info.last_rejected = c.last_rejected;
+    info.n_beams = rc.nb;
+    info.r_km = c.r;
+    info.dr_km = c.h_prop;
+    info.accepted = c.nacc;
+    info.rejected = c.nrej;
+    std::FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(h, NUOSC_E_INVALID, std::string("cannot create ") + path);
+    uint64_t hash = kFnvBasis;
+    auto put = [&](const void* d, size_t bytes) {
+        hash = fnv1a(d, bytes, hash);
+        return std::fwrite(d, 1, bytes, f) == bytes;
+    };
+    bool ok = put(kSnapTag, sizeof(kSnapTag)) && put(&info, sizeof(info)) && put(psi.data(), psi.size() * 8) &&
+              put(phase.data(), phase.size() * 8);
+    ok = ok && std::fwrite(&hash, 8, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(h, NUOSC_E_INVALID, std::string("cannot write ") + path);
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_snapshot_read(nuosc_handle* h, const char* path)
+{
+    if (!h || !path) return fail(h, NUOSC_E_INVALID, "NULL argument");
+    const RunConst& rc = h->run.rc;
+    const nuosc_params& P = h->run.p;
+    std::FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(h, NUOSC_E_INVALID, std::string("cannot open ") + path);
+    uint64_t hash;
+    nuosc_snapshot_header info{};
+    const char* e = read_snapshot_header(f, info, hash);
+    if (!e && (info.n_flavors != rc.n || info.n_energy != rc.ne || info.n_angle != P.n_angle ||
+               info.frame != rc.frame))
+        e = "snapshot grid, flavors or frame differ from the run's";
+    std::vector<double> psi, phase;
+    if (!e) {
+        psi.resize((size_t)rc.n * 2 * rc.nb);
+        phase.resize((size_t)rc.na * rc.n);
+        uint64_t stored = 0;
+        if (!read_exact(f, psi.data(), psi.size() * 8, hash) || !read_exact(f, phase.data(), phase.size() * 8, hash) ||
+            std::fread(&stored, 8, 1, f) != 1)
+            e = "truncated snapshot payload";
+        else if (stored != hash)
+            e = "snapshot checksum mismatch";
+    }
+    std::fclose(f);
+    if (e) return fail(h, NUOSC_E_INVALID, e);
+    nuosc_status st = nuosc_set_state(h, psi.data(), phase.data(), info.r_km, info.dr_km);
+    if (st != NUOSC_OK) return st;
+    Control& c = h->run.hctl;
+    c.nacc = info.accepted;
+    c.nrej = info.rejected;
+    c.attempts = info.accepted + info.rejected;
+    c.last_rejected = info.last_rejected != 0;
+    return hwrite(h);
 }
 
 nuosc_status nuosc_stats(nuosc_handle* h, int64_t* accepted, int64_t* rejected, double* r_km, double* dr_km)

@@ -28,7 +28,9 @@ EXPORTS = (
     "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
     "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_timing_enable",
     "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
-    "nuosc_get_state", "nuosc_set_state", "nuosc_stats", "nuosc_num_beams",
+    "nuosc_get_state", "nuosc_set_state", "nuosc_energy_average", "nuosc_enqueue_energy_average",
+    "nuosc_snapshot_write",
+    "nuosc_snapshot_read", "nuosc_snapshot_info", "nuosc_stats", "nuosc_num_beams",
     "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
     "nuosc_batch_create", "nuosc_batch_admit", "nuosc_batch_step", "nuosc_batch_query",
     "nuosc_batch_num_beams", "nuosc_batch_retire", "nuosc_batch_occupied", "nuosc_batch_last_error",
@@ -40,6 +42,28 @@ class NuoscError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"nuosc {STATUS_NAMES.get(status, status)}: {message}")
         self.status = status
+
+
+class SnapshotHeader(C.Structure):
+    """nuosc_snapshot_header (72 bytes, no padding)."""
+    _fields_ = [
+        ("n_flavors", C.c_int32),
+        ("n_energy", C.c_int32),
+        ("n_angle", C.c_int32),
+        ("precision", C.c_int32),
+        ("integrator", C.c_int32),
+        ("frame", C.c_int32),
+        ("last_rejected", C.c_int32),
+        ("reserved", C.c_int32),
+        ("n_beams", C.c_int64),
+        ("r_km", C.c_double),
+        ("dr_km", C.c_double),
+        ("accepted", C.c_int64),
+        ("rejected", C.c_int64),
+    ]
+
+
+SNAPSHOT_TAG = b"NUOSCSN1"
 
 
 class Params(C.Structure):
@@ -121,6 +145,16 @@ def lib() -> C.CDLL:
     L.nuosc_get_state.restype = C.c_int
     L.nuosc_set_state.argtypes = [C.c_void_p, _D, _D, C.c_double, C.c_double]
     L.nuosc_set_state.restype = C.c_int
+    L.nuosc_energy_average.argtypes = [C.c_void_p, _D]
+    L.nuosc_energy_average.restype = C.c_int
+    L.nuosc_enqueue_energy_average.argtypes = [C.c_void_p, C.c_void_p]
+    L.nuosc_enqueue_energy_average.restype = C.c_int
+    L.nuosc_snapshot_write.argtypes = [C.c_void_p, C.c_char_p]
+    L.nuosc_snapshot_write.restype = C.c_int
+    L.nuosc_snapshot_read.argtypes = [C.c_void_p, C.c_char_p]
+    L.nuosc_snapshot_read.restype = C.c_int
+    L.nuosc_snapshot_info.argtypes = [C.c_char_p, C.POINTER(SnapshotHeader)]
+    L.nuosc_snapshot_info.restype = C.c_int
     L.nuosc_stats.argtypes = [C.c_void_p, _I64, _I64, _D, _D]
     L.nuosc_stats.restype = C.c_int
     L.nuosc_num_beams.argtypes = [C.c_void_p]
@@ -153,6 +187,15 @@ def lib() -> C.CDLL:
     L.nuosc_batch_destroy.restype = None
     _lib = L
     return L
+
+
+def snapshot_info(path: str) -> Dict:
+    """Header of a snapshot file (checked, including its hash)."""
+    h = SnapshotHeader()
+    st = lib().nuosc_snapshot_info(os.fsencode(path), C.byref(h))
+    if st != OK:
+        raise NuoscError(st, (lib().nuosc_last_error(None) or b"").decode())
+    return {name: getattr(h, name) for name, _ in SnapshotHeader._fields_}
 
 
 def params_from(w: Dict) -> Params:
@@ -296,6 +339,22 @@ class Run:
         p = np.empty(self.nb)
         self._check(lib().nuosc_probabilities(self.h, _ptr(p)))
         return p
+
+    def energy_average(self) -> np.ndarray:
+        """[2 species][NA][n] energy-averaged flavor probabilities."""
+        out = np.empty((2, self.na, self.n))
+        self._check(lib().nuosc_energy_average(self.h, _ptr(out)))
+        return out
+
+    def enqueue_energy_average(self, out_device_ptr: int) -> None:
+        """Queue the average into device memory (2*NA*n doubles) on the run's stream."""
+        self._check(lib().nuosc_enqueue_energy_average(self.h, C.c_void_p(out_device_ptr)))
+
+    def snapshot_write(self, path: str) -> None:
+        self._check(lib().nuosc_snapshot_write(self.h, os.fsencode(path)))
+
+    def snapshot_read(self, path: str) -> None:
+        self._check(lib().nuosc_snapshot_read(self.h, os.fsencode(path)))
 
     def get_state(self):
         psi = np.empty((self.n, 2, self.nb))
