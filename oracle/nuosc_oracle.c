@@ -59,6 +59,7 @@ double or_vacuum_coefficient(void) { return 1.0 / (2.0e6 * HBARC_EV_KM); }
 
 /* Reference number luminosity used to normalise the beam weights (reading C):
  * 1e51 erg/s carried at a mean energy of 11 MeV. */
+static const double OR_PI = 3.14159265358979323846;
 static const double LREF_ERG_S = 1e51;
 static const double EREF_MEV = 11.0;
 
@@ -67,7 +68,9 @@ struct or_run {
     or_params p;
     int n;          /* flavors */
     int ne;         /* energy bins */
-    int na;         /* trajectories: N_A, or 1 for the single-angle model */
+    int na;         /* trajectories: N_A (x N_phi azimuth bins), or 1 for the single-angle model */
+    int nth;        /* emission (zenith) angle bins */
+    int np;         /* azimuth bins per emission angle (1: the bulb model) */
     int ma;         /* 1 = multi-angle bulb model, 0 = single angle */
     int64_t nb;     /* beams = 2 * ne * na */
     int64_t ylen;   /* 2*n*nb amplitude reals followed by n*na phases */
@@ -82,6 +85,7 @@ struct or_run {
     cplx* S;        /* [na][n][n] per-trajectory lab-frame sums */
     double* c;      /* [na] */
     double* w;      /* [na] */
+    double* phi;    /* [na] azimuth angle of each trajectory */
     /* stepping */
     double r, h;
     int64_t istep;  /* RK4 steps taken */
@@ -161,11 +165,13 @@ static void geometry(const or_run* R, double r, double* c, double* w)
     }
     const double x = (Rn / r) * (Rn / r);
     const double y = (r - Rn) * (r + Rn) / (r * r);  /* 1 - (R/r)^2 */
-    const double du = 1.0 / (double)R->na;
+    const double du = 1.0 / (double)R->nth;
     for (int j = 0; j < R->na; ++j) {
-        double u = ((double)j + 0.5) * du;          /* reading A */
+        /* trajectory j: emission angle bin j / N_phi, azimuth bin j % N_phi;
+         * the azimuth bins share the emission-angle weight equally */
+        double u = ((double)(j / R->np) + 0.5) * du; /* reading A */
         c[j] = sqrt(u * u + (1.0 - u * u) * y);
-        w[j] = x * u * du / c[j];
+        w[j] = x * u * du / c[j] / (double)R->np;
     }
 }
 
@@ -248,14 +254,17 @@ void or_tables(const or_run* R, double* energy, double* g, double* gbar, double*
 /* ------------------------------------------------------------ create / destroy */
 or_run* or_create(const or_params* p)
 {
-    if (!p || (p->n_flavors != 2 && p->n_flavors != 3) || p->n_energy < 1 || p->n_angle < 0)
+    if (!p || (p->n_flavors != 2 && p->n_flavors != 3) || p->n_energy < 1 || p->n_angle < 0 ||
+        p->n_azimuth < 0 || (p->n_azimuth > 1 && p->n_angle < 1))
         return NULL;
     or_run* R = (or_run*)calloc(1, sizeof(or_run));
     R->p = *p;
     R->n = p->n_flavors;
     R->ne = p->n_energy;
     R->ma = p->n_angle > 0;
-    R->na = R->ma ? p->n_angle : 1;
+    R->nth = R->ma ? p->n_angle : 1;
+    R->np = p->n_azimuth > 1 ? p->n_azimuth : 1;
+    R->na = R->nth * R->np;
     R->nb = 2 * (int64_t)R->ne * R->na;
     R->ylen = 2 * (int64_t)R->n * R->nb + (int64_t)R->n * R->na;
     const int n = R->n;
@@ -270,6 +279,10 @@ or_run* or_create(const or_params* p)
     R->S = (cplx*)calloc((size_t)R->na * n * n, sizeof(cplx));
     R->c = (double*)calloc(R->na, sizeof(double));
     R->w = (double*)calloc(R->na, sizeof(double));
+    R->phi = (double*)calloc(R->na, sizeof(double));
+    /* Reading P: azimuth bins at the midpoints of [0, 2 pi). */
+    if (R->np > 1)
+        for (int j = 0; j < R->na; ++j) R->phi[j] = 2.0 * OR_PI * ((double)(j % R->np) + 0.5) / (double)R->np;
 
     /* Energy bins at midpoints of [E0, E1]. */
     const double de = (p->e_max_mev - p->e_min_mev) / (double)R->ne;
@@ -311,7 +324,7 @@ void or_destroy(or_run* R)
     if (!R) return;
     free(R->energy); free(R->g); free(R->gbar); free(R->hvac); free(R->y);
     for (int i = 0; i < 7; ++i) free(R->k[i]);
-    free(R->ytmp); free(R->S); free(R->c); free(R->w);
+    free(R->ytmp); free(R->S); free(R->c); free(R->w); free(R->phi);
     free(R);
 }
 
@@ -368,7 +381,7 @@ static cplx amp(const or_run* R, const double* y, int64_t b, int a)
  *   J0 = sum_j w_j S_j  and  J1 = sum_j w_j c_j S_j,
  * so that H_nunu on trajectory i is mu0 * traceless(J0 - c_i J1).
  * Single angle: J0 = D(r/R) S_0 and J1 = 0 (c = 1 for the radial ray). */
-static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cplx* J1)
+static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cplx* J1, cplx* J2, cplx* J3)
 {
     const int n = R->n, ne = R->ne, na = R->na;
     const double* phase = y + 2 * (int64_t)n * R->nb;
@@ -398,7 +411,12 @@ static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cpl
                 R->S[(j * n + a) * n + c] = c_scale(c_mul(c_expi(-dphi), acc[a * n + c]), 2.0);
             }
     }
-    for (int i = 0; i < n * n; ++i) { J0[i] = c_make(0, 0); J1[i] = c_make(0, 0); }
+    for (int i = 0; i < n * n; ++i) {
+        J0[i] = c_make(0, 0);
+        J1[i] = c_make(0, 0);
+        J2[i] = c_make(0, 0);
+        J3[i] = c_make(0, 0);
+    }
     if (!R->ma) {
         for (int i = 0; i < n * n; ++i) J0[i] = c_scale(R->S[i], R->w[0]);
         return;
@@ -408,13 +426,32 @@ static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cpl
             J0[i] = c_add(J0[i], c_scale(R->S[j * n * n + i], R->w[j]));
             J1[i] = c_add(J1[i], c_scale(R->S[j * n * n + i], R->w[j] * R->c[j]));
         }
+    if (R->np == 1) return;
+    /* Extended bulb model (eq 3.18): 1 - cos(gamma) = 1 - c c' - s s' cos(phi - phi')
+     * = 1 - c c' - s cos(phi) s' cos(phi') - s sin(phi) s' sin(phi'), so two more
+     * moments carry the azimuth dependence; s = sin(theta) = sqrt(1 - c^2). */
+    for (int j = 0; j < na; ++j) {
+        const double s = sqrt((1.0 - R->c[j]) * (1.0 + R->c[j]));
+        for (int i = 0; i < n * n; ++i) {
+            J2[i] = c_add(J2[i], c_scale(R->S[j * n * n + i], R->w[j] * s * cos(R->phi[j])));
+            J3[i] = c_add(J3[i], c_scale(R->S[j * n * n + i], R->w[j] * s * sin(R->phi[j])));
+        }
+    }
 }
 
-/* H_nunu = mu0 * traceless(J0 - c J1)  (readings E, G). */
-static void collective(const or_run* R, const cplx* J0, const cplx* J1, double c, cplx* C)
+/* H_nunu of trajectory j = mu0 * traceless(J0 - c J1)  (readings E, G); the
+ * extended model subtracts s cos(phi) J2 + s sin(phi) J3 as well (eq 3.18). */
+static void collective(const or_run* R, const cplx* J0, const cplx* J1, const cplx* J2, const cplx* J3, int j,
+                       cplx* C)
 {
     const int n = R->n;
+    const double c = R->c[j];
     for (int i = 0; i < n * n; ++i) C[i] = c_sub(J0[i], c_scale(J1[i], c));
+    if (R->np > 1) {
+        const double s = sqrt((1.0 - c) * (1.0 + c));
+        const double sc = s * cos(R->phi[j]), ss = s * sin(R->phi[j]);
+        for (int i = 0; i < n * n; ++i) C[i] = c_sub(c_sub(C[i], c_scale(J2[i], sc)), c_scale(J3[i], ss));
+    }
     double tr = 0.0;
     for (int a = 0; a < n; ++a) tr += C[a * n + a].re;
     for (int a = 0; a < n; ++a) C[a * n + a].re -= tr / (double)n;
@@ -445,14 +482,14 @@ static void rhs(const or_run* R, double r, const double* y, double* dy)
     const int corot = (R->p.frame == 0);
     const double* phase = y + 2 * (int64_t)n * R->nb;
     double* dphase = dy + 2 * (int64_t)n * R->nb;
-    cplx J0[9], J1[9];
-    moments_at(R, r, y, J0, J1); /* also leaves c_j, w_j in R->c, R->w */
+    cplx J0[9], J1[9], J2[9], J3[9];
+    moments_at(R, r, y, J0, J1, J2, J3); /* also leaves c_j, w_j in R->c, R->w */
     const double lam = matter_potential(R, r);
 
     for (int j = 0; j < na; ++j) {
         const double cj = R->c[j];
         cplx C[9], Hm[9];
-        collective(R, J0, J1, cj, C);
+        collective(R, J0, J1, J2, J3, j, C);
         for (int i = 0; i < n * n; ++i) Hm[i] = c_make(0, 0);
         for (int a = 0; a < n; ++a) Hm[a * n + a] = c_make(lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / (double)n), 0.0);
         double G[3] = {0, 0, 0};
@@ -505,20 +542,33 @@ static void write_moments(const cplx* J, double* out, int n)
 
 void or_moments(const or_run* R, double* j0, double* j1)
 {
-    cplx J0[9], J1[9];
-    moments_at(R, R->r, R->y, J0, J1);
+    cplx J0[9], J1[9], J2[9], J3[9];
+    moments_at(R, R->r, R->y, J0, J1, J2, J3);
     if (j0) write_moments(J0, j0, R->n);
     if (j1) write_moments(J1, j1, R->n);
+}
+
+void or_moments_azimuth(const or_run* R, double* j2, double* j3)
+{
+    cplx J0[9], J1[9], J2[9], J3[9];
+    moments_at(R, R->r, R->y, J0, J1, J2, J3);
+    if (j2) write_moments(J2, j2, R->n);
+    if (j3) write_moments(J3, j3, R->n);
+}
+
+void or_azimuth(const or_run* R, double* phi)
+{
+    for (int j = 0; j < R->na; ++j) phi[j] = R->phi[j];
 }
 
 void or_collective(const or_run* R, double* out)
 {
     const int n = R->n;
-    cplx J0[9], J1[9];
-    moments_at(R, R->r, R->y, J0, J1);
+    cplx J0[9], J1[9], J2[9], J3[9];
+    moments_at(R, R->r, R->y, J0, J1, J2, J3);
     for (int j = 0; j < R->na; ++j) {
         cplx C[9];
-        collective(R, J0, J1, R->c[j], C);
+        collective(R, J0, J1, J2, J3, j, C);
         write_moments(C, out + (size_t)j * n * n * 2, n);
     }
 }

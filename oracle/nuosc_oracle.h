@@ -38,6 +38,8 @@ typedef struct {
     int32_t frame;          /* 0 co-rotating, 1 lab */
     int32_t renormalize;    /* 1: rescale every beam to unit norm after each
                                accepted step (the FP32-amplitude scheme) */
+    int32_t n_azimuth;      /* azimuth bins per emission angle: the extended
+                               bulb model (eq 3.18); 0 or 1: the bulb model */
 } or_params;
 
 typedef struct or_run or_run;
@@ -59,6 +61,10 @@ int  or_set_state(or_run* R, const double* psi, const double* phase, double r_km
 /* J0 and J1 (n*n complex each, row-major, interleaved re/im) of the current
  * state at the current radius. */
 void or_moments(const or_run* R, double* j0, double* j1);
+/* the extended model's azimuth moments J2 = sum w s cos(phi) S, J3 = sum w s sin(phi) S */
+void or_moments_azimuth(const or_run* R, double* j2, double* j3);
+/* azimuth angle phi_j of every trajectory (0 for the bulb model) */
+void or_azimuth(const or_run* R, double* phi);
 /* Collective Hamiltonian H_nunu for every trajectory in the lab frame for the
  * current state: out[j][a][b] complex (interleaved). */
 void or_collective(const or_run* R, double* out);

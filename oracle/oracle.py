@@ -64,6 +64,7 @@ class _Params(C.Structure):
         ("safety", C.c_double),
         ("frame", C.c_int32),
         ("renormalize", C.c_int32),
+        ("n_azimuth", C.c_int32),
     ]
 
 
@@ -101,6 +102,8 @@ def lib() -> C.CDLL:
         L.or_evolve_dp54.argtypes = [C.c_void_p, C.c_double, C.c_int64]
         L.or_probabilities.argtypes = [C.c_void_p, _P]
         L.or_energy_average.argtypes = [C.c_void_p, _P]
+        L.or_moments_azimuth.argtypes = [C.c_void_p, _P, _P]
+        L.or_azimuth.argtypes = [C.c_void_p, _P]
         L.or_stats.argtypes = [C.c_void_p, _I64P, _I64P, _P, _P]
         L.or_fermi_integral.restype = C.c_double
         L.or_fermi_integral.argtypes = [C.c_int, C.c_double]
@@ -190,6 +193,19 @@ class Run:
         j1 = np.empty(n * n * 2)
         lib().or_moments(self.h, _ptr(j0), _ptr(j1))
         return (j0[0::2] + 1j * j0[1::2]).reshape(n, n), (j1[0::2] + 1j * j1[1::2]).reshape(n, n)
+
+    def moments_azimuth(self):
+        """J2, J3 of the extended bulb model (zero for the bulb model)."""
+        n = self.n
+        j2 = np.empty(n * n * 2)
+        j3 = np.empty(n * n * 2)
+        lib().or_moments_azimuth(self.h, _ptr(j2), _ptr(j3))
+        return (j2[0::2] + 1j * j2[1::2]).reshape(n, n), (j3[0::2] + 1j * j3[1::2]).reshape(n, n)
+
+    def azimuth(self) -> np.ndarray:
+        phi = np.empty(self.na)
+        lib().or_azimuth(self.h, _ptr(phi))
+        return phi
 
     def collective(self) -> np.ndarray:
         n = self.n
