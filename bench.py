@@ -227,6 +227,35 @@ def energy_average_timing(run, torch, amp_bytes, reps=50):
             "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
+def extended(nuosc, W, torch, precision, attempts, warmup=5):
+    """The extended bulb model (eq 3.18: 100 energies x 100 emission angles x
+    32 azimuth bins x 2 species = 640k beams, four angle moments), started
+    from the seeded azimuthally perturbed state: beam-steps/s over `attempts`
+    attempts after `warmup`."""
+    w = W.extended_bulb_3f(100, 100, 32, precision)
+    run = nuosc.Run.with_torch(w)
+    try:
+        psi = W.azimuth_perturbed_states(3, run.nb, run.na, seed=W.SEED_BASE + 5)
+        run.set_state(psi, None, w["r_start_km"])
+        run.step(warmup)
+        s0 = run.stats()
+        stream = run.torch_stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run.enqueue_steps(attempts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        s1 = run.stats()
+        acc = s1["accepted"] - s0["accepted"]
+        return {"workload": "3-flavor extended bulb model, 100 E x 100 angles x 32 azimuth bins x 2 species",
+                "beams": run.nb, "attempts": attempts, "accepted": acc, "ms_per_step": ms / attempts,
+                "value": run.nb * acc / (ms / 1e3), "unit": "beam-steps/s"}
+    finally:
+        run.close()
+
+
 def batched(nuosc, W, torch, attempts):
     """The 64-run batched workload: every run admitted into one batch and
     advanced together; aggregate beam-steps/s over `attempts` attempts."""
@@ -279,6 +308,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-attempts", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extended-attempts", type=int, default=50,
+                    help="attempts of the extended bulb model workload (0: skip)")
     ap.add_argument("--forms", default="fp32,fp32math64,fp64",
                     help="precision forms to run (the first is the headline value)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -356,6 +387,15 @@ def main() -> int:
         "control_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
         "energy_average": averages,
     }
+    if args.extended_attempts > 0:
+        line["extended"] = {}
+        for name, prec in (("fp32", W.FP32_AMP), ("fp64", W.FP64)):
+            print(f"bench: extended bulb model {name} ({args.extended_attempts} attempts)", file=sys.stderr,
+                  flush=True)
+            ex = extended(nuosc, W, torch, prec, args.extended_attempts)
+            line["extended"][name] = ex
+            print(f"bench: extended {name}: {ex['ms_per_step']:.3f} ms/step, {ex['value']:.3e} beam-steps/s",
+                  file=sys.stderr, flush=True)
     if args.batched_attempts > 0:
         print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)
         line["batched"] = batched(nuosc, W, torch, args.batched_attempts)

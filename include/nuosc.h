@@ -22,10 +22,13 @@
  * Beams.  A beam is (species s, trajectory j, energy bin k) with s = 0 for
  * neutrinos born as nu_e and s = 1 for antineutrinos born as nubar_e; nu_x
  * and nubar_x enter through the spectral weights.  The beam index is
- *     b = (s * NA + j) * NE + k,      NA = max(n_angle, 1),
+ *     b = (s * NA + j) * NE + k,      NA = max(n_angle, 1) * max(n_azimuth, 1),
  * and the number of beams is NB = 2 * NE * NA.  Energy bins sit at the
  * midpoints of [e_min, e_max]; emission-angle bins at the midpoints of
- * cos(theta_0) in (0, 1].
+ * cos(theta_0) in (0, 1].  In the extended bulb model (n_azimuth > 1, eq
+ * 3.18) trajectory j is emission-angle bin j / n_azimuth and azimuth bin
+ * j % n_azimuth, azimuth bins at the midpoints of [0, 2 pi) sharing the
+ * emission-angle weight equally.
  *
  * Frame.  Amplitudes are held in the frame co-rotating with the flavor-
  * diagonal part of the matter and self-interaction Hamiltonian of each
@@ -103,6 +106,8 @@ typedef struct nuosc_params {
     double  max_wall_s;            /* [Tn] wall-clock limit of one evolve call, 0 = none */
     int32_t precision;             /* NUOSC_FP64, NUOSC_FP32_AMP or NUOSC_FP32_AMP_FP64_MATH */
     int32_t frame;                 /* NUOSC_FRAME_COROTATING (default) or NUOSC_FRAME_LAB */
+    int32_t n_azimuth;             /* azimuth bins per emission angle: the extended bulb
+                                      model (eq 3.18, needs n_angle >= 1); 0 or 1 = bulb model */
 } nuosc_params;
 
 typedef struct nuosc_handle nuosc_handle;
@@ -179,6 +184,11 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km);
  * in the lab frame.  j0, j1: n*n complex each, row-major, interleaved re/im
  * (host memory, written).  r_km (nullable) receives the radius. */
 nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km);
+
+/* The extended model's azimuth moments of the current state (eq 3.18):
+ *   J2 = sum_j w_j s_j cos(phi_j) S_j,  J3 = sum_j w_j s_j sin(phi_j) S_j,
+ * s_j = sin(theta_j); zero for the bulb model.  Layout as nuosc_moments. */
+nuosc_status nuosc_moments_azimuth(nuosc_handle* h, double* j2, double* j3);
 
 /* Survival probabilities P_b = |psi_b,1|^2 of every beam (host, NB doubles). */
 nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out);
@@ -273,8 +283,9 @@ nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t pr
 
 /* Admit a run in its initial state; *slot receives its slot.  NUOSC_E_BUSY:
  * no free slot or no arena gap large enough (nothing changes); NUOSC_E_INVALID:
- * invalid parameters, or n_flavors / precision / integrator differ from the
- * batch's.  Synchronises the stream. */
+ * invalid parameters, n_flavors / precision / integrator differ from the
+ * batch's, or the run is an extended-model run (n_azimuth > 1: batches serve
+ * the bulb model).  Synchronises the stream. */
 nuosc_status nuosc_batch_admit(nuosc_batch* b, const nuosc_params* p, int32_t* slot);
 
 /* Make n_attempts step attempts of every admitted run that is still running

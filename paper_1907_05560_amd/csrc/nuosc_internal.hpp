@@ -60,6 +60,8 @@ struct RunConst {
     int32_t n, ne, na, ma;       // flavors, energy bins, trajectories, multi-angle flag
     int64_t nb, nb_pad;          // beams, padded stride of one component array
     int32_t frame, precision, integrator, nblk;  // nblk: stage workgroups (partials)
+    int32_t np, nj;              // azimuth bins per emission angle (1: bulb model); angle moments (2 or 4)
+    int32_t nth, pad2;           // emission-angle bins (na / np)
     double r_nu, mu0, lambda0, lambda_rref, lambda_power;
     double rtol, safety, dr_max;
     double r_start, h_fixed;
@@ -72,8 +74,9 @@ struct RunConst {
     const float* uinv32;         // [2 ne] the same in FP32
     const double* wgt;           // [2 ne] g (neutrino slots), -gbar (antineutrino slots)
     const double* flux;          // [2 ne] number flux of the slot's birth flavor in its energy bin
-    double* jhist;               // [kMaxStages + 1][2 n n] packed J0, J1 per stage
-    double* partial;             // [2][2 n n][nblk] per-workgroup weighted sums of the last two
+    const double* azi;           // [na][2] cos, sin of each trajectory's azimuth
+    double* jhist;               // [kMaxStages + 1][nj n n] packed J0, J1 (J2, J3) per stage
+    double* partial;             // [2][nj n n][nblk] per-workgroup weighted sums of the last two
                                  // beam launches (launch I uses [I & 1]), value-major
     double* errpart;             // [nblk]
     void* errv;                  // [2n][nb_pad] of the arithmetic type: sum_{i<S-1} e_i k_i of

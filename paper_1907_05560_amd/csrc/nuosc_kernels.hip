@@ -247,10 +247,13 @@ __device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double 
     const double x = (rc.r_nu / r) * (rc.r_nu / r);
     const double y = (r - rc.r_nu) * (r + rc.r_nu) / (r * r);
     if (rc.ma) {
-        const double du = 1.0 / (double)rc.na;
-        const double u = ((double)j + 0.5) * du;
+        // trajectory j: emission-angle bin j / np, azimuth bin j % np (the
+        // azimuth bins share the emission-angle weight)
+        const double du = 1.0 / (double)rc.nth;
+        const double u = ((double)(rc.np > 1 ? j / rc.np : j) + 0.5) * du;
         c = sqrt(fma(1.0 - u * u, y, u * u));
         w = x * u * du / c;
+        if (rc.np > 1) w /= (double)rc.np;
     } else {
         c = 1.0;
         const double s = 1.0 - sqrt(y);
@@ -268,7 +271,7 @@ __device__ __forceinline__ double matter(const RunConst& rc, double r)
 // Frame data of one trajectory at one stage radius.
 template <int N>
 struct Frame {
-    double c, w, wc, ic;
+    double c, w, wc, ic, s;
     double z[Shape<N>::NU > 0 ? Shape<N>::NU : 1][2];  // e^{i(Phi_a - Phi_b)}, upper pairs
 };
 
@@ -295,6 +298,7 @@ __device__ Frame<N> prepare_wave(const RunConst& rc, int j, int l, double c, dou
     f.w = w;
     f.wc = rc.ma ? f.w * f.c : 0.0;
     f.ic = 1.0 / f.c;
+    f.s = sqrt((1.0 - f.c) * (1.0 + f.c));
     int a, b;
     pair_of<N>(lane < NU ? lane : 0, a, b);
     double sn, cs;
@@ -339,23 +343,32 @@ __device__ void prepare_thread(const RunConst& rc, int j, int l, double rl, cons
     }
 }
 
-// Completes stage l of trajectory j from J_l (J0 then J1, packed) and the
-// matter potential lam at the stage radius (uniform values in every lane):
+// Completes stage l of trajectory j from J_l (J0, J1 and for the extended
+// model J2, J3, packed) and the matter potential lam at the stage radius
+// (uniform values in every lane):
 //   C = mu0 traceless(J0 - c J1)                       (eq 3.13; single angle: J1 = 0)
+//   extended model (eq 3.18): C = mu0 traceless(J0 - c J1 - sc J2 - ss J3),
+//     sc = sin(theta) cos(phi), ss = sin(theta) sin(phi) of the trajectory
 //   G = diag(H_m + C) / c in the co-rotating frame, 0 in the lab frame
 //   A_ab = e^{i(Phi_a - Phi_b)} C_ab / c (a < b), A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab)
 //   B_ab = e^{i(Phi_a - Phi_b)} V_ab / c,  B_aa = V_aa / c  (H_vac = V / E)
 // Stores h A and h B (the step size folded in: the beam kernels form
 // h k = -i h K y directly) in mat[l] and in M (LDS); G is returned.
-template <typename T, int N>
-__device__ void complete_wave(const RunConst& rc, int j, int l, const double c, const double ic,
-                              const double (*z)[2], double lam, const double* J, double h, double* G,
+template <typename T, int N, int NJ>
+__device__ void complete_wave(const RunConst& rc, int j, int l, const double c, const double ic, double sc,
+                              double ss, const double (*z)[2], double lam, const double* J, double h, double* G,
                               StageMat<T, N>* M, int lane)
 {
     constexpr int NM = Shape<N>::NM;
+    // the angle-kernel combination of the moments for value x of the packed matrix
+    auto kern = [&](int x) __attribute__((always_inline)) {
+        double v = J[x] - c * J[NM + x];
+        if constexpr (NJ == 4) v = (v - sc * J[2 * NM + x]) - ss * J[3 * NM + x];
+        return v;
+    };
     double Cd[N], tr = 0.0;
     for (int a = 0; a < N; ++a) {
-        Cd[a] = J[a] - c * J[NM + a];
+        Cd[a] = kern(a);
         tr += Cd[a];
     }
     double av[NM], bv[NM];
@@ -369,8 +382,8 @@ __device__ void complete_wave(const RunConst& rc, int j, int l, const double c, 
         for (int b = a + 1; b < N; ++b) {
             const int q = Shape<N>::up(a, b);
             const double cs = z[q][0], sn = z[q][1];
-            const double cr = rc.mu0 * (J[N + 2 * q] - c * J[NM + N + 2 * q]) * ic;
-            const double ci = rc.mu0 * (J[N + 2 * q + 1] - c * J[NM + N + 2 * q + 1]) * ic;
+            const double cr = rc.mu0 * kern(N + 2 * q) * ic;
+            const double ci = rc.mu0 * kern(N + 2 * q + 1) * ic;
             const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
             av[N + 2 * q] = cs * cr - sn * ci;
             av[N + 2 * q + 1] = cs * ci + sn * cr;
@@ -580,14 +593,15 @@ template <typename TS, typename T, typename TAB, int I> struct BeamPlan {
 // density sum of the formed state is rotated, weighted and added per
 // workgroup.  TS: amplitude type in HBM; T: arithmetic type of the stage
 // update (density sums are FP64 in every form).
-template <typename TS, typename T, int N, typename TAB, int I>
+template <typename TS, typename T, int N, typename TAB, int I, int NJ>
 __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 {
     constexpr int kTrajPerBlock = BeamShape<T>::traj;
     constexpr int S = TAB::S;
     constexpr bool FINAL = (I == S);
     constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU;
-    constexpr int NV = 2 * NM;
+    constexpr int NV = NJ * NM;                          // angle moments J0, J1 (J2, J3)
+    constexpr int NF = NJ == 4 ? 4 : 2;                  // epilogue weights per trajectory
     constexpr bool ERROR = FINAL && TAB::embedded;
     constexpr bool FSAL_FINAL = FINAL && TAB::fsal;      // derivatives and error only
     constexpr bool MOMENTS = !FSAL_FINAL;                // density sum of the formed state
@@ -612,7 +626,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     __shared__ Mat smat[kTrajPerBlock][NK > 0 ? NK : 1];
     __shared__ double swave[kTrajPerBlock][NV + 1];
     __shared__ double sJ[NV];
-    __shared__ double sF[kTrajPerBlock][2 + 2 * (NU > 0 ? NU : 1)];  // w, wc, z of stage I (-> epilogue)
+    __shared__ double sF[kTrajPerBlock][NF + 2 * (NU > 0 ? NU : 1)];  // weights, z of stage I (-> epilogue)
 
     // ---- the control block first (the longest dependent chain starts here);
     //      ctrl[1] holds it between attempts, ctrl[0] during one
@@ -654,14 +668,20 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
     PartialRegs<NV, kTrajPerBlock> xp;
     if constexpr (I >= 2) load_partials_waves<NV, kTrajPerBlock>(rc, I - 1, xp);
     double cP = 1.0, icP = 1.0, zP[NU > 0 ? NU : 1][2];
+    double sP = 0.0, cph = 1.0, sph = 0.0;                 // sin(theta) of stage I-1; azimuth
     double psum[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) psum[a] = 0.0;
     if (active) {
+        if constexpr (NJ == 4) {
+            cph = rc.azi[2 * (size_t)j];
+            sph = rc.azi[2 * (size_t)j + 1];
+        }
         if constexpr (I >= 2) {
             const TrajGeo& g = rc.geo[(size_t)(I - 1) * rc.na + j];
             cP = g.c;
             icP = g.ic;
+            if constexpr (NJ == 4) sP = sqrt((1.0 - g.c) * (1.0 + g.c));
             for (int q = 0; q < NU; ++q) {
                 zP[q][0] = g.z[q][0];
                 zP[q][1] = g.z[q][1];
@@ -936,14 +956,15 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 const Frame<N> f0 = prepare_wave<N>(rc, j, 0, c0, w0, phn, lane);
                 cP = f0.c;
                 icP = f0.ic;
+                sP = f0.s;
                 for (int q = 0; q < NU; ++q) {
                     zP[q][0] = f0.z[q][0];
                     zP[q][1] = f0.z[q][1];
                 }
             }
             double GP[N];
-            complete_wave<T, N>(rc, j, I - 1, cP, icP, zP, matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, h, GP,
-                                &smat[jt][NK - 1], lane);
+            complete_wave<T, N, NJ>(rc, j, I - 1, cP, icP, sP * cph, sP * sph, zP,
+                                    matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, h, GP, &smat[jt][NK - 1], lane);
             if constexpr (!EARLY_FETCH) fetch_first();
             if constexpr (MOMENTS) {
                 // phase sums sum_{m < l} coef(l, m) G_m: lane k adds the term of
@@ -961,12 +982,16 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 const Frame<N> f = prepare_wave<N>(rc, j, I, cN, wN, ph, lane);
                 if (I == LASTPREP)  // the new state's phase; kept only if the attempt is accepted
                     lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
-                double fw[2 + 2 * (NU > 0 ? NU : 1)];
+                double fw[NF + 2 * (NU > 0 ? NU : 1)];
                 fw[0] = f.w;
                 fw[1] = f.wc;
+                if constexpr (NJ == 4) {
+                    fw[2] = (f.w * f.s) * cph;
+                    fw[3] = (f.w * f.s) * sph;
+                }
                 for (int q = 0; q < NU; ++q) {
-                    fw[2 + 2 * q] = f.z[q][0];
-                    fw[3 + 2 * q] = f.z[q][1];
+                    fw[NF + 2 * q] = f.z[q][0];
+                    fw[NF + 1 + 2 * q] = f.z[q][1];
                 }
                 lane_scatter(sF[jt], fw, lane);
             }
@@ -999,6 +1024,7 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
         for (int v = 0; v < NV; ++v) sl[v] = 0.0;
         if (active) {
             Frame<N> f;
+            double wsc = 0.0, wss = 0.0;  // w sin(theta) cos(phi), w sin(theta) sin(phi)
             if constexpr (I == 0) {
                 // stage-0 frame prepared before this launch
                 const TrajGeo& g = rc.geo[j];
@@ -1006,6 +1032,11 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 f.w = g.w;
                 f.wc = g.wc;
                 f.ic = g.ic;
+                if constexpr (NJ == 4) {
+                    const double s0 = sqrt((1.0 - g.c) * (1.0 + g.c));
+                    wsc = (g.w * s0) * cph;
+                    wss = (g.w * s0) * sph;
+                }
                 for (int q = 0; q < NU; ++q) {
                     f.z[q][0] = g.z[q][0];
                     f.z[q][1] = g.z[q][1];
@@ -1014,9 +1045,13 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
                 // frame of stage I prepared in the prologue
                 f.w = sF[jt][0];
                 f.wc = sF[jt][1];
+                if constexpr (NJ == 4) {
+                    wsc = sF[jt][2];
+                    wss = sF[jt][3];
+                }
                 for (int q = 0; q < NU; ++q) {
-                    f.z[q][0] = sF[jt][2 + 2 * q];
-                    f.z[q][1] = sF[jt][3 + 2 * q];
+                    f.z[q][0] = sF[jt][NF + 2 * q];
+                    f.z[q][1] = sF[jt][NF + 1 + 2 * q];
                 }
             }
             // S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa, weighted by w and w c
@@ -1031,6 +1066,10 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
             for (int v = 0; v < NM; ++v) {
                 sl[v] = f.w * Sv[v];
                 sl[NM + v] = f.wc * Sv[v];
+                if constexpr (NJ == 4) {
+                    sl[2 * NM + v] = wsc * Sv[v];
+                    sl[3 * NM + v] = wss * Sv[v];
+                }
             }
         }
         if (lane == 0)
@@ -1062,20 +1101,20 @@ __device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
 // Beam launch over a launch set (any number of runs) and over one run whose
 // constants travel as the kernel argument (no table lookup before the first
 // loads).
-template <typename TS, typename T, int N, typename TAB, int I>
+template <typename TS, typename T, int N, typename TAB, int I, int NJ>
 __global__ void __launch_bounds__(BeamShape<T>::block)
 __attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
-    stage_body<TS, T, N, TAB, I>(rc, blk);
+    stage_body<TS, T, N, TAB, I, NJ>(rc, blk);
 }
 
-template <typename TS, typename T, int N, typename TAB, int I>
+template <typename TS, typename T, int N, typename TAB, int I, int NJ>
 __global__ void __launch_bounds__(BeamShape<T>::block)
 __attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage_one(const RunConst rc)
 {
-    stage_body<TS, T, N, TAB, I>(rc, blockIdx.x);
+    stage_body<TS, T, N, TAB, I, NJ>(rc, blockIdx.x);
 }
 
 // After the last beam launch of an attempt, one workgroup per run: the global
@@ -1083,11 +1122,11 @@ __attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_st
 // attempt (J of the accepted state, else unchanged).  For a tableau without
 // first-same-as-last, J of the new state is summed from the last launch's
 // partials here.  Also used after a stage-0 launch (I == 0) to sum J_0.
-template <int N, typename TAB, int I>
+template <int N, typename TAB, int I, int NJ>
 __device__ __forceinline__ void control_body(const RunConst& rc)
 {
     constexpr int S = TAB::S;
-    constexpr int NV = 2 * Shape<N>::NM;
+    constexpr int NV = NJ * Shape<N>::NM;
     constexpr bool SUM = (I == 0) || !TAB::fsal;
     __shared__ double sred[NV][kFinBlock / NV];
     __shared__ double sJ[NV];
@@ -1117,18 +1156,18 @@ __device__ __forceinline__ void control_body(const RunConst& rc)
     }
 }
 
-template <int N, typename TAB, int I>
+template <int N, typename TAB, int I, int NJ>
 __global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
-    control_body<N, TAB, I>(rc);
+    control_body<N, TAB, I, NJ>(rc);
 }
 
-template <int N, typename TAB, int I>
+template <int N, typename TAB, int I, int NJ>
 __global__ void __launch_bounds__(kFinBlock) k_control_one(const RunConst rc)
 {
-    control_body<N, TAB, I>(rc);
+    control_body<N, TAB, I, NJ>(rc);
 }
 
 // Stage-0 frame of the current state (before a stage-0 launch).
@@ -1260,24 +1299,24 @@ __global__ void k_init(const LaunchSet ls)
 // ------------------------------------------------------------------ dispatch
 using KernFn = void (*)(const LaunchSet);
 
-template <typename TS, typename T, int N, typename TAB>
+template <typename TS, typename T, int N, typename TAB, int NJ>
 struct StageTable {
     template <int... Is>
     static constexpr std::array<KernFn, kMaxStages> make(std::integer_sequence<int, Is...>)
     {
-        return {{(Is <= TAB::S ? (KernFn)&k_stage<TS, T, N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+        return {{(Is <= TAB::S ? (KernFn)&k_stage<TS, T, N, TAB, (Is <= TAB::S ? Is : 0), NJ> : nullptr)...}};
     }
     static constexpr std::array<KernFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
 
 using OneFn = void (*)(const RunConst);
 
-template <typename TS, typename T, int N, typename TAB>
+template <typename TS, typename T, int N, typename TAB, int NJ>
 struct StageOneTable {
     template <int... Is>
     static constexpr std::array<OneFn, kMaxStages> make(std::integer_sequence<int, Is...>)
     {
-        return {{(Is <= TAB::S ? (OneFn)&k_stage_one<TS, T, N, TAB, (Is <= TAB::S ? Is : 0)> : nullptr)...}};
+        return {{(Is <= TAB::S ? (OneFn)&k_stage_one<TS, T, N, TAB, (Is <= TAB::S ? Is : 0), NJ> : nullptr)...}};
     }
     static constexpr std::array<OneFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
 };
@@ -1290,30 +1329,38 @@ struct StageKernels {
     OneFn k1 = nullptr, f1 = nullptr;
 };
 
-template <typename TS, typename T, int N, typename TAB>
+template <typename TS, typename T, int N, typename TAB, int NJ>
 void pick_tab(int stage, StageKernels& K)
 {
-    K.k = StageTable<TS, T, N, TAB>::fns[stage];
-    K.k1 = StageOneTable<TS, T, N, TAB>::fns[stage];
+    K.k = StageTable<TS, T, N, TAB, NJ>::fns[stage];
+    K.k1 = StageOneTable<TS, T, N, TAB, NJ>::fns[stage];
     if (stage == 0) {
-        K.f = (KernFn)&k_control<N, TAB, 0>;
-        K.f1 = (OneFn)&k_control_one<N, TAB, 0>;
+        K.f = (KernFn)&k_control<N, TAB, 0, NJ>;
+        K.f1 = (OneFn)&k_control_one<N, TAB, 0, NJ>;
     } else if (stage == TAB::S) {
-        K.f = (KernFn)&k_control<N, TAB, TAB::S>;
-        K.f1 = (OneFn)&k_control_one<N, TAB, TAB::S>;
+        K.f = (KernFn)&k_control<N, TAB, TAB::S, NJ>;
+        K.f1 = (OneFn)&k_control_one<N, TAB, TAB::S, NJ>;
     }
 }
 
-template <typename TS, typename T>
+template <typename TS, typename T, int NJ>
 void pick_n(int n, int integrator, int stage, StageKernels& K)
 {
     if (n == 2) {
-        if (integrator == 0) pick_tab<TS, T, 2, TabRK4>(stage, K);
-        else pick_tab<TS, T, 2, TabDP54>(stage, K);
+        if (integrator == 0) pick_tab<TS, T, 2, TabRK4, NJ>(stage, K);
+        else pick_tab<TS, T, 2, TabDP54, NJ>(stage, K);
     } else {
-        if (integrator == 0) pick_tab<TS, T, 3, TabRK4>(stage, K);
-        else pick_tab<TS, T, 3, TabDP54>(stage, K);
+        if (integrator == 0) pick_tab<TS, T, 3, TabRK4, NJ>(stage, K);
+        else pick_tab<TS, T, 3, TabDP54, NJ>(stage, K);
     }
+}
+
+// The bulb model (two angle moments) or the extended one (four).
+template <typename TS, typename T>
+void pick_nj(int nj, int n, int integrator, int stage, StageKernels& K)
+{
+    if (nj == 4) pick_n<TS, T, 4>(n, integrator, stage, K);
+    else pick_n<TS, T, 2>(n, integrator, stage, K);
 }
 
 // Launches fn over the listed runs, at most kMaxRuns runs per launch, with
@@ -1345,7 +1392,7 @@ bool same_kind(const RunList& runs)
     for (int i = 1; i < runs.count; ++i) {
         const RunConst& a = *runs.rc[0];
         const RunConst& b = *runs.rc[i];
-        if (a.n != b.n || a.precision != b.precision || a.integrator != b.integrator) return false;
+        if (a.n != b.n || a.precision != b.precision || a.integrator != b.integrator || a.nj != b.nj) return false;
     }
     return true;
 }
@@ -1365,9 +1412,9 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
     if ((r0.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(r0.precision))
         return hipErrorInvalidValue;
     switch (r0.precision) {
-    case 0: pick_n<double, double>(r0.n, r0.integrator, stage, K); break;  // FP64
-    case 1: pick_n<float, float>(r0.n, r0.integrator, stage, K); break;    // FP32 amplitudes
-    case 2: pick_n<float, double>(r0.n, r0.integrator, stage, K); break;   // FP32 amplitudes, FP64 math
+    case 0: pick_nj<double, double>(r0.nj, r0.n, r0.integrator, stage, K); break;  // FP64
+    case 1: pick_nj<float, float>(r0.nj, r0.n, r0.integrator, stage, K); break;    // FP32 amplitudes
+    case 2: pick_nj<float, double>(r0.nj, r0.n, r0.integrator, stage, K); break;   // FP32 amplitudes, FP64 math
     default: break;
     }
     if (!K.k || !K.k1) return hipErrorInvalidValue;

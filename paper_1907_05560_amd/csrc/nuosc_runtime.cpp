@@ -178,9 +178,10 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, flux, mat, geo, ctrl, prob, eavg, rconst, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, flux, azi, mat, geo, ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk;
+    int nj;      // angle moments: 2 (bulb model), 4 (extended: azimuth)
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -191,6 +192,9 @@ const char* validate(const nuosc_params* p)
     if (p->n_flavors != 2 && p->n_flavors != 3) return "n_flavors must be 2 or 3";
     if (p->n_energy < 1) return "n_energy must be >= 1";
     if (p->n_angle < 0) return "n_angle must be >= 0";
+    if (p->n_azimuth < 0) return "n_azimuth must be >= 0";
+    if (p->n_azimuth > 1 && p->n_angle < 1) return "azimuth bins need emission-angle bins (n_angle >= 1)";
+    if ((int64_t)std::max(p->n_angle, 1) * std::max(p->n_azimuth, 1) > (1 << 24)) return "too many trajectories";
     if (!(p->e_min_mev >= 0.0) || !(p->e_max_mev > p->e_min_mev)) return "need 0 <= e_min < e_max";
     for (int s = 0; s < 4; ++s) {
         if (!(p->mean_e_mev[s] > 0.0)) return "mean energies must be > 0";
@@ -211,7 +215,7 @@ const char* validate(const nuosc_params* p)
         return "unknown precision";
     if (p->frame != NUOSC_FRAME_COROTATING && p->frame != NUOSC_FRAME_LAB) return "unknown frame";
     if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
-    const int64_t na = std::max(p->n_angle, 1);
+    const int64_t na = (int64_t)std::max(p->n_angle, 1) * std::max(p->n_azimuth, 1);
     // each amplitude component array is addressed with 32-bit byte offsets
     // (and so is the per-beam error sum, held in the arithmetic type)
     const int64_t tsz = p->precision == NUOSC_FP32_AMP ? 4 : 8;
@@ -224,7 +228,8 @@ Layout make_layout(const nuosc_params& p)
 {
     Layout L{};
     const int n = p.n_flavors;
-    L.na = std::max(p.n_angle, 1);
+    L.na = std::max(p.n_angle, 1) * std::max(p.n_azimuth, 1);
+    L.nj = p.n_azimuth > 1 ? 4 : 2;
     L.nb = 2 * (int64_t)p.n_energy * L.na;
     L.nb_pad = (int64_t)align_up((size_t)L.nb, 64);
     const size_t tsz = p.precision == NUOSC_FP64 ? 8 : 4;
@@ -242,8 +247,9 @@ Layout make_layout(const nuosc_params& p)
     L.uinv32 = take((size_t)2 * p.n_energy * 4);
     L.wgt = take((size_t)2 * p.n_energy * 8);
     L.flux = take((size_t)2 * p.n_energy * 8);
-    L.jhist = take((size_t)(nuosc::kMaxStages + 1) * 2 * n * n * 8);
-    L.partial = take((size_t)2 * 2 * n * n * L.nblk * 8);  // two launches' partials (alternating)
+    L.jhist = take((size_t)(nuosc::kMaxStages + 1) * L.nj * n * n * 8);
+    L.partial = take((size_t)2 * L.nj * n * n * L.nblk * 8);  // two launches' partials (alternating)
+    L.azi = take((size_t)2 * L.na * 8);
     L.errpart = take((size_t)L.nblk * 8);
     const size_t asz = p.precision == NUOSC_FP32_AMP ? 4 : 8;
     L.errv = take(p.integrator == NUOSC_RK_DP54 ? 2 * n * (size_t)L.nb_pad * asz : 0);
@@ -361,6 +367,9 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.nb = L.nb;
     rc.nb_pad = L.nb_pad;
     rc.nblk = L.nblk;
+    rc.np = std::max(p->n_azimuth, 1);
+    rc.nth = L.na / rc.np;
+    rc.nj = L.nj;
     rc.frame = p->frame;
     rc.precision = p->precision;
     rc.integrator = p->integrator;
@@ -385,6 +394,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.uinv32 = (const float*)(base + L.uinv32);
     rc.wgt = (const double*)(base + L.wgt);
     rc.flux = (const double*)(base + L.flux);
+    rc.azi = (const double*)(base + L.azi);
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
@@ -410,7 +420,15 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     HIP_CHECK(hipMemcpyAsync((void*)rc.uinv32, tab.uinv32.data(), tab.uinv32.size() * 4, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync((void*)rc.wgt, tab.wgt.data(), tab.wgt.size() * 8, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync((void*)rc.flux, tab.flux.data(), tab.flux.size() * 8, hipMemcpyHostToDevice, s), err);
-    HIP_CHECK(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * 2 * rc.n * rc.n * 8, s), err);
+    // azimuth of every trajectory (extended model: midpoints of [0, 2 pi)): cos, sin
+    std::vector<double> azi((size_t)2 * rc.na, 0.0);
+    for (int j = 0; j < rc.na; ++j) {
+        const double phi = rc.np > 1 ? 2.0 * M_PI * ((j % rc.np) + 0.5) / rc.np : 0.0;
+        azi[2 * j] = std::cos(phi);
+        azi[2 * j + 1] = std::sin(phi);
+    }
+    HIP_CHECK(hipMemcpyAsync((void*)rc.azi, azi.data(), azi.size() * 8, hipMemcpyHostToDevice, s), err);
+    HIP_CHECK(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * rc.nj * rc.n * rc.n * 8, s), err);
     HIP_CHECK(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync(runs_dev + slot, &rc, sizeof(RunConst), hipMemcpyHostToDevice, s), err);
     OneRun one(r);
@@ -552,6 +570,7 @@ void nuosc_default_params(nuosc_params* p)
     p->integrator = NUOSC_RK4_FIXED; p->n_fixed_steps = 10000;
     p->rtol = 1e-9; p->dr_init_km = 1e-5; p->dr_max_km = 1.0; p->safety = 0.9;
     p->precision = NUOSC_FP64; p->frame = NUOSC_FRAME_COROTATING;
+    p->n_azimuth = 0;
 }
 
 size_t nuosc_footprint_bytes(const nuosc_params* p)
@@ -700,20 +719,24 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
     return hstatus(h);
 }
 
-nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km)
+// Angle moments first, first + 1 of the current state (0, 1: J0, J1; 2, 3:
+// the extended model's J2, J3, zero for the bulb model) as full complex
+// matrices.
+static nuosc_status moments_pair(nuosc_handle* h, int first, double* ja, double* jb, double* r_km)
 {
     if (!h) return fail(nullptr, NUOSC_E_INVALID, "handle is NULL");
     nuosc_status st = checked(h, restart(h->run, h->stream, h->err), h->err);
     if (st != NUOSC_OK) return st;
-    const int n = h->run.rc.n, nm = n * n;
-    std::vector<double> J(2 * nm);
-    HIP_CHECK(hipMemcpyAsync(J.data(), h->run.rc.jhist, J.size() * 8, hipMemcpyDeviceToHost, h->stream), h->err);
+    const int n = h->run.rc.n, nm = n * n, nj = h->run.rc.nj;
+    std::vector<double> J(4 * nm, 0.0);
+    HIP_CHECK(hipMemcpyAsync(J.data(), h->run.rc.jhist, (size_t)nj * nm * 8, hipMemcpyDeviceToHost, h->stream),
+              h->err);
     st = hread(h);
     if (st != NUOSC_OK) return st;
     for (int m = 0; m < 2; ++m) {
-        double* out = m == 0 ? j0 : j1;
+        double* out = m == 0 ? ja : jb;
         if (!out) continue;
-        const double* src = J.data() + m * nm;
+        const double* src = J.data() + (first + m) * nm;
         for (int a = 0; a < n; ++a) {
             out[(a * n + a) * 2] = src[a];
             out[(a * n + a) * 2 + 1] = 0.0;
@@ -730,6 +753,16 @@ nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km
     }
     if (r_km) *r_km = h->run.hctl.r;
     return NUOSC_OK;
+}
+
+nuosc_status nuosc_moments(nuosc_handle* h, double* j0, double* j1, double* r_km)
+{
+    return moments_pair(h, 0, j0, j1, r_km);
+}
+
+nuosc_status nuosc_moments_azimuth(nuosc_handle* h, double* j2, double* j3)
+{
+    return moments_pair(h, 2, j2, j3, nullptr);
 }
 
 nuosc_status nuosc_probabilities(nuosc_handle* h, double* p_out)
@@ -1192,6 +1225,7 @@ nuosc_status nuosc_batch_admit(nuosc_batch* b, const nuosc_params* p, int32_t* s
     if (const char* why = validate(p)) return bfail(b, NUOSC_E_INVALID, why);
     if (p->n_flavors != b->n || p->precision != b->precision || p->integrator != b->integrator)
         return bfail(b, NUOSC_E_INVALID, "n_flavors, precision and integrator must match the batch");
+    if (p->n_azimuth > 1) return bfail(b, NUOSC_E_INVALID, "batches serve bulb-model runs (n_azimuth 0 or 1)");
     int free_slot = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (!b->used[i]) {

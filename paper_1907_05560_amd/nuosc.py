@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NONFINIT
 EXPORTS = (
     "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
     "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_timing_enable",
-    "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_probabilities",
+    "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_moments_azimuth", "nuosc_probabilities",
     "nuosc_get_state", "nuosc_set_state", "nuosc_energy_average", "nuosc_enqueue_energy_average",
     "nuosc_snapshot_write",
     "nuosc_snapshot_read", "nuosc_snapshot_info", "nuosc_stats", "nuosc_num_beams",
@@ -101,6 +101,7 @@ class Params(C.Structure):
         ("max_wall_s", C.c_double),
         ("precision", C.c_int32),
         ("frame", C.c_int32),
+        ("n_azimuth", C.c_int32),
     ]
 
 
@@ -139,6 +140,8 @@ def lib() -> C.CDLL:
     L.nuosc_evolve.restype = C.c_int
     L.nuosc_moments.argtypes = [C.c_void_p, _D, _D, _D]
     L.nuosc_moments.restype = C.c_int
+    L.nuosc_moments_azimuth.argtypes = [C.c_void_p, _D, _D]
+    L.nuosc_moments_azimuth.restype = C.c_int
     L.nuosc_probabilities.argtypes = [C.c_void_p, _D]
     L.nuosc_probabilities.restype = C.c_int
     L.nuosc_get_state.argtypes = [C.c_void_p, _D, _D]
@@ -334,6 +337,15 @@ class Run:
         self._check(lib().nuosc_moments(self.h, _ptr(j0), _ptr(j1), C.byref(r)))
         f = lambda a: (a[0::2] + 1j * a[1::2]).reshape(n, n)  # noqa: E731
         return f(j0), f(j1), r.value
+
+    def moments_azimuth(self):
+        """J2, J3 of the extended bulb model (zero for the bulb model)."""
+        n = self.n
+        j2 = np.empty(2 * n * n)
+        j3 = np.empty(2 * n * n)
+        self._check(lib().nuosc_moments_azimuth(self.h, _ptr(j2), _ptr(j3)))
+        f = lambda a: (a[0::2] + 1j * a[1::2]).reshape(n, n)  # noqa: E731
+        return f(j2), f(j3)
 
     def probabilities(self) -> np.ndarray:
         p = np.empty(self.nb)

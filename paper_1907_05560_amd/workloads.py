@@ -115,6 +115,17 @@ def multi_angle_3f_large(precision: int = FP32_AMP) -> Dict:
     return w
 
 
+def extended_bulb_3f(n_energy: int = 100, n_angle: int = 100, n_azimuth: int = 32,
+                     precision: int = FP32_AMP) -> Dict:
+    """Three-flavor extended bulb model (eq 3.18): n_angle emission angles x
+    n_azimuth azimuth bins per angle, adaptive pair; the physics of the bulb
+    workloads.  Starts from azimuth_perturbed_states (the seed that breaks the
+    azimuthal symmetry)."""
+    w = multi_angle_3f(n_energy, n_angle)
+    w.update(n_azimuth=n_azimuth, precision=precision)
+    return w
+
+
 def error_subsample(n_beams: int, count: int = 4096) -> np.ndarray:
     """Sorted seeded subsample of beam indices used to report FP32 error."""
     rng = np.random.default_rng(SEED_BASE + 2)
@@ -184,6 +195,24 @@ def random_states(n_flavors: int, n_beams: int, seed: int) -> np.ndarray:
     """
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((n_flavors, n_beams)) + 1j * rng.standard_normal((n_flavors, n_beams))
+    z /= np.sqrt((np.abs(z) ** 2).sum(axis=0, keepdims=True))
+    out = np.empty((n_flavors, 2, n_beams))
+    out[:, 0, :] = z.real
+    out[:, 1, :] = z.imag
+    return out
+
+
+def azimuth_perturbed_states(n_flavors: int, n_beams: int, n_traj: int, seed: int,
+                             amplitude: float = 1e-6) -> np.ndarray:
+    """Birth-flavor states (component 0) with seeded complex perturbations of
+    size `amplitude` in the other components, different for every beam: the
+    small symmetry-breaking seed the extended bulb model's azimuth bins need.
+    Unit norm; host state layout, shape (n_flavors, 2, n_beams)."""
+    rng = np.random.default_rng(seed)
+    z = np.zeros((n_flavors, n_beams), complex)
+    z[0] = 1.0
+    z[1:] = amplitude * (rng.standard_normal((n_flavors - 1, n_beams))
+                         + 1j * rng.standard_normal((n_flavors - 1, n_beams)))
     z /= np.sqrt((np.abs(z) ** 2).sum(axis=0, keepdims=True))
     out = np.empty((n_flavors, 2, n_beams))
     out[:, 0, :] = z.real
