@@ -46,8 +46,8 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    """'void nuosc::(anonymous namespace)::k_stage_one<float, float, 3, ...TabDP54, 7>(nuosc::RunConst)'
-    -> 'k_stage_one<float,float,3,DP54,7>'."""
+    """'void nuosc::(anonymous namespace)::k_stage_one<float, float, 3, ...TabDP54, 7, 2>(nuosc::RunConst)'
+    -> 'k_stage_one<float,float,3,DP54,7,2>'."""
     n = name.replace("nuosc::(anonymous namespace)::", "").replace("void ", "")
     n = re.sub(r"\(nuosc::(RunConst|LaunchSet).*\)$", "", n)
     n = n.replace("TabDP54", "DP54").replace("TabRK4", "RK4").replace(" ", "")
@@ -55,11 +55,13 @@ def short_name(name: str) -> str:
 
 
 def stage_key(name: str):
-    """(stage, precision) of a beam-kernel instantiation (one run or a launch set), or None."""
-    m = re.search(r"k_stage(?:_one)?<(\w+),(\w+),(\d),\w+,(\d)>", short_name(name))
-    if not m:
+    """(stage, precision) of a bulb-model beam-kernel instantiation (one run or a
+    launch set), or None.  The last template argument is the number of angle
+    moments: 2 for the bulb model, 4 for the extended model (no key)."""
+    m = re.search(r"k_stage(?:_one)?<(\w+),(\w+),(\d),\w+,(\d)(?:,(\d))?>", short_name(name))
+    if not m or m.group(5) not in (None, "2"):
         return None
-    ts, t, _, stage = m.groups()
+    ts, t, _, stage, _ = m.groups()
     prec = 0 if ts == "double" else (1 if t == "float" else 2)
     return int(stage), prec
 

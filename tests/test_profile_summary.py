@@ -10,8 +10,8 @@ from paper_1907_05560_amd import profile_summary as PS
 NS = "nuosc::(anonymous namespace)::"
 
 
-def _name(kernel, ts, t, tab, stage, arg):
-    return f"void {NS}{kernel}<{ts}, {t}, 3, {NS}{tab}, {stage}>(nuosc::{arg})"
+def _name(kernel, ts, t, tab, stage, arg, nj=2):
+    return f"void {NS}{kernel}<{ts}, {t}, 3, {NS}{tab}, {stage}, {nj}>(nuosc::{arg})"
 
 
 @pytest.mark.parametrize("kernel,arg", [("k_stage_one", "RunConst"), ("k_stage", "LaunchSet")])
@@ -19,11 +19,17 @@ def _name(kernel, ts, t, tab, stage, arg):
 def test_stage_key_reads_stage_and_precision(kernel, arg, ts, t, prec):
     n = _name(kernel, ts, t, "TabDP54", 6, arg)
     assert PS.stage_key(n) == (6, prec)
-    assert PS.short_name(n) == f"{kernel}<{ts},{t},3,DP54,6>"
+    assert PS.short_name(n) == f"{kernel}<{ts},{t},3,DP54,6,2>"
+
+
+def test_extended_model_kernels_have_no_stage_key():
+    n = _name("k_stage_one", "float", "float", "TabDP54", 6, "RunConst", nj=4)
+    assert PS.stage_key(n) is None
+    assert PS.short_name(n) == "k_stage_one<float,float,3,DP54,6,4>"
 
 
 def test_other_kernels_have_no_stage_key():
-    assert PS.stage_key(f"void {NS}k_control_one<3, {NS}TabDP54, 7>(nuosc::RunConst)") is None
+    assert PS.stage_key(f"void {NS}k_control_one<3, {NS}TabDP54, 7, 2>(nuosc::RunConst)") is None
     assert PS.stage_key(PS.COPY_KERNEL) is None
 
 
@@ -48,4 +54,4 @@ def test_traffic_is_scaled_by_the_calibration_copy(tmp_path):
     assert doc["fetch_scale"] == pytest.approx(0.5)
     assert doc["write_scale"] == pytest.approx(1.0)
     assert doc["bytes_per_launch"]["stage6_prec1"] == round(1000 * 1024 * 0.5 + 500 * 1024)
-    assert "k_stage_one<float,float,3,DP54,6>" in text
+    assert "k_stage_one<float,float,3,DP54,6,2>" in text
