@@ -32,6 +32,9 @@
  *      |h sum_i e_i k_i| / rtol; the co-rotating phases are excluded.
  *   N  only nu_e-born and nubar_e-born beams are evolved; the nu_x flavors
  *      enter through the weights (unitarity of the flavor basis).
+ *   Q  the paper's own stepper (eq 3.10-3.12 inside the half/full-step loop of
+ *      Sections 4.2.3 and 5): which states are averaged and compared (see
+ *      exp_attempt()); lab frame only.
  */
 #include "nuosc_oracle.h"
 
@@ -92,6 +95,7 @@ struct or_run {
     int64_t nacc, nrej;
     int last_rejected;
     int k1_valid;   /* Dormand-Prince first-same-as-last derivative held in k[0] */
+    double last_err; /* scaled error of the last adaptive attempt */
     int done;
 };
 
@@ -672,6 +676,7 @@ static int dp54_attempt(or_run* R)
         else if (d > err) err = d;
     }
     if (!finite) return OR_NONFINITE;
+    R->last_err = err;
 
     const double fmin = 0.2, fmax = 5.0;
     double fac;
@@ -729,6 +734,206 @@ int or_evolve_dp54(or_run* R, double r_target, int64_t max_attempts)
     return st;
 }
 
+/* ------------------------------------------------------------ exponential stepper */
+/* U = exp(-i K t) of a Hermitian n x n matrix K (row-major), taken from the
+ * definition: the power series of exp(X), X = -i K t / 2^m, with m chosen so
+ * that the 1-norm of X is at most 1/2, summed until a term no longer changes
+ * the sum, then squared m times. */
+static void expm_herm(int n, const cplx* K, double t, cplx* U)
+{
+    double norm = 0.0;
+    for (int c = 0; c < n; ++c) {
+        double col = 0.0;
+        for (int a = 0; a < n; ++a) col += hypot(K[a * n + c].re, K[a * n + c].im);
+        if (col > norm) norm = col;
+    }
+    norm *= fabs(t);
+    int m = 0;
+    while (norm > 0.5) { norm *= 0.5; ++m; }
+    const double scale = ldexp(t, -m);
+    cplx X[9], term[9], next[9];
+    for (int i = 0; i < n * n; ++i) {
+        X[i] = c_make(K[i].im * scale, -K[i].re * scale); /* -i K t / 2^m */
+        term[i] = c_make(0, 0);
+    }
+    for (int a = 0; a < n; ++a) term[a * n + a] = c_make(1, 0);
+    for (int i = 0; i < n * n; ++i) U[i] = term[i];
+    for (int k = 1; k < 60; ++k) {
+        double big = 0.0;
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                cplx acc = c_make(0, 0);
+                for (int q = 0; q < n; ++q) acc = c_add(acc, c_mul(term[a * n + q], X[q * n + c]));
+                next[a * n + c] = c_scale(acc, 1.0 / (double)k);
+                double v = fabs(next[a * n + c].re) + fabs(next[a * n + c].im);
+                if (v > big) big = v;
+            }
+        for (int i = 0; i < n * n; ++i) { term[i] = next[i]; U[i] = c_add(U[i], term[i]); }
+        if (big < 1e-18) break;
+    }
+    for (int s = 0; s < m; ++s) {
+        cplx sq[9];
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                cplx acc = c_make(0, 0);
+                for (int q = 0; q < n; ++q) acc = c_add(acc, c_mul(U[a * n + q], U[q * n + c]));
+                sq[a * n + c] = acc;
+            }
+        for (int i = 0; i < n * n; ++i) U[i] = sq[i];
+    }
+}
+
+void or_expm_herm(int n, const double* k, double t, double* u)
+{
+    cplx K[9] = {{0, 0}}, U[9];
+    if (n < 2 || n > 3) return;
+    for (int i = 0; i < n * n; ++i) K[i] = c_make(k[2 * i], k[2 * i + 1]);
+    expm_herm(n, K, t, U);
+    for (int i = 0; i < n * n; ++i) { u[2 * i] = U[i].re; u[2 * i + 1] = U[i].im; }
+}
+
+/* One exponential step of every beam (eq 3.10-3.12, lab frame):
+ *   out_b = exp(-i K_b t) x_b,  K_b = H_b(r_s) / c_j(r_s),
+ * where the Hamiltonian of beam b is formed at radius r_s from the moments of
+ * state ymom (eq 3.13 and 3.4, as in rhs() with Phi = 0):
+ *   neutrino      H  = H_vac(E) + H_m(r_s) + H_nunu
+ *   antineutrino  Hb = conj(H_vac(E)) - H_m(r_s) - conj(H_nunu).
+ * 1/c_j turns the path length of eq 3.3 into the radial step.  The phase part
+ * of the flat state is copied from x unchanged (zero in the lab frame). */
+static void exp_step(const or_run* R, double rs, const double* ymom, double t, const double* x, double* out)
+{
+    const int n = R->n, ne = R->ne, na = R->na;
+    cplx J0[9], J1[9], J2[9], J3[9];
+    moments_at(R, rs, ymom, J0, J1, J2, J3); /* also leaves c_j(r_s), w_j(r_s) in R->c, R->w */
+    const double lam = matter_potential(R, rs);
+    for (int j = 0; j < na; ++j) {
+        const double cj = R->c[j];
+        cplx C[9];
+        collective(R, J0, J1, J2, J3, j, C);
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < ne; ++k) {
+                const cplx* hv = &R->hvac[(size_t)k * n * n];
+                cplx K[9], U[9];
+                for (int a = 0; a < n; ++a)
+                    for (int c = 0; c < n; ++c) {
+                        const double hm = (a == c) ? lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / (double)n) : 0.0;
+                        cplx H;
+                        if (s == 0)
+                            H = c_add(c_add(hv[a * n + c], c_make(hm, 0.0)), C[a * n + c]);
+                        else
+                            H = c_sub(c_sub(c_conj(hv[a * n + c]), c_make(hm, 0.0)), c_conj(C[a * n + c]));
+                        K[a * n + c] = c_scale(H, 1.0 / cj);
+                    }
+                expm_herm(n, K, t, U);
+                const int64_t b = (int64_t)(s * na + j) * ne + k;
+                for (int a = 0; a < n; ++a) {
+                    cplx acc = c_make(0, 0);
+                    for (int c = 0; c < n; ++c) acc = c_add(acc, c_mul(U[a * n + c], amp(R, x, b, c)));
+                    out[(b * n + a) * 2 + 0] = acc.re;
+                    out[(b * n + a) * 2 + 1] = acc.im;
+                }
+            }
+    }
+    for (int64_t q = 2 * (int64_t)n * R->nb; q < R->ylen; ++q) out[q] = x[q];
+}
+
+static void average(const or_run* R, const double* a, const double* b, double* out)
+{
+    for (int64_t q = 0; q < R->ylen; ++q) out[q] = 0.5 * (a[q] + b[q]);
+}
+
+/* One attempt of the paper's own stepper (Section 4.2.3 and the evolution
+ * loop of Section 5; reading Q).  From psi0 at r with step h:
+ *   H0 from psi0 at r;      psi1 = U(H0, h) psi0,  psi4 = U(H0, h/2) psi0
+ *   H1 from psi1 at r+h;    H2 from psi4 at r+h/2
+ *   psi3 = (psi1 + U(H1, h) psi0) / 2                   full-step estimate
+ *   psi5 = U(H2, h/2) psi4;  H3 from psi5 at r+h
+ *   psi7 = (psi1 + U(H3, h) psi0) / 2                   two-half-step estimate
+ * with U(H, t) = exp(-i K t), K = H / c_j.  Both estimates are second order and
+ * differ only through the predicted end Hamiltonian (H1 from one full step,
+ * H3 from two half steps), so psi3 - psi7 = O(h^3).  The error is the maximum
+ * over beams, components and re/im parts of |psi3 - psi7| / rtol; an accepted
+ * attempt advances to psi7.  Controller as reading J with the exponent of a
+ * third-order local error: factor safety * err^(-1/3), clamped to [0.2, 5]. */
+static int exp_attempt(or_run* R)
+{
+    const int64_t namp = 2 * (int64_t)R->n * R->nb;
+    const double r = R->r, h = R->h;
+    double *psi1 = R->k[0], *psi2 = R->k[1], *psi3 = R->k[2], *psi4 = R->k[3], *psi5 = R->k[4], *psi6 = R->k[5],
+           *psi7 = R->k[6];
+    exp_step(R, r, R->y, h, R->y, psi1);
+    exp_step(R, r, R->y, 0.5 * h, R->y, psi4);
+    exp_step(R, r + h, psi1, h, R->y, psi2);
+    average(R, psi1, psi2, psi3);
+    exp_step(R, r + 0.5 * h, psi4, 0.5 * h, psi4, psi5);
+    exp_step(R, r + h, psi5, h, R->y, psi6);
+    average(R, psi1, psi6, psi7);
+
+    double err = 0.0;
+    int finite = 1;
+    for (int64_t q = 0; q < namp; ++q) {
+        double d = fabs(psi3[q] - psi7[q]) / R->p.rtol;
+        if (!isfinite(d)) finite = 0;
+        else if (d > err) err = d;
+    }
+    if (!finite) return OR_NONFINITE;
+    R->last_err = err;
+
+    const double fmin = 0.2, fmax = 5.0;
+    double fac;
+    if (err <= 1.0) {
+        memcpy(R->y, psi7, sizeof(double) * (size_t)R->ylen);
+        if (R->p.renormalize) renormalize(R);
+        R->r = r + h;
+        R->nacc += 1;
+        fac = (err == 0.0) ? fmax : R->p.safety * pow(err, -1.0 / 3.0);
+        if (fac > fmax) fac = fmax;
+        if (fac < fmin) fac = fmin;
+        if (R->last_rejected && fac > 1.0) fac = 1.0;
+        R->last_rejected = 0;
+    } else {
+        R->nrej += 1;
+        fac = R->p.safety * pow(err, -1.0 / 3.0);
+        if (fac < fmin) fac = fmin;
+        R->last_rejected = 1;
+    }
+    double hn = h * fac;
+    if (hn > R->p.dr_max_km) hn = R->p.dr_max_km;
+    if (R->r >= R->p.r_end_km) { R->done = 1; R->h = hn; return OR_DONE; }
+    if (hn < 1e-14 * R->r) { R->h = hn; return OR_UNDERFLOW; }
+    if (R->r + hn > R->p.r_end_km) hn = R->p.r_end_km - R->r;
+    R->h = hn;
+    return OR_OK;
+}
+
+int or_step_exp(or_run* R, int64_t nattempts)
+{
+    if (R->p.frame != 1) return OR_INVALID;
+    for (int64_t s = 0; s < nattempts; ++s) {
+        if (R->done) return OR_DONE;
+        int st = exp_attempt(R);
+        if (st != OR_OK) return st;
+    }
+    return OR_OK;
+}
+
+int or_evolve_exp(or_run* R, double r_target, int64_t max_attempts)
+{
+    if (R->p.frame != 1) return OR_INVALID;
+    double save_end = R->p.r_end_km;
+    if (r_target < save_end) R->p.r_end_km = r_target;
+    if (R->r + R->h > R->p.r_end_km) R->h = R->p.r_end_km - R->r;
+    int st = OR_OK;
+    for (int64_t s = 0; (max_attempts <= 0 || s < max_attempts); ++s) {
+        if (R->r >= R->p.r_end_km) { st = OR_DONE; break; }
+        st = exp_attempt(R);
+        if (st != OR_OK) break;
+    }
+    R->p.r_end_km = save_end;
+    if (R->r < save_end) R->done = 0;
+    return st;
+}
+
 /* ------------------------------------------------------------ output */
 void or_probabilities(const or_run* R, double* p)
 {
@@ -770,6 +975,8 @@ void or_energy_average(const or_run* R, double* out)
             }
     }
 }
+
+double or_last_error(const or_run* R) { return R->last_err; }
 
 void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr)
 {

@@ -32,7 +32,8 @@ typedef struct {
     double  lambda0_km, lambda_rref_km, lambda_power;
     double  mu0_km, r_nu_km;
     double  r_start_km, r_end_km;
-    int32_t integrator;     /* 0 classic RK4 fixed step, 1 Dormand-Prince 5(4) */
+    int32_t integrator;     /* 0 classic RK4 fixed step, 1 Dormand-Prince 5(4),
+                               2 the paper's exponential stepper (lab frame) */
     int64_t n_fixed_steps;
     double  rtol, dr_init_km, dr_max_km, safety;
     int32_t frame;          /* 0 co-rotating, 1 lab */
@@ -75,11 +76,17 @@ int64_t or_state_len(const or_run* R);
 int  or_step_rk4(or_run* R, int64_t nsteps);            /* fixed-step RK4 */
 int  or_step_dp54(or_run* R, int64_t nattempts);        /* adaptive attempts */
 int  or_evolve_dp54(or_run* R, double r_target, int64_t max_attempts);
+/* the paper's exponential stepper (reading Q); frame must be 1 (lab) */
+int  or_step_exp(or_run* R, int64_t nattempts);
+int  or_evolve_exp(or_run* R, double r_target, int64_t max_attempts);
+/* u = exp(-i k t) of a Hermitian n x n matrix k (row-major, interleaved re/im) */
+void or_expm_herm(int n, const double* k, double t, double* u);
 
 void or_probabilities(const or_run* R, double* p);      /* |psi_1|^2 per beam */
 /* energy-averaged flavor content [2 species][na][n] (reading O) */
 void or_energy_average(const or_run* R, double* out);
 void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr);
+double or_last_error(const or_run* R);  /* scaled error of the last adaptive attempt */
 
 /* Tables and pieces, exposed for the tests. */
 double or_fermi_integral(int k, double eta);

@@ -100,11 +100,18 @@ def lib() -> C.CDLL:
         L.or_step_dp54.argtypes = [C.c_void_p, C.c_int64]
         L.or_evolve_dp54.restype = C.c_int
         L.or_evolve_dp54.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        L.or_step_exp.restype = C.c_int
+        L.or_step_exp.argtypes = [C.c_void_p, C.c_int64]
+        L.or_evolve_exp.restype = C.c_int
+        L.or_evolve_exp.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+        L.or_expm_herm.argtypes = [C.c_int, _P, C.c_double, _P]
         L.or_probabilities.argtypes = [C.c_void_p, _P]
         L.or_energy_average.argtypes = [C.c_void_p, _P]
         L.or_moments_azimuth.argtypes = [C.c_void_p, _P, _P]
         L.or_azimuth.argtypes = [C.c_void_p, _P]
         L.or_stats.argtypes = [C.c_void_p, _I64P, _I64P, _P, _P]
+        L.or_last_error.restype = C.c_double
+        L.or_last_error.argtypes = [C.c_void_p]
         L.or_fermi_integral.restype = C.c_double
         L.or_fermi_integral.argtypes = [C.c_int, C.c_double]
         L.or_temperature.restype = C.c_double
@@ -139,7 +146,7 @@ def params_from(w: Dict) -> _Params:
     return p
 
 
-OK, DONE, NONFINITE, UNDERFLOW = 0, 1, -4, -5
+OK, DONE, NONFINITE, UNDERFLOW, INVALID = 0, 1, -4, -5, -1
 
 
 class Run:
@@ -247,9 +254,28 @@ class Run:
     def evolve_dp54(self, r_target: float, max_attempts: int = 0) -> int:
         return int(lib().or_evolve_dp54(self.h, float(r_target), int(max_attempts)))
 
+    def step_exp(self, nattempts: int) -> int:
+        """Attempts of the paper's exponential stepper (lab frame only)."""
+        return int(lib().or_step_exp(self.h, int(nattempts)))
+
+    def evolve_exp(self, r_target: float, max_attempts: int = 0) -> int:
+        return int(lib().or_evolve_exp(self.h, float(r_target), int(max_attempts)))
+
+    def step(self, nattempts: int) -> int:
+        """Attempts (steps for RK4) of the run's own integrator."""
+        kind = int(self.w.get("integrator", 0))
+        if kind == 0:
+            return self.step_rk4(nattempts)
+        if kind == 2:
+            return self.step_exp(nattempts)
+        return self.step_dp54(nattempts)
+
     def run_to_end(self) -> int:
-        if int(self.w.get("integrator", 0)) == 0:
+        kind = int(self.w.get("integrator", 0))
+        if kind == 0:
             return self.step_rk4(int(self.w["n_fixed_steps"]))
+        if kind == 2:
+            return self.evolve_exp(float(self.w["r_end_km"]))
         return self.evolve_dp54(float(self.w["r_end_km"]))
 
     def probabilities(self) -> np.ndarray:
@@ -261,6 +287,10 @@ class Run:
         out = np.empty((2, self.na, self.n))
         lib().or_energy_average(self.h, _ptr(out))
         return out
+
+    def last_error(self) -> float:
+        """Scaled error (err / rtol) of the last adaptive attempt."""
+        return float(lib().or_last_error(self.h))
 
     def stats(self):
         a = C.c_int64()
@@ -293,6 +323,16 @@ def dp54_tableau():
     e = np.empty(7)
     lib().or_dp54_tableau(_ptr(c), _ptr(a), _ptr(e))
     return c, a.reshape(7, 6), e
+
+
+def expm_herm(k: np.ndarray, t: float) -> np.ndarray:
+    """exp(-i k t) of a Hermitian 2x2 or 3x3 matrix, as the oracle computes it."""
+    k = np.asarray(k, dtype=complex)
+    n = k.shape[0]
+    kin = np.ascontiguousarray(np.stack([k.real, k.imag], axis=-1).reshape(-1))
+    out = np.empty(2 * n * n)
+    lib().or_expm_herm(int(n), _ptr(kin), float(t), _ptr(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(n, n)
 
 
 def vacuum_coefficient() -> float:

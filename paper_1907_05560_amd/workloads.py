@@ -21,6 +21,8 @@ not datasets):
   200 energies x 1000 emission angles, embedded adaptive RK, rtol 1e-9, FP64.
 * ``multi_angle_3f_large``: 400 energies x 4000 angles (3.2M beams), FP32
   amplitudes with FP64 moments, step error and phases.
+* ``exp_stepper_3f`` / ``exp_stepper_2f``: the paper's own stepper on the
+  multi-angle three-flavor and single-angle two-flavor bulb models.
 * ``batched_runs``: 64 independent multi-angle runs with seeded uneven grids.
 * ``serving_requests``: a seeded Poisson arrival stream of such runs, each
   evolved over a short radius window from the neutrinosphere.
@@ -36,6 +38,7 @@ import numpy as np
 # Integrator and precision codes (same values as include/nuosc.h).
 RK4_FIXED = 0
 RK_DP54 = 1
+EXP_STEPPER = 2
 FP64 = 0
 FP32_AMP = 1
 FP32_AMP_FP64_MATH = 2
@@ -123,6 +126,23 @@ def extended_bulb_3f(n_energy: int = 100, n_angle: int = 100, n_azimuth: int = 3
     azimuthal symmetry)."""
     w = multi_angle_3f(n_energy, n_angle)
     w.update(n_azimuth=n_azimuth, precision=precision)
+    return w
+
+
+def exp_stepper_3f(n_energy: int = 200, n_angle: int = 1000) -> Dict:
+    """The paper's own stepper (exponential steps of eq 3.10-3.12 in the
+    half/full-step loop with averaging and max-error control) on the
+    three-flavor multi-angle bulb model, lab frame, FP64, rtol 1e-9."""
+    w = multi_angle_3f(n_energy, n_angle)
+    w.update(integrator=EXP_STEPPER, frame=FRAME_LAB, precision=FP64)
+    return w
+
+
+def exp_stepper_2f() -> Dict:
+    """The paper's own stepper on the two-flavor single-angle model (eq 3.11
+    is then the closed-form 2x2 exponential), lab frame, FP64."""
+    w = base_bulb()
+    w.update(integrator=EXP_STEPPER, frame=FRAME_LAB, precision=FP64)
     return w
 
 
