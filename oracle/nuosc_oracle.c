@@ -792,39 +792,47 @@ void or_expm_herm(int n, const double* k, double t, double* u)
     for (int i = 0; i < n * n; ++i) { u[2 * i] = U[i].re; u[2 * i + 1] = U[i].im; }
 }
 
-/* One exponential step of every beam (eq 3.10-3.12, lab frame):
- *   out_b = exp(-i K_b t) x_b,  K_b = H_b(r_s) / c_j(r_s),
- * where the Hamiltonian of beam b is formed at radius r_s from the moments of
- * state ymom (eq 3.13 and 3.4, as in rhs() with Phi = 0):
- *   neutrino      H  = H_vac(E) + H_m(r_s) + H_nunu
- *   antineutrino  Hb = conj(H_vac(E)) - H_m(r_s) - conj(H_nunu).
- * 1/c_j turns the path length of eq 3.3 into the radial step.  The phase part
- * of the flat state is copied from x unchanged (zero in the lab frame). */
-static void exp_step(const or_run* R, double rs, const double* ymom, double t, const double* x, double* out)
+/* One exponential step of every beam (eq 3.10-3.12, lab frame) from radius
+ * r_from to r_to:
+ *   out_b = exp(-i H_b dl_j) x_b,  dl_j = (r_to - r_from) / ((c_j(r_from) + c_j(r_to)) / 2),
+ * the path length of trajectory j across the step from the mean of its
+ * cosines at the two ends (Appendix A.4.3; eq 3.3).  The Hamiltonian of beam
+ * b is formed at radius r_h from the moments of state ymom (eq 3.13 and 3.4,
+ * as in rhs() with Phi = 0):
+ *   neutrino      H  = H_vac(E) + H_m(r_h) + H_nunu
+ *   antineutrino  Hb = conj(H_vac(E)) - H_m(r_h) - conj(H_nunu).
+ * The phase part of the flat state is copied from x unchanged (zero in the
+ * lab frame). */
+static void exp_step(const or_run* R, double r_h, const double* ymom, double r_from, double r_to, const double* x,
+                     double* out)
 {
     const int n = R->n, ne = R->ne, na = R->na;
     cplx J0[9], J1[9], J2[9], J3[9];
-    moments_at(R, rs, ymom, J0, J1, J2, J3); /* also leaves c_j(r_s), w_j(r_s) in R->c, R->w */
-    const double lam = matter_potential(R, rs);
+    double* cf = (double*)malloc(sizeof(double) * (size_t)na * 2);
+    double* ct = cf + na;
+    double* wtmp = (double*)malloc(sizeof(double) * (size_t)na);
+    geometry(R, r_from, cf, wtmp);
+    geometry(R, r_to, ct, wtmp);
+    free(wtmp);
+    moments_at(R, r_h, ymom, J0, J1, J2, J3); /* also leaves c_j(r_h), w_j(r_h) in R->c, R->w */
+    const double lam = matter_potential(R, r_h);
     for (int j = 0; j < na; ++j) {
-        const double cj = R->c[j];
+        const double dl = (r_to - r_from) / (0.5 * (cf[j] + ct[j]));
         cplx C[9];
         collective(R, J0, J1, J2, J3, j, C);
         for (int s = 0; s < 2; ++s)
             for (int k = 0; k < ne; ++k) {
                 const cplx* hv = &R->hvac[(size_t)k * n * n];
-                cplx K[9], U[9];
+                cplx H[9], U[9];
                 for (int a = 0; a < n; ++a)
                     for (int c = 0; c < n; ++c) {
                         const double hm = (a == c) ? lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / (double)n) : 0.0;
-                        cplx H;
                         if (s == 0)
-                            H = c_add(c_add(hv[a * n + c], c_make(hm, 0.0)), C[a * n + c]);
+                            H[a * n + c] = c_add(c_add(hv[a * n + c], c_make(hm, 0.0)), C[a * n + c]);
                         else
-                            H = c_sub(c_sub(c_conj(hv[a * n + c]), c_make(hm, 0.0)), c_conj(C[a * n + c]));
-                        K[a * n + c] = c_scale(H, 1.0 / cj);
+                            H[a * n + c] = c_sub(c_sub(c_conj(hv[a * n + c]), c_make(hm, 0.0)), c_conj(C[a * n + c]));
                     }
-                expm_herm(n, K, t, U);
+                expm_herm(n, H, dl, U);
                 const int64_t b = (int64_t)(s * na + j) * ne + k;
                 for (int a = 0; a < n; ++a) {
                     cplx acc = c_make(0, 0);
@@ -834,6 +842,7 @@ static void exp_step(const or_run* R, double rs, const double* ymom, double t, c
                 }
             }
     }
+    free(cf);
     for (int64_t q = 2 * (int64_t)n * R->nb; q < R->ylen; ++q) out[q] = x[q];
 }
 
@@ -844,12 +853,13 @@ static void average(const or_run* R, const double* a, const double* b, double* o
 
 /* One attempt of the paper's own stepper (Section 4.2.3 and the evolution
  * loop of Section 5; reading Q).  From psi0 at r with step h:
- *   H0 from psi0 at r;      psi1 = U(H0, h) psi0,  psi4 = U(H0, h/2) psi0
+ *   H0 from psi0 at r;      psi1 = U(H0; r, r+h) psi0,  psi4 = U(H0; r, r+h/2) psi0
  *   H1 from psi1 at r+h;    H2 from psi4 at r+h/2
- *   psi3 = (psi1 + U(H1, h) psi0) / 2                   full-step estimate
- *   psi5 = U(H2, h/2) psi4;  H3 from psi5 at r+h
- *   psi7 = (psi1 + U(H3, h) psi0) / 2                   two-half-step estimate
- * with U(H, t) = exp(-i K t), K = H / c_j.  Both estimates are second order and
+ *   psi3 = (psi1 + U(H1; r, r+h) psi0) / 2              full-step estimate
+ *   psi5 = U(H2; r+h/2, r+h) psi4;  H3 from psi5 at r+h
+ *   psi7 = (psi1 + U(H3; r, r+h) psi0) / 2              two-half-step estimate
+ * with U(H; r_a, r_b) the exponential step of exp_step() from r_a to r_b (path
+ * length from the mean cosine of its two ends).  Both estimates are second order and
  * differ only through the predicted end Hamiltonian (H1 from one full step,
  * H3 from two half steps), so psi3 - psi7 = O(h^3).  The error is the maximum
  * over beams, components and re/im parts of |psi3 - psi7| / rtol; an accepted
@@ -861,12 +871,13 @@ static int exp_attempt(or_run* R)
     const double r = R->r, h = R->h;
     double *psi1 = R->k[0], *psi2 = R->k[1], *psi3 = R->k[2], *psi4 = R->k[3], *psi5 = R->k[4], *psi6 = R->k[5],
            *psi7 = R->k[6];
-    exp_step(R, r, R->y, h, R->y, psi1);
-    exp_step(R, r, R->y, 0.5 * h, R->y, psi4);
-    exp_step(R, r + h, psi1, h, R->y, psi2);
+    const double rm = r + 0.5 * h, re = r + h;
+    exp_step(R, r, R->y, r, re, R->y, psi1);
+    exp_step(R, r, R->y, r, rm, R->y, psi4);
+    exp_step(R, re, psi1, r, re, R->y, psi2);
     average(R, psi1, psi2, psi3);
-    exp_step(R, r + 0.5 * h, psi4, 0.5 * h, psi4, psi5);
-    exp_step(R, r + h, psi5, h, R->y, psi6);
+    exp_step(R, rm, psi4, rm, re, psi4, psi5);
+    exp_step(R, re, psi5, r, re, R->y, psi6);
     average(R, psi1, psi6, psi7);
 
     double err = 0.0;

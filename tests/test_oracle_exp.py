@@ -192,6 +192,20 @@ def test_rejection_shrinks_the_step():
     assert R.stats()["accepted"] > 0
 
 
+def test_norm_kept_on_tangential_trajectories_near_the_neutrinosphere():
+    """Near R the cosine of the most tangential trajectories changes by orders
+    of magnitude within a step; with the path length taken from the mean cosine
+    of each evolution's two ends (Appendix A.4.3) the averaged estimates keep
+    every beam normalised to the tolerance's order."""
+    w = W.exp_stepper_3f(10, 400)
+    w.update(dr_init_km=1e-5)
+    R = O.Run(w)
+    assert R.step_exp(6) == O.OK
+    assert R.stats()["accepted"] >= 1
+    psi = R.psi_complex()
+    assert np.abs((np.abs(psi) ** 2).sum(axis=0) - 1.0).max() < 1e-8
+
+
 def test_requires_the_lab_frame():
     w = W.exp_stepper_2f()
     w.update(frame=W.FRAME_COROTATING)
