@@ -792,19 +792,20 @@ void or_expm_herm(int n, const double* k, double t, double* u)
     for (int i = 0; i < n * n; ++i) { u[2 * i] = U[i].re; u[2 * i + 1] = U[i].im; }
 }
 
-/* One exponential step of every beam (eq 3.10-3.12, lab frame) from radius
- * r_from to r_to:
- *   out_b = exp(-i H_b dl_j) x_b,  dl_j = (r_to - r_from) / ((c_j(r_from) + c_j(r_to)) / 2),
+/* One exponential step of every beam (eq 3.10-3.12, lab frame) of radial
+ * length dr from radius r_from to r_to:
+ *   out_b = exp(-i H_b dl_j) x_b,  dl_j = dr / ((c_j(r_from) + c_j(r_to)) / 2),
  * the path length of trajectory j across the step from the mean of its
- * cosines at the two ends (Appendix A.4.3; eq 3.3).  The Hamiltonian of beam
+ * cosines at the two ends (Appendix A.4.3; eq 3.3).  dr is the step itself,
+ * not r_to - r_from, which loses digits when the step is small against r.  The Hamiltonian of beam
  * b is formed at radius r_h from the moments of state ymom (eq 3.13 and 3.4,
  * as in rhs() with Phi = 0):
  *   neutrino      H  = H_vac(E) + H_m(r_h) + H_nunu
  *   antineutrino  Hb = conj(H_vac(E)) - H_m(r_h) - conj(H_nunu).
  * The phase part of the flat state is copied from x unchanged (zero in the
  * lab frame). */
-static void exp_step(const or_run* R, double r_h, const double* ymom, double r_from, double r_to, const double* x,
-                     double* out)
+static void exp_step(const or_run* R, double r_h, const double* ymom, double r_from, double r_to, double dr,
+                     const double* x, double* out)
 {
     const int n = R->n, ne = R->ne, na = R->na;
     cplx J0[9], J1[9], J2[9], J3[9];
@@ -817,7 +818,7 @@ static void exp_step(const or_run* R, double r_h, const double* ymom, double r_f
     moments_at(R, r_h, ymom, J0, J1, J2, J3); /* also leaves c_j(r_h), w_j(r_h) in R->c, R->w */
     const double lam = matter_potential(R, r_h);
     for (int j = 0; j < na; ++j) {
-        const double dl = (r_to - r_from) / (0.5 * (cf[j] + ct[j]));
+        const double dl = dr / (0.5 * (cf[j] + ct[j]));
         cplx C[9];
         collective(R, J0, J1, J2, J3, j, C);
         for (int s = 0; s < 2; ++s)
@@ -872,12 +873,12 @@ static int exp_attempt(or_run* R)
     double *psi1 = R->k[0], *psi2 = R->k[1], *psi3 = R->k[2], *psi4 = R->k[3], *psi5 = R->k[4], *psi6 = R->k[5],
            *psi7 = R->k[6];
     const double rm = r + 0.5 * h, re = r + h;
-    exp_step(R, r, R->y, r, re, R->y, psi1);
-    exp_step(R, r, R->y, r, rm, R->y, psi4);
-    exp_step(R, re, psi1, r, re, R->y, psi2);
+    exp_step(R, r, R->y, r, re, h, R->y, psi1);
+    exp_step(R, r, R->y, r, rm, 0.5 * h, R->y, psi4);
+    exp_step(R, re, psi1, r, re, h, R->y, psi2);
     average(R, psi1, psi2, psi3);
-    exp_step(R, rm, psi4, rm, re, psi4, psi5);
-    exp_step(R, re, psi5, r, re, R->y, psi6);
+    exp_step(R, rm, psi4, rm, re, 0.5 * h, psi4, psi5);
+    exp_step(R, re, psi5, r, re, h, R->y, psi6);
     average(R, psi1, psi6, psi7);
 
     double err = 0.0;
