@@ -66,7 +66,19 @@ typedef enum {
     NUOSC_E_BUSY = -7           /* batch has no free slot or memory */
 } nuosc_status;
 
-enum { NUOSC_RK4_FIXED = 0, NUOSC_RK_DP54 = 1 };
+/* Integrators.
+ *   NUOSC_RK4_FIXED    classic RK4, n_fixed_steps equal steps.
+ *   NUOSC_RK_DP54      adaptive embedded Dormand-Prince 5(4), max-norm error.
+ *   NUOSC_EXP_STEPPER  the paper's own stepper: exponential steps
+ *                      psi <- exp(-i H dl) psi (eq 3.10-3.12) inside its
+ *                      half-step / full-step loop with averaging and a
+ *                      maximum-error step control (Sections 4.2.3 and 5).
+ *                      Lab frame, FP64, the bulb model (n_azimuth <= 1), one
+ *                      run per handle (not in batches).  Per attempt: three
+ *                      beam launches and three reduction launches; an
+ *                      accepted attempt advances to the two-half-step estimate,
+ *                      the error is its max-norm distance to the full-step one. */
+enum { NUOSC_RK4_FIXED = 0, NUOSC_RK_DP54 = 1, NUOSC_EXP_STEPPER = 2 };
 /* Precision of a run.
  *   NUOSC_FP64                amplitudes stored and advanced in FP64.
  *   NUOSC_FP32_AMP            amplitudes stored and advanced in FP32, renormalised
@@ -96,9 +108,9 @@ typedef struct nuosc_params {
     double  mu0_km;                /* self-interaction strength at the neutrinosphere */
     double  r_nu_km;               /* [Rv] neutrinosphere radius R */
     double  r_start_km, r_end_km;  /* [R0] [Rn], R <= r_start < r_end */
-    int32_t integrator;            /* NUOSC_RK4_FIXED or NUOSC_RK_DP54 */
+    int32_t integrator;            /* NUOSC_RK4_FIXED, NUOSC_RK_DP54 or NUOSC_EXP_STEPPER */
     int64_t n_fixed_steps;         /* RK4: equal steps from r_start to r_end */
-    double  rtol;                  /* [eps0] DP54: max-norm error tolerance */
+    double  rtol;                  /* [eps0] adaptive integrators: max-norm error tolerance */
     double  dr_init_km;            /* [dr] first adaptive step */
     double  dr_max_km;             /* [max_dr] step cap */
     double  safety;                /* [ksi] controller safety factor in (0, 1] */
@@ -147,9 +159,11 @@ nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted
  * is picked up by the next nuosc_step / nuosc_stats call. */
 nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts);
 
-/* Queue one launch of the current attempt: stage in 1..S, where S = 4 (RK4)
- * or 7 (Dormand-Prince) and stage S forms the new state, reduces the step
- * error and runs the controller.  A full attempt is stages 1..S in order;
+/* Queue one launch of the current attempt: stage in 1..S, where S = 4 (RK4),
+ * 7 (Dormand-Prince) or 3 (exponential stepper) and stage S forms the new
+ * state, reduces the step error and runs the controller.  For the
+ * exponential stepper every stage is a beam kernel followed by a reduction
+ * kernel (the second timing interval below).  A full attempt is stages 1..S in order;
  * nuosc_enqueue_steps does exactly that.  For timing tools that bracket
  * individual kernels with events.  NUOSC_E_INVALID for a stage out of range. */
 nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage);

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnuosc.so")
-SOURCES = [os.path.join(CSRC, "nuosc_kernels.hip"), os.path.join(CSRC, "nuosc_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "nuosc_kernels.hip"), os.path.join(CSRC, "nuosc_exp.hip"),
+           os.path.join(CSRC, "nuosc_runtime.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -130,4 +130,11 @@ hipError_t launch_init_state(const RunList& runs, hipStream_t s);
 hipError_t launch_energy_average(const RunList& runs, double* out_dev, hipStream_t s);
 int num_stages(int integrator);
 
+// The paper's own stepper (exponential steps with averaging, lab frame, FP64):
+// launch `stage` 1..kExpLaunches of an attempt (a beam kernel and a reduction
+// kernel; the last reduction is the step control), or 0: J of the current
+// state.  One run per call.  ev as for launch_stage.
+constexpr int kExpLaunches = 3;
+hipError_t launch_exp_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
+
 }  // namespace nuosc

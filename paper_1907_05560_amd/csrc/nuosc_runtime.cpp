@@ -204,9 +204,15 @@ const char* validate(const nuosc_params* p)
     if (!(p->r_nu_km > 0.0)) return "r_nu must be > 0";
     if (!(p->r_start_km >= p->r_nu_km)) return "r_start must be >= r_nu";
     if (!(p->r_end_km > p->r_start_km)) return "r_end must be > r_start";
-    if (p->integrator != NUOSC_RK4_FIXED && p->integrator != NUOSC_RK_DP54) return "unknown integrator";
+    if (p->integrator != NUOSC_RK4_FIXED && p->integrator != NUOSC_RK_DP54 && p->integrator != NUOSC_EXP_STEPPER)
+        return "unknown integrator";
     if (p->integrator == NUOSC_RK4_FIXED && p->n_fixed_steps < 1) return "n_fixed_steps must be >= 1";
-    if (p->integrator == NUOSC_RK_DP54) {
+    if (p->integrator == NUOSC_EXP_STEPPER) {
+        if (p->frame != NUOSC_FRAME_LAB) return "the exponential stepper runs in the lab frame (frame = NUOSC_FRAME_LAB)";
+        if (p->precision != NUOSC_FP64) return "the exponential stepper runs in FP64 (precision = NUOSC_FP64)";
+        if (p->n_azimuth > 1) return "the exponential stepper runs the bulb model (n_azimuth <= 1)";
+    }
+    if (p->integrator != NUOSC_RK4_FIXED) {
         if (!(p->rtol > 0.0)) return "rtol must be > 0";
         if (!(p->dr_init_km > 0.0) || !(p->dr_max_km > 0.0)) return "dr_init and dr_max must be > 0";
         if (!(p->safety > 0.0 && p->safety <= 1.0)) return "safety must be in (0, 1]";
@@ -331,6 +337,10 @@ nuosc_status status_of(const Control& c, std::string& err)
 nuosc_status restart(RunState& r, hipStream_t s, std::string& err)
 {
     OneRun one(r);
+    if (r.rc.integrator == NUOSC_EXP_STEPPER) {
+        HIP_CHECK(nuosc::launch_exp_stage(one.list, 0, s), err);
+        return NUOSC_OK;
+    }
     HIP_CHECK(nuosc::launch_prepare(one.list, s), err);
     HIP_CHECK(nuosc::launch_stage(one.list, 0, s), err);
     return NUOSC_OK;
@@ -353,7 +363,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     }
     r.p = *p;
     r.L = make_layout(*p);
-    r.S = nuosc::num_stages(p->integrator);
+    r.S = p->integrator == NUOSC_EXP_STEPPER ? nuosc::kExpLaunches : nuosc::num_stages(p->integrator);
     r.base = base;
     r.runs_dev = runs_dev;
     r.slot = slot;
@@ -529,7 +539,10 @@ nuosc_status stage(nuosc_handle* h, int st)
         h->ev_used += 1;
     }
     OneRun one(h->run);
-    HIP_CHECK(nuosc::launch_stage(one.list, st, h->stream, ev), h->err);
+    if (h->run.rc.integrator == NUOSC_EXP_STEPPER)
+        HIP_CHECK(nuosc::launch_exp_stage(one.list, st, h->stream, ev), h->err);
+    else
+        HIP_CHECK(nuosc::launch_stage(one.list, st, h->stream, ev), h->err);
     return NUOSC_OK;
 }
 
@@ -697,7 +710,7 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
     // resume towards the new target
     c.r_end = target;
     c.status = 0;
-    if (h->run.p.integrator == NUOSC_RK_DP54) c.h = std::min(c.h_prop, target - c.r);
+    if (h->run.p.integrator != NUOSC_RK4_FIXED) c.h = std::min(c.h_prop, target - c.r);
     st = hwrite(h);
     if (st != NUOSC_OK) return st;
     st = checked(h, restart(h->run, h->stream, h->err), h->err);  // stage tables for the (possibly clipped) step
