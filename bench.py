@@ -262,6 +262,71 @@ def extended(nuosc, W, torch, precision, attempts, warmup=5):
         run.close()
 
 
+EXP_VALU_FILE = os.path.join(ROOT, "profiles", "exp_valu.json")
+# wavefront-instruction issue peak of the vector ALUs: 256 CUs x 4 SIMDs, one
+# 64-lane FP64 (or unpacked FP32) instruction per SIMD every 4 cycles at 2.4 GHz
+PEAK_VALU_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 4
+
+
+def exp_stepper(nuosc, W, torch, attempts, warmup=10):
+    """The paper's own stepper (exponential steps of eq 3.10-3.12 in the
+    half/full-step loop with averaging and max-error control) on the 400 x
+    4000 x 2 grid, lab frame, FP64, rtol 1e-9, from 10 km: beam-steps/s over
+    `attempts` attempts after `warmup`, per-launch kernel times, the HBM view
+    of its state traffic (each of the three beam launches reads psi_n once,
+    the third also writes psi_{n+1}) and, from the committed rocprofv3 VALU
+    instruction counts of the same kernels, the fraction of the vector-ALU
+    issue peak it reaches (the kernels are bound by VALU issue)."""
+    from paper_1907_05560_amd.profile_summary import exp_source_hash
+
+    w = W.exp_stepper_3f(400, 4000)
+    run = nuosc.Run.with_torch(w)
+    try:
+        run.step(warmup)
+        s0 = run.stats()
+        stream = run.torch_stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run.enqueue_steps(attempts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        s1 = run.stats()
+        run.timing_enable(True)
+        run.enqueue_steps(attempts)
+        beam, fin, cnt = run.timing_read()
+        run.timing_enable(False)
+        acc = s1["accepted"] - s0["accepted"]
+        rej = s1["rejected"] - s0["rejected"]
+        n = [max(int(c), 1) for c in cnt]
+        launch_us = [round(1e3 * beam[i] / n[i], 2) for i in range(1, 4)]
+        reduce_us = [round(1e3 * fin[i] / n[i], 2) for i in range(1, 4)]
+        state = 2 * 3 * 8 * run.nb
+        hbm_bytes = [state, state, 2 * state]
+        hbm = [round(b / (u * 1e3), 1) for b, u in zip(hbm_bytes, launch_us)]
+        out = {"workload": "the paper's exponential stepper, 3-flavor multi-angle bulb model, 400 E x 4000 angles "
+                           "x 2 species, lab frame, FP64, rtol 1e-9, from r = 10 km",
+               "beams": run.nb, "attempts": attempts, "accepted": acc, "rejected": rej,
+               "ms_per_step": ms / attempts, "value": run.nb * acc / (ms / 1e3),
+               "attempt_rate": run.nb * attempts / (ms / 1e3), "unit": "beam-steps/s",
+               "launch_us": launch_us, "reduce_us": reduce_us,
+               "hbm": {"alg_bytes_per_launch": hbm_bytes, "achieved_gbs": hbm, "peak_gbs": PEAK_HBM_GBS,
+                       "frac": [round(g / PEAK_HBM_GBS, 4) for g in hbm]},
+               "valu": None}
+        if os.path.exists(EXP_VALU_FILE):
+            t = json.load(open(EXP_VALU_FILE))
+            if t.get("source_sha256_16") == exp_source_hash():
+                ins = [t["valu_wave_instr_per_launch"].get(f"launch{i}") for i in (1, 2, 3)]
+                if all(ins):
+                    frac = [round(i / (u * 1e-6) / PEAK_VALU_WAVE_INSTR_S, 4) for i, u in zip(ins, launch_us)]
+                    out["valu"] = {"wave_instr_per_launch": ins, "peak_wave_instr_s": PEAK_VALU_WAVE_INSTR_S,
+                                   "issue_frac": frac}
+        return out
+    finally:
+        run.close()
+
+
 def batched(nuosc, W, torch, attempts):
     """The 64-run batched workload: every run admitted into one batch and
     advanced together; aggregate beam-steps/s over `attempts` attempts."""
@@ -316,6 +381,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extended-attempts", type=int, default=50,
                     help="attempts of the extended bulb model workload (0: skip)")
+    ap.add_argument("--exp-attempts", type=int, default=30,
+                    help="attempts of the paper's exponential stepper on the 400x4000 grid (0: skip)")
     ap.add_argument("--forms", default="fp32,fp32math64,fp64",
                     help="precision forms to run (the first is the headline value)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -402,6 +469,12 @@ def main() -> int:
             line["extended"][name] = ex
             print(f"bench: extended {name}: {ex['ms_per_step']:.3f} ms/step, {ex['value']:.3e} beam-steps/s",
                   file=sys.stderr, flush=True)
+    if args.exp_attempts > 0:
+        print(f"bench: exponential stepper ({args.exp_attempts} attempts)", file=sys.stderr, flush=True)
+        ex = exp_stepper(nuosc, W, torch, args.exp_attempts)
+        line["exp_stepper"] = ex
+        print(f"bench: exponential stepper: {ex['ms_per_step']:.3f} ms/attempt, {ex['value']:.3e} beam-steps/s, "
+              f"launches {ex['launch_us']} us, reductions {ex['reduce_us']} us", file=sys.stderr, flush=True)
     if args.batched_attempts > 0:
         print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)
         line["batched"] = batched(nuosc, W, torch, args.batched_attempts)

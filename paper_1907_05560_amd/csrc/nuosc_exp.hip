@@ -122,6 +122,49 @@ __device__ __forceinline__ void herm_apply(const double* K, const double* x, dou
         }
 }
 
+// sin and cos of x.  For |x| < 1e6: x = k pi/2 + r, pi/2 split into three
+// doubles whose products with k are subtracted with one rounding each (fma;
+// the reduction of Cody and Waite), then the Taylor series of sin and cos to
+// r^17 and r^18 on |r| <= pi/4 (truncation below 1e-19) and the quadrant
+// k mod 4.  Larger arguments go to the library.
+__device__ __forceinline__ void xsincos(double x, double& s, double& c)
+{
+    if (!(fabs(x) < 1.0e6)) {
+        sincos(x, &s, &c);
+        return;
+    }
+    const double k = rint(x * 0.6366197723675814);  // 2 / pi
+    double r = fma(-k, 1.5707963267948966, x);
+    r = fma(-k, 6.123233995736766e-17, r);
+    r = fma(-k, -1.4973849048591698e-33, r);
+    const double z = r * r;
+    // (-1)^n / (2n+1)!, n = 1..8, and (-1)^n / (2n)!, n = 1..9
+    double ps = 2.8114572543455206e-15;
+    ps = fma(ps, z, -7.647163731819816e-13);
+    ps = fma(ps, z, 1.6059043836821613e-10);
+    ps = fma(ps, z, -2.505210838544172e-08);
+    ps = fma(ps, z, 2.7557319223985893e-06);
+    ps = fma(ps, z, -0.0001984126984126984);
+    ps = fma(ps, z, 0.008333333333333333);
+    ps = fma(ps, z, -0.16666666666666666);
+    const double sr = fma(r * z, ps, r);
+    double pc = -1.5619206968586225e-16;
+    pc = fma(pc, z, 4.779477332387385e-14);
+    pc = fma(pc, z, -1.1470745597729725e-11);
+    pc = fma(pc, z, 2.08767569878681e-09);
+    pc = fma(pc, z, -2.755731922398589e-07);
+    pc = fma(pc, z, 2.48015873015873e-05);
+    pc = fma(pc, z, -0.001388888888888889);
+    pc = fma(pc, z, 0.041666666666666664);
+    pc = fma(pc, z, -0.5);
+    const double cr = fma(z, pc, 1.0);
+    const int q = (int)k & 3;
+    s = (q & 1) ? cr : sr;
+    c = (q & 1) ? sr : cr;
+    if (q == 1 || q == 2) c = -c;
+    if (q & 2) s = -s;
+}
+
 // sin(w) / w
 __device__ __forceinline__ double sinc_of(double w, double sw)
 {
@@ -156,13 +199,21 @@ __device__ __forceinline__ Spec spectrum_of(const double* K)
         const double c0 = d0 * d1 * d2 - d0 * nc - d1 * nb - d2 * na + 2.0 * acb.re;
         s.zero = !(c1 > 0.0);
         s.neg = c0 < 0.0;
-        const double r3 = sqrt(c1 / 3.0);
-        const double c0max = 2.0 * r3 * r3 * r3;
-        const double ct = s.zero ? 1.0 : fmin(fabs(c0) / c0max, 1.0);
-        double st3, ct3;
-        sincos(acos(ct) / 3.0, &st3, &ct3);
-        s.ub = r3 * ct3;
-        s.wb = sqrt(c1) * st3;
+        // largest eigenvalue 2u of K for |c0|: the largest root of
+        // q^3 - c1 q - |c0| = 0, by Newton's method from its upper bound
+        // 2 sqrt(c1/3) (the cubic is convex there: monotone convergence);
+        // then w^2 = c1 - 3u^2 (c1 = 3u^2 + w^2)
+        const double ac0 = fabs(c0);
+        double q = 2.0 * sqrt(c1 / 3.0);
+        if (!s.zero) {
+#pragma unroll
+            for (int it = 0; it < 5; ++it) {
+                const double q2 = q * q;
+                q -= fma(q, q2 - c1, -ac0) / fma(3.0, q2, -c1);
+            }
+        }
+        s.ub = 0.5 * q;
+        s.wb = sqrt(fmax(fma(-3.0 * s.ub, s.ub, c1), 0.0));
     }
     return s;
 }
@@ -179,9 +230,9 @@ __device__ __forceinline__ Angles angles_of(const Spec& s, double t)
     g.t = t;
     g.u = s.ub * t;
     g.w = s.wb * t;
-    sincos(g.u, &g.su, &g.cu);
+    xsincos(g.u, g.su, g.cu);
     if constexpr (N == 3) {
-        sincos(g.w, &g.sw, &g.cw);
+        xsincos(g.w, g.sw, g.cw);
         g.xi = sinc_of(g.w, g.sw);
     } else {
         g.cw = 1.0;
@@ -382,12 +433,16 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
                 if constexpr (L == 1) {
                     double p1[2 * N], p4[2 * N];
                     combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
-                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
                     add_density<N>(wt, p1, acc[0]);
+                    __builtin_amdgcn_sched_barrier(0);  // one exponential at a time
+                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
                     add_density<N>(wt, p4, acc[SETS - 1]);
                 } else if constexpr (L == 2) {
                     double p4[2 * N], p5[2 * N];
                     combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
+                    // one exponential at a time keeps the register file within one
+                    // wavefront's share (interleaved, the two spill)
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][1][1][v], sAB[wave][1][0][v]);
                     const Spec s2 = spectrum_of<N>(K);
@@ -396,23 +451,31 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
                     combine<N>(coef_of<N>(s2, angles_of<N>(s2, dl_h2)), p4, kx, kkx, p5);
                     add_density<N>(wt, p5, acc[0]);
                 } else {
-                    double p1[2 * N], p2[2 * N], p6[2 * N];
+                    // one exponential at a time (interleaved, they spill); only psi1
+                    // and the full-step estimate psi3 stay live between them
+                    double p1[2 * N], p3[2 * N], pk[2 * N];
                     combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int k = 1; k < 3; ++k) {
+                    for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][1][1][v], sAB[wave][1][0][v]);
+                    const Spec s1 = spectrum_of<N>(K);
+                    herm_apply<N>(K, x0, kx);
+                    if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
+                    combine<N>(coef_of<N>(s1, angles_of<N>(s1, dl_full)), x0, kx, kkx, pk);
 #pragma unroll
-                        for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][k][1][v], sAB[wave][k][0][v]);
-                        const Spec sk = spectrum_of<N>(K);
-                        herm_apply<N>(K, x0, kx);
-                        if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
-                        combine<N>(coef_of<N>(sk, angles_of<N>(sk, dl_full)), x0, kx, kkx, k == 1 ? p2 : p6);
-                    }
+                    for (int q = 0; q < 2 * N; ++q) p3[q] = 0.5 * (p1[q] + pk[q]);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][2][1][v], sAB[wave][2][0][v]);
+                    const Spec s3 = spectrum_of<N>(K);
+                    herm_apply<N>(K, x0, kx);
+                    if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
+                    combine<N>(coef_of<N>(s3, angles_of<N>(s3, dl_full)), x0, kx, kkx, pk);
                     double p7[2 * N];
 #pragma unroll
                     for (int q = 0; q < 2 * N; ++q) {
-                        const double p3 = 0.5 * (p1[q] + p2[q]);
-                        p7[q] = 0.5 * (p1[q] + p6[q]);
-                        emax = fmax(emax, fabs(p3 - p7[q]));
+                        p7[q] = 0.5 * (p1[q] + pk[q]);
+                        emax = fmax(emax, fabs(p3[q] - p7[q]));
                         dst[q * ld + b] = p7[q];
                     }
                     add_density<N>(wt, p7, acc[0]);
@@ -505,15 +568,17 @@ __device__ bool exp_control(const RunConst& rc, Control& C, double m)
 // c + CH, ... of value v; one thread per value adds the CH chunk sums), into
 // jhist slots L0: 0;  L1: 1 (psi1), 2 (psi4);  L2: 3 (psi5);  L3: the next
 // attempt's slot 0 if accepted, with the error maximum and the controller.
+constexpr int kExpRed = 1024;  // threads of a reduction launch
+
 template <int N, int L>
-__global__ void __launch_bounds__(kFinBlock) k_exp_reduce(const RunConst rc)
+__global__ void __launch_bounds__(kExpRed) k_exp_reduce(const RunConst rc)
 {
     constexpr int NM = N * N;
     constexpr int NV = (L == 1 ? 2 : 1) * 2 * NM;
-    constexpr int CH = kFinBlock / NV;
+    constexpr int CH = kExpRed / NV;
     __shared__ double sred[NV][CH];
     __shared__ double sJ[NV];
-    __shared__ double serr[kFinBlock / 64];
+    __shared__ double serr[kExpRed / 64];
     if (L != 0 && rc.ctrl[0].status != 0) return;
     const int t = threadIdx.x;
     const int nblk = rc.nblk;
@@ -521,7 +586,15 @@ __global__ void __launch_bounds__(kFinBlock) k_exp_reduce(const RunConst rc)
         const int v = t / CH, c = t - v * CH;
         const double* pv = rc.partial + (size_t)v * nblk;
         double acc = 0.0;
-        for (int p = c; p < nblk; p += CH) acc += pv[p];
+        int p = c;
+        for (; p + 3 * CH < nblk; p += 4 * CH) {  // four loads in flight, added in order
+            const double x0 = pv[p], x1 = pv[p + CH], x2 = pv[p + 2 * CH], x3 = pv[p + 3 * CH];
+            acc += x0;
+            acc += x1;
+            acc += x2;
+            acc += x3;
+        }
+        for (; p < nblk; p += CH) acc += pv[p];
         sred[v][c] = acc;
     }
     __syncthreads();
@@ -539,12 +612,12 @@ __global__ void __launch_bounds__(kFinBlock) k_exp_reduce(const RunConst rc)
         if (t < NV) rc.jhist[3 * 2 * NM + t] = sJ[t];
     } else {
         double m = 0.0;
-        for (int p = t; p < nblk; p += kFinBlock) m = fmax(m, rc.errpart[p]);
+        for (int p = t; p < nblk; p += kExpRed) m = fmax(m, rc.errpart[p]);
         m = xwave_max(m);
         if ((t & 63) == 0) serr[t >> 6] = m;
         __syncthreads();
         if (t == 0) {
-            for (int w = 1; w < kFinBlock / 64; ++w) m = fmax(m, serr[w]);
+            for (int w = 1; w < kExpRed / 64; ++w) m = fmax(m, serr[w]);
             Control c = rc.ctrl[0];
             if (exp_control(rc, c, m))
                 for (int v = 0; v < NV; ++v) rc.jhist[v] = sJ[v];
@@ -570,7 +643,7 @@ hipError_t launch_n(const RunConst& rc, int stage, hipStream_t s, hipEvent_t* ev
     hipLaunchKernelGGL(beam, dim3((unsigned)rc.nblk), dim3(kExpBlock), 0, s, rc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(red, dim3(1), dim3(kFinBlock), 0, s, rc);
+    hipLaunchKernelGGL(red, dim3(1), dim3(kExpRed), 0, s, rc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return hipSuccess;

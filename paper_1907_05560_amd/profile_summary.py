@@ -22,6 +22,8 @@ Usage::
     python -m paper_1907_05560_amd.profile_summary traffic --fetch <csv> --write <csv> \
         --copy-mib M --command-fetch "..." --command-write "..." \
         --json profiles/traffic.json > profiles/y.md
+    python -m paper_1907_05560_amd.profile_summary valu <counter_collection.csv> --command "..." \
+        --json profiles/exp_valu.json > profiles/z.md
 """
 
 from __future__ import annotations
@@ -37,12 +39,48 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(_HERE, "csrc", "nuosc_kernels.hip")
+EXP_SRC = os.path.join(_HERE, "csrc", "nuosc_exp.hip")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
 def kernel_source_hash() -> str:
     with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def exp_source_hash() -> str:
+    """Hash of the exponential-stepper kernel source (nuosc_exp.hip)."""
+    with open(EXP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def exp_launch(name: str):
+    """Beam launch (1..3) of a three-flavor exponential-stepper kernel, or None."""
+    m = re.search(r"k_exp_beam<3,(\d)>", short_name(name))
+    return int(m.group(1)) if m and m.group(1) != "0" else None
+
+
+def valu_summary(csv_path: str, command: str):
+    """VALU wavefront-instruction counts (rocprofv3 SQ_INSTS_VALU) of the
+    exponential-stepper beam kernels, per launch (full dispatches only)."""
+    per = _counter_means(csv_path, "SQ_INSTS_VALU")
+    waves = _counter_means(csv_path, "SQ_WAVES")
+    lines = ["# VALU instructions of the exponential-stepper beam kernels (rocprofv3 SQ_INSTS_VALU)", "",
+             "Command:", "", "```", command, "```", "",
+             f"Kernel source (nuosc_exp.hip) sha256[:16]: `{exp_source_hash()}`", "",
+             "| kernel | dispatches | VALU wave-instructions / dispatch | waves / dispatch | per wave |",
+             "|---|---|---|---|---|"]
+    doc = {"source_sha256_16": exp_source_hash(), "valu_wave_instr_per_launch": {}}
+    for name in sorted(per, key=lambda n: (exp_launch(n) or 9, n)):
+        L = exp_launch(name)
+        if L is None:
+            continue
+        v = _full(per[name])
+        wv = _full(waves.get(name, [])) or [0.0]
+        vm, wm = sum(v) / len(v), sum(wv) / len(wv)
+        lines.append(f"| `{short_name(name)}` | {len(v)} | {vm:.4g} | {wm:.0f} | {vm / wm if wm else 0:.0f} |")
+        doc["valu_wave_instr_per_launch"][f"launch{L}"] = round(vm)
+    return "\n".join(lines) + "\n", doc
 
 
 def short_name(name: str) -> str:
@@ -166,7 +204,18 @@ def main(argv=None) -> int:
     f.add_argument("--command-fetch", required=True)
     f.add_argument("--command-write", required=True)
     f.add_argument("--json", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("counter_csv")
+    v.add_argument("--command", required=True)
+    v.add_argument("--json", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "valu":
+        text, doc = valu_summary(a.counter_csv, a.command)
+        with open(a.json, "w") as fh:
+            json.dump(doc, fh, indent=1)
+            fh.write("\n")
+        sys.stdout.write(text)
+        return 0
     if a.cmd == "trace":
         sys.stdout.write(trace_summary(a.trace_csv, a.command))
     else:

@@ -55,3 +55,21 @@ def test_traffic_is_scaled_by_the_calibration_copy(tmp_path):
     assert doc["write_scale"] == pytest.approx(1.0)
     assert doc["bytes_per_launch"]["stage6_prec1"] == round(1000 * 1024 * 0.5 + 500 * 1024)
     assert "k_stage_one<float,float,3,DP54,6,2>" in text
+
+
+def test_valu_summary_reads_the_exponential_stepper_launches(tmp_path):
+    def nm(L):
+        return f"void {NS}k_exp_beam<3, {L}>(nuosc::RunConst)"
+
+    rows = [(nm(1), 1000.0), (nm(1), 1000.0), (nm(3), 3000.0), (nm(0), 50.0), (nm(2), 2000.0), (nm(2), 10.0)]
+    path = tmp_path / "v.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": value})
+            w.writerow({"Kernel_Name": name, "Counter_Name": "SQ_WAVES", "Counter_Value": 10.0})
+    text, doc = PS.valu_summary(str(path), "cmd")
+    assert doc["valu_wave_instr_per_launch"] == {"launch1": 1000, "launch2": 2000, "launch3": 3000}
+    assert doc["source_sha256_16"] == PS.exp_source_hash()
+    assert "k_exp_beam<3,2>" in text and PS.exp_launch(nm(0)) is None
