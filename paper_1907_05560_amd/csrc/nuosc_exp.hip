@@ -17,17 +17,19 @@
 // The two Hamiltonian reductions the paper fuses (H1 and H2 from the first
 // two evolutions) are one reduction here too.  Per attempt: three beam
 // launches, each followed by one small reduction launch:
-//   k_exp_beam<1>: psi1, psi4; weighted density sums of both;
+//   k_exp_beam<1>: psi1, psi4 (both written); weighted density sums of both;
 //   k_exp_reduce<1>: J of psi1 (at r + h) and of psi4 (at r + h/2);
-//   k_exp_beam<2>: psi4 again, psi5; its density sums;
+//   k_exp_beam<2>: psi5 from psi4; its density sums;
 //   k_exp_reduce<2>: J of psi5 (at r + h);
-//   k_exp_beam<3>: psi1, U(H1) psi0, U(H3) psi0, psi3, psi7, the error;
+//   k_exp_beam<3>: U(H1) psi0, U(H3) psi0, psi3, psi7 (with psi1), the error;
 //     writes psi7 and its density sums;
 //   k_exp_reduce<3>: error maximum, step control, J of the next attempt's H0
 //     (of psi7 if accepted, else unchanged).
 // Launch 0 (k_exp_beam<0>, k_exp_reduce<0>) forms J of the current state.
-// No intermediate state is stored: each beam launch reads psi0 once and
-// recomputes what it needs; only launch 3 writes (psi7).
+// The kernels are bound by vector-ALU issue, with HBM mostly idle: launch 1
+// stores psi1 and psi4 (FP64) for launches 3 and 2 rather than have them
+// recompute the two exponentials; launch 2 reads psi4 only, launch 3 psi0
+// and psi1, and writes psi7.
 //
 // Beams: one wavefront per trajectory j, lanes over its 2 N_E beam slots,
 // eight trajectories per workgroup (one partial density sum per workgroup,
@@ -356,7 +358,7 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
     constexpr int NM = N * N;
     constexpr int SETS = (L == 1) ? 2 : 1;           // density sums formed by this launch
     constexpr int NV = SETS * 2 * NM;                 // J0, J1 per set
-    constexpr int NK = (L == 0) ? 0 : (L == 3 ? 3 : (L == 2 ? 2 : 1));  // Hamiltonians used
+    constexpr int NK = (L == 0) ? 0 : (L == 3 ? 2 : 1);  // Hamiltonians used
     __shared__ double sAB[kExpTraj][3][2][NM];
     __shared__ double sP[kExpTraj][NV];
     __shared__ double sE[kExpTraj];
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
     const double r = C.r, h = C.h;
 
     // Hamiltonian k of this launch: J slot and radius
-    //   L1: K0 (slot 0, r);  L2: K0, K2 (slot 2, r + h/2);  L3: K0, K1 (slot 1, r + h), K3 (slot 3, r + h)
+    //   L1: H0 (slot 0, r);  L2: H2 (slot 2, r + h/2);  L3: H1 (slot 1, r + h), H3 (slot 3, r + h)
     // cosines and weights at r, r + h/2, r + h; path lengths of the full step
     // and of the two half steps
     double cs[3] = {1.0, 1.0, 1.0}, ws[3] = {0.0, 0.0, 0.0};
@@ -387,8 +389,8 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
         xgeometry(rc, j, r + h, cs[2], ws[2]);
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            const int set = k == 0 ? 0 : (L == 2 ? 2 : (k == 1 ? 1 : 3));
-            const int at = k == 0 ? 0 : (L == 2 ? 1 : 2);
+            const int set = L == 1 ? 0 : (L == 2 ? 2 : (k == 0 ? 1 : 3));
+            const int at = L == 1 ? 0 : (L == 2 ? 1 : 2);
             const double rs = r + 0.5 * h * (double)at;
             if (lane < NM) traj_tables<N>(rc, set, rs, cs[at], lane, sAB[wave][k][0], sAB[wave][k][1]);
         }
@@ -409,9 +411,12 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
     double emax = 0.0;
 
     const int cur = C.cur;
-    const double* __restrict__ src = reinterpret_cast<const double*>(rc.psi[cur]);
-    double* __restrict__ dst = reinterpret_cast<double*>(rc.psi[cur ^ 1]);
     const size_t ld = (size_t)rc.nb_pad;
+    // launch 2 starts from psi4, the others from psi0
+    const double* __restrict__ src = L == 2 ? rc.xbuf + 2 * N * ld : reinterpret_cast<const double*>(rc.psi[cur]);
+    double* __restrict__ dst = reinterpret_cast<double*>(rc.psi[cur ^ 1]);
+    double* __restrict__ x1 = rc.xbuf;            // psi1
+    double* __restrict__ x4 = rc.xbuf + 2 * N * ld;  // psi4
     const int ne = rc.ne;
     if (live) {
         for (int t = lane; t < 2 * ne; t += 64) {
@@ -423,63 +428,63 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
             for (int q = 0; q < 2 * N; ++q) x0[q] = src[q * ld + b];
             if constexpr (L == 0) {
                 add_density<N>(wt, x0, acc[0]);
-            } else {
+            } else if constexpr (L == 1) {
                 double K[NM], kx[2 * N], kkx[2 * N];
 #pragma unroll
                 for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][0][1][v], sAB[wave][0][0][v]);
                 const Spec s0 = spectrum_of<N>(K);
                 herm_apply<N>(K, x0, kx);
                 if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
-                if constexpr (L == 1) {
-                    double p1[2 * N], p4[2 * N];
-                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
-                    add_density<N>(wt, p1, acc[0]);
-                    __builtin_amdgcn_sched_barrier(0);  // one exponential at a time
-                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
-                    add_density<N>(wt, p4, acc[SETS - 1]);
-                } else if constexpr (L == 2) {
-                    double p4[2 * N], p5[2 * N];
-                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
-                    // one exponential at a time keeps the register file within one
-                    // wavefront's share (interleaved, the two spill)
-                    __builtin_amdgcn_sched_barrier(0);
+                double p1[2 * N], p4[2 * N];
+                combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
+                add_density<N>(wt, p1, acc[0]);
 #pragma unroll
-                    for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][1][1][v], sAB[wave][1][0][v]);
-                    const Spec s2 = spectrum_of<N>(K);
-                    herm_apply<N>(K, p4, kx);
-                    if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
-                    combine<N>(coef_of<N>(s2, angles_of<N>(s2, dl_h2)), p4, kx, kkx, p5);
-                    add_density<N>(wt, p5, acc[0]);
-                } else {
-                    // one exponential at a time (interleaved, they spill); only psi1
-                    // and the full-step estimate psi3 stay live between them
-                    double p1[2 * N], p3[2 * N], pk[2 * N];
-                    combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int q = 0; q < 2 * N; ++q) x1[q * ld + b] = p1[q];
+                __builtin_amdgcn_sched_barrier(0);  // one exponential at a time
+                combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
+                add_density<N>(wt, p4, acc[SETS - 1]);
 #pragma unroll
-                    for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][1][1][v], sAB[wave][1][0][v]);
-                    const Spec s1 = spectrum_of<N>(K);
-                    herm_apply<N>(K, x0, kx);
-                    if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
-                    combine<N>(coef_of<N>(s1, angles_of<N>(s1, dl_full)), x0, kx, kkx, pk);
+                for (int q = 0; q < 2 * N; ++q) x4[q * ld + b] = p4[q];
+            } else if constexpr (L == 2) {
+                // x0 holds psi4 here
+                double K[NM], kx[2 * N], kkx[2 * N], p5[2 * N];
 #pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) p3[q] = 0.5 * (p1[q] + pk[q]);
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][0][1][v], sAB[wave][0][0][v]);
+                const Spec s2 = spectrum_of<N>(K);
+                herm_apply<N>(K, x0, kx);
+                if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
+                combine<N>(coef_of<N>(s2, angles_of<N>(s2, dl_h2)), x0, kx, kkx, p5);
+                add_density<N>(wt, p5, acc[0]);
+            } else {
+                // one exponential at a time (interleaved, they spill); psi1 (stored
+                // by launch 1) and the full-step estimate psi3 stay live between them
+                double K[NM], kx[2 * N], kkx[2 * N];
+                double p1[2 * N], p3[2 * N], pk[2 * N];
 #pragma unroll
-                    for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][2][1][v], sAB[wave][2][0][v]);
-                    const Spec s3 = spectrum_of<N>(K);
-                    herm_apply<N>(K, x0, kx);
-                    if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
-                    combine<N>(coef_of<N>(s3, angles_of<N>(s3, dl_full)), x0, kx, kkx, pk);
-                    double p7[2 * N];
+                for (int q = 0; q < 2 * N; ++q) p1[q] = x1[q * ld + b];
 #pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) {
-                        p7[q] = 0.5 * (p1[q] + pk[q]);
-                        emax = fmax(emax, fabs(p3[q] - p7[q]));
-                        dst[q * ld + b] = p7[q];
-                    }
-                    add_density<N>(wt, p7, acc[0]);
+                for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][0][1][v], sAB[wave][0][0][v]);
+                const Spec s1 = spectrum_of<N>(K);
+                herm_apply<N>(K, x0, kx);
+                if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
+                combine<N>(coef_of<N>(s1, angles_of<N>(s1, dl_full)), x0, kx, kkx, pk);
+#pragma unroll
+                for (int q = 0; q < 2 * N; ++q) p3[q] = 0.5 * (p1[q] + pk[q]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][1][1][v], sAB[wave][1][0][v]);
+                const Spec s3 = spectrum_of<N>(K);
+                herm_apply<N>(K, x0, kx);
+                if constexpr (N == 3) herm_apply<N>(K, kx, kkx);
+                combine<N>(coef_of<N>(s3, angles_of<N>(s3, dl_full)), x0, kx, kkx, pk);
+                double p7[2 * N];
+#pragma unroll
+                for (int q = 0; q < 2 * N; ++q) {
+                    p7[q] = 0.5 * (p1[q] + pk[q]);
+                    emax = fmax(emax, fabs(p3[q] - p7[q]));
+                    dst[q * ld + b] = p7[q];
                 }
+                add_density<N>(wt, p7, acc[0]);
             }
         }
     }

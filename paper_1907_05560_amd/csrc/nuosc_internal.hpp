@@ -81,6 +81,8 @@ struct RunConst {
     double* errpart;             // [nblk]
     void* errv;                  // [2n][nb_pad] of the arithmetic type: sum_{i<S-1} e_i k_i of
                                  // an embedded first-same-as-last pair (else unused)
+    double* xbuf;                // [2][2n][nb_pad] FP64: psi1 and psi4 of the exponential stepper's
+                                 // attempt (else unused)
     void* mat;                   // [kMaxStages][na] StageMat<T, n>
     TrajGeo* geo;                // [kMaxStages + 1][na]
     Control* ctrl;               // [2]

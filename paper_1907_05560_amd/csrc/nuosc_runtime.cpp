@@ -178,7 +178,8 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, flux, azi, mat, geo, ctrl, prob, eavg, rconst, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, xbuf, flux, azi, mat, geo, ctrl, prob, eavg,
+        rconst, total;
     int64_t nb, nb_pad;
     int na, nblk;
     int nj;      // angle moments: 2 (bulb model), 4 (extended: azimuth)
@@ -259,6 +260,7 @@ Layout make_layout(const nuosc_params& p)
     L.errpart = take((size_t)L.nblk * 8);
     const size_t asz = p.precision == NUOSC_FP32_AMP ? 4 : 8;
     L.errv = take(p.integrator == NUOSC_RK_DP54 ? 2 * n * (size_t)L.nb_pad * asz : 0);
+    L.xbuf = take(p.integrator == NUOSC_EXP_STEPPER ? 2 * 2 * n * (size_t)L.nb_pad * 8 : 0);
     L.mat = take((size_t)nuosc::kMaxStages * L.na * nuosc::kStageMatBytes);
     L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
     L.ctrl = take(2 * sizeof(Control));
@@ -409,6 +411,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
     rc.errv = (void*)(base + L.errv);
+    rc.xbuf = (double*)(base + L.xbuf);
     rc.mat = (void*)(base + L.mat);
     rc.geo = (nuosc::TrajGeo*)(base + L.geo);
     rc.ctrl = (Control*)(base + L.ctrl);
