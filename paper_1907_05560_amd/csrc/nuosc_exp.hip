@@ -211,7 +211,9 @@ __device__ __forceinline__ Spec spectrum_of(const double* K)
 #pragma unroll
             for (int it = 0; it < 5; ++it) {
                 const double q2 = q * q;
-                q -= fma(q, q2 - c1, -ac0) / fma(3.0, q2, -c1);
+                // an approximate reciprocal leaves the fixed point unchanged and the
+                // convergence quadratic down to its own relative error
+                q -= fma(q, q2 - c1, -ac0) * __builtin_amdgcn_rcp(fma(3.0, q2, -c1));
             }
         }
         s.ub = 0.5 * q;
@@ -439,12 +441,12 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
                 combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_full)), x0, kx, kkx, p1);
                 add_density<N>(wt, p1, acc[0]);
 #pragma unroll
-                for (int q = 0; q < 2 * N; ++q) x1[q * ld + b] = p1[q];
+                for (int q = 0; q < 2 * N; ++q) __builtin_nontemporal_store(p1[q], &x1[q * ld + b]);
                 __builtin_amdgcn_sched_barrier(0);  // one exponential at a time
                 combine<N>(coef_of<N>(s0, angles_of<N>(s0, dl_h1)), x0, kx, kkx, p4);
                 add_density<N>(wt, p4, acc[SETS - 1]);
 #pragma unroll
-                for (int q = 0; q < 2 * N; ++q) x4[q * ld + b] = p4[q];
+                for (int q = 0; q < 2 * N; ++q) __builtin_nontemporal_store(p4[q], &x4[q * ld + b]);
             } else if constexpr (L == 2) {
                 // x0 holds psi4 here
                 double K[NM], kx[2 * N], kkx[2 * N], p5[2 * N];
@@ -461,7 +463,7 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
                 double K[NM], kx[2 * N], kkx[2 * N];
                 double p1[2 * N], p3[2 * N], pk[2 * N];
 #pragma unroll
-                for (int q = 0; q < 2 * N; ++q) p1[q] = x1[q * ld + b];
+                for (int q = 0; q < 2 * N; ++q) p1[q] = __builtin_nontemporal_load(&x1[q * ld + b]);
 #pragma unroll
                 for (int v = 0; v < NM; ++v) K[v] = fma(u, sAB[wave][0][1][v], sAB[wave][0][0][v]);
                 const Spec s1 = spectrum_of<N>(K);
@@ -482,7 +484,7 @@ __global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
                 for (int q = 0; q < 2 * N; ++q) {
                     p7[q] = 0.5 * (p1[q] + pk[q]);
                     emax = fmax(emax, fabs(p3[q] - p7[q]));
-                    dst[q * ld + b] = p7[q];
+                    __builtin_nontemporal_store(p7[q], &dst[q * ld + b]);
                 }
                 add_density<N>(wt, p7, acc[0]);
             }
