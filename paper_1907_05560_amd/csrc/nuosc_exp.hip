@@ -124,17 +124,14 @@ __device__ __forceinline__ void herm_apply(const double* K, const double* x, dou
         }
 }
 
-// sin and cos of x.  For |x| < 1e6: x = k pi/2 + r, pi/2 split into three
-// doubles whose products with k are subtracted with one rounding each (fma;
-// the reduction of Cody and Waite), then the Taylor series of sin and cos to
-// r^17 and r^18 on |r| <= pi/4 (truncation below 1e-19) and the quadrant
-// k mod 4.  Larger arguments go to the library.
+// sin and cos of x: x = k pi/2 + r, pi/2 split into three doubles whose
+// products with k are subtracted with one rounding each (fma; the reduction
+// of Cody and Waite, exact in k P1 and k P2 for |k| < 2^53, so accurate to
+// |x| ~ 7e15, beyond which the ulp of x itself exceeds pi), then the Taylor
+// series of sin and cos to r^17 and r^18 on |r| <= pi/4 (truncation below
+// 1e-19) and the quadrant k mod 4.  NaN in, NaN out.
 __device__ __forceinline__ void xsincos(double x, double& s, double& c)
 {
-    if (!(fabs(x) < 1.0e6)) {
-        sincos(x, &s, &c);
-        return;
-    }
     const double k = rint(x * 0.6366197723675814);  // 2 / pi
     double r = fma(-k, 1.5707963267948966, x);
     r = fma(-k, 6.123233995736766e-17, r);
@@ -160,7 +157,7 @@ __device__ __forceinline__ void xsincos(double x, double& s, double& c)
     pc = fma(pc, z, 0.041666666666666664);
     pc = fma(pc, z, -0.5);
     const double cr = fma(z, pc, 1.0);
-    const int q = (int)k & 3;
+    const int q = (int)fma(-4.0, floor(0.25 * k), k);  // k mod 4 in [0, 4), exact for integer k
     s = (q & 1) ? cr : sr;
     c = (q & 1) ? sr : cr;
     if (q == 1 || q == 2) c = -c;
