@@ -188,3 +188,63 @@ def test_bench_grid_invariants_and_determinism():
     assert np.abs(norm - 1.0).max() < 1e-5
     p = np.abs(psi[0]) ** 2
     assert p.min() >= 0.0 and p.max() <= 1.0 + 1e-12
+
+
+def test_single_trajectory_single_energy():
+    """The smallest multi-angle grid: one emission angle, one energy bin (two
+    beams in one wavefront of one workgroup)."""
+    w = _w(3, 1, 1, r_start_km=30.0, dr_init_km=1e-4)
+    say("case: exp stepper 1x1")
+    with nuosc.Run(w) as run:
+        run.step(15)
+        s = run.stats()
+        p = run.probabilities()
+        psi = run.psi_complex()
+    assert s["accepted"] > 5
+    _compare(s, p, psi, O.Run(w))
+
+
+def test_evolve_lands_on_r_end_like_the_oracle():
+    w = _w(3, 12, 7, r_start_km=60.0, r_end_km=60.02, dr_init_km=1e-4)
+    say("case: exp stepper evolve to r_end")
+    with nuosc.Run(w) as run:
+        run.evolve(60.02)
+        s = run.stats()
+        p = run.probabilities()
+        psi = run.psi_complex()
+    assert s["r_km"] == 60.02
+    ref = O.Run(w)
+    assert ref.run_to_end() == O.DONE
+    rs = ref.stats()
+    assert rs["r_km"] == 60.02 and rs["rejected"] == s["rejected"]
+    assert abs(rs["accepted"] - s["accepted"]) <= 1
+    np.testing.assert_allclose(p, ref.probabilities(), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(psi, ref.psi_complex(), rtol=0, atol=1e-10)
+
+
+def test_max_steps_stops_the_run():
+    w = _w(2, 10, 3, r_start_km=60.0, dr_init_km=1e-4, max_steps=7)
+    say("case: exp stepper max_steps")
+    with nuosc.Run(w) as run:
+        _, st = run.step(20, check=False)
+        s = run.stats()
+    assert st == nuosc.E_LIMIT
+    assert s["accepted"] + s["rejected"] == 7
+
+
+def test_snapshot_resume_is_bitwise_the_uninterrupted_run(tmp_path):
+    w = _w(3, 14, 9, r_start_km=60.0, dr_init_km=1e-4)
+    say("case: exp stepper snapshot resume")
+    path = str(tmp_path / "exp.snap")
+    with nuosc.Run(w) as a:
+        a.step(10)
+        a.snapshot_write(path)
+        a.step(10)
+        sa, pa = a.stats(), a.psi_complex()
+    with nuosc.Run(w) as b:
+        b.snapshot_read(path)
+        b.step(10)
+        sb, pb = b.stats(), b.psi_complex()
+    assert (sa["accepted"], sa["rejected"], sa["r_km"], sa["dr_km"]) == (sb["accepted"], sb["rejected"], sb["r_km"],
+                                                                        sb["dr_km"])
+    assert np.array_equal(pa, pb)
