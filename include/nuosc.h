@@ -289,8 +289,9 @@ typedef struct nuosc_batch nuosc_batch;
  *   hip_stream        stream to order all work on, borrowed; NULL => own stream
  *   device_arena      optional caller-owned device memory of hbm_budget_bytes
  *                     (kept alive until nuosc_batch_destroy); NULL => allocated
- * NUOSC_E_INVALID for bad arguments, NUOSC_E_NOMEM when the arena cannot be
- * allocated.  On failure *out is NULL. */
+ * integrator is NUOSC_RK4_FIXED or NUOSC_RK_DP54 (the exponential stepper runs
+ * as single runs only).  NUOSC_E_INVALID for bad arguments, NUOSC_E_NOMEM when
+ * the arena cannot be allocated.  On failure *out is NULL. */
 nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t precision, int32_t integrator,
                                 size_t hbm_budget_bytes, void* hip_stream, void* device_arena,
                                 nuosc_batch** out);

@@ -1193,6 +1193,8 @@ nuosc_status nuosc_batch_create(int32_t max_slots, int32_t n_flavors, int32_t pr
     if (n_flavors != 2 && n_flavors != 3) return bfail(nullptr, NUOSC_E_INVALID, "n_flavors must be 2 or 3");
     if (precision != NUOSC_FP64 && precision != NUOSC_FP32_AMP && precision != NUOSC_FP32_AMP_FP64_MATH)
         return bfail(nullptr, NUOSC_E_INVALID, "unknown precision");
+    if (integrator == NUOSC_EXP_STEPPER)
+        return bfail(nullptr, NUOSC_E_INVALID, "the exponential stepper runs as single runs, not in batches");
     if (integrator != NUOSC_RK4_FIXED && integrator != NUOSC_RK_DP54)
         return bfail(nullptr, NUOSC_E_INVALID, "unknown integrator");
     const size_t runs_bytes = align_up((size_t)max_slots * sizeof(RunConst), 256);

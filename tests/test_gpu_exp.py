@@ -248,3 +248,8 @@ def test_snapshot_resume_is_bitwise_the_uninterrupted_run(tmp_path):
     assert (sa["accepted"], sa["rejected"], sa["r_km"], sa["dr_km"]) == (sb["accepted"], sb["rejected"], sb["r_km"],
                                                                         sb["dr_km"])
     assert np.array_equal(pa, pb)
+
+
+def test_batches_refuse_the_exponential_stepper():
+    with pytest.raises(nuosc.NuoscError, match="single runs"):
+        nuosc.Batch(4, 3, W.FP64, W.EXP_STEPPER, 1 << 26)
