@@ -184,6 +184,43 @@ def roofline(form):
     return out
 
 
+def step_roofline(form):
+    """Whole-step figures (every launch of an attempt): beam-steps/s against
+    (1) the method's floor, one read of y_n per derivative evaluation plus one
+    write of y_{n+1}: B_alg = (evaluations + 1) x S bytes per beam-step
+    (Dormand-Prince first-same-as-last: 7 S; classic RK4: 5 S), and (2) the
+    design's bytes per beam-step, the copy-calibrated rocprofv3 FETCH + WRITE
+    bytes of all its stage launches (null without counters for this kernel
+    source); and the achieved vector-ALU rate of the stage_flops model."""
+    S = len(form["stage_ms"])
+    state = 2 * form["n"] * form["amp_bytes"]
+    b_alg = (S if S == 7 else S + 1) * state
+    v = form["value"]
+    out = {"alg_bytes_per_beam_step": b_alg, "alg_ceiling": round(PEAK_HBM_GBS * 1e9 / b_alg),
+           "frac_alg": round(v * b_alg / (PEAK_HBM_GBS * 1e9), 4), "design_bytes_per_beam_step": None,
+           "frac_design": None}
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            from paper_1907_05560_amd.profile_summary import kernel_source_hash
+
+            t = json.load(open(TRAFFIC_FILE))
+            keys = [f"stage{i}_prec{form['precision']}" for i in range(1, S + 1)]
+            bpl = t.get("bytes_per_launch", {})
+            if t.get("kernel_source_sha256_16") == kernel_source_hash() and all(k in bpl for k in keys):
+                d = sum(bpl[k] for k in keys) / form["beams"]
+                out["design_bytes_per_beam_step"] = round(d, 1)
+                out["frac_design"] = round(v * d / (PEAK_HBM_GBS * 1e9), 4)
+        except (OSError, ValueError):
+            pass
+    flops = sum(stage_flops(form["n"], "dp54" if S == 7 else "rk4", st, form["amp_bytes"] == 4)
+                for st in range(1, S + 1))
+    tfs = v * flops / 1e12
+    peak = PEAK_FP32_TFS if form["precision"] == 1 else PEAK_FP64_TFS
+    out.update({"flops_per_beam_step": flops, "valu_tflops": round(tfs, 2), "valu_peak": peak,
+                "valu_frac": round(tfs / peak, 4)})
+    return out
+
+
 def cpu_baseline(W, attempts):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of the
     same workload: `attempts` adaptive step attempts of the full grid from 10 km.
@@ -453,8 +490,10 @@ def main() -> int:
         },
         "roofline": roofline(head),
         "accepted_per_attempt": head["accepted"] / head["attempts"],
+        "step_roofline": step_roofline(head),
         "forms": {f: {"value": forms[names[f]]["value"], "ms_per_step": forms[names[f]]["ms_per_step"],
-                      "roofline": roofline(forms[names[f]])} for f in args.forms.split(",")},
+                      "roofline": roofline(forms[names[f]]), "step_roofline": step_roofline(forms[names[f]])}
+                  for f in args.forms.split(",")},
         "fp32_vs_fp64_error": err,
         "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
         "control_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
