@@ -32,8 +32,7 @@
 // and psi1, and writes psi7.
 //
 // Beams: one wavefront per trajectory j, lanes over its 2 N_E beam slots,
-// eight trajectories per workgroup (one partial density sum per workgroup,
-// the layout of the FP64 stage kernels).  Antineutrino amplitudes are held
+// four trajectories per workgroup (one partial density sum per workgroup).  Antineutrino amplitudes are held
 // complex-conjugated on the device, so one matrix pair per trajectory serves
 // both species: H = A + u B with A = H_m + H_nunu, B = V, H_vac(E) = V / E,
 // and u = +1/E (neutrinos) or -1/E (antineutrinos).
@@ -51,7 +50,7 @@
 namespace nuosc {
 namespace {
 
-constexpr int kExpTraj = 8;                 // trajectories (wavefronts) per workgroup
+constexpr int kExpTraj = kExpTrajPerBlock;  // trajectories (wavefronts) per workgroup
 constexpr int kExpBlock = 64 * kExpTraj;
 
 __device__ __forceinline__ double xwave_sum(double v)
@@ -352,7 +351,13 @@ __device__ __forceinline__ void add_density(double wt, const double* x, double* 
 
 // Beam launch L (see the file header).
 template <int N, int L>
-__global__ void __launch_bounds__(kExpBlock) k_exp_beam(const RunConst rc)
+// Launches 1 and 2: three wavefronts per SIMD (at most 168 VGPRs; a few
+// spill): their evaluations are long FP64 dependency chains, and two
+// wavefronts per SIMD leave the vector ALU idle more often than the spills
+// cost.  Launch 3 (two full evaluations live) spills too much at that budget
+// and runs two wavefronts per SIMD.
+__global__ void __launch_bounds__(kExpBlock) __attribute__((amdgpu_waves_per_eu(L == 3 ? 2 : 3)))
+k_exp_beam(const RunConst rc)
 {
     constexpr int NM = N * N;
     constexpr int SETS = (L == 1) ? 2 : 1;           // density sums formed by this launch

@@ -137,6 +137,7 @@ int num_stages(int integrator);
 // kernel; the last reduction is the step control), or 0: J of the current
 // state.  One run per call.  ev as for launch_stage.
 constexpr int kExpLaunches = 3;
+constexpr int kExpTrajPerBlock = 4;  // trajectories (wavefronts) per workgroup of its beam kernels
 hipError_t launch_exp_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
 
 }  // namespace nuosc

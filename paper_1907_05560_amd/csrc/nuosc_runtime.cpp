@@ -246,7 +246,7 @@ Layout make_layout(const nuosc_params& p)
         off = align_up(off + bytes, 256);
         return at;
     };
-    const int tpb = nuosc::traj_per_block(p.precision);
+    const int tpb = p.integrator == NUOSC_EXP_STEPPER ? nuosc::kExpTrajPerBlock : nuosc::traj_per_block(p.precision);
     L.nblk = (L.na + tpb - 1) / tpb;
     for (int b = 0; b < 2; ++b) L.psi[b] = take(2 * n * (size_t)L.nb_pad * tsz);
     for (int b = 0; b < 2; ++b) L.phase[b] = take((size_t)L.na * n * 8);
