@@ -163,12 +163,24 @@ __device__ __forceinline__ void xsincos(double x, double& s, double& c)
     if (q & 2) s = -s;
 }
 
-// sin(w) / w
+// 1 / d: the hardware reciprocal refined by two Newton steps r <- r (2 - d r)
+// (each squares the relative error), for d away from 0 and overflow.
+__device__ __forceinline__ double xrcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// sin(w) / w (near 0 its Taylor series; the divisions by constants are
+// written as products, which the compiler keeps as exact divisions otherwise)
 __device__ __forceinline__ double sinc_of(double w, double sw)
 {
     const double w2 = w * w;
-    if (fabs(w) < 0.05) return 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0));
-    return sw / w;
+    if (fabs(w) < 0.05)
+        return 1.0 - w2 * (1.0 / 6.0) * (1.0 - w2 * (1.0 / 20.0) * (1.0 - w2 * (1.0 / 42.0)));
+    return sw * xrcp(w);
 }
 
 // Spectrum of K, independent of the step length t: with Q = t K,
@@ -202,7 +214,7 @@ __device__ __forceinline__ Spec spectrum_of(const double* K)
         // 2 sqrt(c1/3) (the cubic is convex there: monotone convergence);
         // then w^2 = c1 - 3u^2 (c1 = 3u^2 + w^2)
         const double ac0 = fabs(c0);
-        double q = 2.0 * sqrt(c1 / 3.0);
+        double q = 2.0 * sqrt(c1 * (1.0 / 3.0));
         if (!s.zero) {
 #pragma unroll
             for (int it = 0; it < 5; ++it) {
@@ -268,7 +280,7 @@ __device__ __forceinline__ Coef coef_of(const Spec& s, const Angles& a)
         const cd h0 = cadd(cscale(e2, u2 - w2), cmul(em, cd{8.0 * u2 * a.cw, 2.0 * u * (3.0 * u2 + w2) * a.xi}));
         const cd h1 = csub(cscale(e2, 2.0 * u), cmul(em, cd{2.0 * u * a.cw, -(3.0 * u2 - w2) * a.xi}));
         const cd h2 = csub(e2, cmul(em, cd{a.cw, 3.0 * u * a.xi}));
-        const double inv = 1.0 / (9.0 * u2 - w2);
+        const double inv = xrcp(9.0 * u2 - w2);  // >= 2 c1 t^2 > 0
         const cd f0 = cscale(h0, inv), f1 = cscale(h1, inv), f2 = cscale(h2, inv);
         const double t = a.t;
         if (!s.neg) {
