@@ -4,9 +4,9 @@
 // and the evolution loop of Section 5), in the lab frame, FP64.
 //
 // One attempt from psi0 at radius r with step h, U(H; a, b) = exp(-i H dl) the
-// exponential step from radius a to b, dl = (b - a) / ((c_j(a) + c_j(b)) / 2)
-// the trajectory's path length across it (mean cosine of the two ends,
-// Appendix A.4.3; eq 3.3):
+// exponential step from radius a to b, dl = dr / ((c_j(a) + c_j(b)) / 2) the
+// trajectory's path length across it (dr = b - a, taken as the step h or h/2
+// itself; mean cosine of the two ends, Appendix A.4.3; eq 3.3):
 //   H0 from psi0 at r;       psi1 = U(H0; r, r+h) psi0,  psi4 = U(H0; r, r+h/2) psi0
 //   H1 from psi1 at r + h;   H2 from psi4 at r + h/2
 //   psi3 = (psi1 + U(H1; r, r+h) psi0) / 2             full-step estimate
@@ -32,15 +32,15 @@
 // and psi1, and writes psi7.
 //
 // Beams: one wavefront per trajectory j, lanes over its 2 N_E beam slots,
-// four trajectories per workgroup (one partial density sum per workgroup).  Antineutrino amplitudes are held
-// complex-conjugated on the device, so one matrix pair per trajectory serves
-// both species: H = A + u B with A = H_m + H_nunu, B = V, H_vac(E) = V / E,
+// four trajectories per workgroup (one partial density sum per workgroup).
+// Antineutrino amplitudes are held complex-conjugated on the device, so one
+// matrix pair per trajectory serves both species: H = A + u B with A = H_m + H_nunu, B = V, H_vac(E) = V / E,
 // and u = +1/E (neutrinos) or -1/E (antineutrinos).
 //
 // 3x3 exponential: for traceless Hermitian Q with c0 = det Q, c1 = tr(Q^2)/2,
 // Cayley-Hamilton gives exp(iQ) = f0 + f1 Q + f2 Q^2 with closed-form f_j
 // of the eigenvalue parametrisation q = 2u, -u +- w (Morningstar and
-// Peardon, Phys. Rev. D 69, 054501 (2004), eq 29-34), evaluated for c0 >= 0
+// Peardon, Phys. Rev. D 69, 054501 (2004)), evaluated for c0 >= 0
 // and mapped to c0 < 0 by Q -> -Q.  Two flavors: eq 3.11.  Steps of different
 // length with the same H share its spectrum (u and w scale with the length).
 #include "nuosc_internal.hpp"
