@@ -191,6 +191,27 @@ def test_fp32_amplitudes_within_1e4_on_a_multi_angle_window(prec):
     assert err.max() <= 1e-4
 
 
+@pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
+def test_fp32_amplitudes_400x4000_window_at_full_size(prec):
+    """The benchmarked workload in its launch configuration (3.2M beams, FP32
+    amplitudes) against the FP64 oracle with the same renormalisation, over
+    the first attempts from the neutrinosphere, within 1e-4 in P."""
+    w = W.multi_angle_3f_large(prec)
+    say(f"case: 400x4000 FP32 amplitudes precision {prec}, 12 attempts")
+    with nuosc.Run(w) as run:
+        run.step(12)
+        p = run.probabilities()
+        s = run.stats()
+    assert s["accepted"] >= 1
+    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
+    ref.evolve_dp54(s["r_km"])
+    assert ref.stats()["r_km"] == s["r_km"]
+    err = np.abs(p - ref.probabilities())
+    say(f"400x4000 precision {prec}: r = {s['r_km']:.9f} km, max {err.max():.3e} "
+        f"rms {np.sqrt((err ** 2).mean()):.3e}")
+    assert err.max() <= 1e-4
+
+
 def test_runs_are_bitwise_deterministic():
     w = W.multi_angle_3f(50, 20)
     out = []
