@@ -37,6 +37,23 @@ def test_energy_average_of_random_states_matches_the_oracle(n, ne, na, prec):
     np.testing.assert_allclose(avg, ref.energy_average(), rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP64])
+def test_energy_average_at_the_bench_grid_matches_the_oracle(prec):
+    """The 400 x 4000 x 2 grid the bench times the average on (3.2M beams),
+    from a seeded random state."""
+    w = W.multi_angle_3f_large(prec)
+    say(f"case: energy average 400x4000 prec={prec}")
+    with nuosc.Run(w) as run:
+        psi = W.random_states(3, run.nb, seed=311)
+        if prec != W.FP64:
+            psi = psi.astype(np.float32).astype(np.float64)
+        run.set_state(psi, None, 10.0)
+        avg = run.energy_average()
+    ref = O.Run(w)
+    ref.set_state(psi, None, 10.0)
+    np.testing.assert_allclose(avg, ref.energy_average(), rtol=0, atol=1e-14)
+
+
 def test_energy_average_after_evolution_matches_the_oracle():
     w = W.multi_angle_3f(24, 6)
     say("case: energy average after 40 adaptive attempts")
