@@ -217,7 +217,7 @@ nuosc_status nuosc_set_state(nuosc_handle* h, const double* psi, const double* p
                              double r_km, double dr_km);
 
 /* Energy-averaged flavor content of every trajectory: the paper's second
- * dump mode (Section 4.2.5, the average flavor state over the energy bins of
+ * dump mode (Section 4.2.4, the average flavor state over the energy bins of
  * one trajectory), computed on the device from the current state:
  *   out[s][j][a] = sum_k f_sk |psi_{s,j,k,a}|^2 / sum_k f_sk
  * for species s (0 neutrino, 1 antineutrino), trajectory j < NA and flavor
@@ -231,7 +231,7 @@ nuosc_status nuosc_energy_average(nuosc_handle* h, double* out);
  * callers that keep the result on the device and for timing. */
 nuosc_status nuosc_enqueue_energy_average(nuosc_handle* h, double* out_device);
 
-/* Snapshots: the paper's first dump mode and resume (Section 4.2.5).  A
+/* Snapshots: the paper's first dump mode and resume (Section 4.2.4).  A
  * snapshot file holds this header, then the state in the host layout above
  * (psi: n*2*NB doubles, phase: NA*n doubles), then a 64-bit FNV-1a hash of
  * all preceding bytes; integers and doubles are little-endian as in memory:

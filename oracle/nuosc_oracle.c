@@ -956,7 +956,7 @@ void or_probabilities(const or_run* R, double* p)
 }
 
 /* Energy-averaged flavor content of every trajectory: the second dump mode
- * of Section 4.2.5 (the flavor state of one trajectory averaged over its
+ * of Section 4.2.4 (the flavor state of one trajectory averaged over its
  * energy bins).  Reading O: each bin counts with the number flux of the
  * beam's birth flavor in it (nu_e for neutrino beams, nubar_e for
  * antineutrino beams; spectra eq 4.1-4.2 with the luminosities of reading C),

@@ -1198,7 +1198,7 @@ __global__ void k_probabilities(const LaunchSet ls, double* __restrict__ p)
 }
 
 // Energy-averaged flavor content of every trajectory (the paper's second
-// dump mode, Section 4.2.5): for species s and trajectory j,
+// dump mode, Section 4.2.4): for species s and trajectory j,
 //   out[s][j][a] = sum_k f_sk |psi_{s,j,k,a}|^2 / sum_k f_sk,
 // f_sk the number flux of the species' birth flavor (nu_e, nubar_e) in
 // energy bin k (eq 4.1-4.2); the plain mean over bins if it sums to zero.

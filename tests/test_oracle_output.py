@@ -1,5 +1,5 @@
 """Pins of the oracle's energy-averaged output (the paper's second dump mode,
-Section 4.2.5; reading O: bins weighted by the number flux of the beam's
+Section 4.2.4; reading O: bins weighted by the number flux of the beam's
 birth flavor).  The expected values come from closed forms: the two-flavor
 vacuum probability and Fermi-Dirac spectra at eta = 0, whose temperature
 T = <E> F2(0) / F3(0) uses F2(0) = 3 zeta(3) / 2 and F3(0) = 7 pi^4 / 120."""

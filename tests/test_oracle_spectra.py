@@ -1,4 +1,4 @@
-"""Pins of the oracle's spectra and beam weights (eq 4.1-4.2, Section 4.3).
+"""Pins of the oracle's spectra and beam weights (eq 4.1-4.2, Section 4.5).
 
 Each check compares the oracle with something it does not compute itself:
 closed forms of the Fermi integrals, the temperatures the paper prints, and
