@@ -1,38 +1,47 @@
-// gfx950 kernels of the bulb-model flavor evolution.
+// gfx950 kernels of the bulb-model flavor evolution: explicit Runge-Kutta
+// attempts in stage-polynomial form.
 //
-// One step attempt of an explicit Runge-Kutta tableau with S stages runs as S
-// beam launches k_stage<I>, I = 1..S, and one control launch:
-//   * k_stage<I> (one wavefront per emission-angle trajectory j, lanes over
-//     its 2 N_E beams):
-//       prologue: every workgroup adds the partial density sums of launch I-1
-//         in one fixed order (all workgroups get the same J_{I-1}; launch 1
-//         takes J_0 of the accepted state) and completes stage I-1 of its own
-//         trajectories: collective Hamiltonian (eq 3.13 / 3.16), matter term,
-//         frame rate G, stage matrices h K_{I-1} = h (A + B u);
-//       beam loop: reads y_n once, recomputes k_0..k_{I-1} from y_n and the
-//         stage matrices, forms the input of stage I (the new state in the
-//         launch that forms it, written back in the storage type) and adds
-//         its weighted density matrix in FP64.  Embedded pair with first
-//         same as last (k_{S-1} = f(y_{n+1})): launch S-1 also writes the
-//         partial error sum sum_{i<S-1} e_i k_i per beam, and launch S reads
-//         it with y_{n+1}, evaluates k_{S-1} only and forms the step error
-//         h sum_i e_i k_i;
-//       epilogue: prepares stage I (geometry eq 3.14-3.15, co-rotating phase,
-//         rotation factors) and adds the rotated, angle-weighted density sums
-//         of its trajectories into one partial per workgroup.
-//   * k_control (one workgroup per run): global error maximum, step
-//     controller, and J_0 of the next attempt.
-// Only y_n is read from HBM per beam launch and only y_{n+1} is written (by
-// the launch that forms it, with the partial error sum): every stage
-// derivative is recomputed from y_n and the small per-trajectory tables
-// instead of being stored.
+// Within one attempt the Hamiltonian of stage l depends on the beams only
+// through the global angle moments J_l (eq 3.13-3.17).  Once J_l is known,
+// every beam of trajectory j obeys a linear map: the stage derivative is
+// h k_l = -i h K_l(u) Y_l with K_l(u) = A_l + B_l u, where u = +1/E for
+// neutrinos and u = -1/E for antineutrinos (held complex-conjugated, see
+// below), A_l the per-trajectory collective and matter part and B_l the
+// vacuum part divided by the propagation cosine.  Every stage input is
+// therefore a matrix polynomial in u applied to y_n:
+//   Y_l = C_l(u) y_n,   C_0 = 1,   C_l(u) = 1 + sum_{m<l} a_lm D_m(u),
+//   h k_m = D_m(u) y_n, D_m(u) = -i h (A_m + B_m u) C_m(u),
+// and so are the new state y_{n+1} = (1 + sum_m b_m D_m(u)) y_n and the
+// embedded error h sum_m e_m k_m = (sum_m e_m D_m(u)) y_n.  The density sum of
+// stage l over the energies of a trajectory needs only power moments of y_n:
+//   sum_k w_k Y_k Y_k^+ = sum_{d,d'} C_{l,d} Q_{d+d'} C_{l,d'}^+,
+//   Q_p = sum_k w_k u_k^p y_k y_k^+,   p = 0 .. 2(S-1).
+// This is exact algebra on the Runge-Kutta stages (only the rounding order
+// differs from forming every stage state).  One attempt of an S-stage tableau
+// is S + 2 launches:
+//   k_traj<l>, l = 1..S-1 (one wavefront per trajectory, no beam data): J_{l-1}
+//     as the fixed-order sum of the previous launch's partials; completion of
+//     stage l-1 (matter term, collective term, co-rotating frame rate, the
+//     coefficient matrices D_{l-1}); the coefficients C_l and the stage-l
+//     density sum from Q, rotated to the lab frame and weighted by the angle
+//     weights of stage l (eq 3.14-3.15) into one partial per workgroup;
+//   k_traj<S>: completion of the last stage and the coefficient tables of the
+//     update polynomial (arithmetic type) and the error polynomial (FP64);
+//   k_final (beam pass): y_{n+1} by Horner's rule with the coefficients in
+//     scalar registers, renormalisation of FP32 amplitudes, the error
+//     polynomial in FP64, per-workgroup error maxima;
+//   k_power (beam pass): global error maximum and the step controller (every
+//     workgroup gets the same result); for an accepted attempt the power
+//     moments of the new state and its J partials, which the next attempt's
+//     first launch sums.
+// The beams are read twice and written once per attempt.
 //
 // Antineutrino amplitudes are held complex-conjugated on the device.  With
 // phi = conj(psibar), the antineutrino equation in the co-rotating frame reads
 // d phi / dr = -i (A - B / E) phi with the neutrino's A and B, so one matrix
-// per trajectory and stage serves both species (u = +1/E or -1/E per beam),
-// and the density sum takes the same form g psi psi^dagger for both species
-// with weight g or -gbar.
+// pair per trajectory and stage serves both species (u = +1/E or -1/E per
+// beam slot), and the density sum takes the same form w psi psi^dagger for
+// both species with weight w = g or -gbar.
 #include "nuosc_internal.hpp"
 
 #include <math.h>
@@ -52,7 +61,7 @@ struct TabRK4 {
     static constexpr double C[8] = {0.0, 0.5, 0.5, 1.0};
     static constexpr double A[8][8] = {{0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}};
     static constexpr double B[8] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    [[maybe_unused]] static constexpr double E[8] = {0};
+    static constexpr double E[8] = {0};
 };
 
 // Dormand-Prince RK5(4)7M: the last stage is the new state (first same as
@@ -76,12 +85,26 @@ struct TabDP54 {
                                     -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
 };
 
-// Coefficient of k_m in the state formed for stage l (l == S: the new state).
+// Degrees and table sizes of the stage polynomials of a tableau.
 template <typename TAB>
-__host__ __device__ constexpr double coef(int l, int m)
-{
-    return l < TAB::S ? TAB::A[l][m] : TAB::B[m];
-}
+struct Poly {
+    static constexpr int S = TAB::S;
+    static constexpr int NQ = 2 * (S - 1) + 1;          // power moments Q_0 .. Q_{NQ-1}
+    // D_m has degree m + 1; the update 1 + sum b_m D_m and the error sum e_m D_m
+    // have the degree of their last nonzero weight plus one
+    static constexpr int last_nonzero(const double* w)
+    {
+        int d = -1;
+        for (int m = 0; m < S; ++m)
+            if (w[m] != 0.0) d = m;
+        return d;
+    }
+    static constexpr int DN = last_nonzero(TAB::B) + 1;
+    static constexpr int DE = TAB::embedded ? last_nonzero(TAB::E) + 1 : 0;
+    // D_m occupies m + 2 coefficient matrices; offset of D_m in matrices
+    __host__ __device__ static constexpr int doff(int m) { return m * (m + 3) / 2; }
+    static constexpr int ND = doff(S - 1);               // stored: D_0 .. D_{S-2}
+};
 
 // ------------------------------------------------------------------ helpers
 template <int B, int E, typename F>
@@ -91,18 +114,6 @@ __device__ __forceinline__ void static_for(F&& f)
         f(std::integral_constant<int, B>{});
         static_for<B + 1, E>(f);
     }
-}
-
-// coef(l, M) for a runtime stage l in (M, LAST], else 0.
-template <typename TAB, int M, int LAST>
-__device__ __forceinline__ double coef_of_column(int l)
-{
-    double r = 0.0;
-    static_for<M + 1, LAST + 1>([&](auto Lc) {
-        constexpr int ll = decltype(Lc)::value;
-        if (l == ll) r = coef<TAB>(ll, M);
-    });
-    return r;
 }
 
 // Lane k < NV stores v[k] to dst[k]: NV values that every lane of the
@@ -121,31 +132,19 @@ __device__ __forceinline__ void lane_scatter(D* dst, const double (&v)[NV], int 
     }
 }
 
-// Empty asm that takes v as a register operand: the computation of v must be
-// complete here, which bounds how far the scheduler spreads one stage's loads
-// and arithmetic into the next (register pressure).  Emits no instruction.
-template <typename T>
-__device__ __forceinline__ void pin(T& v)
+// Orders the LDS accesses of one wavefront (its own LDS region only).
+__device__ __forceinline__ void wave_sync()
 {
-    asm volatile("" : "+v"(v));
-}
-
-// Element i of an array at a wave-uniform base: a 32-bit byte offset from a
-// 64-bit base, which maps onto the scalar-base + vector-offset addressing of
-// global loads and stores (every array indexed this way is below 4 GiB).
-template <typename T>
-__device__ __forceinline__ T* elem(T* base, uint32_t i)
-{
-    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
-    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Global-memory views of the beam arrays.  uniform_global(p) takes a
 // wave-uniform pointer into a scalar register as a global-address-space
 // pointer: loads and stores through it become global (not flat) operations
-// with a scalar base and a 32-bit vector offset, and one such base per
-// amplitude component keeps the per-component address arithmetic out of the
-// vector ALU.
+// with a scalar base and a 32-bit vector offset (every array indexed this way
+// is below 4 GiB).
 template <typename T> using global = __attribute__((address_space(1))) T;
 
 template <typename T>
@@ -164,40 +163,10 @@ __device__ __forceinline__ global<T>* elem(global<T>* base, uint32_t i)
     return reinterpret_cast<global<T>*>(reinterpret_cast<global<B>*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
 }
 
-// K y for one beam with K = A + B u (packed Hermitian).  y, ky: [2N] as (re,
-// im) per component.  The derivative is k = -i K y: Re k_a = Im (K y)_a and
-// Im k_a = -Re (K y)_a.  The kernels keep K y and fold -i into the Runge-Kutta
-// coefficients (c k[q] = ksign(q) c ky[q ^ 1]), which saves the negations.
-template <typename T, int N>
-__device__ __forceinline__ void eval_ky(const T* A, const T* B, T u, const T* y, T* k)
-{
-    constexpr int NU = Shape<N>::NU;
-    T kd[N], ku[NU][2];
-#pragma unroll
-    for (int a = 0; a < N; ++a) kd[a] = fma(B[a], u, A[a]);
-#pragma unroll
-    for (int q = 0; q < NU; ++q) {
-        ku[q][0] = fma(B[N + 2 * q], u, A[N + 2 * q]);
-        ku[q][1] = fma(B[N + 2 * q + 1], u, A[N + 2 * q + 1]);
-    }
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        T p = kd[a] * y[2 * a], q = kd[a] * y[2 * a + 1];
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-            if (b == a) continue;
-            T kr, ki;
-            if (a < b) { kr = ku[Shape<N>::up(a, b)][0]; ki = ku[Shape<N>::up(a, b)][1]; }
-            else { kr = ku[Shape<N>::up(b, a)][0]; ki = -ku[Shape<N>::up(b, a)][1]; }
-            p = fma(kr, y[2 * b], fma(-ki, y[2 * b + 1], p));
-            q = fma(kr, y[2 * b + 1], fma(ki, y[2 * b], q));
-        }
-        k[2 * a] = p;
-        k[2 * a + 1] = q;
-    }
-}
-
-__host__ __device__ constexpr double ksign(int q) { return (q & 1) ? -1.0 : 1.0; }
+// Read-only data of the launch through the constant address space: a
+// wave-uniform address turns into scalar loads, and the values feed the
+// vector ALU as scalar-register operands.
+template <typename T> using cptr = const __attribute__((address_space(4))) T*;
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -231,13 +200,23 @@ template <typename T> __device__ __forceinline__ const T* uinv_table(const RunCo
 template <> __device__ __forceinline__ const float* uinv_table<float>(const RunConst& rc) { return rc.uinv32; }
 template <> __device__ __forceinline__ const double* uinv_table<double>(const RunConst& rc) { return rc.uinv64; }
 
-// ------------------------------------------------------------------ per-trajectory tables
-// Stage radius l of the attempt described by C (l == S: the new state).
-template <typename TAB>
-__device__ __forceinline__ double stage_radius(const RunConst& rc, const Control& C, int l)
+// Index pair (a, b), a < b, of upper entry q.
+template <int N>
+__host__ __device__ constexpr void pair_of(int q, int& a, int& b)
 {
-    if (l < TAB::S) return C.r + TAB::C[l] * C.h;
-    return (rc.integrator == 0) ? rc.r_start + (double)(C.istep + 1) * rc.h_fixed : C.r + C.h;
+    a = 0;
+    b = 1;
+    for (int aa = 0; aa < N; ++aa)
+        for (int bb = aa + 1; bb < N; ++bb)
+            if (Shape<N>::up(aa, bb) == q) { a = aa; b = bb; }
+}
+
+// ------------------------------------------------------------------ physics
+// Stage radius l of the attempt described by C (l < S).
+template <typename TAB>
+__device__ __forceinline__ double stage_radius(const Control& C, int l)
+{
+    return fma(TAB::C[l], C.h, C.r);
 }
 
 // Geometry of trajectory j at radius r (eq 3.14-3.15, with 1 - (R/r)^2 formed
@@ -268,136 +247,45 @@ __device__ __forceinline__ double matter(const RunConst& rc, double r)
     return rc.lambda0 * pow(x, p);
 }
 
-// Frame data of one trajectory at one stage radius.
-template <int N>
-struct Frame {
-    double c, w, wc, ic, s;
-    double z[Shape<N>::NU > 0 ? Shape<N>::NU : 1][2];  // e^{i(Phi_a - Phi_b)}, upper pairs
-};
-
-// Index pair (a, b), a < b, of upper entry q.
-template <int N>
-__device__ __forceinline__ void pair_of(int q, int& a, int& b)
+// Co-rotating phase of stage l: Phi_n + h sum_{m<l} a_lm G_m (explicit fma
+// chain, so every launch that forms it gets the same bits).
+template <typename TAB, int N>
+__device__ __forceinline__ void stage_phase(int l, double h, const double* phn, const double (*G)[N], double* ph)
 {
-    a = 0;
-    b = 1;
-    for (int aa = 0; aa < N; ++aa)
-        for (int bb = aa + 1; bb < N; ++bb)
-            if (Shape<N>::up(aa, bb) == q) { a = aa; b = bb; }
-}
-
-// Frame of stage l of trajectory j with geometry (c, w) and co-rotating
-// phases ph[], computed by one wavefront: the NU rotation factors one per lane
-// (lanes 0..NU-1) and broadcast.  Lane 0 stores it in geo[l].
-template <int N>
-__device__ Frame<N> prepare_wave(const RunConst& rc, int j, int l, double c, double w, const double* ph, int lane)
-{
-    constexpr int NU = Shape<N>::NU;
-    Frame<N> f;
-    f.c = c;
-    f.w = w;
-    f.wc = rc.ma ? f.w * f.c : 0.0;
-    f.ic = 1.0 / f.c;
-    f.s = sqrt((1.0 - f.c) * (1.0 + f.c));
-    int a, b;
-    pair_of<N>(lane < NU ? lane : 0, a, b);
-    double sn, cs;
-    sincos(ph[a] - ph[b], &sn, &cs);
 #pragma unroll
-    for (int q = 0; q < NU; ++q) {
-        f.z[q][0] = __shfl(cs, q, 64);
-        f.z[q][1] = __shfl(sn, q, 64);
+    for (int a = 0; a < N; ++a) {
+        double acc = 0.0;
+        for (int m = 0; m < l; ++m) acc = fma(l < TAB::S ? TAB::A[l][m] : TAB::B[m], G[m][a], acc);
+        ph[a] = fma(h, acc, phn[a]);
     }
-    TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
-    const double head[4] = {f.c, f.w, f.wc, f.ic};
-    double zz[2 * (NU > 0 ? NU : 1)];
-    for (int q = 0; q < NU; ++q) {
-        zz[2 * q] = f.z[q][0];
-        zz[2 * q + 1] = f.z[q][1];
-    }
-    lane_scatter(&g.c, head, lane);    // c, w, wc, ic are contiguous
-    if constexpr (NU > 0) lane_scatter(&g.z[0][0], zz, lane);
-    return f;
 }
 
-// The same frame computed by one thread (for the stage-0 preparation kernel);
-// the same arithmetic, so the same bits.
+// e^{i(Phi_a - Phi_b)} of the upper pairs.
 template <int N>
-__device__ void prepare_thread(const RunConst& rc, int j, int l, double rl, const double* ph)
+__device__ __forceinline__ void rotation(const double* ph, double (*z)[2])
 {
-    constexpr int NU = Shape<N>::NU;
-    TrajGeo& g = rc.geo[(size_t)l * rc.na + j];
-    double c, w;
-    traj_geometry(rc, j, rl, c, w);
-    g.c = c;
-    g.w = w;
-    g.wc = rc.ma ? w * c : 0.0;
-    g.ic = 1.0 / c;
-    for (int q = 0; q < NU; ++q) {
+#pragma unroll
+    for (int q = 0; q < Shape<N>::NU; ++q) {
         int a, b;
         pair_of<N>(q, a, b);
-        double sn, cs;
-        sincos(ph[a] - ph[b], &sn, &cs);
-        g.z[q][0] = cs;
-        g.z[q][1] = sn;
+        sincos(ph[a] - ph[b], &z[q][1], &z[q][0]);
     }
 }
 
-// Completes stage l of trajectory j from J_l (J0, J1 and for the extended
-// model J2, J3, packed) and the matter potential lam at the stage radius
-// (uniform values in every lane):
-//   C = mu0 traceless(J0 - c J1)                       (eq 3.13; single angle: J1 = 0)
-//   extended model (eq 3.18): C = mu0 traceless(J0 - c J1 - sc J2 - ss J3),
-//     sc = sin(theta) cos(phi), ss = sin(theta) sin(phi) of the trajectory
-//   G = diag(H_m + C) / c in the co-rotating frame, 0 in the lab frame
-//   A_ab = e^{i(Phi_a - Phi_b)} C_ab / c (a < b), A_aa = 0 (co-rotating) or (H_m + C)_aa / c (lab)
-//   B_ab = e^{i(Phi_a - Phi_b)} V_ab / c,  B_aa = V_aa / c  (H_vac = V / E)
-// Stores h A and h B (the step size folded in: the beam kernels form
-// h k = -i h K y directly) in mat[l] and in M (LDS); G is returned.
-template <typename T, int N, int NJ>
-__device__ void complete_wave(const RunConst& rc, int j, int l, const double c, const double ic, double sc,
-                              double ss, const double (*z)[2], double lam, const double* J, double h, double* G,
-                              StageMat<T, N>* M, int lane)
+// Angle weights of one trajectory for the NJ moments at a stage radius:
+// w, w c (0 single angle) and, for the extended model (eq 3.18), w s cos(phi),
+// w s sin(phi) with s = sin(theta).
+template <int NJ>
+__device__ __forceinline__ void angle_weights(const RunConst& rc, double c, double w, double cph, double sph,
+                                              double* f)
 {
-    constexpr int NM = Shape<N>::NM;
-    // the angle-kernel combination of the moments for value x of the packed matrix
-    auto kern = [&](int x) __attribute__((always_inline)) {
-        double v = J[x] - c * J[NM + x];
-        if constexpr (NJ == 4) v = (v - sc * J[2 * NM + x]) - ss * J[3 * NM + x];
-        return v;
-    };
-    double Cd[N], tr = 0.0;
-    for (int a = 0; a < N; ++a) {
-        Cd[a] = kern(a);
-        tr += Cd[a];
+    f[0] = w;
+    f[1] = rc.ma ? w * c : 0.0;
+    if constexpr (NJ == 4) {
+        const double s = sqrt((1.0 - c) * (1.0 + c));
+        f[2] = (w * s) * cph;
+        f[3] = (w * s) * sph;
     }
-    double av[NM], bv[NM];
-    for (int a = 0; a < N; ++a) {
-        const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
-        G[a] = (rc.frame == 0) ? hd * ic : 0.0;
-        av[a] = (rc.frame == 0) ? 0.0 : hd * ic;
-        bv[a] = rc.vac[a][a][0] * ic;
-    }
-    for (int a = 0; a < N; ++a)
-        for (int b = a + 1; b < N; ++b) {
-            const int q = Shape<N>::up(a, b);
-            const double cs = z[q][0], sn = z[q][1];
-            const double cr = rc.mu0 * kern(N + 2 * q) * ic;
-            const double ci = rc.mu0 * kern(N + 2 * q + 1) * ic;
-            const double vr = rc.vac[a][b][0] * ic, vi = rc.vac[a][b][1] * ic;
-            av[N + 2 * q] = cs * cr - sn * ci;
-            av[N + 2 * q + 1] = cs * ci + sn * cr;
-            bv[N + 2 * q] = cs * vr - sn * vi;
-            bv[N + 2 * q + 1] = cs * vi + sn * vr;
-        }
-    double hab[2 * NM];
-    for (int x = 0; x < NM; ++x) {
-        hab[x] = h * av[x];
-        hab[NM + x] = h * bv[x];
-    }
-    StageMat<T, N>& Mh = reinterpret_cast<StageMat<T, N>*>(rc.mat)[(size_t)l * rc.na + j];
-    lane_scatter(Mh.a, hab, lane);   // a and b are contiguous
-    lane_scatter(M->a, hab, lane);
 }
 
 // Step controller (readings J, K of the oracle's header; fixed-step RK4 always
@@ -459,47 +347,13 @@ __device__ bool control_step(const RunConst& rc, Control& C, double m)
     return accepted;
 }
 
-// Sum of the value-major partials of stage `st` (nblk workgroups) into
-// out[NV] (LDS), by all BLK threads of a workgroup in one fixed order: thread
-// (v, c) adds partials c, c + CH, ... of value v (CH = BLK / NV chunks per
-// value), then one thread per value adds the CH chunk sums.  Every workgroup
-// running this gets the same bits.
-template <int NV, int BLK>
-__device__ void reduce_partials(const RunConst& rc, int st, double* out, double (*sred)[BLK / NV])
-{
-    constexpr int CH = BLK / NV;
-    const int t = threadIdx.x;
-    const int nblk = rc.nblk;
-    const double* src = rc.partial + (size_t)(st & 1) * NV * nblk;
-    if (t < NV * CH) {
-        const int v = t / CH, c = t - v * CH;
-        const double* pv = src + (size_t)v * nblk;
-        double acc = 0.0;
-        int p = c;
-        for (; p + 3 * CH < nblk; p += 4 * CH) {
-            const double x0 = pv[p], x1 = pv[p + CH], x2 = pv[p + 2 * CH], x3 = pv[p + 3 * CH];
-            acc += x0;
-            acc += x1;
-            acc += x2;
-            acc += x3;
-        }
-        for (; p < nblk; p += CH) acc += pv[p];
-        sred[v][c] = acc;
-    }
-    __syncthreads();
-    if (t < NV) {
-        double sum = sred[t][0];
-        for (int c = 1; c < CH; ++c) sum += sred[t][c];
-        out[t] = sum;
-    }
-    __syncthreads();
-}
-
-// The same sum done by the NW wavefronts of a workgroup: value v by wavefront
-// v mod NW, lane l adding partials l, l + 64, ... in order, then a butterfly
-// whose lane-0 result is kept (one fixed order).  Every workgroup running this
-// gets the same bits.  Split in two so that the loads of the first 256
-// partials are in flight while independent work runs.
+// ------------------------------------------------------------------ partial sums
+// Sum of the value-major partials of buffer `par` (nblk workgroups) by the NW
+// wavefronts of a workgroup: value v by wavefront v mod NW, lane l adding
+// partials l, l + 64, ... in order, then a butterfly whose lane-0 result is
+// kept (one fixed order).  Every workgroup running this gets the same bits.
+// Split in two so that the loads of the first 256 partials are in flight while
+// independent work runs.
 template <int NV, int NW>
 struct PartialRegs {
     static constexpr int VPW = (NV + NW - 1) / NW;  // values per wavefront
@@ -507,11 +361,11 @@ struct PartialRegs {
 };
 
 template <int NV, int NW>
-__device__ __forceinline__ void load_partials_waves(const RunConst& rc, int st, PartialRegs<NV, NW>& r)
+__device__ __forceinline__ void load_partials(const RunConst& rc, int par, PartialRegs<NV, NW>& r)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nblk = rc.nblk;
-    const double* src = rc.partial + (size_t)(st & 1) * NV * nblk;
+    const double* src = rc.partial + (size_t)(par & 1) * NV * nblk;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
@@ -524,664 +378,903 @@ __device__ __forceinline__ void load_partials_waves(const RunConst& rc, int st, 
 }
 
 template <int NV, int NW>
-__device__ void finish_partials_waves(const RunConst& rc, int st, const PartialRegs<NV, NW>& r, double* out)
+__device__ void finish_partials(const RunConst& rc, int par, const PartialRegs<NV, NW>& r, double* out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nblk = rc.nblk;
-    const double* src = rc.partial + (size_t)(st & 1) * NV * nblk;
+    const double* src = rc.partial + (size_t)(par & 1) * NV * nblk;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
         if (v >= NV) continue;
-        // partials 256..511 (launches with more than 256 workgroups): all four
-        // loads issued before the first add, then any further ones in turn
-        double t[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int p = lane + 256 + 64 * k;
-            t[k] = p < nblk ? src[(size_t)v * nblk + p] : 0.0;
-        }
         double acc = r.x[i][0];
         acc += r.x[i][1];
         acc += r.x[i][2];
         acc += r.x[i][3];
-        acc += t[0];
-        acc += t[1];
-        acc += t[2];
-        acc += t[3];
-        for (int p = lane + 512; p < nblk; p += 64) acc += src[(size_t)v * nblk + p];
+        for (int p = lane + 256; p < nblk; p += 64) acc += src[(size_t)v * nblk + p];
         acc = wave_sum(acc);
         if (lane == 0) out[v] = acc;
     }
     __syncthreads();
 }
 
-// ------------------------------------------------------------------ beam kernel
-// Launch shape of the beam kernels: one wavefront per trajectory.  FP32
-// arithmetic: 16 trajectories per workgroup, three beams of each lane in
-// flight, at most 128 VGPRs, so every wavefront of a 4000-trajectory grid is
-// resident at once.  FP64 arithmetic: 8 trajectories per workgroup.
-template <typename T> struct BeamShape {
-    static constexpr bool fp64 = std::is_same<T, double>::value;
-    static constexpr int traj = fp64 ? 8 : 16;
-    static constexpr int block = 64 * traj;
-};
+// ------------------------------------------------------------------ power moments
+// Launch S + 2 of an attempt (TAIL) and the moment launch after a new state or
+// radius (FORCE).  TAIL first takes the global maximum of the state-update
+// launch's error maxima and runs the controller in every workgroup (the same
+// result everywhere; workgroup 0 stores the control block); a rejected attempt
+// ends here.  Then, for the current state y (the accepted new state):
+//   Q_p[j] = sum_k w_k u_k^p y y^+,  p = 0 .. NQ-1  (packed Hermitian, FP64),
+// with two trajectories per wavefront (32 lanes each) and two lanes per beam
+// (the first adds powers 0..H-1, the second H..2H-1), 16 beams of a
+// trajectory per wavefront iteration; the lanes' sums are added by a
+// butterfly over the 16 lanes of a trajectory and parity.  Q_0 is the
+// density sum of the state itself: rotated to the lab frame and weighted at
+// the state's radius, it gives the workgroup's partial of J_0 (buffer 0).
+constexpr int kPowerWaves = kTrajPerBlock / 2;
 
-// Beams in flight per lane and the wavefronts per SIMD the register
-// allocation must allow, per launch.  FP32 arithmetic: three beams, four
-// wavefronts.  FP64 arithmetic needs about twice the registers per beam;
-// with two beams in flight the middle launches exceed 128 VGPRs and their
-// grid runs in two rounds.  Measured on the 3.2M-beam grid, these launches
-// are faster with one beam in flight and four wavefronts per SIMD (the
-// compiler spills a few registers of the prologue), the others with two
-// beams: stages 2-4 (FP64 storage; also its final launch of a split error)
-// and 3-5 (FP32 storage).
-template <typename TS, typename T, typename TAB, int I> struct BeamPlan {
-    static constexpr bool fp64 = BeamShape<T>::fp64;
-    static constexpr bool split_final = TAB::fsal && TAB::embedded && I == TAB::S;
-    static constexpr bool narrow =
-        fp64 && (std::is_same<TS, double>::value ? ((I >= 2 && I <= 4) || split_final) : (I >= 3 && I <= 5));
-    static constexpr int slots = fp64 ? (narrow ? 1 : 2) : 3;
-    static constexpr int waves_per_eu = (!fp64 || narrow) ? 4 : 1;
-};
-
-// Beam launch I of the attempt (the file header describes the whole step).
-// Prologue: J_{I-1} from the previous launch's partials, then stage I-1 of
-// this workgroup's trajectories is completed (launch 1 also prepares stage 0
-// for the new control block).  Beam loop: k_0..k_{I-1} recomputed from y_n.
-// Epilogue: stage I is prepared (phase, rotation factors, geometry) and the
-// density sum of the formed state is rotated, weighted and added per
-// workgroup.  TS: amplitude type in HBM; T: arithmetic type of the stage
-// update (density sums are FP64 in every form).
-template <typename TS, typename T, int N, typename TAB, int I, int NJ>
-__device__ __forceinline__ void stage_body(const RunConst& rc, const int blk)
+template <typename TS, int N, typename TAB, int NJ, bool FORCE>
+__device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 {
-    constexpr int kTrajPerBlock = BeamShape<T>::traj;
-    constexpr int S = TAB::S;
-    constexpr bool FINAL = (I == S);
-    constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU;
-    constexpr int NV = NJ * NM;                          // angle moments J0, J1 (J2, J3)
-    constexpr int NF = NJ == 4 ? 4 : 2;                  // epilogue weights per trajectory
-    constexpr bool ERROR = FINAL && TAB::embedded;
-    constexpr bool FSAL_FINAL = FINAL && TAB::fsal;      // derivatives and error only
-    constexpr bool MOMENTS = !FSAL_FINAL;                // density sum of the formed state
-    constexpr bool NEWSTATE = TAB::fsal ? (I == S - 1) : FINAL;
-    // Embedded pair with first-same-as-last: the launch that forms y_{n+1}
-    // also stores sum_{m<S-1} e_m k_m per beam component, and the final launch
-    // evaluates only k_{S-1} = f(y_{n+1}) and adds its term.
-    constexpr bool SPLIT = TAB::fsal && TAB::embedded;
-    constexpr bool ERRSTORE = SPLIT && I == S - 1;
-    constexpr bool ERRLAST = SPLIT && FINAL;
-    constexpr int NSLOT = BeamPlan<TS, T, TAB, I>::slots;
-    constexpr int NK = ERRLAST ? 1 : I;                  // derivatives evaluated per beam
-    constexpr uint32_t STRIDE = 64;                      // beam-slot stride of one lane
-    using Mat = StageMat<T, N>;
+    constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU, NV = NJ * NM;
+    constexpr int NQ = Poly<TAB>::NQ;
+    constexpr int H = (NQ + 1) / 2;  // powers per lane
+    constexpr int NSLOT = 2;         // beams of a lane in flight
+    constexpr uint32_t STRIDE = 16;  // beam-slot stride of a lane pair
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int jt = wave;
+    __shared__ double swave[kTrajPerBlock][NV];
+    __shared__ double serr[kPowerWaves];
+
+    Control C;
+    if constexpr (FORCE) {
+        C = rc.ctrl[1];
+    } else {
+        C = rc.ctrl[0];
+        if (C.status != 0) return;  // the attempt did not run
+        double m = 0.0;
+        for (int p = tid; p < rc.nblkf; p += 64 * kPowerWaves) m = fmax(m, rc.errpart[p]);
+        m = wave_max(m);
+        if (lane == 0) serr[wave] = m;
+        __syncthreads();
+        m = serr[0];
+        for (int w = 1; w < kPowerWaves; ++w) m = fmax(m, serr[w]);
+        const bool accepted = control_step<TAB>(rc, C, m);
+        C.fresh = accepted ? 1 : 0;
+        if (blk == 0 && tid == 0) rc.ctrl[1] = C;
+        if (!accepted) return;
+    }
+
+    const int cur = C.cur;
+    const int g = lane >> 5, hb = lane & 1, q = (lane & 31) >> 1;
+    const int jt = 2 * wave + g;
     const int j = blk * kTrajPerBlock + jt;
     const bool active = j < rc.na;
-
-    __shared__ Mat smat[kTrajPerBlock][NK > 0 ? NK : 1];
-    __shared__ double swave[kTrajPerBlock][NV + 1];
-    __shared__ double sJ[NV];
-    __shared__ double sF[kTrajPerBlock][NF + 2 * (NU > 0 ? NU : 1)];  // weights, z of stage I (-> epilogue)
-
-    // ---- the control block first (the longest dependent chain starts here);
-    //      ctrl[1] holds it between attempts, ctrl[0] during one
-    // (relaxed atomic loads: issued here rather than sunk to their first use)
-    Control C{};
-    {
-        Control* vc = rc.ctrl + (I <= 1 ? 1 : 0);
-        C.r = __hip_atomic_load(&vc->r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        C.h = __hip_atomic_load(&vc->h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        C.istep = __hip_atomic_load(&vc->istep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        C.cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        C.status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-
-    // ---- stage matrices of k_0..k_{I-2} (raw dwords, by the trajectory's
-    //      wavefront), in flight while the control block arrives; stored to
-    //      LDS after the stage completion
-    constexpr int MPER = sizeof(Mat) / 4;
-    constexpr int NKS = NK > 1 ? NK - 1 : 0;             // stored matrices
-    constexpr int MREG = (NKS * MPER + (int)STRIDE - 1) / (int)STRIDE;
-    uint32_t mreg[MREG > 0 ? MREG : 1];
-    if constexpr (NKS > 0) {
-        const uint32_t* msrc = reinterpret_cast<const uint32_t*>(rc.mat);
-#pragma unroll
-        for (int i = 0; i < MREG; ++i) {
-            const int x = lane + i * (int)STRIDE;
-            if (active && x < NKS * MPER) {
-                const int l = x / MPER, q = x - l * MPER;
-                mreg[i] = msrc[((size_t)l * rc.na + j) * MPER + q];
-            }
-        }
-    }
-
-    // ---- prologue inputs that do not depend on the control block (in flight
-    //      while it is read): launch I-1's partial density sums, the frame of
-    //      stage I-1, and the phase sums of stages I, I+1, ... (lane k: stage
-    //      I + k) that the earlier launches of this attempt accumulated
-    constexpr int LASTPREP = TAB::fsal ? S - 1 : S;      // last launch that prepares a stage frame
-    PartialRegs<NV, kTrajPerBlock> xp;
-    if constexpr (I >= 2) load_partials_waves<NV, kTrajPerBlock>(rc, I - 1, xp);
-    double cP = 1.0, icP = 1.0, zP[NU > 0 ? NU : 1][2];
-    double sP = 0.0, cph = 1.0, sph = 0.0;                 // sin(theta) of stage I-1; azimuth
-    double psum[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) psum[a] = 0.0;
-    if (active) {
-        if constexpr (NJ == 4) {
-            cph = rc.azi[2 * (size_t)j];
-            sph = rc.azi[2 * (size_t)j + 1];
-        }
-        if constexpr (I >= 2) {
-            const TrajGeo& g = rc.geo[(size_t)(I - 1) * rc.na + j];
-            cP = g.c;
-            icP = g.ic;
-            if constexpr (NJ == 4) sP = sqrt((1.0 - g.c) * (1.0 + g.c));
-            for (int q = 0; q < NU; ++q) {
-                zP[q][0] = g.z[q][0];
-                zP[q][1] = g.z[q][1];
-            }
-            if constexpr (MOMENTS) {
-                if (I + lane <= LASTPREP)
-                    for (int a = 0; a < N; ++a) psum[a] = rc.geo[(size_t)(I + lane) * rc.na + j].P[a];
-            }
-        }
-    }
-
-    // the first launch of an attempt takes the control block between attempts
-    if (I == 1 && blk == 0 && threadIdx.x == 0) rc.ctrl[0] = rc.ctrl[1];
-    if (I > 0 && C.status != 0) return;  // run finished: attempts are no-ops
-    const int cur = C.cur;
-    const double h = C.h;
-
-    // ---- per-beam data
-    // slot t < N_E: neutrino of energy bin t; t >= N_E: antineutrino of bin t - N_E
     const uint32_t ne = (uint32_t)rc.ne;
     const uint32_t nbt = active ? 2u * ne : 0u;
     const uint32_t base0 = (uint32_t)j * ne;
     const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
-    const TS* src = reinterpret_cast<const TS*>(rc.psi[ERRLAST ? cur ^ 1 : cur]);
-    TS* dst = reinterpret_cast<TS*>(rc.psi[cur ^ 1]);
-    T* errv = reinterpret_cast<T*>(rc.errv);
     const size_t ld = (size_t)rc.nb_pad;
-    global<const T>* __restrict__ uinv = uniform_global(uinv_table<T>(rc));
-    global<const double>* __restrict__ wgtp = uniform_global(rc.wgt);
-    // per-component bases: state read (y_n, or y_{n+1} for the final launch of
-    // a split error), state written, partial error sums
+    const TS* src = reinterpret_cast<const TS*>(rc.psi[cur]);
     global<const TS>* __restrict__ srcq[2 * N];
-    global<TS>* __restrict__ dstq[2 * N];
-    global<T>* __restrict__ errq[2 * N];
 #pragma unroll
-    for (int q = 0; q < 2 * N; ++q) {
-        srcq[q] = uniform_global(src + q * ld);
-        dstq[q] = uniform_global(dst + q * ld);
-        errq[q] = uniform_global(errv + q * ld);
-    }
-    const Mat* mats = smat[jt];
+    for (int x = 0; x < 2 * N; ++x) srcq[x] = uniform_global(src + x * ld);
+    global<const double>* __restrict__ uinv = uniform_global(rc.uinv64);
+    global<const double>* __restrict__ wgtp = uniform_global(rc.wgt);
 
-    double macc[NM];
+    double acc[H][NM];
 #pragma unroll
-    for (int i = 0; i < NM; ++i) macc[i] = 0.0;
-    T emax = 0;
-    bool bad = false;
+    for (int k = 0; k < H; ++k)
+#pragma unroll
+        for (int x = 0; x < NM; ++x) acc[k][x] = 0.0;
 
-    auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
-    auto fetch = [&](uint32_t t, TS* yv, T* dv, T& uv, double& wv) __attribute__((always_inline)) {
+    auto fetch = [&](uint32_t t, TS* yv, double& uv, double& wv) __attribute__((always_inline)) {
         if (t < nbt) {
-            const uint32_t off = offset(t);
+            const uint32_t off = t + base0 + (t >= ne ? delta : 0u);
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) yv[q] = *elem(srcq[q], off);
-            if constexpr (ERRLAST) {
-#pragma unroll
-                for (int q = 0; q < 2 * N; ++q) dv[q] = *elem(errq[q], off);
-            }
+            for (int x = 0; x < 2 * N; ++x) yv[x] = *elem(srcq[x], off);
             uv = *elem(uinv, t);
-            if constexpr (MOMENTS) wv = *elem(wgtp, t);
+            wv = *elem(wgtp, t);
         }
     };
-    auto process = [&](uint32_t t, const TS* yv, const T* dv, T u, double wt) __attribute__((always_inline)) {
-        T y[2 * N];
+    auto process = [&](const TS* yv, double u, double w) __attribute__((always_inline)) {
+        double y[2 * N], wy[2 * N], r[NM];
 #pragma unroll
-        for (int q = 0; q < 2 * N; ++q) y[q] = (T)yv[q];
-        if constexpr (ERRLAST) {
-            // y = y_{n+1}, dv = sum_{m<S-1} e_m k_m: the error h sum_m e_m k_m
-            T k[2 * N];
-            eval_ky<T, N>(mats[0].a, mats[0].b, u, y, k);
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                T d = dv[q];
-                if constexpr (TAB::E[S - 1] != 0.0) d = fma((T)(ksign(q) * TAB::E[S - 1]), k[q ^ 1], d);
-                const T e = fabs(d);
-                bad |= !isfinite(e);
-                emax = fmax(emax, e);
-            }
-            return;
+        for (int x = 0; x < 2 * N; ++x) {
+            y[x] = (double)yv[x];
+            wy[x] = w * y[x];
         }
-        // Compiler-only barrier: re-read the (wave-uniform) stage matrices from
-        // LDS for every beam instead of holding all of them in registers.
-        asm volatile("" ::: "memory");
-
-        T kk[NK > 0 ? NK : 1][2 * N];
-        static_for<0, NK>([&](auto Lc) {
-            constexpr int l = decltype(Lc)::value;
-            T Y[2 * N];
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                // Y_l = y_n + sum_m a_lm (h k_m), added onto y_n term by term
-                T acc = y[q];
-                static_for<0, l>([&](auto Mc) {
-                    constexpr int m = decltype(Mc)::value;
-                    if constexpr (TAB::A[l][m] != 0.0) {
-                        constexpr double a_lm = TAB::A[l][m];
-                        acc = fma((T)(ksign(q) * a_lm), kk[m][q ^ 1], acc);
-                    }
-                });
-                Y[q] = acc;
+        for (int a = 0; a < N; ++a) r[a] = fma(wy[2 * a], y[2 * a], wy[2 * a + 1] * y[2 * a + 1]);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = a + 1; b < N; ++b) {
+                const int x = N + 2 * Shape<N>::up(a, b);
+                r[x] = fma(wy[2 * a], y[2 * b], wy[2 * a + 1] * y[2 * b + 1]);      // Re w y_a conj(y_b)
+                r[x + 1] = fma(wy[2 * a + 1], y[2 * b], -(wy[2 * a] * y[2 * b + 1]));  // Im
             }
-            // keep only this stage's matrix live: no LDS reads hoisted across stages
-            asm volatile("" ::: "memory");
-            eval_ky<T, N>(mats[l].a, mats[l].b, u, Y, kk[l]);
+        // u^(H hb): the second lane of the pair starts at power H
+        double uh = 1.0, bpow = u;
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) pin(kk[l][q]);
-        });
-
-        if constexpr (ERRSTORE) {
-            // the error terms of k_0..k_{S-2}, summed in the order of the final sum
-            const uint32_t off = offset(t);
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                T d = 0;
-                bool first = true;
-                static_for<0, NK>([&](auto Mc) {
-                    constexpr int m = decltype(Mc)::value;
-                    if constexpr (TAB::E[m] != 0.0) {
-                        d = first ? (T)(ksign(q) * TAB::E[m]) * kk[m][q ^ 1] : fma((T)(ksign(q) * TAB::E[m]), kk[m][q ^ 1], d);
-                        first = false;
-                    }
-                });
-                *elem(errq[q], off) = d;
-            }
+        for (int e = H; e > 0; e >>= 1) {
+            if (e & 1) uh *= bpow;
+            bpow *= bpow;
         }
-
-        if constexpr (ERROR && !SPLIT) {
-            // h sum_m e_m k_m per real component
+        double pw = hb ? uh : 1.0;
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                T d = 0;
-                bool first = true;
-                static_for<0, S>([&](auto Mc) {
-                    constexpr int m = decltype(Mc)::value;
-                    if constexpr (TAB::E[m] != 0.0) {
-                        d = first ? (T)(ksign(q) * TAB::E[m]) * kk[m][q ^ 1] : fma((T)(ksign(q) * TAB::E[m]), kk[m][q ^ 1], d);
-                        first = false;
-                    }
-                });
-                const T e = fabs(d);
-                bad |= !isfinite(e);
-                emax = fmax(emax, e);
-            }
-        }
-
-        if constexpr (MOMENTS) {
-            // the state this launch forms: Y_I, or y_{n+1} for the last launch of
-            // a tableau without first-same-as-last (y_n itself for I == 0)
-            T Yo[2 * N];
+        for (int k = 0; k < H; ++k) {
 #pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                if constexpr (I == 0) {
-                    Yo[q] = y[q];
-                } else if constexpr (NEWSTATE) {
-                    // y_{n+1}: the increment summed first, then added to y_n once
-                    T acc = 0;
-                    bool first = true;
-                    static_for<0, NK>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        if constexpr (coef<TAB>(I, m) != 0.0) {
-                            constexpr double c_im = coef<TAB>(I, m);
-                            acc = first ? (T)(ksign(q) * c_im) * kk[m][q ^ 1] : fma((T)(ksign(q) * c_im), kk[m][q ^ 1], acc);
-                            first = false;
-                        }
-                    });
-                    Yo[q] = y[q] + acc;
-                } else {
-                    // a stage input: the same operations as its recomputation
-                    // in the later launches
-                    T acc = y[q];
-                    static_for<0, NK>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        if constexpr (coef<TAB>(I, m) != 0.0) {
-                            constexpr double c_im = coef<TAB>(I, m);
-                            acc = fma((T)(ksign(q) * c_im), kk[m][q ^ 1], acc);
-                        }
-                    });
-                    Yo[q] = acc;
-                }
-            }
-            if constexpr (NEWSTATE) {
-                // FP32 amplitudes are renormalised whenever a new state is
-                // formed; the moments are those of the stored values.
-                if constexpr (std::is_same<TS, float>::value) {
-                    T nn = 0;
-#pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) nn = fma(Yo[q], Yo[q], nn);
-                    const T sc = T(1) / sqrt(nn);
-#pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) Yo[q] = (T)(TS)(Yo[q] * sc);
-                }
-                const uint32_t off = offset(t);
-#pragma unroll
-                for (int q = 0; q < 2 * N; ++q) *elem(dstq[q], off) = (TS)Yo[q];
-                if constexpr (!TAB::embedded) {
-#pragma unroll
-                    for (int q = 0; q < 2 * N; ++q) bad |= !isfinite(Yo[q]);
-                }
-            }
-            // weighted density sum in the rotated frame: wt psi_a conj(psi_b)
-            double z[2 * N], wz[2 * N];
-#pragma unroll
-            for (int q = 0; q < 2 * N; ++q) {
-                z[q] = (double)Yo[q];
-                wz[q] = wt * z[q];
-            }
-#pragma unroll
-            for (int a = 0; a < N; ++a) macc[a] = fma(wz[2 * a], z[2 * a], fma(wz[2 * a + 1], z[2 * a + 1], macc[a]));
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-#pragma unroll
-                for (int b = a + 1; b < N; ++b) {
-                    const int q = Shape<N>::up(a, b);
-                    macc[N + 2 * q] = fma(wz[2 * a], z[2 * b], fma(wz[2 * a + 1], z[2 * b + 1], macc[N + 2 * q]));
-                    macc[N + 2 * q + 1] = fma(wz[2 * a + 1], z[2 * b], fma(-wz[2 * a], z[2 * b + 1], macc[N + 2 * q + 1]));
-                }
+            for (int x = 0; x < NM; ++x) acc[k][x] = fma(r[x], pw, acc[k][x]);
+            pw *= u;
         }
     };
 
-    // ---- phase of the accepted state and geometry of stage I (wave-uniform)
-    double phn[N];
-    double cN = 1.0, wN = 0.0;
-    if (active) {
-        if constexpr (MOMENTS && I > 0) {
-            for (int a = 0; a < N; ++a) phn[a] = rc.phase[cur][(size_t)j * N + a];
-            traj_geometry(rc, j, stage_radius<TAB>(rc, C, I), cN, wN);
-        }
-    }
-
-    // ---- the first beam of every slot: in flight from here on (no stage
-    //      frame to prepare), else (register pressure) from the end of the
-    //      stage completion on, overlapping the frame preparation
-    constexpr bool EARLY_FETCH = !(MOMENTS && I > 0);
     TS ys[NSLOT][2 * N];
-    T ds[NSLOT][ERRLAST ? 2 * N : 1];
-    T us[NSLOT];
-    double ws[NSLOT];
-    const uint32_t t0 = (uint32_t)lane;
-    auto fetch_first = [&]() __attribute__((always_inline)) {
-        static_for<0, NSLOT>([&](auto Sc) {
-            constexpr int sl = decltype(Sc)::value;
-            us[sl] = 0;
-            ws[sl] = 0.0;
-            fetch(t0 + sl * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
-        });
-    };
-    if constexpr (EARLY_FETCH) fetch_first();
-
-
-    // ---- J_{I-1}: the previous launch's partials (launch 1: J_0 of the state)
-    if constexpr (NK > 0) {
-        if constexpr (I == 1) {
-            if ((int)threadIdx.x < NV) sJ[threadIdx.x] = rc.jhist[threadIdx.x];
-            __syncthreads();
-        } else {
-            finish_partials_waves<NV, kTrajPerBlock>(rc, I - 1, xp, sJ);
-            if (blk == 0 && (int)threadIdx.x < NV) rc.jhist[(size_t)(I - 1) * NV + threadIdx.x] = sJ[threadIdx.x];
-        }
-        // stored matrices -> LDS; stage I-1 completed for this trajectory
-        uint32_t* mdst = reinterpret_cast<uint32_t*>(&smat[jt][0]);
-#pragma unroll
-        for (int i = 0; i < MREG; ++i) {
-            const int x = lane + i * (int)STRIDE;
-            if (active && x < NKS * MPER) mdst[x] = mreg[i];
-        }
-        if (active) {
-            double J[NV];
-            for (int v = 0; v < NV; ++v) J[v] = sJ[v];
-            if constexpr (I == 1) {
-                double c0, w0;
-                traj_geometry(rc, j, stage_radius<TAB>(rc, C, 0), c0, w0);
-                const Frame<N> f0 = prepare_wave<N>(rc, j, 0, c0, w0, phn, lane);
-                cP = f0.c;
-                icP = f0.ic;
-                sP = f0.s;
-                for (int q = 0; q < NU; ++q) {
-                    zP[q][0] = f0.z[q][0];
-                    zP[q][1] = f0.z[q][1];
-                }
-            }
-            double GP[N];
-            complete_wave<T, N, NJ>(rc, j, I - 1, cP, icP, sP * cph, sP * sph, zP,
-                                    matter(rc, stage_radius<TAB>(rc, C, I - 1)), J, h, GP, &smat[jt][NK - 1], lane);
-            if constexpr (!EARLY_FETCH) fetch_first();
-            if constexpr (MOMENTS) {
-                // phase sums sum_{m < l} coef(l, m) G_m: lane k adds the term of
-                // G_{I-1} to that of stage l = I + k and passes it on to launch l
-                const int l = I + lane;
-                const double cf = coef_of_column<TAB, I - 1, LASTPREP>(l);
-                if (cf != 0.0)
-                    for (int a = 0; a < N; ++a) psum[a] += cf * GP[a];
-                if (lane >= 1 && l <= LASTPREP)
-                    for (int a = 0; a < N; ++a) rc.geo[(size_t)l * rc.na + j].P[a] = psum[a];
-                // stage I prepared now, its frame kept for the epilogue: phase
-                // Phi_n + h sum_{m < I} coef(I, m) G_m, rotation factors, geometry
-                double ph[N];
-                for (int a = 0; a < N; ++a) ph[a] = phn[a] + h * __shfl(psum[a], 0, 64);
-                const Frame<N> f = prepare_wave<N>(rc, j, I, cN, wN, ph, lane);
-                if (I == LASTPREP)  // the new state's phase; kept only if the attempt is accepted
-                    lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
-                double fw[NF + 2 * (NU > 0 ? NU : 1)];
-                fw[0] = f.w;
-                fw[1] = f.wc;
-                if constexpr (NJ == 4) {
-                    fw[2] = (f.w * f.s) * cph;
-                    fw[3] = (f.w * f.s) * sph;
-                }
-                for (int q = 0; q < NU; ++q) {
-                    fw[NF + 2 * q] = f.z[q][0];
-                    fw[NF + 1 + 2 * q] = f.z[q][1];
-                }
-                lane_scatter(sF[jt], fw, lane);
-            }
-        }
-        // the stage matrices in LDS are this wavefront's own: a wavefront-level
-        // barrier orders its LDS writes before the beam loop reads them
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
-    // ---- beam loop: NSLOT-slot load pipeline, the next beams of the other
-    //      slots in flight while one is computed (unrolled by NSLOT, no copies)
+    double us[NSLOT], ws[NSLOT];
+    const uint32_t t0 = (uint32_t)q;
+    static_for<0, NSLOT>([&](auto Sc) {
+        constexpr int sl = decltype(Sc)::value;
+        us[sl] = 0.0;
+        ws[sl] = 0.0;
+        fetch(t0 + sl * STRIDE, ys[sl], us[sl], ws[sl]);
+    });
 #pragma unroll 1
     for (uint32_t t = t0; t < nbt; t += NSLOT * STRIDE) {
         static_for<0, NSLOT>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
             const uint32_t ts = t + sl * STRIDE;
-            if (sl == 0 || ts < nbt) process(ts, ys[sl], ds[sl], us[sl], ws[sl]);
-            fetch(ts + NSLOT * STRIDE, ys[sl], ds[sl], us[sl], ws[sl]);
+            if (sl == 0 || ts < nbt) process(ys[sl], us[sl], ws[sl]);
+            fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], ws[sl]);
         });
     }
 
-    // ---- epilogue: stage I prepared, density sum rotated and weighted
-    if constexpr (MOMENTS) {
+    // sums over the 16 lanes of one trajectory and parity
 #pragma unroll
-        for (int i = 0; i < NM; ++i) macc[i] = wave_sum(macc[i]);
+    for (int off = 2; off < 32; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < H; ++k)
+#pragma unroll
+            for (int x = 0; x < NM; ++x) acc[k][x] += __shfl_xor(acc[k][x], off, 64);
+
+    if (active && q == 0) {
+        double* dst = rc.qbuf[cur] + (size_t)j * rc.qstride;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const int p = hb * H + k;
+            if (p < NQ)
+#pragma unroll
+                for (int x = 0; x < NM; ++x) dst[p * NM + x] = acc[k][x];
+        }
+    }
+
+    // the J_0 partial: Q_0 (lane 32 g) rotated to the lab frame and weighted
+    if ((lane & 31) == 0) {
         double sl[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) sl[v] = 0.0;
         if (active) {
-            Frame<N> f;
-            double wsc = 0.0, wss = 0.0;  // w sin(theta) cos(phi), w sin(theta) sin(phi)
-            if constexpr (I == 0) {
-                // stage-0 frame prepared before this launch
-                const TrajGeo& g = rc.geo[j];
-                f.c = g.c;
-                f.w = g.w;
-                f.wc = g.wc;
-                f.ic = g.ic;
-                if constexpr (NJ == 4) {
-                    const double s0 = sqrt((1.0 - g.c) * (1.0 + g.c));
-                    wsc = (g.w * s0) * cph;
-                    wss = (g.w * s0) * sph;
-                }
-                for (int q = 0; q < NU; ++q) {
-                    f.z[q][0] = g.z[q][0];
-                    f.z[q][1] = g.z[q][1];
-                }
-            } else {
-                // frame of stage I prepared in the prologue
-                f.w = sF[jt][0];
-                f.wc = sF[jt][1];
-                if constexpr (NJ == 4) {
-                    wsc = sF[jt][2];
-                    wss = sF[jt][3];
-                }
-                for (int q = 0; q < NU; ++q) {
-                    f.z[q][0] = sF[jt][NF + 2 * q];
-                    f.z[q][1] = sF[jt][NF + 1 + 2 * q];
-                }
+            double c, w, ph[N], z[NU > 0 ? NU : 1][2], f[4];
+            traj_geometry(rc, j, C.r, c, w);
+            for (int a = 0; a < N; ++a) ph[a] = rc.phase[cur][(size_t)j * N + a];
+            rotation<N>(ph, z);
+            double cph = 1.0, sph = 0.0;
+            if constexpr (NJ == 4) {
+                cph = rc.azi[2 * (size_t)j];
+                sph = rc.azi[2 * (size_t)j + 1];
             }
-            // S_ab = 2 e^{-i(Phi_a - Phi_b)} S~_ab ; S_aa = 2 S~_aa, weighted by w and w c
+            angle_weights<NJ>(rc, c, w, cph, sph, f);
             double Sv[NM];
-            for (int a = 0; a < N; ++a) Sv[a] = 2.0 * macc[a];
-            for (int q = 0; q < NU; ++q) {
-                const double cs = f.z[q][0], sn = f.z[q][1];
-                const double xr = macc[N + 2 * q], xi = macc[N + 2 * q + 1];
-                Sv[N + 2 * q] = 2.0 * (cs * xr + sn * xi);
-                Sv[N + 2 * q + 1] = 2.0 * (cs * xi - sn * xr);
+            for (int a = 0; a < N; ++a) Sv[a] = 2.0 * acc[0][a];
+            for (int u = 0; u < NU; ++u) {
+                const double cs = z[u][0], sn = z[u][1];
+                const double xr = acc[0][N + 2 * u], xi = acc[0][N + 2 * u + 1];
+                Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
+                Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
             }
-            for (int v = 0; v < NM; ++v) {
-                sl[v] = f.w * Sv[v];
-                sl[NM + v] = f.wc * Sv[v];
-                if constexpr (NJ == 4) {
-                    sl[2 * NM + v] = wsc * Sv[v];
-                    sl[3 * NM + v] = wss * Sv[v];
-                }
-            }
+            for (int m = 0; m < NJ; ++m)
+                for (int v = 0; v < NM; ++v) sl[m * NM + v] = f[m] * Sv[v];
         }
-        if (lane == 0)
-            for (int v = 0; v < NV; ++v) swave[jt][v] = sl[v];
-    }
-    if constexpr (FINAL) {
-        double e = bad ? (double)INFINITY : (double)emax;
-        e = wave_max(e);
-        if (lane == 0) swave[jt][NV] = active ? e : 0.0;
+        for (int v = 0; v < NV; ++v) swave[jt][v] = sl[v];
     }
     __syncthreads();
-    if constexpr (MOMENTS) {
-        if ((int)threadIdx.x < NV) {
-            const int v = threadIdx.x;
-            double acc = swave[0][v];
-            for (int w = 1; w < kTrajPerBlock; ++w) acc += swave[w][v];
-            rc.partial[((size_t)(I & 1) * NV + v) * rc.nblk + blk] = acc;
-        }
-    }
-    if constexpr (FINAL) {
-        if (threadIdx.x == 0) {
-            double e = swave[0][NV];
-            for (int w = 1; w < kTrajPerBlock; ++w) e = fmax(e, swave[w][NV]);
-            rc.errpart[blk] = e;
-        }
+    if (tid < NV) {
+        double s = swave[0][tid];
+        for (int w = 1; w < kTrajPerBlock; ++w) s += swave[w][tid];
+        rc.partial[(size_t)tid * rc.nblk + blk] = s;  // buffer 0
     }
 }
 
-// Beam launch over a launch set (any number of runs) and over one run whose
-// constants travel as the kernel argument (no table lookup before the first
-// loads).
-template <typename TS, typename T, int N, typename TAB, int I, int NJ>
-__global__ void __launch_bounds__(BeamShape<T>::block)
-__attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage(const LaunchSet ls)
+// ------------------------------------------------------------------ per-trajectory stages
+// Launch L of an attempt, one wavefront per trajectory (kTrajPerBlock per
+// workgroup).  Lanes work on items (d, e): coefficient degree d and matrix
+// entry e = (a, b) of a full complex n x n matrix.
+//   1. J_{L-1}: the fixed-order sum of the previous launch's partials (L = 1:
+//      the power-moment launch's, or J_0 kept from a rejected attempt).
+//   2. Completion of stage L-1 at its radius: collective term
+//      C = mu0 traceless(J0 - c J1 [- s cos(phi) J2 - s sin(phi) J3]), frame
+//      rate G = diag(H_m + C) / c (co-rotating frame, 0 in the lab frame),
+//      A = e^{i(Phi_a - Phi_b)} C_ab / c off the diagonal (diagonal 0, lab
+//      frame (H_m + C)_aa / c), B = e^{i(Phi_a - Phi_b)} V_ab / c with
+//      H_vac = V / E; N0 = -i h A, N1 = -i h B.
+//   3. C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m, then
+//      D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1} (stored for later launches).
+//   L < S:
+//   4. C_L = 1 + sum_{m<L} a_Lm D_m; T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+;
+//      X_d = C_{L,d} T_d; the stage-L density sum sum_d X_d (co-rotating).
+//   5. Rotation to the lab frame with the stage-L phase, angle weights of
+//      stage L, one partial per workgroup (buffer L & 1).  Dormand-Prince:
+//      stage S-1 is the new state, whose phase is stored.
+//   L = S:
+//   4. Tables of the update 1 + sum_m b_m D_m (type TF) and of the error
+//      sum_m e_m D_m (FP64) for k_final; RK4: the new state's phase.
+template <int N, typename TAB, int NJ, int L, typename TF>
+__device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 {
-    int blk;
-    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
-    stage_body<TS, T, N, TAB, I, NJ>(rc, blk);
-}
+    using PY = Poly<TAB>;
+    constexpr int S = TAB::S, NM = Shape<N>::NM, NU = Shape<N>::NU, NC = Shape<N>::NC, NN = N * N;
+    constexpr int NV = NJ * NM;
+    constexpr bool TABLES = (L == S);
+    constexpr int DMAX = TABLES ? S : L;                 // largest degree an item handles
+    constexpr int ITEMS = (DMAX + 1) * NN;
+    constexpr int NIT = (ITEMS + 63) / 64;
+    constexpr int NH = L - 1;                            // stored matrices D_0 .. D_{L-2}
+    constexpr int NQL = TABLES ? 1 : 2 * L + 1;          // power moments stage L needs
+    constexpr int TPB = kTrajPerBlock;
 
-template <typename TS, typename T, int N, typename TAB, int I, int NJ>
-__global__ void __launch_bounds__(BeamShape<T>::block)
-__attribute__((amdgpu_waves_per_eu(BeamPlan<TS, T, TAB, I>::waves_per_eu))) k_stage_one(const RunConst rc)
-{
-    stage_body<TS, T, N, TAB, I, NJ>(rc, blockIdx.x);
-}
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = blk * TPB + wave;
+    const bool active = j < rc.na;
 
-// After the last beam launch of an attempt, one workgroup per run: the global
-// step-error maximum (order-independent), the controller, and J_0 of the next
-// attempt (J of the accepted state, else unchanged).  For a tableau without
-// first-same-as-last, J of the new state is summed from the last launch's
-// partials here.  Also used after a stage-0 launch (I == 0) to sum J_0.
-template <int N, typename TAB, int I, int NJ>
-__device__ __forceinline__ void control_body(const RunConst& rc)
-{
-    constexpr int S = TAB::S;
-    constexpr int NV = NJ * Shape<N>::NM;
-    constexpr bool SUM = (I == 0) || !TAB::fsal;
-    __shared__ double sred[NV][kFinBlock / NV];
+    __shared__ double sQ[TPB][NQL * NM];                 // Q_p packed; later the X_d (packed)
+    __shared__ double sC[TPB][S * NC];                   // C_{L-1}, then C_L
+    __shared__ double sT[TPB][TABLES ? 1 : S * NC];      // T_d
+    __shared__ double sN[TPB][2 * NC];                   // N0, N1
+    __shared__ double swave[TPB][NV];
     __shared__ double sJ[NV];
-    __shared__ double serr[kFinBlock / 64];
-    if constexpr (I == 0) {
-        reduce_partials<NV, kFinBlock>(rc, 0, sJ, sred);
-        if ((int)threadIdx.x < NV) rc.jhist[threadIdx.x] = sJ[threadIdx.x];
-        return;
+
+    // ---- control block (ctrl[1] between attempts, ctrl[0] during one)
+    Control C{};
+    {
+        Control* vc = rc.ctrl + (L == 1 ? 1 : 0);
+        C.r = __hip_atomic_load(&vc->r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.h = __hip_atomic_load(&vc->h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        C.fresh = __hip_atomic_load(&vc->fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    // partials of the previous launch, in flight with the control block
+    PartialRegs<NV, TPB> xp;
+    if constexpr (L > 1) load_partials<NV, TPB>(rc, L - 1, xp);
+    if (L == 1 && blk == 0 && tid == 0) rc.ctrl[0] = rc.ctrl[1];
+    if (C.status != 0) return;  // run finished: attempts are no-ops
+    const int cur = C.cur;
+    const double h = C.h;
+
+    // ---- per-trajectory inputs: phase of y_n, frame rates of stages 0..L-2,
+    //      the stored coefficient matrices an item needs, the power moments
+    double phn[N], G[L][N];
+    double Dh[NIT][NH > 0 ? NH : 1][2];
+    if (active) {
+        for (int a = 0; a < N; ++a) phn[a] = rc.phase[cur][(size_t)j * N + a];
+        for (int m = 0; m < NH; ++m)
+            for (int a = 0; a < N; ++a) G[m][a] = rc.gbuf[((size_t)j * kMaxStages + m) * N + a];
+        const double* dsrc = rc.dbuf + (size_t)j * rc.dstride;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+#pragma unroll
+            for (int m = 0; m < NH; ++m) {
+                const bool have = idx < ITEMS && d <= m + 1;
+                const double* p = dsrc + (have ? (size_t)(PY::doff(m) + d) * NC + 2 * e : 0);
+                Dh[it][m][0] = have ? p[0] : 0.0;
+                Dh[it][m][1] = have ? p[1] : 0.0;
+            }
+        }
+        if constexpr (!TABLES) {
+            const double* qs = rc.qbuf[cur] + (size_t)j * rc.qstride;
+            for (int i = lane; i < NQL * NM; i += 64) sQ[wave][i] = qs[i];
+        }
+    }
+
+    // ---- J_{L-1}
+    if constexpr (L > 1) {
+        finish_partials<NV, TPB>(rc, L - 1, xp, sJ);
+        if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
     } else {
-        const Control* ctl = rc.ctrl;
-        if (ctl->status != 0) return;
-        if constexpr (SUM) reduce_partials<NV, kFinBlock>(rc, S, sJ, sred);
-        double m = 0.0;
-        for (int p = threadIdx.x; p < rc.nblk; p += kFinBlock) m = fmax(m, rc.errpart[p]);
-        m = wave_max(m);
-        if ((threadIdx.x & 63) == 0) serr[threadIdx.x >> 6] = m;
+        if (C.fresh) {
+            PartialRegs<NV, TPB> x0;
+            load_partials<NV, TPB>(rc, 0, x0);
+            finish_partials<NV, TPB>(rc, 0, x0, sJ);
+            if (blk == 0 && tid < NV) rc.jhist[tid] = sJ[tid];
+        } else {
+            if (tid < NV) sJ[tid] = rc.jhist[tid];
+            __syncthreads();
+        }
+    }
+
+    if (lane == 0 && !TABLES)
+        for (int v = 0; v < NV; ++v) swave[wave][v] = 0.0;
+    if (active) {
+        double cph = 1.0, sph = 0.0;
+        if constexpr (NJ == 4) {
+            cph = rc.azi[2 * (size_t)j];
+            sph = rc.azi[2 * (size_t)j + 1];
+        }
+        // ---- completion of stage L-1 (every lane, the same values)
+        {
+            const double rP = stage_radius<TAB>(C, L - 1);
+            double cP, wP;
+            traj_geometry(rc, j, rP, cP, wP);
+            const double icP = 1.0 / cP;
+            double sc = 0.0, ss = 0.0;
+            if constexpr (NJ == 4) {
+                const double s = sqrt((1.0 - cP) * (1.0 + cP));
+                sc = s * cph;
+                ss = s * sph;
+            }
+            double ph[N], z[NU > 0 ? NU : 1][2];
+            stage_phase<TAB, N>(L - 1, h, phn, G, ph);
+            rotation<N>(ph, z);
+            const double lam = matter(rc, rP);
+            auto kern = [&](int x) __attribute__((always_inline)) {
+                double v = sJ[x] - cP * sJ[NM + x];
+                if constexpr (NJ == 4) v = (v - sc * sJ[2 * NM + x]) - ss * sJ[3 * NM + x];
+                return v;
+            };
+            double Cd[N], tr = 0.0;
+            for (int a = 0; a < N; ++a) {
+                Cd[a] = kern(a);
+                tr += Cd[a];
+            }
+            double hd[N];
+            for (int a = 0; a < N; ++a) {
+                hd[a] = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
+                G[L - 1][a] = (rc.frame == 0) ? hd[a] * icP : 0.0;
+            }
+            // lane i < 2 NC: value i of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
+            // re/im); -i h X has real part h Im X and imaginary part -h Re X, and the
+            // lower entries follow from X_ba = conj(X_ab)
+            if (lane < 2 * NC) {
+                const int mtx = lane / NC, e = (lane - mtx * NC) >> 1, part = lane & 1;
+                const int a = e / N, b = e - (e / N) * N;
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                double xr, xi;  // X_{lo,hi}
+                if (a == b) {
+                    xr = mtx == 0 ? ((rc.frame == 0) ? 0.0 : hd[a] * icP) : rc.vac[a][a][0] * icP;
+                    xi = 0.0;
+                } else {
+                    const int u = Shape<N>::up(lo, hi);
+                    const double cs = z[u][0], sn = z[u][1];
+                    double vr, vi;
+                    if (mtx == 0) {
+                        vr = rc.mu0 * kern(N + 2 * u) * icP;
+                        vi = rc.mu0 * kern(N + 2 * u + 1) * icP;
+                    } else {
+                        vr = rc.vac[lo][hi][0] * icP;
+                        vi = rc.vac[lo][hi][1] * icP;
+                    }
+                    xr = cs * vr - sn * vi;
+                    xi = cs * vi + sn * vr;
+                    if (a > b) xi = -xi;
+                }
+                sN[wave][lane] = part == 0 ? h * xi : -h * xr;
+            }
+            if (lane == 0)
+                for (int a = 0; a < N; ++a) rc.gbuf[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
+        }
+
+        // ---- C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+            if (idx < ITEMS && d <= L - 1) {
+                const int a = e / N, b = e - (e / N) * N;
+                double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
+                static_for<0, NH>([&](auto Mc) {
+                    constexpr int m = decltype(Mc)::value;
+                    constexpr double cf = TAB::A[L - 1][m];
+                    if constexpr (cf != 0.0) {
+                        re = fma(cf, Dh[it][m][0], re);
+                        im = fma(cf, Dh[it][m][1], im);
+                    }
+                });
+                sC[wave][d * NC + 2 * e] = re;
+                sC[wave][d * NC + 2 * e + 1] = im;
+            }
+        }
+        wave_sync();
+
+        // ---- D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1}
+        double Dn[NIT][2];
+        double* ddst = rc.dbuf + (size_t)j * rc.dstride + (size_t)PY::doff(L - 1) * NC;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+            Dn[it][0] = Dn[it][1] = 0.0;
+            if (idx < ITEMS && d <= L) {
+                const int a = e / N, b = e - (e / N) * N;
+                double re = 0.0, im = 0.0;
+                for (int c = 0; c < N; ++c) {
+                    if (d <= L - 1) {
+                        const double xr = sN[wave][2 * (a * N + c)], xi = sN[wave][2 * (a * N + c) + 1];
+                        const double yr = sC[wave][d * NC + 2 * (c * N + b)], yi = sC[wave][d * NC + 2 * (c * N + b) + 1];
+                        re = fma(xr, yr, fma(-xi, yi, re));
+                        im = fma(xr, yi, fma(xi, yr, im));
+                    }
+                    if (d >= 1) {
+                        const double xr = sN[wave][NC + 2 * (a * N + c)], xi = sN[wave][NC + 2 * (a * N + c) + 1];
+                        const double yr = sC[wave][(d - 1) * NC + 2 * (c * N + b)];
+                        const double yi = sC[wave][(d - 1) * NC + 2 * (c * N + b) + 1];
+                        re = fma(xr, yr, fma(-xi, yi, re));
+                        im = fma(xr, yi, fma(xi, yr, im));
+                    }
+                }
+                Dn[it][0] = re;
+                Dn[it][1] = im;
+                if constexpr (!TABLES) {
+                    ddst[(size_t)d * NC + 2 * e] = re;
+                    ddst[(size_t)d * NC + 2 * e + 1] = im;
+                }
+            }
+        }
+        wave_sync();
+
+        if constexpr (TABLES) {
+            // ---- update and error tables for the state-update launch
+            constexpr int DN = PY::DN, DE = PY::DE;
+            char* tb = reinterpret_cast<char*>(rc.ftab) + (size_t)j * rc.fstride;
+            TF* cn = reinterpret_cast<TF*>(tb);
+            double* ce = reinterpret_cast<double*>(tb + (((DN + 1) * NC * sizeof(TF) + 7) / 8) * 8);
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                if (idx < ITEMS) {
+                    const int a = e / N, b = e - (e / N) * N;
+                    auto coeff = [&](int m, int k) __attribute__((always_inline)) {
+                        return m < S - 1 ? Dh[it][m < NH ? m : 0][k] : Dn[it][k];
+                    };
+                    if (d <= DN) {
+                        double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
+                        static_for<0, S>([&](auto Mc) {
+                            constexpr int m = decltype(Mc)::value;
+                            if constexpr (TAB::B[m] != 0.0) {
+                                re = fma(TAB::B[m], coeff(m, 0), re);
+                                im = fma(TAB::B[m], coeff(m, 1), im);
+                            }
+                        });
+                        cn[d * NC + 2 * e] = (TF)re;
+                        cn[d * NC + 2 * e + 1] = (TF)im;
+                    }
+                    if constexpr (TAB::embedded) {
+                        if (d <= DE) {
+                            double re = 0.0, im = 0.0;
+                            static_for<0, S>([&](auto Mc) {
+                                constexpr int m = decltype(Mc)::value;
+                                if constexpr (TAB::E[m] != 0.0) {
+                                    re = fma(TAB::E[m], coeff(m, 0), re);
+                                    im = fma(TAB::E[m], coeff(m, 1), im);
+                                }
+                            });
+                            ce[d * NC + 2 * e] = re;
+                            ce[d * NC + 2 * e + 1] = im;
+                        }
+                    }
+                }
+            }
+            if constexpr (!TAB::fsal) {
+                // the new state's phase Phi_n + h sum_m b_m G_m
+                double ph[N];
+                stage_phase<TAB, N>(S, h, phn, G, ph);
+                lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
+            }
+        } else {
+            // ---- C_L = 1 + sum_{m<L} a_Lm D_m
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                if (idx < ITEMS && d <= L) {
+                    const int a = e / N, b = e - (e / N) * N;
+                    double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
+                    static_for<0, NH>([&](auto Mc) {
+                        constexpr int m = decltype(Mc)::value;
+                        constexpr double cf = TAB::A[L][m];
+                        if constexpr (cf != 0.0) {
+                            re = fma(cf, Dh[it][m][0], re);
+                            im = fma(cf, Dh[it][m][1], im);
+                        }
+                    });
+                    constexpr double cl = TAB::A[L][L - 1];
+                    if constexpr (cl != 0.0) {
+                        re = fma(cl, Dn[it][0], re);
+                        im = fma(cl, Dn[it][1], im);
+                    }
+                    sC[wave][d * NC + 2 * e] = re;
+                    sC[wave][d * NC + 2 * e + 1] = im;
+                }
+            }
+            wave_sync();
+
+            // ---- T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+   (item (d, a, b))
+            auto qv = [&](int p, int a, int c, double& re, double& im) __attribute__((always_inline)) {
+                const double* Qp = &sQ[wave][p * NM];
+                if (a == c) {
+                    re = Qp[a];
+                    im = 0.0;
+                } else if (a < c) {
+                    re = Qp[N + 2 * Shape<N>::up(a, c)];
+                    im = Qp[N + 2 * Shape<N>::up(a, c) + 1];
+                } else {
+                    re = Qp[N + 2 * Shape<N>::up(c, a)];
+                    im = -Qp[N + 2 * Shape<N>::up(c, a) + 1];
+                }
+            };
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                if (idx < ITEMS && d <= L) {
+                    const int a = e / N, b = e - (e / N) * N;
+                    double re = 0.0, im = 0.0;
+#pragma unroll 1
+                    for (int dd = 0; dd <= L; ++dd)
+#pragma unroll
+                        for (int c = 0; c < N; ++c) {
+                            double qr, qi;
+                            qv(d + dd, a, c, qr, qi);
+                            const double cr = sC[wave][dd * NC + 2 * (b * N + c)];
+                            const double ci = sC[wave][dd * NC + 2 * (b * N + c) + 1];
+                            // Q_{d+dd}[a][c] conj(C_dd[b][c])
+                            re = fma(qr, cr, fma(qi, ci, re));
+                            im = fma(qi, cr, fma(-qr, ci, im));
+                        }
+                    sT[wave][d * NC + 2 * e] = re;
+                    sT[wave][d * NC + 2 * e + 1] = im;
+                }
+            }
+            wave_sync();
+
+            // ---- X_d = C_{L,d} T_d, packed entries only (into sQ's space)
+            constexpr int NK = N + NU;
+            constexpr int XITEMS = (L + 1) * NK;
+#pragma unroll
+            for (int it = 0; it < (XITEMS + 63) / 64; ++it) {
+                const int idx = lane + 64 * it;
+                if (idx < XITEMS) {
+                    const int d = idx / NK, k = idx - d * NK;
+                    int a = k, b = k;
+                    if (k >= N) pair_of<N>(k - N, a, b);
+                    double re = 0.0, im = 0.0;
+                    for (int c = 0; c < N; ++c) {
+                        const double xr = sC[wave][d * NC + 2 * (a * N + c)], xi = sC[wave][d * NC + 2 * (a * N + c) + 1];
+                        const double yr = sT[wave][d * NC + 2 * (c * N + b)], yi = sT[wave][d * NC + 2 * (c * N + b) + 1];
+                        re = fma(xr, yr, fma(-xi, yi, re));
+                        im = fma(xr, yi, fma(xi, yr, im));
+                    }
+                    double* X = &sQ[wave][d * NM];
+                    if (k < N) {
+                        X[k] = re;
+                    } else {
+                        X[N + 2 * (k - N)] = re;
+                        X[N + 2 * (k - N) + 1] = im;
+                    }
+                }
+            }
+            wave_sync();
+
+            // ---- density sum of stage L, its lab-frame rotation and weights
+            double Sx[NM];
+            for (int v = 0; v < NM; ++v) {
+                double s = sQ[wave][v];
+                for (int d = 1; d <= L; ++d) s += sQ[wave][d * NM + v];
+                Sx[v] = s;
+            }
+            const double rL = stage_radius<TAB>(C, L);
+            double cL, wL, f[4];
+            traj_geometry(rc, j, rL, cL, wL);
+            double ph[N], z[NU > 0 ? NU : 1][2];
+            stage_phase<TAB, N>(L, h, phn, G, ph);
+            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
+            rotation<N>(ph, z);
+            angle_weights<NJ>(rc, cL, wL, cph, sph, f);
+            double Sv[NM];
+            for (int a = 0; a < N; ++a) Sv[a] = 2.0 * Sx[a];
+            for (int u = 0; u < NU; ++u) {
+                const double cs = z[u][0], sn = z[u][1];
+                const double xr = Sx[N + 2 * u], xi = Sx[N + 2 * u + 1];
+                Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
+                Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
+            }
+            if (lane == 0)
+                for (int m = 0; m < NJ; ++m)
+                    for (int v = 0; v < NM; ++v) swave[wave][m * NM + v] = f[m] * Sv[v];
+        }
+    }
+    if constexpr (!TABLES) {
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < kFinBlock / 64; ++w) m = fmax(m, serr[w]);
-            Control c = *ctl;
-            const bool acc = control_step<TAB>(rc, c, m);
-            if (acc)
-                for (int v = 0; v < NV; ++v)
-                    rc.jhist[v] = TAB::fsal ? rc.jhist[(size_t)(S - 1) * NV + v] : sJ[v];
-            rc.ctrl[1] = c;
+        if (tid < NV) {
+            double s = swave[0][tid];
+            for (int w = 1; w < TPB; ++w) s += swave[w][tid];
+            rc.partial[((size_t)(L & 1) * NV + tid) * rc.nblk + blk] = s;
         }
     }
 }
 
-template <int N, typename TAB, int I, int NJ>
-__global__ void __launch_bounds__(kFinBlock) k_control(const LaunchSet ls)
+// ------------------------------------------------------------------ state update
+// Launch S + 1: one wavefront per trajectory, lanes over its 2 N_E beam slots
+// (NSLOT beams of a lane in flight).  Per beam:
+//   y_{n+1} = M(u) y_n,  M(u) = sum_d Cn_d u^d (Horner, arithmetic type T),
+//   FP32 amplitudes: y_{n+1} / |y_{n+1}|, written in the storage type;
+//   embedded pair: delta = E(u) y_n in FP64 (E = sum_m e_m D_m, the step error
+//   h sum_m e_m k_m), and the maximum of |Re|, |Im| over the components;
+//   RK4: whether the new state is finite.
+// The coefficients are wave-uniform: they are read through the constant
+// address space into scalar registers, once per beam.
+// p, passed through an empty asm that also takes v: loads through the result
+// cannot be issued before v has been computed.
+template <typename V>
+__device__ __forceinline__ uint64_t after(uint64_t p, V v)
+{
+    asm volatile("" : "+s"(p) : "v"(v));
+    return p;
+}
+// The same after all NR values of v.
+template <int NR, typename V>
+__device__ __forceinline__ uint64_t after_all(uint64_t p, const V (&v)[NR])
+{
+#pragma unroll
+    for (int x = 0; x < NR; ++x) asm volatile("" : "+s"(p) : "v"(v[x]));
+    return p;
+}
+
+// M[x] = sum_{d<=D} c[d STRIDE + x] u^d, x < NR, by Horner's rule: one row of
+// a coefficient matrix polynomial whose wave-uniform coefficients start at
+// byte address `base` (read through the constant address space, so they
+// arrive in scalar registers and feed the FMAs as scalar operands).  The
+// coefficients of degree d-1 are requested while degree d is applied; the
+// address of each request depends on the previous step's result, so the
+// compiler cannot hoist the requests of later degrees (which would exhaust
+// the scalar registers).
+template <int D, int NR, int STRIDE, typename T, typename CT>
+__device__ __forceinline__ void horner_row(uint64_t base, T u, T (&M)[NR])
+{
+    auto load = [&](uint64_t p, int d, CT (&v)[NR]) __attribute__((always_inline)) {
+        const cptr<CT> c = reinterpret_cast<cptr<CT>>(p);
+#pragma unroll
+        for (int x = 0; x < NR; ++x) v[x] = c[d * STRIDE + x];
+    };
+    CT cu[NR], nx[NR];
+    load(base, D, cu);
+    load(base, D - 1, nx);
+#pragma unroll
+    for (int x = 0; x < NR; ++x) M[x] = (T)cu[x];
+    static_for<0, D>([&](auto Ic) {
+        constexpr int d = D - 1 - decltype(Ic)::value;
+#pragma unroll
+        for (int x = 0; x < NR; ++x) cu[x] = nx[x];
+        if constexpr (d > 0) load(after_all(base, M), d - 1, nx);
+#pragma unroll
+        for (int x = 0; x < NR; ++x) M[x] = fma(M[x], u, (T)cu[x]);
+    });
+}
+
+// out = P(u) y for a matrix polynomial P of degree D whose coefficients (full
+// complex N x N matrices, row-major re/im, NC reals of type CT per degree)
+// start at byte address `base`, one row at a time (each row's first request
+// waits for the previous row's result).
+template <int D, int N, typename T, typename CT>
+__device__ __forceinline__ void poly_apply(uint64_t base, T u, const T* y, T* out)
+{
+    constexpr int NC = Shape<N>::NC;
+    T M[2 * N];
+#pragma unroll
+    for (int x = 0; x < 2 * N; ++x) M[x] = y[x];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        horner_row<D, 2 * N, NC, T, CT>(after_all(base + (uint64_t)(2 * N * a * (int)sizeof(CT)), M), u, M);
+        T re = 0, im = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            re = fma(M[2 * b], y[2 * b], fma(-M[2 * b + 1], y[2 * b + 1], re));
+            im = fma(M[2 * b], y[2 * b + 1], fma(M[2 * b + 1], y[2 * b], im));
+        }
+        out[2 * a] = re;
+        out[2 * a + 1] = im;
+    }
+}
+
+template <typename T> struct FinalShape {
+    static constexpr int traj = std::is_same<T, double>::value ? 8 : 16;
+    static constexpr int block = 64 * traj;
+};
+
+template <typename TS, typename T, int N, typename TAB, int NJ>
+__device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
+{
+    using PY = Poly<TAB>;
+    constexpr int NC = Shape<N>::NC;
+    constexpr int DN = PY::DN, DE = PY::DE;
+    constexpr bool ERROR = TAB::embedded;
+    constexpr int TPB = FinalShape<T>::traj;
+    constexpr int NSLOT = 2;
+    constexpr uint32_t STRIDE = 64;
+    constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 7) / 8) * 8;  // byte offset of the error table
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = blk * TPB + wave;
+    const bool active = j < rc.na;
+    __shared__ double swave[TPB];
+
+    const Control* vc = rc.ctrl;  // ctrl[0]
+    const int status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (status != 0) return;
+
+    const uint32_t ne = (uint32_t)rc.ne;
+    const uint32_t nbt = active ? 2u * ne : 0u;
+    const uint32_t base0 = (uint32_t)j * ne;
+    const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
+    const size_t ld = (size_t)rc.nb_pad;
+    // one scalar base per state buffer; component x of a beam at byte offset
+    // sizeof(TS) (off + x nb_pad) (all below 4 GiB)
+    global<const char>* __restrict__ srcb = uniform_global(reinterpret_cast<const char*>(rc.psi[cur]));
+    global<char>* __restrict__ dstb = uniform_global(reinterpret_cast<char*>(rc.psi[cur ^ 1]));
+    const uint32_t ldb = (uint32_t)(ld * sizeof(TS));
+    global<const T>* __restrict__ uinv = uniform_global(uinv_table<T>(rc));
+    global<const double>* __restrict__ uinv64 = uniform_global(rc.uinv64);
+    const uint64_t tb0 = reinterpret_cast<uint64_t>(rc.ftab) + (uint64_t)(active ? j : 0) * (uint64_t)rc.fstride;
+    // (readfirstlane returns a signed int: both halves are taken as uint32_t
+    // before widening, so the low word is not sign-extended)
+    const uint32_t tb_lo = __builtin_amdgcn_readfirstlane((uint32_t)tb0);
+    const uint32_t tb_hi = __builtin_amdgcn_readfirstlane((uint32_t)(tb0 >> 32));
+    const uint64_t tb = ((uint64_t)tb_hi << 32) | (uint64_t)tb_lo;
+
+    double emax = 0.0;
+    bool bad = false;
+    auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
+    auto fetch = [&](uint32_t t, TS* yv, T& uv, double& u64v) __attribute__((always_inline)) {
+        if (t < nbt) {
+            const uint32_t off = offset(t) * (uint32_t)sizeof(TS);
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x)
+                yv[x] = *reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb));
+            uv = *elem(uinv, t);
+            if constexpr (ERROR && !std::is_same<T, double>::value) u64v = *elem(uinv64, t);
+        }
+    };
+    auto process = [&](uint32_t t, const TS* yv, T u, double u64) __attribute__((always_inline)) {
+        if constexpr (std::is_same<T, double>::value) u64 = u;
+        T y[2 * N];
+#pragma unroll
+        for (int x = 0; x < 2 * N; ++x) y[x] = (T)yv[x];
+        T yn[2 * N];
+        poly_apply<DN, N, T, T>(tb, u, y, yn);
+        if constexpr (std::is_same<TS, float>::value) {
+            // FP32 amplitudes are renormalised whenever a new state is formed
+            T nn = 0;
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) nn = fma(yn[x], yn[x], nn);
+            const T sc = T(1) / sqrt(nn);
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) yn[x] = yn[x] * sc;
+        }
+        const uint32_t off = offset(t) * (uint32_t)sizeof(TS);
+#pragma unroll
+        for (int x = 0; x < 2 * N; ++x)
+            *reinterpret_cast<global<TS>*>(dstb + (uint64_t)(off + (uint32_t)x * ldb)) = (TS)yn[x];
+        if constexpr (!ERROR) {
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) bad |= !isfinite(yn[x]);
+        } else {
+            double y64[2 * N];
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) y64[x] = (double)yv[x];
+            double dl[2 * N];
+            poly_apply<DE, N, double, double>(after_all(tb + EOFF, yn), u64, y64, dl);
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) {
+                const double e = fabs(dl[x]);
+                bad |= !isfinite(e);
+                emax = fmax(emax, e);
+            }
+        }
+    };
+
+    TS ys[NSLOT][2 * N];
+    T us[NSLOT];
+    double u64s[NSLOT];
+    const uint32_t t0 = (uint32_t)lane;
+    static_for<0, NSLOT>([&](auto Sc) {
+        constexpr int sl = decltype(Sc)::value;
+        us[sl] = 0;
+        u64s[sl] = 0.0;
+        fetch(t0 + sl * STRIDE, ys[sl], us[sl], u64s[sl]);
+    });
+#pragma unroll 1
+    for (uint32_t t = t0; t < nbt; t += NSLOT * STRIDE) {
+        static_for<0, NSLOT>([&](auto Sc) {
+            constexpr int sl = decltype(Sc)::value;
+            const uint32_t ts = t + sl * STRIDE;
+            if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
+            fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], u64s[sl]);
+        });
+    }
+
+    double e = bad ? (double)INFINITY : emax;
+    e = wave_max(e);
+    if (lane == 0) swave[wave] = active ? e : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+        double m = swave[0];
+        for (int w = 1; w < TPB; ++w) m = fmax(m, swave[w]);
+        rc.errpart[blk] = m;
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename TS, int N, typename TAB, int NJ, bool FORCE>
+__global__ void __launch_bounds__(64 * kPowerWaves) k_power(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
-    control_body<N, TAB, I, NJ>(rc);
+    power_body<TS, N, TAB, NJ, FORCE>(rc, blk);
 }
-
-template <int N, typename TAB, int I, int NJ>
-__global__ void __launch_bounds__(kFinBlock) k_control_one(const RunConst rc)
+template <typename TS, int N, typename TAB, int NJ, bool FORCE>
+__global__ void __launch_bounds__(64 * kPowerWaves) k_power_one(const RunConst rc)
 {
-    control_body<N, TAB, I, NJ>(rc);
+    power_body<TS, N, TAB, NJ, FORCE>(rc, blockIdx.x);
 }
 
-// Stage-0 frame of the current state (before a stage-0 launch).
-template <int N, typename TAB>
-__global__ void __launch_bounds__(kFinBlock) k_prepare(const LaunchSet ls)
+template <int N, typename TAB, int NJ, int L, typename TF>
+__global__ void __launch_bounds__(64 * kTrajPerBlock) k_traj(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
-    const int j = blk * kFinBlock + threadIdx.x;
-    if (j >= rc.na) return;
-    const Control C = rc.ctrl[1];
-    double ph[N];
-    for (int a = 0; a < N; ++a) ph[a] = rc.phase[C.cur][(size_t)j * N + a];
-    prepare_thread<N>(rc, j, 0, stage_radius<TAB>(rc, C, 0), ph);
+    traj_body<N, TAB, NJ, L, TF>(rc, blk);
+}
+template <int N, typename TAB, int NJ, int L, typename TF>
+__global__ void __launch_bounds__(64 * kTrajPerBlock) k_traj_one(const RunConst rc)
+{
+    traj_body<N, TAB, NJ, L, TF>(rc, blockIdx.x);
+}
+
+template <typename TS, typename T, int N, typename TAB, int NJ>
+__global__ void __launch_bounds__(FinalShape<T>::block) k_final(const LaunchSet ls)
+{
+    int blk;
+    const RunConst& rc = ls.runs[run_of_block(ls, blk)];
+    final_body<TS, T, N, TAB, NJ>(rc, blk);
+}
+template <typename TS, typename T, int N, typename TAB, int NJ>
+__global__ void __launch_bounds__(FinalShape<T>::block) k_final_one(const RunConst rc)
+{
+    final_body<TS, T, N, TAB, NJ>(rc, blockIdx.x);
+}
+
+// J_0 of the current state from the power-moment launch's partials (after a
+// new state or radius): one workgroup per run.
+template <int NV>
+__device__ __forceinline__ void jsum_body(const RunConst& rc)
+{
+    constexpr int NW = kFinBlock / 64;
+    __shared__ double sJ[NV];
+    PartialRegs<NV, NW> x;
+    load_partials<NV, NW>(rc, 0, x);
+    finish_partials<NV, NW>(rc, 0, x, sJ);
+    if ((int)threadIdx.x < NV) rc.jhist[threadIdx.x] = sJ[threadIdx.x];
+}
+template <int NV>
+__global__ void __launch_bounds__(kFinBlock) k_jsum(const LaunchSet ls)
+{
+    int blk;
+    jsum_body<NV>(ls.runs[run_of_block(ls, blk)]);
+}
+template <int NV>
+__global__ void __launch_bounds__(kFinBlock) k_jsum_one(const RunConst rc)
+{
+    jsum_body<NV>(rc);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -1298,48 +1391,65 @@ __global__ void k_init(const LaunchSet ls)
 
 // ------------------------------------------------------------------ dispatch
 using KernFn = void (*)(const LaunchSet);
-
-template <typename TS, typename T, int N, typename TAB, int NJ>
-struct StageTable {
-    template <int... Is>
-    static constexpr std::array<KernFn, kMaxStages> make(std::integer_sequence<int, Is...>)
-    {
-        return {{(Is <= TAB::S ? (KernFn)&k_stage<TS, T, N, TAB, (Is <= TAB::S ? Is : 0), NJ> : nullptr)...}};
-    }
-    static constexpr std::array<KernFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
-};
-
 using OneFn = void (*)(const RunConst);
 
-template <typename TS, typename T, int N, typename TAB, int NJ>
-struct StageOneTable {
-    template <int... Is>
-    static constexpr std::array<OneFn, kMaxStages> make(std::integer_sequence<int, Is...>)
-    {
-        return {{(Is <= TAB::S ? (OneFn)&k_stage_one<TS, T, N, TAB, (Is <= TAB::S ? Is : 0), NJ> : nullptr)...}};
-    }
-    static constexpr std::array<OneFn, kMaxStages> fns = make(std::make_integer_sequence<int, kMaxStages>{});
-};
-
-// The kernels of beam launch `stage`: over launch sets (k, f) and over one
-// run (k1, f1); f, f1: the control kernel that follows stage 0 and the last
-// stage, else nullptr.
+// The kernels of one launch: over launch sets (k, f) and over one run (k1,
+// f1); f, f1: the second kernel (launch 0 only), else nullptr.  grid: which
+// workgroup count the main kernel takes (0: nblk, 1: nblkf).
 struct StageKernels {
     KernFn k = nullptr, f = nullptr;
     OneFn k1 = nullptr, f1 = nullptr;
+    unsigned block = 0;
+    int grid = 0;
+};
+
+template <typename TF, int N, typename TAB, int NJ, int L>
+using TrajTF = typename std::conditional<L == TAB::S, TF, double>::type;
+
+template <typename TF, int N, typename TAB, int NJ>
+struct TrajTable {
+    static constexpr int clamp(int l) { return (l >= 1 && l <= TAB::S) ? l : 1; }
+    template <int... Is>
+    static constexpr std::array<KernFn, kMaxLaunches> make(std::integer_sequence<int, Is...>)
+    {
+        return {{((Is >= 1 && Is <= TAB::S)
+                      ? (KernFn)&k_traj<N, TAB, NJ, clamp(Is), TrajTF<TF, N, TAB, NJ, clamp(Is)>>
+                      : nullptr)...}};
+    }
+    template <int... Is>
+    static constexpr std::array<OneFn, kMaxLaunches> make1(std::integer_sequence<int, Is...>)
+    {
+        return {{((Is >= 1 && Is <= TAB::S)
+                      ? (OneFn)&k_traj_one<N, TAB, NJ, clamp(Is), TrajTF<TF, N, TAB, NJ, clamp(Is)>>
+                      : nullptr)...}};
+    }
+    static constexpr std::array<KernFn, kMaxLaunches> fns = make(std::make_integer_sequence<int, kMaxLaunches>{});
+    static constexpr std::array<OneFn, kMaxLaunches> fns1 = make1(std::make_integer_sequence<int, kMaxLaunches>{});
 };
 
 template <typename TS, typename T, int N, typename TAB, int NJ>
 void pick_tab(int stage, StageKernels& K)
 {
-    K.k = StageTable<TS, T, N, TAB, NJ>::fns[stage];
-    K.k1 = StageOneTable<TS, T, N, TAB, NJ>::fns[stage];
+    constexpr int S = TAB::S;
     if (stage == 0) {
-        K.f = (KernFn)&k_control<N, TAB, 0, NJ>;
-        K.f1 = (OneFn)&k_control_one<N, TAB, 0, NJ>;
-    } else if (stage == TAB::S) {
-        K.f = (KernFn)&k_control<N, TAB, TAB::S, NJ>;
-        K.f1 = (OneFn)&k_control_one<N, TAB, TAB::S, NJ>;
+        K.k = (KernFn)&k_power<TS, N, TAB, NJ, true>;
+        K.k1 = (OneFn)&k_power_one<TS, N, TAB, NJ, true>;
+        K.f = (KernFn)&k_jsum<NJ * N * N>;
+        K.f1 = (OneFn)&k_jsum_one<NJ * N * N>;
+        K.block = 64 * kPowerWaves;
+    } else if (stage <= S) {
+        K.k = TrajTable<T, N, TAB, NJ>::fns[stage];
+        K.k1 = TrajTable<T, N, TAB, NJ>::fns1[stage];
+        K.block = 64 * kTrajPerBlock;
+    } else if (stage == S + 1) {
+        K.k = (KernFn)&k_final<TS, T, N, TAB, NJ>;
+        K.k1 = (OneFn)&k_final_one<TS, T, N, TAB, NJ>;
+        K.block = FinalShape<T>::block;
+        K.grid = 1;
+    } else if (stage == S + 2) {
+        K.k = (KernFn)&k_power<TS, N, TAB, NJ, false>;
+        K.k1 = (OneFn)&k_power_one<TS, N, TAB, NJ, false>;
+        K.block = 64 * kPowerWaves;
     }
 }
 
@@ -1385,8 +1495,6 @@ hipError_t for_launch_sets(const RunList& runs, Blocks blocks, Launch launch)
     return hipSuccess;
 }
 
-long long fin_blocks(const RunConst& rc) { return (rc.na + kFinBlock - 1) / kFinBlock; }
-
 bool same_kind(const RunList& runs)
 {
     for (int i = 1; i < runs.count; ++i) {
@@ -1399,7 +1507,25 @@ bool same_kind(const RunList& runs)
 
 }  // namespace
 
-int num_stages(int integrator) { return integrator == 0 ? TabRK4::S : TabDP54::S; }
+int num_stages(int integrator) { return (integrator == 0 ? TabRK4::S : TabDP54::S) + 2; }
+
+PolySizes poly_sizes(int n, int integrator, int precision)
+{
+    const int nm = n * n, nc = 2 * n * n;
+    const int S = integrator == 0 ? TabRK4::S : TabDP54::S;
+    const int nq = 2 * (S - 1) + 1;
+    const int nd = (S - 1) * (S + 2) / 2;  // matrices of D_0 .. D_{S-2}
+    const int dn = integrator == 0 ? Poly<TabRK4>::DN : Poly<TabDP54>::DN;
+    const int de = integrator == 0 ? -1 : Poly<TabDP54>::DE;
+    const int tsz = precision == 1 ? 4 : 8;
+    PolySizes p;
+    p.qstride = (nq * nm + 7) / 8 * 8;
+    p.dstride = (nd * nc + 7) / 8 * 8;
+    const int cn = ((dn + 1) * nc * tsz + 7) / 8 * 8;
+    const int ce = (de + 1) * nc * 8;
+    p.fstride = (cn + ce + 255) / 256 * 256;
+    return p;
+}
 
 hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev)
 {
@@ -1408,9 +1534,6 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
     const RunConst& r0 = *runs.rc[0];
     if (stage < 0 || stage > num_stages(r0.integrator)) return hipErrorInvalidValue;
     StageKernels K;
-    const unsigned block = r0.precision == 1 ? BeamShape<float>::block : BeamShape<double>::block;
-    if ((r0.precision == 1 ? BeamShape<float>::traj : BeamShape<double>::traj) != traj_per_block(r0.precision))
-        return hipErrorInvalidValue;
     switch (r0.precision) {
     case 0: pick_nj<double, double>(r0.nj, r0.n, r0.integrator, stage, K); break;  // FP64
     case 1: pick_nj<float, float>(r0.nj, r0.n, r0.integrator, stage, K); break;    // FP32 amplitudes
@@ -1419,20 +1542,20 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
     }
     if (!K.k || !K.k1) return hipErrorInvalidValue;
     const bool one = runs.count == 1;
+    auto blocks = [&](const RunConst& rc) { return (long long)(K.grid ? rc.nblkf : rc.nblk); };
     if (ev) {
         hipError_t e = hipEventRecord(ev[0], s);
         if (e != hipSuccess) return e;
     }
     hipError_t e = hipSuccess;
     if (one) {
-        hipLaunchKernelGGL(K.k1, dim3((unsigned)r0.nblk), dim3(block), 0, s, r0);
+        hipLaunchKernelGGL(K.k1, dim3((unsigned)blocks(r0)), dim3(K.block), 0, s, r0);
         e = hipGetLastError();
     } else {
-        e = for_launch_sets(runs, [](const RunConst& rc) { return (long long)rc.nblk; },
-                            [&](const LaunchSet& ls, unsigned grid) {
-                                hipLaunchKernelGGL(K.k, dim3(grid), dim3(block), 0, s, ls);
-                                return hipGetLastError();
-                            });
+        e = for_launch_sets(runs, blocks, [&](const LaunchSet& ls, unsigned grid) {
+            hipLaunchKernelGGL(K.k, dim3(grid), dim3(K.block), 0, s, ls);
+            return hipGetLastError();
+        });
     }
     if (e != hipSuccess) return e;
     if (ev) {
@@ -1455,20 +1578,6 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-hipError_t launch_prepare(const RunList& runs, hipStream_t s)
-{
-    if (runs.count < 1) return hipSuccess;
-    if (!same_kind(runs)) return hipErrorInvalidValue;
-    const RunConst& r0 = *runs.rc[0];
-    KernFn k;
-    if (r0.n == 2) k = r0.integrator == 0 ? (KernFn)&k_prepare<2, TabRK4> : (KernFn)&k_prepare<2, TabDP54>;
-    else k = r0.integrator == 0 ? (KernFn)&k_prepare<3, TabRK4> : (KernFn)&k_prepare<3, TabDP54>;
-    return for_launch_sets(runs, fin_blocks, [&](const LaunchSet& ls, unsigned grid) {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kFinBlock), 0, s, ls);
-        return hipGetLastError();
-    });
 }
 
 hipError_t launch_probabilities(const RunList& runs, double* p, hipStream_t s)

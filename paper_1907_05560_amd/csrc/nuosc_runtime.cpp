@@ -178,11 +178,12 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, errv, xbuf, flux, azi, mat, geo, ctrl, prob, eavg,
-        rconst, total;
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, qbuf[2], dbuf, gbuf, ftab, xbuf, flux, azi,
+        ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
-    int na, nblk;
+    int na, nblk, nblkf;
     int nj;      // angle moments: 2 (bulb model), 4 (extended: azimuth)
+    nuosc::PolySizes poly;  // Runge-Kutta per-trajectory tables (zero for the exponential stepper)
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -224,8 +225,7 @@ const char* validate(const nuosc_params* p)
     if (p->max_steps < 0 || p->max_wall_s < 0) return "limits must be >= 0";
     const int64_t na = (int64_t)std::max(p->n_angle, 1) * std::max(p->n_azimuth, 1);
     // each amplitude component array is addressed with 32-bit byte offsets
-    // (and so is the per-beam error sum, held in the arithmetic type)
-    const int64_t tsz = p->precision == NUOSC_FP32_AMP ? 4 : 8;
+    const int64_t tsz = p->precision == NUOSC_FP64 ? 8 : 4;
     if ((2 * (int64_t)p->n_energy * na + 64) * tsz >= ((int64_t)1 << 32))
         return "too many beams (one amplitude component must stay below 4 GiB)";
     return nullptr;
@@ -246,8 +246,12 @@ Layout make_layout(const nuosc_params& p)
         off = align_up(off + bytes, 256);
         return at;
     };
-    const int tpb = p.integrator == NUOSC_EXP_STEPPER ? nuosc::kExpTrajPerBlock : nuosc::traj_per_block(p.precision);
+    const bool rk = p.integrator != NUOSC_EXP_STEPPER;
+    const int tpb = rk ? nuosc::kTrajPerBlock : nuosc::kExpTrajPerBlock;
+    const int tpbf = rk ? nuosc::final_traj_per_block(p.precision) : nuosc::kExpTrajPerBlock;
     L.nblk = (L.na + tpb - 1) / tpb;
+    L.nblkf = (L.na + tpbf - 1) / tpbf;
+    L.poly = rk ? nuosc::poly_sizes(n, p.integrator, p.precision) : nuosc::PolySizes{0, 0, 0};
     for (int b = 0; b < 2; ++b) L.psi[b] = take(2 * n * (size_t)L.nb_pad * tsz);
     for (int b = 0; b < 2; ++b) L.phase[b] = take((size_t)L.na * n * 8);
     L.uinv64 = take((size_t)2 * p.n_energy * 8);
@@ -257,12 +261,12 @@ Layout make_layout(const nuosc_params& p)
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * L.nj * n * n * 8);
     L.partial = take((size_t)2 * L.nj * n * n * L.nblk * 8);  // two launches' partials (alternating)
     L.azi = take((size_t)2 * L.na * 8);
-    L.errpart = take((size_t)L.nblk * 8);
-    const size_t asz = p.precision == NUOSC_FP32_AMP ? 4 : 8;
-    L.errv = take(p.integrator == NUOSC_RK_DP54 ? 2 * n * (size_t)L.nb_pad * asz : 0);
+    L.errpart = take((size_t)std::max(L.nblk, L.nblkf) * 8);
+    for (int b = 0; b < 2; ++b) L.qbuf[b] = take((size_t)L.na * L.poly.qstride * 8);
+    L.dbuf = take((size_t)L.na * L.poly.dstride * 8);
+    L.gbuf = take(rk ? (size_t)L.na * nuosc::kMaxStages * n * 8 : 0);
+    L.ftab = take((size_t)L.na * L.poly.fstride);
     L.xbuf = take(p.integrator == NUOSC_EXP_STEPPER ? 2 * 2 * n * (size_t)L.nb_pad * 8 : 0);
-    L.mat = take((size_t)nuosc::kMaxStages * L.na * nuosc::kStageMatBytes);
-    L.geo = take((size_t)(nuosc::kMaxStages + 1) * L.na * sizeof(nuosc::TrajGeo));
     L.ctrl = take(2 * sizeof(Control));
     L.prob = take((size_t)L.nb * 8);
     L.eavg = take((size_t)2 * L.na * n * 8);
@@ -343,7 +347,6 @@ nuosc_status restart(RunState& r, hipStream_t s, std::string& err)
         HIP_CHECK(nuosc::launch_exp_stage(one.list, 0, s), err);
         return NUOSC_OK;
     }
-    HIP_CHECK(nuosc::launch_prepare(one.list, s), err);
     HIP_CHECK(nuosc::launch_stage(one.list, 0, s), err);
     return NUOSC_OK;
 }
@@ -379,6 +382,10 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.nb = L.nb;
     rc.nb_pad = L.nb_pad;
     rc.nblk = L.nblk;
+    rc.nblkf = L.nblkf;
+    rc.qstride = L.poly.qstride;
+    rc.dstride = L.poly.dstride;
+    rc.fstride = L.poly.fstride;
     rc.np = std::max(p->n_azimuth, 1);
     rc.nth = L.na / rc.np;
     rc.nj = L.nj;
@@ -410,10 +417,11 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
-    rc.errv = (void*)(base + L.errv);
+    for (int b = 0; b < 2; ++b) rc.qbuf[b] = (double*)(base + L.qbuf[b]);
+    rc.dbuf = (double*)(base + L.dbuf);
+    rc.gbuf = (double*)(base + L.gbuf);
+    rc.ftab = (void*)(base + L.ftab);
     rc.xbuf = (double*)(base + L.xbuf);
-    rc.mat = (void*)(base + L.mat);
-    rc.geo = (nuosc::TrajGeo*)(base + L.geo);
     rc.ctrl = (Control*)(base + L.ctrl);
     r.prob = (double*)(base + L.prob);
     r.eavg = (double*)(base + L.eavg);
@@ -489,9 +497,9 @@ struct nuosc_handle {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_stage;
     size_t ev_used = 0;
-    double t_beam[nuosc::kMaxStages + 1] = {};
-    double t_fin[nuosc::kMaxStages + 1] = {};
-    int64_t t_count[nuosc::kMaxStages + 1] = {};
+    double t_beam[nuosc::kMaxLaunches + 1] = {};
+    double t_fin[nuosc::kMaxLaunches + 1] = {};
+    int64_t t_count[nuosc::kMaxLaunches + 1] = {};
 };
 
 namespace {
@@ -662,7 +670,7 @@ nuosc_status nuosc_timing_enable(nuosc_handle* h, int32_t on)
     }
     h->timing = on != 0;
     h->ev_used = 0;
-    for (int i = 0; i <= nuosc::kMaxStages; ++i) {
+    for (int i = 0; i <= nuosc::kMaxLaunches; ++i) {
         h->t_beam[i] = h->t_fin[i] = 0.0;
         h->t_count[i] = 0;
     }
