@@ -1,0 +1,49 @@
+// Device helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace nuosc {
+
+// sin and cos of x: x = k pi/2 + r, pi/2 split into three doubles whose
+// products with k are subtracted with one rounding each (fma; the reduction
+// of Cody and Waite, exact in k P1 and k P2 for |k| < 2^53, so accurate to
+// |x| ~ 7e15, beyond which the ulp of x itself exceeds pi), then the Taylor
+// series of sin and cos to r^17 and r^18 on |r| <= pi/4 (truncation below
+// 1e-19) and the quadrant k mod 4.  NaN in, NaN out.
+__device__ __forceinline__ void fast_sincos(double x, double& s, double& c)
+{
+    const double k = rint(x * 0.6366197723675814);  // 2 / pi
+    double r = fma(-k, 1.5707963267948966, x);
+    r = fma(-k, 6.123233995736766e-17, r);
+    r = fma(-k, -1.4973849048591698e-33, r);
+    const double z = r * r;
+    // (-1)^n / (2n+1)!, n = 1..8, and (-1)^n / (2n)!, n = 1..9
+    double ps = 2.8114572543455206e-15;
+    ps = fma(ps, z, -7.647163731819816e-13);
+    ps = fma(ps, z, 1.6059043836821613e-10);
+    ps = fma(ps, z, -2.505210838544172e-08);
+    ps = fma(ps, z, 2.7557319223985893e-06);
+    ps = fma(ps, z, -0.0001984126984126984);
+    ps = fma(ps, z, 0.008333333333333333);
+    ps = fma(ps, z, -0.16666666666666666);
+    const double sr = fma(r * z, ps, r);
+    double pc = -1.5619206968586225e-16;
+    pc = fma(pc, z, 4.779477332387385e-14);
+    pc = fma(pc, z, -1.1470745597729725e-11);
+    pc = fma(pc, z, 2.08767569878681e-09);
+    pc = fma(pc, z, -2.755731922398589e-07);
+    pc = fma(pc, z, 2.48015873015873e-05);
+    pc = fma(pc, z, -0.001388888888888889);
+    pc = fma(pc, z, 0.041666666666666664);
+    pc = fma(pc, z, -0.5);
+    const double cr = fma(z, pc, 1.0);
+    const int q = (int)fma(-4.0, floor(0.25 * k), k);  // k mod 4 in [0, 4), exact for integer k
+    s = (q & 1) ? cr : sr;
+    c = (q & 1) ? sr : cr;
+    if (q == 1 || q == 2) c = -c;
+    if (q & 2) s = -s;
+}
+
+}  // namespace nuosc

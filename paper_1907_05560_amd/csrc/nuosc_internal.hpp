@@ -61,7 +61,8 @@ struct RunConst {
     double* partial;             // [2][nj n n][nblk] per-workgroup weighted sums of the last two
                                  // moment launches (launch l uses [l & 1]), value-major
     double* errpart;             // [max(nblk, nblkf)] per-workgroup step-error maxima
-    double* qbuf[2];             // Runge-Kutta forms: [na][qstride] power moments of psi[0] / psi[1]
+    double* qbuf;                // Runge-Kutta forms: [na][qstride] power moments of the current state
+                                 // (rewritten only when a new state is accepted)
     double* dbuf;                // [na][dstride] stage-derivative coefficient matrices of the attempt
     double* gbuf;                // [na][kMaxStages][n] co-rotating frame rates of the attempt's stages
     void* ftab;                  // [na][fstride bytes] coefficients of the state update and the error
@@ -78,9 +79,9 @@ constexpr int kFinBlock = 256;     // threads per small reduction workgroup
 
 // Trajectories per workgroup of the Runge-Kutta launches: the power-moment and
 // per-trajectory launches (which write the moment partials) and the state
-// update (FP32 arithmetic: 16, FP64 arithmetic: 8).
+// update (8).
 constexpr int kTrajPerBlock = 16;
-inline int final_traj_per_block(int precision) { return precision == 1 ? 16 : 8; }
+inline int final_traj_per_block(int) { return 8; }
 
 // The runs one launch covers.  Run i of the launch is runs[slot[i]] and owns
 // the workgroups [first[i], first[i + 1]); a workgroup never spans two runs,

@@ -43,6 +43,7 @@
 // beam slot), and the density sum takes the same form w psi psi^dagger for
 // both species with weight w = g or -gbar.
 #include "nuosc_internal.hpp"
+#include "nuosc_device.hpp"
 
 #include <math.h>
 #include <array>
@@ -260,15 +261,25 @@ __device__ __forceinline__ void stage_phase(int l, double h, const double* phn, 
     }
 }
 
-// e^{i(Phi_a - Phi_b)} of the upper pairs.
+// e^{i(Phi_a - Phi_b)} of the upper pairs, computed by one wavefront: lane q
+// < NU evaluates pair q and every lane receives all NU factors.
 template <int N>
-__device__ __forceinline__ void rotation(const double* ph, double (*z)[2])
+__device__ __forceinline__ void rotation(const double* ph, double (*z)[2], int lane)
 {
+    constexpr int NU = Shape<N>::NU;
+    double d = ph[0] - ph[1];
 #pragma unroll
-    for (int q = 0; q < Shape<N>::NU; ++q) {
-        int a, b;
+    for (int q = 1; q < NU; ++q) {
+        int a = 0, b = 1;
         pair_of<N>(q, a, b);
-        sincos(ph[a] - ph[b], &z[q][1], &z[q][0]);
+        d = (lane == q) ? ph[a] - ph[b] : d;
+    }
+    double sn, cs;
+    fast_sincos(d, sn, cs);
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        z[q][0] = __shfl(cs, q, 64);
+        z[q][1] = __shfl(sn, q, 64);
     }
 }
 
@@ -539,7 +550,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
             for (int x = 0; x < NM; ++x) acc[k][x] += __shfl_xor(acc[k][x], off, 64);
 
     if (active && q == 0) {
-        double* dst = rc.qbuf[cur] + (size_t)j * rc.qstride;
+        double* dst = rc.qbuf + (size_t)j * rc.qstride;
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const int p = hb * H + k;
@@ -549,16 +560,28 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         }
     }
 
-    // the J_0 partial: Q_0 (lane 32 g) rotated to the lab frame and weighted
+    // the J_0 partial: Q_0 (lane 32 g) rotated to the lab frame and weighted;
+    // the rotation factors of both trajectories of the wavefront first
+    double z[NU > 0 ? NU : 1][2];
+    {
+        double ph[N], zz[2][NU > 0 ? NU : 1][2];
+        for (int gg = 0; gg < 2; ++gg) {
+            const int jj = blk * kTrajPerBlock + 2 * wave + gg;
+            for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? rc.phase[cur][(size_t)jj * N + a] : 0.0;
+            rotation<N>(ph, zz[gg], lane);
+        }
+        for (int u = 0; u < NU; ++u) {
+            z[u][0] = g ? zz[1][u][0] : zz[0][u][0];
+            z[u][1] = g ? zz[1][u][1] : zz[0][u][1];
+        }
+    }
     if ((lane & 31) == 0) {
         double sl[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) sl[v] = 0.0;
         if (active) {
-            double c, w, ph[N], z[NU > 0 ? NU : 1][2], f[4];
+            double c, w, f[4];
             traj_geometry(rc, j, C.r, c, w);
-            for (int a = 0; a < N; ++a) ph[a] = rc.phase[cur][(size_t)j * N + a];
-            rotation<N>(ph, z);
             double cph = 1.0, sph = 0.0;
             if constexpr (NJ == 4) {
                 cph = rc.azi[2 * (size_t)j];
@@ -621,7 +644,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     constexpr int NIT = (ITEMS + 63) / 64;
     constexpr int NH = L - 1;                            // stored matrices D_0 .. D_{L-2}
     constexpr int NQL = TABLES ? 1 : 2 * L + 1;          // power moments stage L needs
+    constexpr int QV = (NQL * NM + 63) / 64;             // of them per lane
     constexpr int TPB = kTrajPerBlock;
+    constexpr int NUA = NU > 0 ? NU : 1;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -635,7 +660,10 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     __shared__ double swave[TPB][NV];
     __shared__ double sJ[NV];
 
-    // ---- control block (ctrl[1] between attempts, ctrl[0] during one)
+    // ---- everything that does not depend on J_{L-1} is requested at entry:
+    //      control block (ctrl[1] between attempts, ctrl[0] during one), the
+    //      previous launch's partials, both phase buffers, the frame rates and
+    //      coefficient matrices of the earlier stages, the power moments
     Control C{};
     {
         Control* vc = rc.ctrl + (L == 1 ? 1 : 0);
@@ -645,23 +673,20 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         C.status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         C.fresh = __hip_atomic_load(&vc->fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    // partials of the previous launch, in flight with the control block
     PartialRegs<NV, TPB> xp;
-    if constexpr (L > 1) load_partials<NV, TPB>(rc, L - 1, xp);
-    if (L == 1 && blk == 0 && tid == 0) rc.ctrl[0] = rc.ctrl[1];
-    if (C.status != 0) return;  // run finished: attempts are no-ops
-    const int cur = C.cur;
-    const double h = C.h;
-
-    // ---- per-trajectory inputs: phase of y_n, frame rates of stages 0..L-2,
-    //      the stored coefficient matrices an item needs, the power moments
-    double phn[N], G[L][N];
+    load_partials<NV, TPB>(rc, L - 1, xp);  // L = 1: the power-moment launch's (used if fresh)
+    double ph01[2][N], G[L][N];
     double Dh[NIT][NH > 0 ? NH : 1][2];
-    if (active) {
-        for (int a = 0; a < N; ++a) phn[a] = rc.phase[cur][(size_t)j * N + a];
-        for (int m = 0; m < NH; ++m)
-            for (int a = 0; a < N; ++a) G[m][a] = rc.gbuf[((size_t)j * kMaxStages + m) * N + a];
-        const double* dsrc = rc.dbuf + (size_t)j * rc.dstride;
+    double qv[QV];
+    const int jl = active ? j : 0;
+    for (int a = 0; a < N; ++a) {
+        ph01[0][a] = rc.phase[0][(size_t)jl * N + a];
+        ph01[1][a] = rc.phase[1][(size_t)jl * N + a];
+    }
+    for (int m = 0; m < NH; ++m)
+        for (int a = 0; a < N; ++a) G[m][a] = rc.gbuf[((size_t)jl * kMaxStages + m) * N + a];
+    {
+        const double* dsrc = rc.dbuf + (size_t)jl * rc.dstride;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
@@ -673,100 +698,43 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 Dh[it][m][1] = have ? p[1] : 0.0;
             }
         }
-        if constexpr (!TABLES) {
-            const double* qs = rc.qbuf[cur] + (size_t)j * rc.qstride;
-            for (int i = lane; i < NQL * NM; i += 64) sQ[wave][i] = qs[i];
-        }
+        const double* qs = rc.qbuf + (size_t)jl * rc.qstride;
+#pragma unroll
+        for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && lane + 64 * i < NQL * NM) ? qs[lane + 64 * i] : 0.0;
     }
-
-    // ---- J_{L-1}
-    if constexpr (L > 1) {
-        finish_partials<NV, TPB>(rc, L - 1, xp, sJ);
-        if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
-    } else {
-        if (C.fresh) {
-            PartialRegs<NV, TPB> x0;
-            load_partials<NV, TPB>(rc, 0, x0);
-            finish_partials<NV, TPB>(rc, 0, x0, sJ);
-            if (blk == 0 && tid < NV) rc.jhist[tid] = sJ[tid];
-        } else {
-            if (tid < NV) sJ[tid] = rc.jhist[tid];
-            __syncthreads();
-        }
+    double cph = 1.0, sph = 0.0;
+    if constexpr (NJ == 4) {
+        cph = rc.azi[2 * (size_t)jl];
+        sph = rc.azi[2 * (size_t)jl + 1];
     }
+    if (L == 1 && blk == 0 && tid == 0) rc.ctrl[0] = rc.ctrl[1];
+    if (C.status != 0) return;  // run finished: attempts are no-ops
+    const int cur = C.cur;
+    const double h = C.h;
+    double phn[N];
+    for (int a = 0; a < N; ++a) phn[a] = cur ? ph01[1][a] : ph01[0][a];
 
-    if (lane == 0 && !TABLES)
-        for (int v = 0; v < NV; ++v) swave[wave][v] = 0.0;
+    // ---- while J_{L-1} is summed: geometry and frame of stage L-1 (and the
+    //      geometry of stage L), C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m, Q to LDS
+    const double rP = stage_radius<TAB>(C, L - 1);
+    double cP, wP;
+    traj_geometry(rc, jl, rP, cP, wP);
+    const double icP = 1.0 / cP;
+    double sc = 0.0, ss = 0.0;
+    if constexpr (NJ == 4) {
+        const double s0 = sqrt((1.0 - cP) * (1.0 + cP));
+        sc = s0 * cph;
+        ss = s0 * sph;
+    }
+    double zP[NUA][2];
+    {
+        double ph[N];
+        stage_phase<TAB, N>(L - 1, h, phn, G, ph);
+        rotation<N>(ph, zP, lane);
+    }
+    double cL = 1.0, wL = 0.0;
+    if constexpr (!TABLES) traj_geometry(rc, jl, stage_radius<TAB>(C, L), cL, wL);
     if (active) {
-        double cph = 1.0, sph = 0.0;
-        if constexpr (NJ == 4) {
-            cph = rc.azi[2 * (size_t)j];
-            sph = rc.azi[2 * (size_t)j + 1];
-        }
-        // ---- completion of stage L-1 (every lane, the same values)
-        {
-            const double rP = stage_radius<TAB>(C, L - 1);
-            double cP, wP;
-            traj_geometry(rc, j, rP, cP, wP);
-            const double icP = 1.0 / cP;
-            double sc = 0.0, ss = 0.0;
-            if constexpr (NJ == 4) {
-                const double s = sqrt((1.0 - cP) * (1.0 + cP));
-                sc = s * cph;
-                ss = s * sph;
-            }
-            double ph[N], z[NU > 0 ? NU : 1][2];
-            stage_phase<TAB, N>(L - 1, h, phn, G, ph);
-            rotation<N>(ph, z);
-            const double lam = matter(rc, rP);
-            auto kern = [&](int x) __attribute__((always_inline)) {
-                double v = sJ[x] - cP * sJ[NM + x];
-                if constexpr (NJ == 4) v = (v - sc * sJ[2 * NM + x]) - ss * sJ[3 * NM + x];
-                return v;
-            };
-            double Cd[N], tr = 0.0;
-            for (int a = 0; a < N; ++a) {
-                Cd[a] = kern(a);
-                tr += Cd[a];
-            }
-            double hd[N];
-            for (int a = 0; a < N; ++a) {
-                hd[a] = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
-                G[L - 1][a] = (rc.frame == 0) ? hd[a] * icP : 0.0;
-            }
-            // lane i < 2 NC: value i of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
-            // re/im); -i h X has real part h Im X and imaginary part -h Re X, and the
-            // lower entries follow from X_ba = conj(X_ab)
-            if (lane < 2 * NC) {
-                const int mtx = lane / NC, e = (lane - mtx * NC) >> 1, part = lane & 1;
-                const int a = e / N, b = e - (e / N) * N;
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                double xr, xi;  // X_{lo,hi}
-                if (a == b) {
-                    xr = mtx == 0 ? ((rc.frame == 0) ? 0.0 : hd[a] * icP) : rc.vac[a][a][0] * icP;
-                    xi = 0.0;
-                } else {
-                    const int u = Shape<N>::up(lo, hi);
-                    const double cs = z[u][0], sn = z[u][1];
-                    double vr, vi;
-                    if (mtx == 0) {
-                        vr = rc.mu0 * kern(N + 2 * u) * icP;
-                        vi = rc.mu0 * kern(N + 2 * u + 1) * icP;
-                    } else {
-                        vr = rc.vac[lo][hi][0] * icP;
-                        vi = rc.vac[lo][hi][1] * icP;
-                    }
-                    xr = cs * vr - sn * vi;
-                    xi = cs * vi + sn * vr;
-                    if (a > b) xi = -xi;
-                }
-                sN[wave][lane] = part == 0 ? h * xi : -h * xr;
-            }
-            if (lane == 0)
-                for (int a = 0; a < N; ++a) rc.gbuf[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
-        }
-
-        // ---- C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
@@ -785,6 +753,84 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 sC[wave][d * NC + 2 * e + 1] = im;
             }
         }
+        if constexpr (!TABLES) {
+#pragma unroll
+            for (int i = 0; i < QV; ++i)
+                if (lane + 64 * i < NQL * NM) sQ[wave][lane + 64 * i] = qv[i];
+        }
+    }
+
+    // ---- J_{L-1}
+    if (L > 1 || C.fresh) {
+        finish_partials<NV, TPB>(rc, L - 1, xp, sJ);
+        if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
+    } else {
+        if (tid < NV) sJ[tid] = rc.jhist[tid];
+        __syncthreads();
+    }
+
+    if (lane == 0 && !TABLES)
+        for (int v = 0; v < NV; ++v) swave[wave][v] = 0.0;
+    if (active) {
+        // ---- completion of stage L-1 (uniform values in every lane)
+        const double lam = matter(rc, rP);
+        auto kern = [&](int x) __attribute__((always_inline)) {
+            double v = sJ[x] - cP * sJ[NM + x];
+            if constexpr (NJ == 4) v = (v - sc * sJ[2 * NM + x]) - ss * sJ[3 * NM + x];
+            return v;
+        };
+        double Cd[N], tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            Cd[a] = kern(a);
+            tr += Cd[a];
+        }
+        double adg[N], bdg[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
+            G[L - 1][a] = (rc.frame == 0) ? hd * icP : 0.0;
+            adg[a] = (rc.frame == 0) ? 0.0 : hd * icP;
+            bdg[a] = rc.vac[a][a][0] * icP;
+        }
+        // A_ab and B_ab (a < b), rotated: e^{i(Phi_a - Phi_b)} X_ab / c
+        double axr[NUA], axi[NUA], bxr[NUA], bxi[NUA];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            int a = 0, b = 1;
+            pair_of<N>(u, a, b);
+            const double cs = zP[u][0], sn = zP[u][1];
+            const double cr = rc.mu0 * kern(N + 2 * u) * icP, ci = rc.mu0 * kern(N + 2 * u + 1) * icP;
+            const double vr = rc.vac[a][b][0] * icP, vi = rc.vac[a][b][1] * icP;
+            axr[u] = cs * cr - sn * ci;
+            axi[u] = cs * ci + sn * cr;
+            bxr[u] = cs * vr - sn * vi;
+            bxi[u] = cs * vi + sn * vr;
+        }
+        // lane i < 2 NC: value i of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
+        // re/im); -i h X has real part h Im X and imaginary part -h Re X, and the
+        // lower entries follow from X_ba = conj(X_ab)
+        if (lane < 2 * NC) {
+            const int mtx = lane / NC, e = (lane - mtx * NC) >> 1, part = lane & 1;
+            const int a = e / N, b = e - (e / N) * N;
+            double xr = 0.0, xi = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa)
+                if (a == aa && b == aa) xr = mtx == 0 ? adg[aa] : bdg[aa];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                int lo = 0, hi = 1;
+                pair_of<N>(u, lo, hi);
+                if ((a == lo && b == hi) || (a == hi && b == lo)) {
+                    xr = mtx == 0 ? axr[u] : bxr[u];
+                    xi = mtx == 0 ? axi[u] : bxi[u];
+                    if (a > b) xi = -xi;
+                }
+            }
+            sN[wave][lane] = part == 0 ? h * xi : -h * xr;
+        }
+        if (lane == 0)
+            for (int a = 0; a < N; ++a) rc.gbuf[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
         wave_sync();
 
         // ---- D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1}
@@ -797,6 +843,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             if (idx < ITEMS && d <= L) {
                 const int a = e / N, b = e - (e / N) * N;
                 double re = 0.0, im = 0.0;
+#pragma unroll
                 for (int c = 0; c < N; ++c) {
                     if (d <= L - 1) {
                         const double xr = sN[wave][2 * (a * N + c)], xi = sN[wave][2 * (a * N + c) + 1];
@@ -845,8 +892,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                                 im = fma(TAB::B[m], coeff(m, 1), im);
                             }
                         });
-                        cn[d * NC + 2 * e] = (TF)re;
-                        cn[d * NC + 2 * e + 1] = (TF)im;
+                        cn[(a * (DN + 1) + d) * 2 * N + 2 * b] = (TF)re;
+                        cn[(a * (DN + 1) + d) * 2 * N + 2 * b + 1] = (TF)im;
                     }
                     if constexpr (TAB::embedded) {
                         if (d <= DE) {
@@ -858,8 +905,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                                     im = fma(TAB::E[m], coeff(m, 1), im);
                                 }
                             });
-                            ce[d * NC + 2 * e] = re;
-                            ce[d * NC + 2 * e + 1] = im;
+                            ce[(a * (DE + 1) + d) * 2 * N + 2 * b] = re;
+                            ce[(a * (DE + 1) + d) * 2 * N + 2 * b + 1] = im;
                         }
                     }
                 }
@@ -895,10 +942,15 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                     sC[wave][d * NC + 2 * e + 1] = im;
                 }
             }
+            // frame of stage L (its phase needs G_{L-1}), while the LDS writes land
+            double zL[NUA][2], ph[N];
+            stage_phase<TAB, N>(L, h, phn, G, ph);
+            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
+            rotation<N>(ph, zL, lane);
             wave_sync();
 
             // ---- T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+   (item (d, a, b))
-            auto qv = [&](int p, int a, int c, double& re, double& im) __attribute__((always_inline)) {
+            auto qval = [&](int p, int a, int c, double& re, double& im) __attribute__((always_inline)) {
                 const double* Qp = &sQ[wave][p * NM];
                 if (a == c) {
                     re = Qp[a];
@@ -917,12 +969,12 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 if (idx < ITEMS && d <= L) {
                     const int a = e / N, b = e - (e / N) * N;
                     double re = 0.0, im = 0.0;
-#pragma unroll 1
+#pragma unroll 2
                     for (int dd = 0; dd <= L; ++dd)
 #pragma unroll
                         for (int c = 0; c < N; ++c) {
                             double qr, qi;
-                            qv(d + dd, a, c, qr, qi);
+                            qval(d + dd, a, c, qr, qi);
                             const double cr = sC[wave][dd * NC + 2 * (b * N + c)];
                             const double ci = sC[wave][dd * NC + 2 * (b * N + c) + 1];
                             // Q_{d+dd}[a][c] conj(C_dd[b][c])
@@ -946,6 +998,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                     int a = k, b = k;
                     if (k >= N) pair_of<N>(k - N, a, b);
                     double re = 0.0, im = 0.0;
+#pragma unroll
                     for (int c = 0; c < N; ++c) {
                         const double xr = sC[wave][d * NC + 2 * (a * N + c)], xi = sC[wave][d * NC + 2 * (a * N + c) + 1];
                         const double yr = sT[wave][d * NC + 2 * (c * N + b)], yi = sT[wave][d * NC + 2 * (c * N + b) + 1];
@@ -964,53 +1017,49 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             wave_sync();
 
             // ---- density sum of stage L, its lab-frame rotation and weights
-            double Sx[NM];
-            for (int v = 0; v < NM; ++v) {
-                double s = sQ[wave][v];
-                for (int d = 1; d <= L; ++d) s += sQ[wave][d * NM + v];
-                Sx[v] = s;
-            }
-            const double rL = stage_radius<TAB>(C, L);
-            double cL, wL, f[4];
-            traj_geometry(rc, j, rL, cL, wL);
-            double ph[N], z[NU > 0 ? NU : 1][2];
-            stage_phase<TAB, N>(L, h, phn, G, ph);
-            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
-            rotation<N>(ph, z);
-            angle_weights<NJ>(rc, cL, wL, cph, sph, f);
-            double Sv[NM];
-            for (int a = 0; a < N; ++a) Sv[a] = 2.0 * Sx[a];
-            for (int u = 0; u < NU; ++u) {
-                const double cs = z[u][0], sn = z[u][1];
-                const double xr = Sx[N + 2 * u], xi = Sx[N + 2 * u + 1];
-                Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
-                Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
-            }
-            if (lane == 0)
+            if (lane == 0) {
+                double Sx[NM];
+                for (int v = 0; v < NM; ++v) {
+                    double s0 = sQ[wave][v];
+                    for (int d = 1; d <= L; ++d) s0 += sQ[wave][d * NM + v];
+                    Sx[v] = s0;
+                }
+                double f[4];
+                angle_weights<NJ>(rc, cL, wL, cph, sph, f);
+                double Sv[NM];
+                for (int a = 0; a < N; ++a) Sv[a] = 2.0 * Sx[a];
+                for (int u = 0; u < NU; ++u) {
+                    const double cs = zL[u][0], sn = zL[u][1];
+                    const double xr = Sx[N + 2 * u], xi = Sx[N + 2 * u + 1];
+                    Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
+                    Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
+                }
                 for (int m = 0; m < NJ; ++m)
                     for (int v = 0; v < NM; ++v) swave[wave][m * NM + v] = f[m] * Sv[v];
+            }
         }
     }
     if constexpr (!TABLES) {
         __syncthreads();
         if (tid < NV) {
-            double s = swave[0][tid];
-            for (int w = 1; w < TPB; ++w) s += swave[w][tid];
-            rc.partial[((size_t)(L & 1) * NV + tid) * rc.nblk + blk] = s;
+            double s0 = swave[0][tid];
+            for (int w = 1; w < TPB; ++w) s0 += swave[w][tid];
+            rc.partial[((size_t)(L & 1) * NV + tid) * rc.nblk + blk] = s0;
         }
     }
 }
 
 // ------------------------------------------------------------------ state update
 // Launch S + 1: one wavefront per trajectory, lanes over its 2 N_E beam slots
-// (NSLOT beams of a lane in flight).  Per beam:
-//   y_{n+1} = M(u) y_n,  M(u) = sum_d Cn_d u^d (Horner, arithmetic type T),
+// (two groups of two beams of a lane in flight).  Per beam:
+//   y_{n+1} = M(u) y_n,  M(u) = sum_d Cn_d u^d (arithmetic type T),
 //   FP32 amplitudes: y_{n+1} / |y_{n+1}|, written in the storage type;
 //   embedded pair: delta = E(u) y_n in FP64 (E = sum_m e_m D_m, the step error
 //   h sum_m e_m k_m), and the maximum of |Re|, |Im| over the components;
 //   RK4: whether the new state is finite.
 // The coefficients are wave-uniform: they are read through the constant
-// address space into scalar registers, once per beam.
+// address space into scalar registers, once per group of beams.
+
 // p, passed through an empty asm that also takes v: loads through the result
 // cannot be issued before v has been computed.
 template <typename V>
@@ -1028,64 +1077,88 @@ __device__ __forceinline__ uint64_t after_all(uint64_t p, const V (&v)[NR])
     return p;
 }
 
-// M[x] = sum_{d<=D} c[d STRIDE + x] u^d, x < NR, by Horner's rule: one row of
-// a coefficient matrix polynomial whose wave-uniform coefficients start at
-// byte address `base` (read through the constant address space, so they
-// arrive in scalar registers and feed the FMAs as scalar operands).  The
-// coefficients of degree d-1 are requested while degree d is applied; the
-// address of each request depends on the previous step's result, so the
-// compiler cannot hoist the requests of later degrees (which would exhaust
-// the scalar registers).
-template <int D, int NR, int STRIDE, typename T, typename CT>
-__device__ __forceinline__ void horner_row(uint64_t base, T u, T (&M)[NR])
+// M_g[x] = sum_{d<=D} c[d NR + x] u_g^d, x < NR, for the G beams of a group:
+// one row of a coefficient matrix polynomial, stored degree after degree from
+// byte address `base` (wave-uniform, read through the constant address space,
+// so the coefficients arrive in scalar registers and serve all G beams),
+// summed in ascending degree with the powers up[g][d] = u_g^d.  The
+// coefficient is the multiplicand of every fma, so it is used straight from
+// its scalar register.  The row is requested in chunks of at most 48 scalar
+// registers; the address of each chunk depends on the partial sums of the
+// previous one, so the compiler cannot hoist later requests (which would
+// exhaust the scalar registers).
+template <int D, int NR, int G, typename T, typename CT>
+__device__ __forceinline__ void powsum_row(uint64_t base, const T (&up)[G][D + 1], T (&M)[G][NR])
 {
-    auto load = [&](uint64_t p, int d, CT (&v)[NR]) __attribute__((always_inline)) {
+    constexpr int K = (48 * 4) / (NR * (int)sizeof(CT));  // degrees per request
+    constexpr int NK = (D + 1 + K - 1) / K;
+    static_for<0, NK>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        constexpr int d0 = k * K;
+        constexpr int d1 = (d0 + K < D + 1) ? d0 + K : D + 1;
+        uint64_t p = base;
+        if constexpr (k > 0) p = after_all(after_all(base, M[0]), M[G - 1]);
         const cptr<CT> c = reinterpret_cast<cptr<CT>>(p);
+        CT cv[d1 - d0][NR];
 #pragma unroll
-        for (int x = 0; x < NR; ++x) v[x] = c[d * STRIDE + x];
-    };
-    CT cu[NR], nx[NR];
-    load(base, D, cu);
-    load(base, D - 1, nx);
+        for (int d = d0; d < d1; ++d)
 #pragma unroll
-    for (int x = 0; x < NR; ++x) M[x] = (T)cu[x];
-    static_for<0, D>([&](auto Ic) {
-        constexpr int d = D - 1 - decltype(Ic)::value;
+            for (int x = 0; x < NR; ++x) cv[d - d0][x] = c[d * NR + x];
 #pragma unroll
-        for (int x = 0; x < NR; ++x) cu[x] = nx[x];
-        if constexpr (d > 0) load(after_all(base, M), d - 1, nx);
+        for (int d = d0; d < d1; ++d)
 #pragma unroll
-        for (int x = 0; x < NR; ++x) M[x] = fma(M[x], u, (T)cu[x]);
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int x = 0; x < NR; ++x)
+                    M[g][x] = (d == 0) ? (T)cv[0][x] : fma((T)cv[d - d0][x], up[g][d], M[g][x]);
     });
 }
 
-// out = P(u) y for a matrix polynomial P of degree D whose coefficients (full
-// complex N x N matrices, row-major re/im, NC reals of type CT per degree)
-// start at byte address `base`, one row at a time (each row's first request
-// waits for the previous row's result).
-template <int D, int N, typename T, typename CT>
-__device__ __forceinline__ void poly_apply(uint64_t base, T u, const T* y, T* out)
+// out_g = P(u_g) y_g for the G beams of a group, P a matrix polynomial of
+// degree D over full complex N x N matrices, stored row by row: row a holds
+// the 2N reals (re/im of its N entries) of degree 0, then of degree 1, ...,
+// (D + 1) 2N values of type CT from byte address base + a (D + 1) 2N
+// sizeof(CT).  Each row's request waits for the previous row's result.
+template <int D, int N, int G, typename T, typename CT>
+__device__ __forceinline__ void poly_apply(uint64_t base, const T (&up)[G][D + 1], const T (&y)[G][2 * N],
+                                           T (&out)[G][2 * N])
 {
-    constexpr int NC = Shape<N>::NC;
-    T M[2 * N];
+    T M[G][2 * N];
 #pragma unroll
-    for (int x = 0; x < 2 * N; ++x) M[x] = y[x];
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int x = 0; x < 2 * N; ++x) M[g][x] = y[g][x];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-        horner_row<D, 2 * N, NC, T, CT>(after_all(base + (uint64_t)(2 * N * a * (int)sizeof(CT)), M), u, M);
-        T re = 0, im = 0;
+        const uint64_t row = after_all(after_all(base + (uint64_t)(a * (D + 1) * 2 * N * (int)sizeof(CT)), M[0]),
+                                       M[G - 1]);
+        powsum_row<D, 2 * N, G, T, CT>(row, up, M);
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-            re = fma(M[2 * b], y[2 * b], fma(-M[2 * b + 1], y[2 * b + 1], re));
-            im = fma(M[2 * b], y[2 * b + 1], fma(M[2 * b + 1], y[2 * b], im));
+        for (int g = 0; g < G; ++g) {
+            T re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                re = fma(M[g][2 * b], y[g][2 * b], fma(-M[g][2 * b + 1], y[g][2 * b + 1], re));
+                im = fma(M[g][2 * b], y[g][2 * b + 1], fma(M[g][2 * b + 1], y[g][2 * b], im));
+            }
+            out[g][2 * a] = re;
+            out[g][2 * a + 1] = im;
         }
-        out[2 * a] = re;
-        out[2 * a + 1] = im;
     }
 }
 
+// u^0 .. u^D.
+template <int D, typename T>
+__device__ __forceinline__ void powers(T u, T (&up)[D + 1])
+{
+    up[0] = T(1);
+    up[1] = u;
+#pragma unroll
+    for (int d = 2; d <= D; ++d) up[d] = up[d - 1] * u;
+}
+
 template <typename T> struct FinalShape {
-    static constexpr int traj = std::is_same<T, double>::value ? 8 : 16;
+    static constexpr int traj = 8;
     static constexpr int block = 64 * traj;
 };
 
@@ -1097,7 +1170,8 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     constexpr int DN = PY::DN, DE = PY::DE;
     constexpr bool ERROR = TAB::embedded;
     constexpr int TPB = FinalShape<T>::traj;
-    constexpr int NSLOT = 2;
+    constexpr int G = 2;       // beams of a lane sharing each coefficient load
+    constexpr int NGRP = 2;    // groups of a lane in flight
     constexpr uint32_t STRIDE = 64;
     constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 7) / 8) * 8;  // byte offset of the error table
 
@@ -1134,71 +1208,102 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     double emax = 0.0;
     bool bad = false;
     auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
-    auto fetch = [&](uint32_t t, TS* yv, T& uv, double& u64v) __attribute__((always_inline)) {
-        if (t < nbt) {
-            const uint32_t off = offset(t) * (uint32_t)sizeof(TS);
+    // one group: the G beams t, t + 64, ... of the lane (beams past the end are
+    // computed on zeros and neither stored nor counted)
+    auto fetch = [&](uint32_t t, TS (&yv)[G][2 * N], T (&uv)[G], double (&u64v)[G]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x)
-                yv[x] = *reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb));
-            uv = *elem(uinv, t);
-            if constexpr (ERROR && !std::is_same<T, double>::value) u64v = *elem(uinv64, t);
+        for (int g = 0; g < G; ++g) {
+            const uint32_t tg = t + g * STRIDE;
+            if (tg < nbt) {
+                const uint32_t off = offset(tg) * (uint32_t)sizeof(TS);
+#pragma unroll
+                for (int x = 0; x < 2 * N; ++x)
+                    yv[g][x] = *reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb));
+                uv[g] = *elem(uinv, tg);
+                if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = *elem(uinv64, tg);
+            } else {
+#pragma unroll
+                for (int x = 0; x < 2 * N; ++x) yv[g][x] = (TS)0;
+                uv[g] = 0;
+                if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = 0.0;
+            }
         }
     };
-    auto process = [&](uint32_t t, const TS* yv, T u, double u64) __attribute__((always_inline)) {
-        if constexpr (std::is_same<T, double>::value) u64 = u;
-        T y[2 * N];
+    auto process = [&](uint32_t t, const TS (&yv)[G][2 * N], const T (&u)[G], const double (&u64v)[G])
+                       __attribute__((always_inline)) {
+        T y[G][2 * N], yn[G][2 * N];
+        {
+            T up[G][DN + 1];
 #pragma unroll
-        for (int x = 0; x < 2 * N; ++x) y[x] = (T)yv[x];
-        T yn[2 * N];
-        poly_apply<DN, N, T, T>(tb, u, y, yn);
-        if constexpr (std::is_same<TS, float>::value) {
-            // FP32 amplitudes are renormalised whenever a new state is formed
-            T nn = 0;
+            for (int g = 0; g < G; ++g) {
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x) nn = fma(yn[x], yn[x], nn);
-            const T sc = T(1) / sqrt(nn);
-#pragma unroll
-            for (int x = 0; x < 2 * N; ++x) yn[x] = yn[x] * sc;
+                for (int x = 0; x < 2 * N; ++x) y[g][x] = (T)yv[g][x];
+                powers<DN>(u[g], up[g]);
+            }
+            poly_apply<DN, N, G, T, T>(tb, up, y, yn);
         }
-        const uint32_t off = offset(t) * (uint32_t)sizeof(TS);
 #pragma unroll
-        for (int x = 0; x < 2 * N; ++x)
-            *reinterpret_cast<global<TS>*>(dstb + (uint64_t)(off + (uint32_t)x * ldb)) = (TS)yn[x];
-        if constexpr (!ERROR) {
+        for (int g = 0; g < G; ++g) {
+            if constexpr (std::is_same<TS, float>::value) {
+                // FP32 amplitudes are renormalised whenever a new state is formed
+                T nn = 0;
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x) bad |= !isfinite(yn[x]);
-        } else {
-            double y64[2 * N];
+                for (int x = 0; x < 2 * N; ++x) nn = fma(yn[g][x], yn[g][x], nn);
+                const T sc = T(1) / sqrt(nn);
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x) y64[x] = (double)yv[x];
-            double dl[2 * N];
-            poly_apply<DE, N, double, double>(after_all(tb + EOFF, yn), u64, y64, dl);
+                for (int x = 0; x < 2 * N; ++x) yn[g][x] = yn[g][x] * sc;
+            }
+            const uint32_t tg = t + g * STRIDE;
+            if (tg < nbt) {
+                const uint32_t off = offset(tg) * (uint32_t)sizeof(TS);
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x) {
-                const double e = fabs(dl[x]);
-                bad |= !isfinite(e);
-                emax = fmax(emax, e);
+                for (int x = 0; x < 2 * N; ++x)
+                    *reinterpret_cast<global<TS>*>(dstb + (uint64_t)(off + (uint32_t)x * ldb)) = (TS)yn[g][x];
+                if constexpr (!ERROR) {
+#pragma unroll
+                    for (int x = 0; x < 2 * N; ++x) bad |= !isfinite(yn[g][x]);
+                }
+            }
+        }
+        if constexpr (ERROR) {
+            double y64[G][2 * N], dl[G][2 * N], up[G][DE + 1];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int x = 0; x < 2 * N; ++x) y64[g][x] = (double)yv[g][x];
+                if constexpr (std::is_same<T, double>::value) powers<DE>((double)u[g], up[g]);
+                else powers<DE>(u64v[g], up[g]);
+            }
+            poly_apply<DE, N, G, double, double>(after_all(tb + EOFF, yn[0]), up, y64, dl);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (t + g * STRIDE < nbt) {
+#pragma unroll
+                    for (int x = 0; x < 2 * N; ++x) {
+                        const double e = fabs(dl[g][x]);
+                        bad |= !isfinite(e);
+                        emax = fmax(emax, e);
+                    }
+                }
             }
         }
     };
 
-    TS ys[NSLOT][2 * N];
-    T us[NSLOT];
-    double u64s[NSLOT];
+    TS ys[NGRP][G][2 * N];
+    T us[NGRP][G];
+    double u64s[NGRP][G] = {};
     const uint32_t t0 = (uint32_t)lane;
-    static_for<0, NSLOT>([&](auto Sc) {
+    static_for<0, NGRP>([&](auto Sc) {
         constexpr int sl = decltype(Sc)::value;
-        us[sl] = 0;
-        u64s[sl] = 0.0;
-        fetch(t0 + sl * STRIDE, ys[sl], us[sl], u64s[sl]);
+        fetch(t0 + sl * G * STRIDE, ys[sl], us[sl], u64s[sl]);
     });
 #pragma unroll 1
-    for (uint32_t t = t0; t < nbt; t += NSLOT * STRIDE) {
-        static_for<0, NSLOT>([&](auto Sc) {
+    for (uint32_t t = t0; t < nbt; t += NGRP * G * STRIDE) {
+        static_for<0, NGRP>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
-            const uint32_t ts = t + sl * STRIDE;
+            const uint32_t ts = t + sl * G * STRIDE;
             if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
-            fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], u64s[sl]);
+            fetch(ts + NGRP * G * STRIDE, ys[sl], us[sl], u64s[sl]);
         });
     }
 

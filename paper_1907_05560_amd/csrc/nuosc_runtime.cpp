@@ -178,7 +178,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
 
 // ---------------------------------------------------------------- layout
 struct Layout {
-    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, qbuf[2], dbuf, gbuf, ftab, xbuf, flux, azi,
+    size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, qbuf, dbuf, gbuf, ftab, xbuf, flux, azi,
         ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk, nblkf;
@@ -262,7 +262,7 @@ Layout make_layout(const nuosc_params& p)
     L.partial = take((size_t)2 * L.nj * n * n * L.nblk * 8);  // two launches' partials (alternating)
     L.azi = take((size_t)2 * L.na * 8);
     L.errpart = take((size_t)std::max(L.nblk, L.nblkf) * 8);
-    for (int b = 0; b < 2; ++b) L.qbuf[b] = take((size_t)L.na * L.poly.qstride * 8);
+    L.qbuf = take((size_t)L.na * L.poly.qstride * 8);
     L.dbuf = take((size_t)L.na * L.poly.dstride * 8);
     L.gbuf = take(rk ? (size_t)L.na * nuosc::kMaxStages * n * 8 : 0);
     L.ftab = take((size_t)L.na * L.poly.fstride);
@@ -417,7 +417,7 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
-    for (int b = 0; b < 2; ++b) rc.qbuf[b] = (double*)(base + L.qbuf[b]);
+    rc.qbuf = (double*)(base + L.qbuf);
     rc.dbuf = (double*)(base + L.dbuf);
     rc.gbuf = (double*)(base + L.gbuf);
     rc.ftab = (void*)(base + L.ftab);
