@@ -261,10 +261,12 @@ __device__ __forceinline__ void stage_phase(int l, double h, const double* phn, 
     }
 }
 
-// e^{i(Phi_a - Phi_b)} of the upper pairs, computed by one wavefront: lane q
-// < NU evaluates pair q and every lane receives all NU factors.
+// e^{i(Phi_a - Phi_b)} of the upper pairs, computed by a group of lanes that
+// share one trajectory (first lane `base`, lane li within the group): lane q <
+// NU of the group evaluates pair q and every lane of the group receives all NU
+// factors.
 template <int N>
-__device__ __forceinline__ void rotation(const double* ph, double (*z)[2], int lane)
+__device__ __forceinline__ void rotation(const double* ph, double (*z)[2], int li, int base)
 {
     constexpr int NU = Shape<N>::NU;
     double d = ph[0] - ph[1];
@@ -272,14 +274,14 @@ __device__ __forceinline__ void rotation(const double* ph, double (*z)[2], int l
     for (int q = 1; q < NU; ++q) {
         int a = 0, b = 1;
         pair_of<N>(q, a, b);
-        d = (lane == q) ? ph[a] - ph[b] : d;
+        d = (li == q) ? ph[a] - ph[b] : d;
     }
     double sn, cs;
     fast_sincos(d, sn, cs);
 #pragma unroll
     for (int q = 0; q < NU; ++q) {
-        z[q][0] = __shfl(cs, q, 64);
-        z[q][1] = __shfl(sn, q, 64);
+        z[q][0] = __shfl(cs, base + q, 64);
+        z[q][1] = __shfl(sn, base + q, 64);
     }
 }
 
@@ -568,7 +570,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         for (int gg = 0; gg < 2; ++gg) {
             const int jj = blk * kTrajPerBlock + 2 * wave + gg;
             for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? rc.phase[cur][(size_t)jj * N + a] : 0.0;
-            rotation<N>(ph, zz[gg], lane);
+            rotation<N>(ph, zz[gg], lane, 0);
         }
         for (int u = 0; u < NU; ++u) {
             z[u][0] = g ? zz[1][u][0] : zz[0][u][0];
@@ -610,19 +612,22 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 }
 
 // ------------------------------------------------------------------ per-trajectory stages
-// Launch L of an attempt, one wavefront per trajectory (kTrajPerBlock per
-// workgroup).  Lanes work on items (d, e): coefficient degree d and matrix
-// entry e = (a, b) of a full complex n x n matrix.
+// Launch L of an attempt.  A group of kTrajLanes lanes works on one trajectory
+// (four per wavefront, kTrajPerBlock per workgroup), its lanes on items (d, e):
+// coefficient degree d and matrix entry e = (a, b) of a full complex n x n
+// matrix.
 //   1. J_{L-1}: the fixed-order sum of the previous launch's partials (L = 1:
-//      the power-moment launch's, or J_0 kept from a rejected attempt).
+//      the power-moment launch's, or J_0 kept from a rejected attempt).  While
+//      it is in flight: geometry and frame of stage L-1, the stored coefficient
+//      matrices summed into C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m and into
+//      the part of C_L (or of the update and error tables) without D_{L-1}.
 //   2. Completion of stage L-1 at its radius: collective term
 //      C = mu0 traceless(J0 - c J1 [- s cos(phi) J2 - s sin(phi) J3]), frame
 //      rate G = diag(H_m + C) / c (co-rotating frame, 0 in the lab frame),
 //      A = e^{i(Phi_a - Phi_b)} C_ab / c off the diagonal (diagonal 0, lab
 //      frame (H_m + C)_aa / c), B = e^{i(Phi_a - Phi_b)} V_ab / c with
 //      H_vac = V / E; N0 = -i h A, N1 = -i h B.
-//   3. C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m, then
-//      D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1} (stored for later launches).
+//   3. D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1} (stored for later launches).
 //   L < S:
 //   4. C_L = 1 + sum_{m<L} a_Lm D_m; T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+;
 //      X_d = C_{L,d} T_d; the stage-L density sum sum_d X_d (co-rotating).
@@ -631,7 +636,11 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 //      stage S-1 is the new state, whose phase is stored.
 //   L = S:
 //   4. Tables of the update 1 + sum_m b_m D_m (type TF) and of the error
-//      sum_m e_m D_m (FP64) for k_final; RK4: the new state's phase.
+//      sum_m e_m D_m (FP64) for k_final, row by row (row a: degree 0, 1, ...
+//      of its 2n reals); RK4: the new state's phase.
+constexpr int kTrajLanes = 32;
+constexpr int kTrajWaves = kTrajPerBlock * kTrajLanes / 64;
+
 template <int N, typename TAB, int NJ, int L, typename TF>
 __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 {
@@ -639,18 +648,23 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     constexpr int S = TAB::S, NM = Shape<N>::NM, NU = Shape<N>::NU, NC = Shape<N>::NC, NN = N * N;
     constexpr int NV = NJ * NM;
     constexpr bool TABLES = (L == S);
+    constexpr int LT = kTrajLanes;
     constexpr int DMAX = TABLES ? S : L;                 // largest degree an item handles
     constexpr int ITEMS = (DMAX + 1) * NN;
-    constexpr int NIT = (ITEMS + 63) / 64;
+    constexpr int NIT = (ITEMS + LT - 1) / LT;
     constexpr int NH = L - 1;                            // stored matrices D_0 .. D_{L-2}
     constexpr int NQL = TABLES ? 1 : 2 * L + 1;          // power moments stage L needs
-    constexpr int QV = (NQL * NM + 63) / 64;             // of them per lane
+    constexpr int QV = (NQL * NM + LT - 1) / LT;         // of them per lane
     constexpr int TPB = kTrajPerBlock;
+    constexpr int NW = kTrajWaves;
     constexpr int NUA = NU > 0 ? NU : 1;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int j = blk * TPB + wave;
+    const int li = lane & (LT - 1);                      // lane within the trajectory's group
+    const int gbase = lane & ~(LT - 1);                  // first lane of the group
+    const int jt = wave * (64 / LT) + lane / LT;         // trajectory within the workgroup
+    const int j = blk * TPB + jt;
     const bool active = j < rc.na;
 
     __shared__ double sQ[TPB][NQL * NM];                 // Q_p packed; later the X_d (packed)
@@ -662,8 +676,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 
     // ---- everything that does not depend on J_{L-1} is requested at entry:
     //      control block (ctrl[1] between attempts, ctrl[0] during one), the
-    //      previous launch's partials, both phase buffers, the frame rates and
-    //      coefficient matrices of the earlier stages, the power moments
+    //      previous launch's partials, both phase buffers, the frame rates of
+    //      the earlier stages, the power moments
     Control C{};
     {
         Control* vc = rc.ctrl + (L == 1 ? 1 : 0);
@@ -673,23 +687,29 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         C.status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         C.fresh = __hip_atomic_load(&vc->fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    PartialRegs<NV, TPB> xp;
-    load_partials<NV, TPB>(rc, L - 1, xp);  // L = 1: the power-moment launch's (used if fresh)
-    double ph01[2][N], G[L][N];
-    double Dh[NIT][NH > 0 ? NH : 1][2];
-    double qv[QV];
+    PartialRegs<NV, NW> xp;
+    load_partials<NV, NW>(rc, L - 1, xp);  // L = 1: the power-moment launch's (used if fresh)
     const int jl = active ? j : 0;
+    double ph01[2][N], G[L][N];
     for (int a = 0; a < N; ++a) {
         ph01[0][a] = rc.phase[0][(size_t)jl * N + a];
         ph01[1][a] = rc.phase[1][(size_t)jl * N + a];
     }
     for (int m = 0; m < NH; ++m)
         for (int a = 0; a < N; ++a) G[m][a] = rc.gbuf[((size_t)jl * kMaxStages + m) * N + a];
+    double qv[QV];
+    {
+        const double* qs = rc.qbuf + (size_t)jl * rc.qstride;
+#pragma unroll
+        for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && li + LT * i < NQL * NM) ? qs[li + LT * i] : 0.0;
+    }
+    // the stored coefficient matrices each item needs (in range for every lane)
+    double Dh[NIT][NH > 0 ? NH : 1][2];
     {
         const double* dsrc = rc.dbuf + (size_t)jl * rc.dstride;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+            const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
 #pragma unroll
             for (int m = 0; m < NH; ++m) {
                 const bool have = idx < ITEMS && d <= m + 1;
@@ -698,9 +718,6 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 Dh[it][m][1] = have ? p[1] : 0.0;
             }
         }
-        const double* qs = rc.qbuf + (size_t)jl * rc.qstride;
-#pragma unroll
-        for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && lane + 64 * i < NQL * NM) ? qs[lane + 64 * i] : 0.0;
     }
     double cph = 1.0, sph = 0.0;
     if constexpr (NJ == 4) {
@@ -715,7 +732,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     for (int a = 0; a < N; ++a) phn[a] = cur ? ph01[1][a] : ph01[0][a];
 
     // ---- while J_{L-1} is summed: geometry and frame of stage L-1 (and the
-    //      geometry of stage L), C_{L-1} = 1 + sum_{m<L-1} a_{L-1,m} D_m, Q to LDS
+    //      geometry of stage L), the stored coefficient matrices summed into
+    //      C_{L-1} (to LDS) and into the parts of C_L or of the tables
+    //      without D_{L-1} (registers), Q to LDS
     const double rP = stage_radius<TAB>(C, L - 1);
     double cP, wP;
     traj_geometry(rc, jl, rP, cP, wP);
@@ -730,49 +749,72 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     {
         double ph[N];
         stage_phase<TAB, N>(L - 1, h, phn, G, ph);
-        rotation<N>(ph, zP, lane);
+        rotation<N>(ph, zP, li, gbase);
     }
     double cL = 1.0, wL = 0.0;
     if constexpr (!TABLES) traj_geometry(rc, jl, stage_radius<TAB>(C, L), cL, wL);
+    // per item: next = C_L without its D_{L-1} term (L < S), or the update
+    // (next) and error (nerr) tables without it (L = S), each summed from the
+    // identity in ascending m as C_{L-1} is
+    double next[NIT][2], nerr[NIT][2];
     if (active) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
-            if (idx < ITEMS && d <= L - 1) {
-                const int a = e / N, b = e - (e / N) * N;
-                double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
+            const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
+            const int a = e / N, b = e - (e / N) * N;
+            const double id = (d == 0 && a == b) ? 1.0 : 0.0;
+            double cr = id, ci = 0.0, xr = id, xi = 0.0, er = 0.0, ei = 0.0;
+            if (idx < ITEMS) {
                 static_for<0, NH>([&](auto Mc) {
                     constexpr int m = decltype(Mc)::value;
-                    constexpr double cf = TAB::A[L - 1][m];
-                    if constexpr (cf != 0.0) {
-                        re = fma(cf, Dh[it][m][0], re);
-                        im = fma(cf, Dh[it][m][1], im);
+                    {
+                        const double dr = Dh[it][m][0], di = Dh[it][m][1];
+                        constexpr double ca = TAB::A[L - 1][m];
+                        if constexpr (ca != 0.0) {
+                            cr = fma(ca, dr, cr);
+                            ci = fma(ca, di, ci);
+                        }
+                        constexpr double cn = TABLES ? TAB::B[m] : TAB::A[L][m];
+                        if constexpr (cn != 0.0) {
+                            xr = fma(cn, dr, xr);
+                            xi = fma(cn, di, xi);
+                        }
+                        if constexpr (TABLES && TAB::E[m] != 0.0) {
+                            er = fma(TAB::E[m], dr, er);
+                            ei = fma(TAB::E[m], di, ei);
+                        }
                     }
                 });
-                sC[wave][d * NC + 2 * e] = re;
-                sC[wave][d * NC + 2 * e + 1] = im;
+                if (d <= L - 1) {
+                    sC[jt][d * NC + 2 * e] = cr;
+                    sC[jt][d * NC + 2 * e + 1] = ci;
+                }
             }
+            next[it][0] = xr;
+            next[it][1] = xi;
+            nerr[it][0] = er;
+            nerr[it][1] = ei;
         }
         if constexpr (!TABLES) {
 #pragma unroll
             for (int i = 0; i < QV; ++i)
-                if (lane + 64 * i < NQL * NM) sQ[wave][lane + 64 * i] = qv[i];
+                if (li + LT * i < NQL * NM) sQ[jt][li + LT * i] = qv[i];
         }
     }
 
     // ---- J_{L-1}
     if (L > 1 || C.fresh) {
-        finish_partials<NV, TPB>(rc, L - 1, xp, sJ);
+        finish_partials<NV, NW>(rc, L - 1, xp, sJ);
         if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
     } else {
         if (tid < NV) sJ[tid] = rc.jhist[tid];
         __syncthreads();
     }
 
-    if (lane == 0 && !TABLES)
-        for (int v = 0; v < NV; ++v) swave[wave][v] = 0.0;
+    if (li == 0 && !TABLES)
+        for (int v = 0; v < NV; ++v) swave[jt][v] = 0.0;
     if (active) {
-        // ---- completion of stage L-1 (uniform values in every lane)
+        // ---- completion of stage L-1 (the same values in every lane of the group)
         const double lam = matter(rc, rP);
         auto kern = [&](int x) __attribute__((always_inline)) {
             double v = sJ[x] - cP * sJ[NM + x];
@@ -807,11 +849,12 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             bxr[u] = cs * vr - sn * vi;
             bxi[u] = cs * vi + sn * vr;
         }
-        // lane i < 2 NC: value i of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
+        // value i < 2 NC of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
         // re/im); -i h X has real part h Im X and imaginary part -h Re X, and the
         // lower entries follow from X_ba = conj(X_ab)
-        if (lane < 2 * NC) {
-            const int mtx = lane / NC, e = (lane - mtx * NC) >> 1, part = lane & 1;
+#pragma unroll
+        for (int i = li; i < 2 * NC; i += LT) {
+            const int mtx = i / NC, e = (i - mtx * NC) >> 1, part = i & 1;
             const int a = e / N, b = e - (e / N) * N;
             double xr = 0.0, xi = 0.0;
 #pragma unroll
@@ -827,9 +870,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                     if (a > b) xi = -xi;
                 }
             }
-            sN[wave][lane] = part == 0 ? h * xi : -h * xr;
+            sN[jt][i] = part == 0 ? h * xi : -h * xr;
         }
-        if (lane == 0)
+        if (li == 0)
             for (int a = 0; a < N; ++a) rc.gbuf[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
         wave_sync();
 
@@ -838,7 +881,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         double* ddst = rc.dbuf + (size_t)j * rc.dstride + (size_t)PY::doff(L - 1) * NC;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+            const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
             Dn[it][0] = Dn[it][1] = 0.0;
             if (idx < ITEMS && d <= L) {
                 const int a = e / N, b = e - (e / N) * N;
@@ -846,15 +889,15 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
                     if (d <= L - 1) {
-                        const double xr = sN[wave][2 * (a * N + c)], xi = sN[wave][2 * (a * N + c) + 1];
-                        const double yr = sC[wave][d * NC + 2 * (c * N + b)], yi = sC[wave][d * NC + 2 * (c * N + b) + 1];
+                        const double xr = sN[jt][2 * (a * N + c)], xi = sN[jt][2 * (a * N + c) + 1];
+                        const double yr = sC[jt][d * NC + 2 * (c * N + b)], yi = sC[jt][d * NC + 2 * (c * N + b) + 1];
                         re = fma(xr, yr, fma(-xi, yi, re));
                         im = fma(xr, yi, fma(xi, yr, im));
                     }
                     if (d >= 1) {
-                        const double xr = sN[wave][NC + 2 * (a * N + c)], xi = sN[wave][NC + 2 * (a * N + c) + 1];
-                        const double yr = sC[wave][(d - 1) * NC + 2 * (c * N + b)];
-                        const double yi = sC[wave][(d - 1) * NC + 2 * (c * N + b) + 1];
+                        const double xr = sN[jt][NC + 2 * (a * N + c)], xi = sN[jt][NC + 2 * (a * N + c) + 1];
+                        const double yr = sC[jt][(d - 1) * NC + 2 * (c * N + b)];
+                        const double yi = sC[jt][(d - 1) * NC + 2 * (c * N + b) + 1];
                         re = fma(xr, yr, fma(-xi, yi, re));
                         im = fma(xr, yi, fma(xi, yr, im));
                     }
@@ -877,34 +920,25 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             double* ce = reinterpret_cast<double*>(tb + (((DN + 1) * NC * sizeof(TF) + 7) / 8) * 8);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
-                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
                 if (idx < ITEMS) {
                     const int a = e / N, b = e - (e / N) * N;
-                    auto coeff = [&](int m, int k) __attribute__((always_inline)) {
-                        return m < S - 1 ? Dh[it][m < NH ? m : 0][k] : Dn[it][k];
-                    };
                     if (d <= DN) {
-                        double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
-                        static_for<0, S>([&](auto Mc) {
-                            constexpr int m = decltype(Mc)::value;
-                            if constexpr (TAB::B[m] != 0.0) {
-                                re = fma(TAB::B[m], coeff(m, 0), re);
-                                im = fma(TAB::B[m], coeff(m, 1), im);
-                            }
-                        });
+                        double re = next[it][0], im = next[it][1];
+                        if constexpr (TAB::B[S - 1] != 0.0) {
+                            re = fma(TAB::B[S - 1], Dn[it][0], re);
+                            im = fma(TAB::B[S - 1], Dn[it][1], im);
+                        }
                         cn[(a * (DN + 1) + d) * 2 * N + 2 * b] = (TF)re;
                         cn[(a * (DN + 1) + d) * 2 * N + 2 * b + 1] = (TF)im;
                     }
                     if constexpr (TAB::embedded) {
                         if (d <= DE) {
-                            double re = 0.0, im = 0.0;
-                            static_for<0, S>([&](auto Mc) {
-                                constexpr int m = decltype(Mc)::value;
-                                if constexpr (TAB::E[m] != 0.0) {
-                                    re = fma(TAB::E[m], coeff(m, 0), re);
-                                    im = fma(TAB::E[m], coeff(m, 1), im);
-                                }
-                            });
+                            double re = nerr[it][0], im = nerr[it][1];
+                            if constexpr (TAB::E[S - 1] != 0.0) {
+                                re = fma(TAB::E[S - 1], Dn[it][0], re);
+                                im = fma(TAB::E[S - 1], Dn[it][1], im);
+                            }
                             ce[(a * (DE + 1) + d) * 2 * N + 2 * b] = re;
                             ce[(a * (DE + 1) + d) * 2 * N + 2 * b + 1] = im;
                         }
@@ -915,43 +949,34 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 // the new state's phase Phi_n + h sum_m b_m G_m
                 double ph[N];
                 stage_phase<TAB, N>(S, h, phn, G, ph);
-                lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
+                lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, li);
             }
         } else {
-            // ---- C_L = 1 + sum_{m<L} a_Lm D_m
+            // ---- C_L = (1 + sum_{m<L-1} a_Lm D_m) + a_{L,L-1} D_{L-1}
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
-                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
                 if (idx < ITEMS && d <= L) {
-                    const int a = e / N, b = e - (e / N) * N;
-                    double re = (d == 0 && a == b) ? 1.0 : 0.0, im = 0.0;
-                    static_for<0, NH>([&](auto Mc) {
-                        constexpr int m = decltype(Mc)::value;
-                        constexpr double cf = TAB::A[L][m];
-                        if constexpr (cf != 0.0) {
-                            re = fma(cf, Dh[it][m][0], re);
-                            im = fma(cf, Dh[it][m][1], im);
-                        }
-                    });
+                    double re = next[it][0], im = next[it][1];
                     constexpr double cl = TAB::A[L][L - 1];
                     if constexpr (cl != 0.0) {
                         re = fma(cl, Dn[it][0], re);
                         im = fma(cl, Dn[it][1], im);
                     }
-                    sC[wave][d * NC + 2 * e] = re;
-                    sC[wave][d * NC + 2 * e + 1] = im;
+                    sC[jt][d * NC + 2 * e] = re;
+                    sC[jt][d * NC + 2 * e + 1] = im;
                 }
             }
             // frame of stage L (its phase needs G_{L-1}), while the LDS writes land
             double zL[NUA][2], ph[N];
             stage_phase<TAB, N>(L, h, phn, G, ph);
-            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, lane);
-            rotation<N>(ph, zL, lane);
+            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, li);
+            rotation<N>(ph, zL, li, gbase);
             wave_sync();
 
             // ---- T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+   (item (d, a, b))
             auto qval = [&](int p, int a, int c, double& re, double& im) __attribute__((always_inline)) {
-                const double* Qp = &sQ[wave][p * NM];
+                const double* Qp = &sQ[jt][p * NM];
                 if (a == c) {
                     re = Qp[a];
                     im = 0.0;
@@ -965,24 +990,35 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             };
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
-                const int idx = lane + 64 * it, d = idx / NN, e = idx - d * NN;
+                const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
                 if (idx < ITEMS && d <= L) {
                     const int a = e / N, b = e - (e / N) * N;
-                    double re = 0.0, im = 0.0;
-#pragma unroll 2
-                    for (int dd = 0; dd <= L; ++dd)
+                    // one accumulator pair per dd (independent chains), added in order
+                    double rdd[L + 1], idd[L + 1];
+#pragma unroll
+                    for (int dd = 0; dd <= L; ++dd) {
+                        double re = 0.0, im = 0.0;
 #pragma unroll
                         for (int c = 0; c < N; ++c) {
                             double qr, qi;
                             qval(d + dd, a, c, qr, qi);
-                            const double cr = sC[wave][dd * NC + 2 * (b * N + c)];
-                            const double ci = sC[wave][dd * NC + 2 * (b * N + c) + 1];
+                            const double cr = sC[jt][dd * NC + 2 * (b * N + c)];
+                            const double ci = sC[jt][dd * NC + 2 * (b * N + c) + 1];
                             // Q_{d+dd}[a][c] conj(C_dd[b][c])
                             re = fma(qr, cr, fma(qi, ci, re));
                             im = fma(qi, cr, fma(-qr, ci, im));
                         }
-                    sT[wave][d * NC + 2 * e] = re;
-                    sT[wave][d * NC + 2 * e + 1] = im;
+                        rdd[dd] = re;
+                        idd[dd] = im;
+                    }
+                    double re = rdd[0], im = idd[0];
+#pragma unroll
+                    for (int dd = 1; dd <= L; ++dd) {
+                        re += rdd[dd];
+                        im += idd[dd];
+                    }
+                    sT[jt][d * NC + 2 * e] = re;
+                    sT[jt][d * NC + 2 * e + 1] = im;
                 }
             }
             wave_sync();
@@ -991,8 +1027,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             constexpr int NK = N + NU;
             constexpr int XITEMS = (L + 1) * NK;
 #pragma unroll
-            for (int it = 0; it < (XITEMS + 63) / 64; ++it) {
-                const int idx = lane + 64 * it;
+            for (int it = 0; it < (XITEMS + LT - 1) / LT; ++it) {
+                const int idx = li + LT * it;
                 if (idx < XITEMS) {
                     const int d = idx / NK, k = idx - d * NK;
                     int a = k, b = k;
@@ -1000,12 +1036,12 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                     double re = 0.0, im = 0.0;
 #pragma unroll
                     for (int c = 0; c < N; ++c) {
-                        const double xr = sC[wave][d * NC + 2 * (a * N + c)], xi = sC[wave][d * NC + 2 * (a * N + c) + 1];
-                        const double yr = sT[wave][d * NC + 2 * (c * N + b)], yi = sT[wave][d * NC + 2 * (c * N + b) + 1];
+                        const double xr = sC[jt][d * NC + 2 * (a * N + c)], xi = sC[jt][d * NC + 2 * (a * N + c) + 1];
+                        const double yr = sT[jt][d * NC + 2 * (c * N + b)], yi = sT[jt][d * NC + 2 * (c * N + b) + 1];
                         re = fma(xr, yr, fma(-xi, yi, re));
                         im = fma(xr, yi, fma(xi, yr, im));
                     }
-                    double* X = &sQ[wave][d * NM];
+                    double* X = &sQ[jt][d * NM];
                     if (k < N) {
                         X[k] = re;
                     } else {
@@ -1017,25 +1053,33 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             wave_sync();
 
             // ---- density sum of stage L, its lab-frame rotation and weights
-            if (lane == 0) {
-                double Sx[NM];
-                for (int v = 0; v < NM; ++v) {
-                    double s0 = sQ[wave][v];
-                    for (int d = 1; d <= L; ++d) s0 += sQ[wave][d * NM + v];
-                    Sx[v] = s0;
+            if (li < NM) {
+                const int v = li;
+                double Sx = sQ[jt][v];
+                for (int d = 1; d <= L; ++d) Sx += sQ[jt][d * NM + v];
+                // pair partner (re with im) of an off-diagonal value
+                const int vo = v < N ? v : (((v - N) & 1) ? v - 1 : v + 1);
+                double So = sQ[jt][vo];
+                for (int d = 1; d <= L; ++d) So += sQ[jt][d * NM + vo];
+                double Sv;
+                if (v < N) {
+                    Sv = 2.0 * Sx;
+                } else {
+                    const int u = (v - N) >> 1;
+                    double cs = zL[0][0], sn = zL[0][1];
+#pragma unroll
+                    for (int q = 1; q < NU; ++q)
+                        if (u == q) {
+                            cs = zL[q][0];
+                            sn = zL[q][1];
+                        }
+                    const double xr = ((v - N) & 1) ? So : Sx, xi = ((v - N) & 1) ? Sx : So;
+                    Sv = ((v - N) & 1) ? 2.0 * (cs * xi - sn * xr) : 2.0 * (cs * xr + sn * xi);
                 }
                 double f[4];
                 angle_weights<NJ>(rc, cL, wL, cph, sph, f);
-                double Sv[NM];
-                for (int a = 0; a < N; ++a) Sv[a] = 2.0 * Sx[a];
-                for (int u = 0; u < NU; ++u) {
-                    const double cs = zL[u][0], sn = zL[u][1];
-                    const double xr = Sx[N + 2 * u], xi = Sx[N + 2 * u + 1];
-                    Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
-                    Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
-                }
-                for (int m = 0; m < NJ; ++m)
-                    for (int v = 0; v < NM; ++v) swave[wave][m * NM + v] = f[m] * Sv[v];
+#pragma unroll
+                for (int m = 0; m < NJ; ++m) swave[jt][m * NM + v] = f[m] * Sv;
             }
         }
     }
@@ -1333,14 +1377,14 @@ __global__ void __launch_bounds__(64 * kPowerWaves) k_power_one(const RunConst r
 }
 
 template <int N, typename TAB, int NJ, int L, typename TF>
-__global__ void __launch_bounds__(64 * kTrajPerBlock) k_traj(const LaunchSet ls)
+__global__ void __launch_bounds__(64 * kTrajWaves) k_traj(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     traj_body<N, TAB, NJ, L, TF>(rc, blk);
 }
 template <int N, typename TAB, int NJ, int L, typename TF>
-__global__ void __launch_bounds__(64 * kTrajPerBlock) k_traj_one(const RunConst rc)
+__global__ void __launch_bounds__(64 * kTrajWaves) k_traj_one(const RunConst rc)
 {
     traj_body<N, TAB, NJ, L, TF>(rc, blockIdx.x);
 }
@@ -1545,7 +1589,7 @@ void pick_tab(int stage, StageKernels& K)
     } else if (stage <= S) {
         K.k = TrajTable<T, N, TAB, NJ>::fns[stage];
         K.k1 = TrajTable<T, N, TAB, NJ>::fns1[stage];
-        K.block = 64 * kTrajPerBlock;
+        K.block = 64 * kTrajWaves;
     } else if (stage == S + 1) {
         K.k = (KernFn)&k_final<TS, T, N, TAB, NJ>;
         K.k1 = (OneFn)&k_final_one<TS, T, N, TAB, NJ>;
