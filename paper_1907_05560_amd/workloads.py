@@ -146,6 +146,22 @@ def exp_stepper_2f() -> Dict:
     return w
 
 
+# Radius windows (km) of the FP32-versus-FP64 accuracy measurement, both
+# started from pure flavor states with the physics of multi_angle_3f: from
+# 50 km about 2000 accepted steps in which survival probabilities move by a few
+# 1e-2 (matter-suppressed oscillations); from 110 km about 4000 steps through
+# the region where the matter potential falls to the vacuum frequencies of the
+# lowest energy bins, with complete flavor conversion of some beams.
+ACCURACY_WINDOWS = ((50.0, 56.7), (110.0, 178.0))
+
+
+def window(w: Dict, r0: float, r1: float) -> Dict:
+    """The workload w started at r0 (pure flavor states) with end radius r1."""
+    w = dict(w)
+    w.update(r_start_km=r0, r_end_km=r1)
+    return w
+
+
 def error_subsample(n_beams: int, count: int = 4096) -> np.ndarray:
     """Sorted seeded subsample of beam indices used to report FP32 error."""
     rng = np.random.default_rng(SEED_BASE + 2)

@@ -5,7 +5,8 @@ by element.  Tolerances:
   * FP64 path: survival probabilities within 1e-10 (relative, with a 1e-13
     absolute floor for probabilities near zero) and amplitudes within 1e-10;
     identical accepted/rejected step counts and radius.
-  * FP32-amplitude path: probabilities within 1e-4 absolute.
+  * FP32-amplitude path: probabilities within 1e-4 absolute of the plain
+    (never renormalised) FP64 oracle.
 The windows are chosen before the onset of collective instability or in the
 non-chaotic 50 -> 250 km single-angle run, where rounding differences of
 order 1e-16 are amplified by less than ~1e3 (measured on the oracle).
@@ -150,28 +151,31 @@ def test_multi_angle_400x4000_fp64_window_at_full_size():
 
 @pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
 def test_fp32_amplitudes_on_the_single_angle_run(prec):
-    # FP32 amplitudes against the FP64 oracle over the whole 50 -> 250 km run.
-    # FP32 stage arithmetic puts a ~6e-8 relative error on every frequency, which
-    # accumulates over ~1e3 rad of vacuum phase in the lowest energy bins; with
-    # FP64 arithmetic only the storage rounding of the amplitudes remains.
-    # The FP32 forms renormalise every step; the reference is the same scheme in
-    # FP64 (oracle with renormalisation).  The unrenormalised FP64 run differs
-    # from it by RK4's own norm defect at this coarse step, reported alongside.
+    """FP32 amplitudes over the whole 50 -> 250 km fixed-step run, against the
+    plain FP64 oracle.  The FP32 forms renormalise every step; RK4 at this
+    coarse step (0.02 km) does not conserve the norm, so the plain FP64
+    solution and the renormalised scheme differ by themselves (the FP64 oracle
+    with renormalisation measures that, printed as a diagnostic).  The bound
+    against the plain oracle is 1e-4 plus that scheme difference; against the
+    renormalising oracle, which isolates FP32 rounding, it is 1e-4."""
     w = W.single_angle_2f()
     w.update(r_start_km=50.0, precision=prec)
     say(f"case: single-angle 2f RK4 50 -> 250 km precision {prec}")
     with nuosc.Run(w) as run:
         run.step(10000)
         p = run.probabilities()
-    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
-    ref.step_rk4(10000)
     plain = O.Run(dict(w, precision=W.FP64))
     plain.step_rk4(10000)
-    err = np.abs(p - ref.probabilities())
-    scheme = np.abs(plain.probabilities() - ref.probabilities()).max()
-    say(f"fp32 single-angle precision {prec}: max {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e} "
-        f"(renormalisation vs none in FP64: {scheme:.3e})")
-    assert err.max() <= 1e-4
+    renorm = O.Run(dict(w, precision=W.FP64, renormalize=1))
+    renorm.step_rk4(10000)
+    err = np.abs(p - plain.probabilities())
+    err_r = np.abs(p - renorm.probabilities())
+    scheme = np.abs(plain.probabilities() - renorm.probabilities())
+    say(f"fp32 single-angle precision {prec}: vs plain FP64 oracle max {err.max():.3e} "
+        f"rms {np.sqrt((err ** 2).mean()):.3e}; diagnostic vs renormalising oracle max {err_r.max():.3e}; "
+        f"renormalisation vs none in FP64: {scheme.max():.3e}")
+    assert err_r.max() <= 1e-4
+    assert np.all(err <= 1e-4 + scheme)
 
 
 @pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
@@ -183,19 +187,22 @@ def test_fp32_amplitudes_within_1e4_on_a_multi_angle_window(prec):
         run.step(300)
         p = run.probabilities()
         r = run.stats()["r_km"]
-    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
+    ref = O.Run(dict(w, precision=W.FP64))
     ref.evolve_dp54(r)
     assert ref.stats()["r_km"] == r
     err = np.abs(p - ref.probabilities())
-    say(f"fp32 window precision {prec}: max {err.max():.3e}")
+    diag = O.Run(dict(w, precision=W.FP64, renormalize=1))
+    diag.evolve_dp54(r)
+    say(f"fp32 window precision {prec}: vs plain FP64 oracle max {err.max():.3e}; "
+        f"diagnostic vs renormalising oracle max {np.abs(p - diag.probabilities()).max():.3e}")
     assert err.max() <= 1e-4
 
 
 @pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
 def test_fp32_amplitudes_400x4000_window_at_full_size(prec):
     """The benchmarked workload in its launch configuration (3.2M beams, FP32
-    amplitudes) against the FP64 oracle with the same renormalisation, over
-    the first attempts from the neutrinosphere, within 1e-4 in P."""
+    amplitudes) against the plain FP64 oracle over the first attempts from the
+    neutrinosphere, within 1e-4 in P."""
     w = W.multi_angle_3f_large(prec)
     say(f"case: 400x4000 FP32 amplitudes precision {prec}, 12 attempts")
     with nuosc.Run(w) as run:
@@ -203,11 +210,67 @@ def test_fp32_amplitudes_400x4000_window_at_full_size(prec):
         p = run.probabilities()
         s = run.stats()
     assert s["accepted"] >= 1
-    ref = O.Run(dict(w, precision=W.FP64, renormalize=1))
+    ref = O.Run(dict(w, precision=W.FP64))
     ref.evolve_dp54(s["r_km"])
     assert ref.stats()["r_km"] == s["r_km"]
     err = np.abs(p - ref.probabilities())
-    say(f"400x4000 precision {prec}: r = {s['r_km']:.9f} km, max {err.max():.3e} "
+    say(f"400x4000 precision {prec}: r = {s['r_km']:.9f} km, vs plain FP64 oracle max {err.max():.3e} "
+        f"rms {np.sqrt((err ** 2).mean()):.3e}")
+    assert err.max() <= 1e-4
+
+
+_WINDOW_GRID = (24, 240)
+_oracle_windows = {}
+
+
+def _oracle_window(r0, r1):
+    """Oracle (FP64, plain) of the window run on the pin grid, evolved to r1 once per window."""
+    if (r0, r1) not in _oracle_windows:
+        ref = O.Run(W.window(W.multi_angle_3f(*_WINDOW_GRID), r0, r1))
+        ref.evolve_dp54(r1)
+        _oracle_windows[(r0, r1)] = (ref.probabilities(), ref.stats())
+    return _oracle_windows[(r0, r1)]
+
+
+@pytest.mark.parametrize("r0,r1", W.ACCURACY_WINDOWS)
+def test_fp64_accuracy_window_matches_the_oracle(r0, r1):
+    """The FP64 form over each accuracy-measurement window on a 24 x 240 grid
+    (the reference of the full-grid FP32 measurement): thousands of accepted
+    steps with real flavor evolution, against the oracle."""
+    w = W.window(W.multi_angle_3f(*_WINDOW_GRID), r0, r1)
+    say(f"case: FP64 window {r0} -> {r1} km, 24x240")
+    pr, sr = _oracle_window(r0, r1)
+    with nuosc.Run(w) as run:
+        p0 = run.probabilities()
+        run.evolve(r1)
+        p = run.probabilities()
+        s = run.stats()
+    moved = np.abs(p - p0).max()
+    err = np.abs(p - pr)
+    say(f"window {r0}-{r1}: GPU accepted {s['accepted']} rejected {s['rejected']}, oracle {sr['accepted']} "
+        f"{sr['rejected']}; max |P - P(r0)| {moved:.3e}; max |dP| vs oracle {err.max():.3e}")
+    assert s["r_km"] == sr["r_km"] == r1
+    assert s["accepted"] >= 1000 and moved >= 1e-3
+    assert abs(s["accepted"] - sr["accepted"]) <= 1 and s["rejected"] == sr["rejected"]
+    np.testing.assert_allclose(p, pr, rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("prec", [W.FP32_AMP, W.FP32_AMP_FP64_MATH])
+@pytest.mark.parametrize("r0,r1", W.ACCURACY_WINDOWS)
+def test_fp32_accuracy_window_against_the_plain_fp64_oracle(r0, r1, prec):
+    """FP32 amplitudes (renormalised every step) over each accuracy window on a
+    24 x 240 grid against the plain (never renormalised) FP64 oracle: every
+    beam's survival probability within 1e-4 at the final radius."""
+    w = W.window(W.multi_angle_3f(*_WINDOW_GRID), r0, r1)
+    w["precision"] = prec
+    say(f"case: FP32 window {r0} -> {r1} km, 24x240, precision {prec}")
+    pr, _ = _oracle_window(r0, r1)
+    with nuosc.Run(w) as run:
+        run.evolve(r1)
+        p32 = run.probabilities()
+        assert run.stats()["r_km"] == r1
+    err = np.abs(p32 - pr)
+    say(f"window {r0}-{r1} precision {prec}: vs plain FP64 oracle max {err.max():.3e} "
         f"rms {np.sqrt((err ** 2).mean()):.3e}")
     assert err.max() <= 1e-4
 
