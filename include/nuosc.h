@@ -146,6 +146,30 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream,
                           void* device_workspace, size_t workspace_bytes,
                           nuosc_handle** out);
 
+/* Create a run in library-owned static device memory, allocating nothing:
+ * for callers that cannot allocate device memory (code that is being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc).
+ * The run behaves exactly as one made by nuosc_create (every other call of
+ * this header applies to it and gives bitwise the same results); only its
+ * device memory differs: all of it (state buffers, tables, reduction scratch,
+ * control block) lies in one array of NUOSC_STATIC_SCRATCH_BYTES per GPU
+ * that the library holds from its load until the process ends.  No device
+ * memory is allocated or freed, here or by nuosc_destroy.
+ *   p           run parameters; nuosc_footprint_bytes(p) must not exceed
+ *               NUOSC_STATIC_SCRATCH_BYTES (else NUOSC_E_INVALID, with the
+ *               two sizes in the message).
+ *   hip_stream  stream to order all work on, borrowed; NULL is the null
+ *               (legacy default) stream.  It must belong to the current
+ *               device, which the run lives on.
+ * The array is shared by every static run on its device and keeps the last
+ * run's contents (creation rewrites all of it that a run reads before
+ * writing): at most one static run per device is alive at a time, a second
+ * nuosc_create_static on the same device returns NUOSC_E_BUSY until the
+ * first is passed to nuosc_destroy.  Work on it from another process or
+ * library copy does not share the array.  Synchronises the stream. */
+#define NUOSC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+nuosc_status nuosc_create_static(const nuosc_params* p, void* hip_stream, nuosc_handle** out);
+
 /* Make n_attempts step attempts (accepted or rejected; RK4 steps are always
  * accepted).  Attempts after the run reached r_end do nothing.  *n_accepted
  * (nullable) receives the number accepted by this call.  Returns

@@ -135,4 +135,12 @@ constexpr int kExpLaunches = 3;
 constexpr int kExpTrajPerBlock = 4;  // trajectories (wavefronts) per workgroup of its beam kernels
 hipError_t launch_exp_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_t* ev = nullptr);
 
+// Library-owned device memory for runs made without allocation: one array of
+// kStaticScratchBytes per device, held until the process ends.  static_scratch
+// gives the current device's index and the array's address on it (looked up
+// once per device and cached).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int* device, void** addr);
+
 }  // namespace nuosc

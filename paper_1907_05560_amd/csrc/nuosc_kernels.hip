@@ -27,7 +27,7 @@
 //     weights of stage l (eq 3.14-3.15) into one partial per workgroup;
 //   k_traj<S>: completion of the last stage and the coefficient tables of the
 //     update polynomial (arithmetic type) and the error polynomial (FP64);
-//   k_final (beam pass): y_{n+1} by Horner's rule with the coefficients in
+//   k_final (beam pass): y_{n+1} as power sums in u with the coefficients in
 //     scalar registers, renormalisation of FP32 amplitudes, the error
 //     polynomial in FP64, per-workgroup error maxima;
 //   k_power (beam pass): global error maximum and the step controller (every
@@ -47,8 +47,13 @@
 
 #include <math.h>
 #include <array>
+#include <mutex>
 #include <type_traits>
 #include <utility>
+
+// Device memory of runs made without allocation (nuosc_create_static): every
+// device holds its own copy from module load until the process ends.
+static __device__ __align__(256) unsigned char scratch[nuosc::kStaticScratchBytes];
 
 namespace nuosc {
 namespace {
@@ -1777,6 +1782,30 @@ hipError_t launch_init_state(const RunList& runs, hipStream_t s)
         hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, ls);
         return hipGetLastError();
     });
+}
+
+// The device memory of runs made without allocation.  Host code never uses
+// the array's name as an address: the kernels get the address that
+// hipGetSymbolAddress reports for the current device.
+hipError_t static_scratch(int* device, void** addr)
+{
+    static std::mutex mu;
+    static void* base[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!base[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        base[dev] = p;
+    }
+    *device = dev;
+    *addr = base[dev];
+    return hipSuccess;
 }
 
 }  // namespace nuosc

@@ -13,6 +13,7 @@
 #include "nuosc_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cstdio>
 #include <cmath>
@@ -500,9 +501,20 @@ struct nuosc_handle {
     double t_beam[nuosc::kMaxLaunches + 1] = {};
     double t_fin[nuosc::kMaxLaunches + 1] = {};
     int64_t t_count[nuosc::kMaxLaunches + 1] = {};
+    // runs made by nuosc_create_static: the handle is a per-device slot and its
+    // device memory the library's static array of that device
+    bool is_static = false;
+    int device = -1;
 };
 
 namespace {
+
+static_assert(nuosc::kStaticScratchBytes == NUOSC_STATIC_SCRATCH_BYTES, "static scratch size");
+
+// One handle slot per device for the static runs, and whether it is taken.
+std::mutex g_static_mu;
+nuosc_handle g_static_handle[nuosc::kMaxDevices];
+bool g_static_busy[nuosc::kMaxDevices] = {};
 
 nuosc_status fail(nuosc_handle* h, nuosc_status st, const std::string& msg)
 {
@@ -640,6 +652,42 @@ nuosc_status nuosc_create(const nuosc_params* p, void* hip_stream, void* device_
     std::string err;
     nuosc_status st = init_run(h->run, p, base, (RunConst*)(base + L.rconst), 0, h->stream, err);
     if (st != NUOSC_OK) return bail(st, "initialisation: " + err);
+    *out = h;
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_create_static(const nuosc_params* p, void* hip_stream, nuosc_handle** out)
+{
+    if (!out) return fail(nullptr, NUOSC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (const char* why = validate(p)) return fail(nullptr, NUOSC_E_INVALID, why);
+    const Layout L = make_layout(*p);
+    if (L.total > NUOSC_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, NUOSC_E_INVALID,
+                    "the run needs " + std::to_string(L.total) + " bytes of device memory, more than the " +
+                        std::to_string(NUOSC_STATIC_SCRATCH_BYTES) + " bytes of the static scratch");
+    int dev = -1;
+    void* base = nullptr;
+    hipError_t e = nuosc::static_scratch(&dev, &base);
+    if (e != hipSuccess) return fail(nullptr, NUOSC_E_DEVICE, hip_msg(e, "address of the static scratch"));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+        return fail(nullptr, NUOSC_E_BUSY, "the static scratch of device " + std::to_string(dev) + " holds a live run");
+    nuosc_handle* h = &g_static_handle[dev];
+    *h = nuosc_handle();
+    h->is_static = true;
+    h->device = dev;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = base;
+    h->ws_bytes = NUOSC_STATIC_SCRATCH_BYTES;
+    std::string err;
+    nuosc_status st = init_run(h->run, p, (char*)base, (RunConst*)((char*)base + L.rconst), 0, h->stream, err);
+    if (st != NUOSC_OK) {
+        *h = nuosc_handle();
+        h->is_static = true;
+        return fail(nullptr, st, "initialisation: " + err);
+    }
+    g_static_busy[dev] = true;
     *out = h;
     return NUOSC_OK;
 }
@@ -1060,6 +1108,18 @@ const char* nuosc_last_error(const nuosc_handle* h) { return h ? h->err.c_str() 
 void nuosc_destroy(nuosc_handle* h)
 {
     if (!h) return;
+    if (h->is_static) {
+        // a slot of g_static_handle: wait for its work, then free the slot
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (h->device < 0) return;  // already released
+        (void)hipStreamSynchronize(h->stream);
+        for (auto& x : h->ev)
+            if (x) (void)hipEventDestroy(x);
+        g_static_busy[h->device] = false;
+        *h = nuosc_handle();
+        h->is_static = true;
+        return;
+    }
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (auto& x : h->ev)
         if (x) (void)hipEventDestroy(x);

@@ -23,9 +23,12 @@ E_INVALID, E_NOMEM, E_DEVICE, E_NONFINITE, E_STEP_UNDERFLOW, E_LIMIT, E_BUSY = -
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NONFINITE",
                 -5: "STEP_UNDERFLOW", -6: "LIMIT", -7: "BUSY"}
 
+# Size of the library's static device memory per GPU (NUOSC_STATIC_SCRATCH_BYTES).
+STATIC_SCRATCH_BYTES = 64 << 20
+
 # Every function the C ABI exports (include/nuosc.h).
 EXPORTS = (
-    "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_step",
+    "nuosc_default_params", "nuosc_footprint_bytes", "nuosc_create", "nuosc_create_static", "nuosc_step",
     "nuosc_enqueue_steps", "nuosc_enqueue_stage", "nuosc_num_stages", "nuosc_timing_enable",
     "nuosc_timing_read", "nuosc_evolve", "nuosc_moments", "nuosc_moments_azimuth", "nuosc_probabilities",
     "nuosc_get_state", "nuosc_set_state", "nuosc_energy_average", "nuosc_enqueue_energy_average",
@@ -124,6 +127,8 @@ def lib() -> C.CDLL:
     L.nuosc_footprint_bytes.restype = C.c_size_t
     L.nuosc_create.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
     L.nuosc_create.restype = C.c_int
+    L.nuosc_create_static.argtypes = [C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]
+    L.nuosc_create_static.restype = C.c_int
     L.nuosc_step.argtypes = [C.c_void_p, C.c_int64, _I64]
     L.nuosc_step.restype = C.c_int
     L.nuosc_enqueue_steps.argtypes = [C.c_void_p, C.c_int64]
@@ -232,16 +237,25 @@ class Run:
                ``torch.cuda.current_stream().cuda_stream``; None => own stream.
     workspace: an optional device tensor (torch, uint8) of at least
                ``footprint_bytes(w)`` bytes; kept alive by this object.
+    static:    place the run in the library's static device memory
+               (``nuosc_create_static``: no allocation; at most
+               ``STATIC_SCRATCH_BYTES`` and one such run per device at a
+               time; ``stream`` None is then the null stream).
     """
 
-    def __init__(self, w: Dict, stream: Optional[int] = None, workspace=None):
+    def __init__(self, w: Dict, stream: Optional[int] = None, workspace=None, static: bool = False):
         self.w = dict(w)
         self._p = params_from(self.w)
         self._ws = workspace
         h = C.c_void_p()
-        ws_ptr = workspace.data_ptr() if workspace is not None else None
-        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
-        st = lib().nuosc_create(C.byref(self._p), stream, ws_ptr, ws_bytes, C.byref(h))
+        if static:
+            if workspace is not None:
+                raise ValueError("a static run takes no workspace")
+            st = lib().nuosc_create_static(C.byref(self._p), stream, C.byref(h))
+        else:
+            ws_ptr = workspace.data_ptr() if workspace is not None else None
+            ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+            st = lib().nuosc_create(C.byref(self._p), stream, ws_ptr, ws_bytes, C.byref(h))
         if st != OK:
             raise NuoscError(st, lib().nuosc_last_error(None).decode())
         self.h = h

@@ -69,6 +69,19 @@ def test_invalid_parameters_are_rejected_without_a_device(bad):
     assert e.value.status == nuosc.E_INVALID
 
 
+def test_static_runs_beyond_the_static_scratch_are_rejected_without_a_device():
+    big = W.multi_angle_3f_large(W.FP32_AMP)
+    need = nuosc.footprint_bytes(big)
+    assert need > nuosc.STATIC_SCRATCH_BYTES
+    with pytest.raises(nuosc.NuoscError) as e:
+        nuosc.Run(big, static=True)
+    assert e.value.status == nuosc.E_INVALID
+    assert str(need) in str(e.value) and str(nuosc.STATIC_SCRATCH_BYTES) in str(e.value)
+    with pytest.raises(nuosc.NuoscError) as e:
+        nuosc.Run(dict(W.single_angle_2f(), n_flavors=4), static=True)
+    assert e.value.status == nuosc.E_INVALID
+
+
 @pytest.mark.parametrize("args", [
     (0, 3, W.FP32_AMP, W.RK_DP54, 1 << 20),      # no slots
     (2000, 3, W.FP32_AMP, W.RK_DP54, 1 << 30),   # too many slots
