@@ -42,6 +42,28 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Built with -fopenmp (the timing variant liboracle_omp.so), the loops marked
+ * OR_PARALLEL_FOR run their independent iterations (trajectories, beams or
+ * state entries, each written by exactly one iteration) on several threads.
+ * Every value is computed by the same code in the same order as in the serial
+ * build; the sums over trajectories and the error maximum stay sequential or
+ * exact, so both builds give bitwise the same results. */
+#ifdef _OPENMP
+#include <omp.h>
+#define OR_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OR_PARALLEL_FOR
+#endif
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------- complex */
 typedef struct { double re, im; } cplx;
 
@@ -390,6 +412,7 @@ static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cpl
     const int n = R->n, ne = R->ne, na = R->na;
     const double* phase = y + 2 * (int64_t)n * R->nb;
     geometry(R, r, R->c, R->w);
+    OR_PARALLEL_FOR
     for (int j = 0; j < na; ++j) {
         cplx acc[9];
         for (int i = 0; i < n * n; ++i) acc[i] = c_make(0, 0);
@@ -490,6 +513,7 @@ static void rhs(const or_run* R, double r, const double* y, double* dy)
     moments_at(R, r, y, J0, J1, J2, J3); /* also leaves c_j, w_j in R->c, R->w */
     const double lam = matter_potential(R, r);
 
+    OR_PARALLEL_FOR
     for (int j = 0; j < na; ++j) {
         const double cj = R->c[j];
         cplx C[9], Hm[9];
@@ -583,6 +607,7 @@ void or_collective(const or_run* R, double* out)
 static void renormalize(or_run* R)
 {
     const int n = R->n;
+    OR_PARALLEL_FOR
     for (int64_t b = 0; b < R->nb; ++b) {
         double s = 0.0;
         for (int a = 0; a < n; ++a) {
@@ -597,6 +622,7 @@ static void renormalize(or_run* R)
 /* Y = y + h * sum_{i < m} a[i] k[i]  (coefficient sum first, ascending i). */
 static void stage_state(const or_run* R, const double* y, double h, const double* a, int m, double* Y)
 {
+    OR_PARALLEL_FOR
     for (int64_t q = 0; q < R->ylen; ++q) {
         double acc = 0.0;
         for (int i = 0; i < m; ++i) acc += a[i] * R->k[i][q];
@@ -668,6 +694,10 @@ static int dp54_attempt(or_run* R)
     /* ytmp now holds stage 7 = the 5th-order solution (a_7j = b_j). */
     double err = 0.0;
     int finite = 1;
+    /* (the maximum is exact, so a parallel reduction of it changes nothing) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(max : err) reduction(& : finite)
+#endif
     for (int64_t q = 0; q < namp; ++q) {
         double acc = 0.0;
         for (int i = 0; i < 7; ++i) acc += DP_E[i] * R->k[i][q];

@@ -87,6 +87,7 @@ void or_probabilities(const or_run* R, double* p);      /* |psi_1|^2 per beam */
 void or_energy_average(const or_run* R, double* out);
 void or_stats(const or_run* R, int64_t* accepted, int64_t* rejected, double* r, double* dr);
 double or_last_error(const or_run* R);  /* scaled error of the last adaptive attempt */
+int    or_num_threads(void);              /* threads of the parallel loops: 1 unless built with OpenMP */
 
 /* Tables and pieces, exposed for the tests. */
 double or_fermi_integral(int k, double eta);

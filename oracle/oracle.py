@@ -18,16 +18,21 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nuosc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP: independent loop iterations on several
+# threads, bitwise the same results (for timing only)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-Wall"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain FP64, no contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain FP64, no contraction), serial and
+    OpenMP builds."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
 
 
@@ -69,17 +74,23 @@ class _Params(C.Structure):
 
 
 _lib: Optional[C.CDLL] = None
+_lib_omp: Optional[C.CDLL] = None
 
 _P = C.POINTER(C.c_double)
 _I64P = C.POINTER(C.c_int64)
 
 
-def lib() -> C.CDLL:
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(openmp: bool = False) -> C.CDLL:
+    """The serial oracle library, or its OpenMP build (threads from
+    OMP_NUM_THREADS as the process starts)."""
+    global _lib, _lib_omp
+    if (_lib_omp if openmp else _lib) is None:
+        path = _LIB_OMP if openmp else _LIB
+        if not os.path.exists(path):
             build(force=False)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
+        L.or_num_threads.restype = C.c_int
+        L.or_num_threads.argtypes = []
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.POINTER(_Params)]
         L.or_destroy.argtypes = [C.c_void_p]
@@ -124,8 +135,15 @@ def lib() -> C.CDLL:
         L.or_tables.argtypes = [C.c_void_p, _P, _P, _P, _P]
         L.or_vacuum_coefficient.restype = C.c_double
         L.or_dp54_tableau.argtypes = [_P, _P, _P]
-        _lib = L
-    return _lib
+        if openmp:
+            _lib_omp = L
+        else:
+            _lib = L
+    return _lib_omp if openmp else _lib
+
+
+def num_threads(openmp: bool = False) -> int:
+    return int(lib(openmp).or_num_threads())
 
 
 def _ptr(a: np.ndarray):
@@ -152,19 +170,20 @@ OK, DONE, NONFINITE, UNDERFLOW, INVALID = 0, 1, -4, -5, -1
 class Run:
     """One oracle run of a workload dict (see paper_1907_05560_amd.workloads)."""
 
-    def __init__(self, w: Dict):
+    def __init__(self, w: Dict, openmp: bool = False):
+        self._L = lib(openmp)
         self.w = dict(w)
         self._p = params_from(self.w)
-        self.h = lib().or_create(C.byref(self._p))
+        self.h = self._L.or_create(C.byref(self._p))
         if not self.h:
             raise ValueError("oracle rejected the parameters")
         self.n = int(self.w["n_flavors"])
-        self.nb = int(lib().or_num_beams(self.h))
-        self.na = int(lib().or_num_traj(self.h))
+        self.nb = int(self._L.or_num_beams(self.h))
+        self.na = int(self._L.or_num_traj(self.h))
 
     def close(self):
         if self.h:
-            lib().or_destroy(self.h)
+            self._L.or_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -177,7 +196,7 @@ class Run:
     def get_state(self):
         psi = np.empty((self.n, 2, self.nb))
         ph = np.empty((self.na, self.n))
-        lib().or_get_state(self.h, _ptr(psi), _ptr(ph))
+        self._L.or_get_state(self.h, _ptr(psi), _ptr(ph))
         return psi, ph
 
     def set_state(self, psi: np.ndarray, phase: Optional[np.ndarray], r: float):
@@ -187,7 +206,7 @@ class Run:
             phase = np.zeros((self.na, self.n))
         phase = np.ascontiguousarray(phase, dtype=np.float64)
         assert phase.shape == (self.na, self.n)
-        lib().or_set_state(self.h, _ptr(psi), _ptr(phase), float(r))
+        self._L.or_set_state(self.h, _ptr(psi), _ptr(phase), float(r))
 
     def psi_complex(self) -> np.ndarray:
         psi, _ = self.get_state()
@@ -198,7 +217,7 @@ class Run:
         n = self.n
         j0 = np.empty(n * n * 2)
         j1 = np.empty(n * n * 2)
-        lib().or_moments(self.h, _ptr(j0), _ptr(j1))
+        self._L.or_moments(self.h, _ptr(j0), _ptr(j1))
         return (j0[0::2] + 1j * j0[1::2]).reshape(n, n), (j1[0::2] + 1j * j1[1::2]).reshape(n, n)
 
     def moments_azimuth(self):
@@ -206,33 +225,33 @@ class Run:
         n = self.n
         j2 = np.empty(n * n * 2)
         j3 = np.empty(n * n * 2)
-        lib().or_moments_azimuth(self.h, _ptr(j2), _ptr(j3))
+        self._L.or_moments_azimuth(self.h, _ptr(j2), _ptr(j3))
         return (j2[0::2] + 1j * j2[1::2]).reshape(n, n), (j3[0::2] + 1j * j3[1::2]).reshape(n, n)
 
     def azimuth(self) -> np.ndarray:
         phi = np.empty(self.na)
-        lib().or_azimuth(self.h, _ptr(phi))
+        self._L.or_azimuth(self.h, _ptr(phi))
         return phi
 
     def collective(self) -> np.ndarray:
         n = self.n
         out = np.empty(self.na * n * n * 2)
-        lib().or_collective(self.h, _ptr(out))
+        self._L.or_collective(self.h, _ptr(out))
         return (out[0::2] + 1j * out[1::2]).reshape(self.na, n, n)
 
     def state_len(self) -> int:
-        return int(lib().or_state_len(self.h))
+        return int(self._L.or_state_len(self.h))
 
     def rhs(self, r: float, y: np.ndarray) -> np.ndarray:
         y = np.ascontiguousarray(y, dtype=np.float64)
         dy = np.empty_like(y)
-        lib().or_rhs(self.h, float(r), _ptr(y), _ptr(dy))
+        self._L.or_rhs(self.h, float(r), _ptr(y), _ptr(dy))
         return dy
 
     def geometry(self, r: float):
         c = np.empty(self.na)
         w = np.empty(self.na)
-        lib().or_geometry(self.h, float(r), _ptr(c), _ptr(w))
+        self._L.or_geometry(self.h, float(r), _ptr(c), _ptr(w))
         return c, w
 
     def tables(self):
@@ -241,25 +260,25 @@ class Run:
         g = np.empty(ne)
         gb = np.empty(ne)
         hv = np.empty(ne * n * n * 2)
-        lib().or_tables(self.h, _ptr(e), _ptr(g), _ptr(gb), _ptr(hv))
+        self._L.or_tables(self.h, _ptr(e), _ptr(g), _ptr(gb), _ptr(hv))
         return e, g, gb, (hv[0::2] + 1j * hv[1::2]).reshape(ne, n, n)
 
     # stepping ---------------------------------------------------------
     def step_rk4(self, nsteps: int) -> int:
-        return int(lib().or_step_rk4(self.h, int(nsteps)))
+        return int(self._L.or_step_rk4(self.h, int(nsteps)))
 
     def step_dp54(self, nattempts: int) -> int:
-        return int(lib().or_step_dp54(self.h, int(nattempts)))
+        return int(self._L.or_step_dp54(self.h, int(nattempts)))
 
     def evolve_dp54(self, r_target: float, max_attempts: int = 0) -> int:
-        return int(lib().or_evolve_dp54(self.h, float(r_target), int(max_attempts)))
+        return int(self._L.or_evolve_dp54(self.h, float(r_target), int(max_attempts)))
 
     def step_exp(self, nattempts: int) -> int:
         """Attempts of the paper's exponential stepper (lab frame only)."""
-        return int(lib().or_step_exp(self.h, int(nattempts)))
+        return int(self._L.or_step_exp(self.h, int(nattempts)))
 
     def evolve_exp(self, r_target: float, max_attempts: int = 0) -> int:
-        return int(lib().or_evolve_exp(self.h, float(r_target), int(max_attempts)))
+        return int(self._L.or_evolve_exp(self.h, float(r_target), int(max_attempts)))
 
     def step(self, nattempts: int) -> int:
         """Attempts (steps for RK4) of the run's own integrator."""
@@ -280,24 +299,24 @@ class Run:
 
     def probabilities(self) -> np.ndarray:
         p = np.empty(self.nb)
-        lib().or_probabilities(self.h, _ptr(p))
+        self._L.or_probabilities(self.h, _ptr(p))
         return p
 
     def energy_average(self) -> np.ndarray:
         out = np.empty((2, self.na, self.n))
-        lib().or_energy_average(self.h, _ptr(out))
+        self._L.or_energy_average(self.h, _ptr(out))
         return out
 
     def last_error(self) -> float:
         """Scaled error (err / rtol) of the last adaptive attempt."""
-        return float(lib().or_last_error(self.h))
+        return float(self._L.or_last_error(self.h))
 
     def stats(self):
         a = C.c_int64()
         rj = C.c_int64()
         r = C.c_double()
         dr = C.c_double()
-        lib().or_stats(self.h, C.byref(a), C.byref(rj), C.byref(r), C.byref(dr))
+        self._L.or_stats(self.h, C.byref(a), C.byref(rj), C.byref(r), C.byref(dr))
         return dict(accepted=a.value, rejected=rj.value, r_km=r.value, dr_km=dr.value)
 
 

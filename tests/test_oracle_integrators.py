@@ -162,3 +162,24 @@ def test_renormalised_scheme_rescales_a_linear_run():
     zr = renorm.psi_complex()
     assert np.abs((np.abs(zr) ** 2).sum(0) - 1).max() <= 1e-15
     np.testing.assert_allclose(zr, z / norm, rtol=0, atol=1e-14)
+
+
+def test_openmp_build_is_bitwise_the_serial_oracle():
+    """The OpenMP build of the oracle (used only to time the CPU baseline on
+    every core) computes every value by the same code in the same order: its
+    states, phases and step counts equal the serial build's bit for bit."""
+    w = W.multi_angle_3f(24, 37)
+    a, b = O.Run(w), O.Run(w, openmp=True)
+    assert O.num_threads(True) >= 1 and O.num_threads(False) == 1
+    a.step_dp54(25)
+    b.step_dp54(25)
+    assert a.stats() == b.stats()
+    pa, ha = a.get_state()
+    pb, hb = b.get_state()
+    np.testing.assert_array_equal(pa, pb)
+    np.testing.assert_array_equal(ha, hb)
+    r = dict(W.single_angle_2f(), r_start_km=50.0, renormalize=1)
+    a, b = O.Run(r), O.Run(r, openmp=True)
+    a.step_rk4(300)
+    b.step_rk4(300)
+    np.testing.assert_array_equal(a.get_state()[0], b.get_state()[0])
