@@ -4,13 +4,20 @@
 Workload: three-flavor multi-angle bulb model, 400 energy bins x 4000 emission
 angles x {nu, nubar} = 3.2M beams, Dormand-Prince 5(4) with rtol 1e-9, evolved
 from the neutrinosphere (r = 10 km) with synthetic Fermi-Dirac spectra; no
-dataset is involved.  One "step" is one attempted adaptive step: every stage
-kernel (moment reductions, fused Hamiltonian + RK stage), the step-error
-reduction and the on-device controller.  beam-steps = beams x accepted steps.
+dataset is involved.  One "step" is one attempted adaptive step: every launch
+of an attempt (the per-trajectory stage launches, the state update with the
+step error, the step control with the power moments of the new state).
+beam-steps = beams x accepted steps.
 
-The headline value is the FP32-amplitude form (FP32 amplitudes in HBM, FP32
-stage arithmetic, FP64 moments / error / phases).  The same grid is also run
-with FP32 amplitudes and FP64 arithmetic and in plain FP64, on the same GPU.
+The headline value is the FP32-amplitude form (FP32 amplitudes in HBM and FP32
+update arithmetic; moments, step error and phases in FP64).  The same grid is
+also run with FP32 amplitudes and FP64 arithmetic and in plain FP64.  The line
+also carries: the FP32 forms' probabilities against the FP64 form over two
+radius windows with real flavor evolution, the two small workloads (the
+two-flavor single-angle fixed-step run and the 200 x 1000 FP64 adaptive run)
+with their oracle times, the extended bulb model, the paper's own exponential
+stepper, the 64-run batched workload (graph replays) and the served Poisson
+mix, and the oracle timed on the host's cores.
 
 Prints one JSON line.  --gpus above 1 is not supported: the path runs on one
 GPU (the angle-sharded multi-GPU design is described, not built).
@@ -21,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -29,21 +37,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "beam-steps/s at 1 GPU (FP32-amp vs FP64) @1e-4 prob error; p50/p99 latency"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-# Vector ALU peaks (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz = 78.6
-# TFLOP/s for FP64 and for unpacked FP32; packed FP32 doubles the FP32 figure).
-PEAK_FP32_TFS = 157.3
-PEAK_FP64_TFS = 78.6
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz =
+# 78.6 TFLOP/s for FP64 and for unpacked FP32.  The build disables packed FP32
+# arithmetic, so 78.6 is the reachable peak of both precisions here.
+PEAK_VALU_TFS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+FORM_NAMES = {"fp32": 1, "fp32math64": 2, "fp64": 0}
+DTYPE = {1: "f32", 2: "f32-storage/f64-math", 0: "f64"}
+
+# Dormand-Prince 5(4): stages, update and error polynomial degrees in u = +-1/E
+# (the update 1 + sum_m b_m D_m(u) reaches degree 6, the error sum_m e_m D_m(u)
+# degree 7), and the power moments Q_0 .. Q_12 the stage densities need.
+DP_S, DP_DN, DP_DE, DP_NQ = 7, 6, 7, 13
+
+
+def kernel_names(prec: int, n: int = 3, nj: int = 2):
+    """Short names of the launches of one attempt (single-run instantiations,
+    as profile_summary.kernel_key writes them), in launch order."""
+    ts = "double" if prec == 0 else "float"
+    t = "float" if prec == 1 else "double"
+    tf = "float" if prec == 1 else "double"
+    # (the stage launches before the last hold no table of the arithmetic type)
+    names = [f"k_traj<{n},DP54,{nj},{L},{tf if L == DP_S else 'double'}>" for L in range(1, DP_S + 1)]
+    names.append(f"k_final<{ts},{t},{n},DP54,{nj}>")
+    names.append(f"k_power<{ts},{n},DP54,{nj},false>")
+    return names
 
 
 def run_form(nuosc, W, torch, precision, steps, warmup):
     """Time `steps` attempts of one precision form on the run's own stream.
 
     Two passes over the same number of attempts: the first is timed as a
-    whole (HIP events around it) and gives the throughput; in the second the
-    library records events around every beam kernel and control kernel,
-    which gives the per-kernel durations (each including the few
-    microseconds an event record adds on the stream)."""
+    whole (HIP events on the run's stream around it) and gives the
+    throughput; in the second the library records HIP events around every
+    launch on the same stream, which gives each launch's mean duration (each
+    including the few microseconds an event record adds)."""
     w = W.multi_angle_3f_large(precision)
     run = nuosc.Run.with_torch(w)
     stream = run.torch_stream
@@ -60,19 +88,20 @@ def run_form(nuosc, W, torch, precision, steps, warmup):
     s1 = run.stats()
     run.timing_enable(True)
     run.enqueue_steps(steps)
-    beam, fin, cnt = run.timing_read()
+    beam, _, cnt = run.timing_read()
     run.timing_enable(False)
     accepted = s1["accepted"] - s0["accepted"]
     n = [max(int(c), 1) for c in cnt]
     out = dict(
         precision=precision,
         beams=run.nb,
+        traj=run.na,
         attempts=steps,
         accepted=accepted,
         ms_per_step=total_ms / steps,
         value=run.nb * accepted / (total_ms / 1e3),
-        stage_ms=[beam[st] / n[st] for st in range(1, S + 1)],
-        fin_ms=[fin[st] / n[st] for st in range(1, S + 1)],
+        launch_us=[1e3 * beam[st] / n[st] for st in range(1, S + 1)],
+        names=kernel_names(precision),
         r_km=s1["r_km"],
         amp_bytes=4 if precision != W.FP64 else 8,
         n=run.n,
@@ -80,96 +109,79 @@ def run_form(nuosc, W, torch, precision, steps, warmup):
     return run, out
 
 
-# Nonzero counts of the tableau rows (stage inputs 1..S-1, then the solution
-# weights) and of the error weights, for the flop model below.
-_NNZ = {
-    "rk4": dict(S=4, fsal=False, rows=[1, 1, 1], sol=4, err=0),
-    "dp54": dict(S=7, fsal=True, rows=[1, 2, 3, 4, 5, 5], sol=5, err=6),
-}
+def beam_model(form, idx):
+    """Algorithmic HBM bytes and vector flops of launch `idx` (0-based) of an
+    attempt, for the whole grid.
+
+    Bytes follow the method's floor (one read of the state per derivative
+    evaluation, one write of the new state): the state update reads psi_n and
+    writes psi_{n+1}; the power-moment launch reads psi_{n+1} (the first
+    evaluation of the next step); the per-trajectory launches touch no beam
+    data.  Flops count one FMA as 2 (powers of u and the renormalisation's
+    multiplies as 1):
+      state update: per row of the n x n complex update matrix, 2n reals x
+        (DN + 1) power-sum FMAs, then n complex multiply-adds (4 FMAs each);
+        the same with degree DE in FP64 for the error; FP32 renormalisation;
+      power moments: the density entries (n diagonal, n(n-1)/2 complex
+        off-diagonal) and NQ x n^2 FMAs for Q_0 .. Q_{NQ-1}."""
+    n, nb = form["n"], form["beams"]
+    state = 2 * n * form["amp_bytes"] * nb
+    S = DP_S
+    if idx < S:
+        return 0, 0
+    if idx == S:
+        upd = 2 * (2 * n * n * (DP_DN + 1) + 4 * n * n) + (DP_DN - 1)
+        err = 2 * (2 * n * n * (DP_DE + 1) + 4 * n * n) + (DP_DE - 1) + 2 * n
+        ren = (2 * 2 * n + 2 * n + 2) if form["precision"] != 0 else 0
+        return 2 * state, (upd + err + ren) * nb
+    nm = n * n
+    dens = 2 * n + 2 * n + (n * (n - 1) // 2) * 2 * 2
+    return state, (dens + 2 * DP_NQ * nm + DP_NQ) * nb
 
 
-def stage_flops(n: int, integrator: str, stage: int, fp32_storage: bool) -> int:
-    """Flops per beam of stage launch `stage` (FMA = 2) in the recompute design.
+def traffic_of(name):
+    """Copy-calibrated rocprofv3 FETCH + WRITE bytes per launch of a kernel, or
+    None when no counters were taken for the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        from paper_1907_05560_amd.profile_summary import kernel_source_hash
 
-    One derivative k = -i (A + B/E) y: n^2 FMAs to form the Hermitian matrix,
-    2n multiplies for its diagonal and n(n-1) complex multiply-adds (4 FMAs) for
-    the off-diagonals.  Launch I evaluates k_0..k_{I-1}, forms the inputs of
-    stages 1..I (2n reals x (nonzeros + 1) FMAs each), the moments of its output
-    state (n diagonal terms of 5 flops, n(n-1)/2 off-diagonal pairs of 10), and
-    the FP32 renormalisation of the new state, and the embedded error.  For a
-    first-same-as-last pair the error is split: the launch that forms y_{n+1}
-    also sums e_i k_i over i < S-1, and the final launch evaluates only
-    k_{S-1} = f(y_{n+1}) and adds h e_{S-1} k_{S-1}."""
-    t = _NNZ[integrator]
-    S = t["S"]
-    f_eval = 2 * n * n + 2 * n + 8 * n * (n - 1)
-    split = t["fsal"] and t["err"] > 0
-    if split and stage == S:
-        return f_eval + 2 * n * 3
-    flops = stage * f_eval
-    last_row = min(stage, S - 1)
-    for l in range(1, last_row + 1):
-        nnz = t["rows"][l - 1]
-        flops += 2 * n * (nnz + 1) * 2
-    final = stage == S
-    if final and not t["fsal"]:
-        flops += 2 * n * (t["sol"] + 1) * 2
-    if not final or not t["fsal"]:
-        flops += 5 * n + 10 * n * (n - 1) // 2
-    if final and t["err"] and not split:
-        flops += 2 * n * (t["err"] * 2 + 1)
-    if split and stage == S - 1:
-        flops += 2 * n * (2 * (t["err"] - 1) - 1)
-    if fp32_storage and stage == (S - 1 if t["fsal"] else S):
-        flops += 6 * n + 2
-    return flops
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return t.get("bytes_per_launch", {}).get(name)
+    except (OSError, ValueError):
+        return None
 
 
 def roofline(form):
-    """Roofline of the dominant kernel (the slowest stage launch).
+    """Roofline of the dominant kernel (the launch with the longest mean
+    duration; for the 3.2M-beam grid the state update, k_final).
 
-    HBM view: algorithmic bytes per launch (every beam launch reads y_n once,
-    N_b x 2n amplitude reals; the launch that forms y_{n+1} -- the last one,
-    or the one before it for a first-same-as-last pair -- also writes it; in
-    the pair, that launch also writes the partial error sum, N_b x 2n reals of
-    the arithmetic type, and the final launch reads y_{n+1} and that sum) /
-    the launch's mean duration.  ALU view: stage_flops x N_b / duration against the vector
-    peak of the arithmetic type.  The reported bound is the view with the
-    larger fraction of its peak; the other view is kept alongside."""
-    S = len(form["stage_ms"])
-    dom = max(range(S), key=lambda i: form["stage_ms"][i])
-    stage = dom + 1
-    state_bytes = 2 * form["n"] * form["amp_bytes"] * form["beams"]
-    write_stage = S - 1 if S == 7 else S
-    alg_bytes = state_bytes * (2 if stage == write_stage else 1)
-    if S == 7 and stage >= S - 1:
-        alg_bytes += 2 * form["n"] * (4 if form["precision"] == 1 else 8) * form["beams"]
-    dur_s = form["stage_ms"][dom] / 1e3
+    HBM view: algorithmic bytes per launch (beam_model) / the launch's mean
+    duration, against 8 TB/s.  ALU view: the launch's vector flops / duration
+    against the unpacked vector peak.  The bound is the view with the larger
+    fraction of its peak; both views are kept.  traffic: the rocprofv3
+    FETCH + WRITE bytes of that kernel (copy-calibrated), null without
+    counters for the current kernel source; waste = traffic / algorithmic
+    bytes."""
+    dom = max(range(len(form["launch_us"])), key=lambda i: form["launch_us"][i])
+    name = form["names"][dom]
+    alg_bytes, flops = beam_model(form, dom)
+    dur_s = form["launch_us"][dom] / 1e6
     gbs = alg_bytes / dur_s / 1e9
-    fp32_math = form["precision"] == 1
-    flops = stage_flops(form["n"], "dp54" if S == 7 else "rk4", stage, form["amp_bytes"] == 4) * form["beams"]
     tfs = flops / dur_s / 1e12
-    peak_alu = PEAK_FP32_TFS if fp32_math else PEAK_FP64_TFS
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            from paper_1907_05560_amd.profile_summary import kernel_source_hash
-
-            t = json.load(open(TRAFFIC_FILE))
-            key = f"stage{stage}_prec{form['precision']}"
-            if t.get("kernel_source_sha256_16") == kernel_source_hash() and key in t.get("bytes_per_launch", {}):
-                traffic = t["bytes_per_launch"][key]
-        except (OSError, ValueError):
-            traffic = None
     hbm = {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
            "alg_bytes_per_launch": alg_bytes}
-    alu = {"achieved": round(tfs, 2), "peak": peak_alu, "unit": "TFLOP/s", "frac": round(tfs / peak_alu, 4),
-           "alg_flops_per_launch": flops, "frac_of_unpacked_peak": round(tfs / PEAK_FP64_TFS, 4)}
+    alu = {"achieved": round(tfs, 2), "peak": PEAK_VALU_TFS, "unit": "TFLOP/s",
+           "frac": round(tfs / PEAK_VALU_TFS, 4), "flops_per_launch": flops}
+    traffic = traffic_of(name)
     use_alu = alu["frac"] > hbm["frac"]
     head = alu if use_alu else hbm
     out = {
         "bound": "alu" if use_alu else "hbm",
-        "kernel": f"k_stage stage {stage}/{S}",
+        "kernel": name,
         "achieved": head["achieved"],
         "peak": head["peak"],
         "unit": head["unit"],
@@ -179,51 +191,58 @@ def roofline(form):
         "hbm": hbm,
         "alu": alu,
     }
-    if traffic is not None:
+    if traffic is not None and alg_bytes:
+        out["waste"] = round(traffic / alg_bytes, 3)
         out["traffic_gbs"] = round(traffic / dur_s / 1e9, 1)
     return out
 
 
 def step_roofline(form):
-    """Whole-step figures (every launch of an attempt): beam-steps/s against
-    (1) the method's floor, one read of y_n per derivative evaluation plus one
-    write of y_{n+1}: B_alg = (evaluations + 1) x S bytes per beam-step
-    (Dormand-Prince first-same-as-last: 7 S; classic RK4: 5 S), and (2) the
-    design's bytes per beam-step, the copy-calibrated rocprofv3 FETCH + WRITE
-    bytes of all its stage launches (null without counters for this kernel
-    source); and the achieved vector-ALU rate of the stage_flops model."""
-    S = len(form["stage_ms"])
+    """Whole-step figures: beam-steps/s against (1) the method's floor, one
+    read of y_n per derivative evaluation plus one write of y_{n+1}:
+    B_alg = 7 S bytes per beam-step (Dormand-Prince, first-same-as-last; S =
+    2n amplitude reals), (2) the design's bytes per beam-step, the copy-
+    calibrated rocprofv3 FETCH + WRITE bytes of every launch of an attempt
+    (null without counters for the current kernel source), and (3) the
+    vector flops per beam-step of the beam launches against the unpacked
+    vector peak."""
     state = 2 * form["n"] * form["amp_bytes"]
-    b_alg = (S if S == 7 else S + 1) * state
+    b_alg = DP_S * state
     v = form["value"]
     out = {"alg_bytes_per_beam_step": b_alg, "alg_ceiling": round(PEAK_HBM_GBS * 1e9 / b_alg),
            "frac_alg": round(v * b_alg / (PEAK_HBM_GBS * 1e9), 4), "design_bytes_per_beam_step": None,
            "frac_design": None}
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            from paper_1907_05560_amd.profile_summary import kernel_source_hash
-
-            t = json.load(open(TRAFFIC_FILE))
-            keys = [f"stage{i}_prec{form['precision']}" for i in range(1, S + 1)]
-            bpl = t.get("bytes_per_launch", {})
-            if t.get("kernel_source_sha256_16") == kernel_source_hash() and all(k in bpl for k in keys):
-                d = sum(bpl[k] for k in keys) / form["beams"]
-                out["design_bytes_per_beam_step"] = round(d, 1)
-                out["frac_design"] = round(v * d / (PEAK_HBM_GBS * 1e9), 4)
-        except (OSError, ValueError):
-            pass
-    flops = sum(stage_flops(form["n"], "dp54" if S == 7 else "rk4", st, form["amp_bytes"] == 4)
-                for st in range(1, S + 1))
+    tr = [traffic_of(nm) for nm in form["names"]]
+    if all(x is not None for x in tr):
+        d = sum(tr) / form["beams"]
+        out["design_bytes_per_beam_step"] = round(d, 1)
+        out["frac_design"] = round(v * d / (PEAK_HBM_GBS * 1e9), 4)
+    flops = sum(beam_model(form, i)[1] for i in range(len(form["names"]))) / form["beams"]
     tfs = v * flops / 1e12
-    peak = PEAK_FP32_TFS if form["precision"] == 1 else PEAK_FP64_TFS
-    out.update({"flops_per_beam_step": flops, "valu_tflops": round(tfs, 2), "valu_peak": peak,
-                "valu_frac": round(tfs / peak, 4)})
+    out.update({"flops_per_beam_step": round(flops), "valu_tflops": round(tfs, 2), "valu_peak": PEAK_VALU_TFS,
+                "valu_frac": round(tfs / PEAK_VALU_TFS, 4)})
     return out
+
+
+def host_info():
+    """Cores this process may use and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cores_allowed": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def cpu_baseline(W, attempts):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of the
-    same workload: `attempts` adaptive step attempts of the full grid from 10 km.
+    same workload: `attempts` adaptive step attempts of the full grid from
+    10 km; and the same sample with its OpenMP build (bitwise the same
+    results) on the threads OMP_NUM_THREADS allows.
 
     Every attempt costs the oracle the same (all stages of every beam).  A fresh
     run rejects its first tries while the step size settles, whereas every timed
@@ -233,19 +252,143 @@ def cpu_baseline(W, attempts):
     from oracle import oracle as O
 
     w = W.multi_angle_3f_large(W.FP64)
-    ref = O.Run(w)
-    t = time.perf_counter()
-    ref.step_dp54(attempts)
-    dt = time.perf_counter() - t
-    acc = ref.stats()["accepted"]
-    return {
-        "value": ref.nb * attempts / dt,
-        "unit": "beam-steps/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{attempts} step attempts ({acc} accepted) of the 400x4000x2 grid from r = 10 km, "
-                  f"FP64, single thread, {dt:.1f} s; rate per attempt",
+    out = {}
+    for omp in (False, True):
+        ref = O.Run(w, openmp=omp)
+        t = time.perf_counter()
+        ref.step_dp54(attempts)
+        dt = time.perf_counter() - t
+        acc = ref.stats()["accepted"]
+        threads = O.num_threads(omp)
+        out[omp] = {
+            "value": ref.nb * attempts / dt,
+            "unit": "beam-steps/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"{attempts} step attempts ({acc} accepted) of the 400x4000x2 grid from r = 10 km, "
+                      f"FP64, {'OpenMP build, ' if omp else ''}{threads} thread(s), {dt:.1f} s; rate per attempt",
+        }
+        ref.close()
+    line = dict(out[False])
+    line["openmp"] = out[True]
+    return line
+
+
+def timed_runs(nuosc, torch, w, attempts, reps):
+    """Median wall time (s) of `attempts` attempts of a fresh run of `w` (run
+    creation and its first moment launch outside the timed region), over
+    `reps` runs after one warm-up run; and the last run's statistics."""
+    ts = []
+    stats = None
+    for i in range(reps + 1):
+        with nuosc.Run(w) as run:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            run.step(attempts)
+            dt = time.perf_counter() - t
+            stats = run.stats()
+        if i:
+            ts.append(dt)
+    return statistics.median(ts), ts, stats
+
+
+def small_configs(nuosc, W, torch, c1_attempts, reps=3):
+    """The two small workloads, GPU against the oracle (serial and OpenMP
+    builds), each GPU figure the median of `reps` runs after one warm-up:
+
+    * two-flavor single-angle run, 200 beams, 1e4 fixed RK4 steps from 50 km
+      to 250 km (started at 50 km, where the explicit step is stable in the
+      co-rotating frame), FP64: the whole run;
+    * three-flavor multi-angle 200 x 1000 x 2 = 400k beams, Dormand-Prince
+      rtol 1e-9 from 10 km, FP64: the first `c1_attempts` attempts (the full
+      10 -> 250 km run takes ~1e10 attempts)."""
+    from oracle import oracle as O
+
+    out = {}
+    w0 = dict(W.single_angle_2f(), r_start_km=50.0)
+    t0, ts0, st0 = timed_runs(nuosc, torch, w0, w0["n_fixed_steps"], reps)
+    nb0 = W.n_beams(w0)
+    oracle0 = {}
+    for omp in (False, True):
+        ref = O.Run(w0, openmp=omp)
+        t = time.perf_counter()
+        ref.step_rk4(w0["n_fixed_steps"])
+        dt = time.perf_counter() - t
+        oracle0["openmp" if omp else "serial"] = {"seconds": round(dt, 3), "threads": O.num_threads(omp),
+                                                 "value": nb0 * w0["n_fixed_steps"] / dt}
+    out["single_angle_2f_rk4"] = {
+        "workload": "2-flavor single-angle bulb model, 100 energies x 2 species = 200 beams, RK4 1e4 fixed "
+                    "steps 50 -> 250 km, FP64",
+        "beams": nb0, "steps": w0["n_fixed_steps"], "seconds": round(t0, 4), "repetitions_s": [round(x, 4) for x in ts0],
+        "value": nb0 * st0["accepted"] / t0, "unit": "beam-steps/s", "oracle": oracle0,
+        "note": "launch-latency bound: 6 launches per step of 200 beams",
     }
+    w1 = W.multi_angle_3f(200, 1000)
+    t1, ts1, s = timed_runs(nuosc, torch, w1, c1_attempts, reps)
+    nb1 = W.n_beams(w1)
+    oracle1 = {}
+    for omp in (False, True):
+        ref = O.Run(w1, openmp=omp)
+        t = time.perf_counter()
+        ref.step_dp54(c1_attempts)
+        dt = time.perf_counter() - t
+        so = ref.stats()
+        oracle1["openmp" if omp else "serial"] = {"seconds": round(dt, 3), "threads": O.num_threads(omp),
+                                                 "accepted": so["accepted"], "value": nb1 * so["accepted"] / dt}
+        ref.close()
+    out["multi_angle_200x1000_fp64"] = {
+        "workload": f"3-flavor multi-angle bulb model, 200 energies x 1000 angles x 2 species = 400k beams, "
+                    f"Dormand-Prince rtol 1e-9, FP64, the first {c1_attempts} attempts from r = 10 km",
+        "beams": nb1, "attempts": c1_attempts, "accepted": s["accepted"], "rejected": s["rejected"],
+        "r_km": s["r_km"], "seconds": round(t1, 5), "repetitions_s": [round(x, 5) for x in ts1],
+        "value": nb1 * s["accepted"] / t1, "unit": "beam-steps/s", "oracle": oracle1,
+        "note": "the 19 MB state arrays fit in the 256 MB MALL; launch-latency bound at this size",
+    }
+    return out
+
+
+def accuracy(nuosc, W, forms):
+    """The FP32 forms against the FP64 form on the full 400 x 4000 x 2 grid over
+    the two radius windows (the same windows on which the FP64 form is
+    pinned to the oracle on a 24 x 240 grid): every run starts from the
+    pure-flavor state at r0 and evolves to r1 adaptively.  Max and RMS |dP|
+    over all beams and over the seeded 4096-beam subsample, at r1."""
+    import numpy as np
+
+    out = []
+    for r0, r1 in W.ACCURACY_WINDOWS:
+        base = W.window(W.multi_angle_3f_large(W.FP64), r0, r1)
+        with nuosc.Run(base) as ref:
+            p0 = ref.probabilities()
+            t = time.perf_counter()
+            ref.evolve(r1)
+            t64 = time.perf_counter() - t
+            p64 = ref.probabilities()
+            s64 = ref.stats()
+        idx = W.error_subsample(p64.size)
+        entry = {"window_km": [r0, r1], "r_km": s64["r_km"], "fp64_accepted": s64["accepted"],
+                 "fp64_rejected": s64["rejected"], "fp64_seconds": round(t64, 3),
+                 "max_dP_over_window": float(np.abs(p64 - p0).max()),
+                 "reference": "GPU FP64 form on the same grid (pinned to the oracle on a 24x240 grid over the "
+                              "same window)", "forms": {}}
+        for name in forms:
+            prec = FORM_NAMES[name]
+            if prec == W.FP64:
+                continue
+            with nuosc.Run(dict(base, precision=prec)) as run:
+                t = time.perf_counter()
+                run.evolve(r1)
+                dt = time.perf_counter() - t
+                p = run.probabilities()
+                s = run.stats()
+            d = p - p64
+            entry["forms"][name] = {
+                "max": float(np.abs(d).max()), "rms": float(np.sqrt((d ** 2).mean())),
+                "subsample_max": float(np.abs(d[idx]).max()), "subsample_rms": float(np.sqrt((d[idx] ** 2).mean())),
+                "accepted": s["accepted"], "rejected": s["rejected"], "r_km": s["r_km"], "seconds": round(dt, 3),
+                "within_1e-4": bool(np.abs(d).max() <= 1e-4)}
+        out.append(entry)
+    return out
 
 
 def energy_average_timing(run, torch, amp_bytes, reps=50):
@@ -299,6 +442,7 @@ def extended(nuosc, W, torch, precision, attempts, warmup=5):
         run.close()
 
 
+SERVING_WINDOW_KM = 3e-5
 EXP_VALU_FILE = os.path.join(ROOT, "profiles", "exp_valu.json")
 # wavefront-instruction issue peak of the vector ALUs: 256 CUs x 4 SIMDs, one
 # 64-lane FP64 (or unpacked FP32) instruction per SIMD every 4 cycles at 2.4 GHz
@@ -366,47 +510,49 @@ def exp_stepper(nuosc, W, torch, attempts, warmup=10):
 
 def batched(nuosc, W, torch, attempts):
     """The 64-run batched workload: every run admitted into one batch and
-    advanced together; aggregate beam-steps/s over `attempts` attempts."""
+    advanced together; the timed batch steps replay the captured HIP graph."""
     from paper_1907_05560_amd import serving
 
-    return serving.run_batched(W.batched_runs(64), attempts, torch=torch)
-
-
-def served(nuosc, W, seconds, precision):
-    """The serving workload for `seconds` of Poisson arrivals: latency
-    percentiles, throughput, and a bitwise check of two completed requests
-    against the same runs alone."""
-    import numpy as np
-
-    from paper_1907_05560_amd import serving
-
-    reqs = W.serving_requests(duration_s=seconds, precision=precision)
-    out = serving.serve(reqs, max_slots=64, keep=2, wall_limit_s=max(120.0, 4 * seconds))
-    same = True
-    for i, p in out.pop("kept"):
-        w = dict(reqs[i])
-        with nuosc.Run(w) as run:
-            run.evolve(w["r_end_km"])
-            same = same and bool(np.array_equal(run.probabilities(), p))
-    out["mix_equals_alone"] = same
+    out = serving.run_batched(W.batched_runs(64), attempts, torch=torch)
+    out["workload"] = ("64 seeded 3-flavor multi-angle runs (N_E in 50..400, N_A log-uniform in 100..4000), "
+                       "FP32 amplitudes, Dormand-Prince rtol 1e-9 from r = 10 km")
     return out
 
 
-def subsample_error(nuosc, W, run32, run64):
-    """FP32-form error against the FP64 form on the seeded 4096-beam subsample,
-    at a common radius (the run that is behind evolves to the other's radius)."""
+def served(nuosc, W, seconds, precision, check_fraction):
+    """The served Poisson mix: 20 requests/s for `seconds`, 10% of them on the
+    400 x 4000 grid, each evolved from 10 km over a 3e-5 km window (offered
+    load above one GPU's capacity, so the queue grows); the loop stops when
+    the arrival period ends.  Latencies include queue wait.  The window is
+    3e-5 km: ~2e9 beam-steps per request on average, ~3e10 beam-steps/s
+    offered at 20 requests/s.  Then a seeded
+    `check_fraction` of the completed requests is run alone (nuosc_create)
+    and compared bitwise with its served result."""
     import numpy as np
 
-    r32, r64 = run32.stats()["r_km"], run64.stats()["r_km"]
-    r = max(r32, r64)
-    if r32 < r:
-        run32.evolve(r)
-    if r64 < r:
-        run64.evolve(r)
-    idx = W.error_subsample(run32.nb)
-    d = run32.probabilities()[idx] - run64.probabilities()[idx]
-    return {"max": float(np.abs(d).max()), "rms": float(np.sqrt((d ** 2).mean())),
-            "subsample": int(idx.size), "r_km": r}
+    from paper_1907_05560_amd import serving
+
+    reqs = W.serving_requests(duration_s=seconds, precision=precision, window_km=SERVING_WINDOW_KM)
+    out = serving.serve(reqs, max_slots=64, duration_s=seconds)
+    digests = out.pop("digests")
+    done = sorted(digests)
+    k = int(np.ceil(check_fraction * len(done))) if done else 0
+    rng = np.random.default_rng(W.SEED_BASE + 6)
+    pick = sorted(rng.choice(done, size=k, replace=False).tolist()) if k else []
+    same = True
+    t = time.perf_counter()
+    for i in pick:
+        w = dict(reqs[i])
+        with nuosc.Run(w) as run:
+            run.evolve(w["r_end_km"])
+            same = same and serving.digest(run.probabilities()) == digests[i]
+    out["mix_equals_alone"] = same
+    out["alone_checked"] = len(pick)
+    out["alone_check_seconds"] = round(time.perf_counter() - t, 2)
+    out["window_km"] = reqs[0]["r_end_km"] - reqs[0]["r_start_km"]
+    out["arrival_rate_per_s"] = len(reqs) / seconds
+    out["mean_completed_beam_steps"] = out["beam_steps_completed"] / max(1, out["completed"])
+    return out
 
 
 def main() -> int:
@@ -416,6 +562,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-attempts", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy windows")
+    ap.add_argument("--small-attempts", type=int, default=20,
+                    help="attempts of the 200x1000 FP64 workload (0: skip both small workloads)")
     ap.add_argument("--extended-attempts", type=int, default=50,
                     help="attempts of the extended bulb model workload (0: skip)")
     ap.add_argument("--exp-attempts", type=int, default=30,
@@ -425,9 +574,11 @@ def main() -> int:
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a device buffer of this size (for scaling HBM counters)")
     ap.add_argument("--batched-attempts", type=int, default=50,
-                    help="attempts of the 64-run batched workload (0 = skip)")
-    ap.add_argument("--serving-seconds", type=float, default=20.0,
+                    help="attempts per batch step of the 64-run batched workload (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=120.0,
                     help="seconds of Poisson arrivals in the serving runs (0 = skip)")
+    ap.add_argument("--serving-check-fraction", type=float, default=0.1,
+                    help="fraction of completed requests re-run alone for the bitwise check")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this path runs on one GPU "
@@ -438,6 +589,9 @@ def main() -> int:
 
     from paper_1907_05560_amd import nuosc, workloads as W
 
+    def say(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.init()
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib * 2 ** 20
@@ -446,27 +600,18 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    names = {"fp32": W.FP32_AMP, "fp32math64": W.FP32_AMP_FP64_MATH, "fp64": W.FP64}
-    order = [names[f] for f in args.forms.split(",")]
+    form_list = args.forms.split(",")
+    order = [FORM_NAMES[f] for f in form_list]
     forms = {}
-    runs = {}
-    for prec in order:
-        print(f"bench: precision {prec}: {args.warmup} warmup + {args.steps} timed attempts", file=sys.stderr, flush=True)
+    averages = {}
+    for name, prec in zip(form_list, order):
+        say(f"{name}: {args.warmup} warmup + {args.steps} timed attempts")
         run, form = run_form(nuosc, W, torch, prec, args.steps, args.warmup)
         forms[prec] = form
-        runs[prec] = run
-        print(f"bench: precision {prec}: {form['ms_per_step']:.3f} ms/step, {form['value']:.3e} beam-steps/s, "
-              f"beam kernels {[round(x * 1e3, 1) for x in form['stage_ms']]} us, "
-              f"control {[round(x * 1e3, 1) for x in form['fin_ms']]} us", file=sys.stderr, flush=True)
-    err = None
-    if W.FP32_AMP in runs and W.FP64 in runs:
-        err = subsample_error(nuosc, W, runs[W.FP32_AMP], runs[W.FP64])
-    averages = {}
-    for prec, r in runs.items():
-        averages[{W.FP32_AMP: "fp32", W.FP32_AMP_FP64_MATH: "fp32math64", W.FP64: "fp64"}[prec]] = \
-            energy_average_timing(r, torch, 4 if prec != W.FP64 else 8)
-    for r in runs.values():
-        r.close()
+        averages[name] = energy_average_timing(run, torch, form["amp_bytes"])
+        run.close()
+        say(f"{name}: {form['ms_per_step']:.4f} ms/step, {form['value']:.4e} beam-steps/s, launches "
+            f"{[round(x, 1) for x in form['launch_us']]} us")
 
     head = forms[order[0]]
     line = {
@@ -480,7 +625,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {W.FP32_AMP: "f32", W.FP32_AMP_FP64_MATH: "f32-storage/f64-math", W.FP64: "f64"}[order[0]],
+        "dtype": DTYPE[order[0]],
         "data": "synthetic",
         "config": {
             "workload": "three-flavor multi-angle bulb model, 400 energies x 4000 angles x 2 species "
@@ -491,43 +636,58 @@ def main() -> int:
         "roofline": roofline(head),
         "accepted_per_attempt": head["accepted"] / head["attempts"],
         "step_roofline": step_roofline(head),
-        "forms": {f: {"value": forms[names[f]]["value"], "ms_per_step": forms[names[f]]["ms_per_step"],
-                      "roofline": roofline(forms[names[f]]), "step_roofline": step_roofline(forms[names[f]])}
-                  for f in args.forms.split(",")},
-        "fp32_vs_fp64_error": err,
-        "stage_us": {str(p): [round(x * 1e3, 2) for x in f["stage_ms"]] for p, f in forms.items()},
-        "control_us": {str(p): [round(x * 1e3, 2) for x in f["fin_ms"]] for p, f in forms.items()},
+        "forms": {f: {"value": forms[FORM_NAMES[f]]["value"], "ms_per_step": forms[FORM_NAMES[f]]["ms_per_step"],
+                      "dtype": DTYPE[FORM_NAMES[f]],
+                      "launch_us": dict(zip(forms[FORM_NAMES[f]]["names"],
+                                            [round(x, 2) for x in forms[FORM_NAMES[f]]["launch_us"]])),
+                      "roofline": roofline(forms[FORM_NAMES[f]]),
+                      "step_roofline": step_roofline(forms[FORM_NAMES[f]])}
+                  for f in form_list},
         "energy_average": averages,
+        "host": host_info(),
     }
+    if not args.no_accuracy and 0 in order:
+        say(f"accuracy windows {W.ACCURACY_WINDOWS} km on the 400x4000 grid")
+        line["accuracy"] = accuracy(nuosc, W, form_list)
+        for e in line["accuracy"]:
+            say(f"window {e['window_km']}: fp64 {e['fp64_accepted']} steps, P moves {e['max_dP_over_window']:.3e}; "
+                + ", ".join(f"{k} max {v['max']:.3e} rms {v['rms']:.3e}" for k, v in e["forms"].items()))
+    if args.small_attempts > 0:
+        say("small workloads (2f single-angle RK4 run, 200x1000 FP64 window) and their oracle times")
+        line["small_workloads"] = small_configs(nuosc, W, torch, args.small_attempts)
+        for k, v in line["small_workloads"].items():
+            say(f"{k}: {v['value']:.3e} beam-steps/s in {v['seconds']} s; oracle serial "
+                f"{v['oracle']['serial']['seconds']} s, OpenMP {v['oracle']['openmp']['seconds']} s")
     if args.extended_attempts > 0:
         line["extended"] = {}
         for name, prec in (("fp32", W.FP32_AMP), ("fp64", W.FP64)):
-            print(f"bench: extended bulb model {name} ({args.extended_attempts} attempts)", file=sys.stderr,
-                  flush=True)
+            say(f"extended bulb model {name} ({args.extended_attempts} attempts)")
             ex = extended(nuosc, W, torch, prec, args.extended_attempts)
             line["extended"][name] = ex
-            print(f"bench: extended {name}: {ex['ms_per_step']:.3f} ms/step, {ex['value']:.3e} beam-steps/s",
-                  file=sys.stderr, flush=True)
+            say(f"extended {name}: {ex['ms_per_step']:.3f} ms/step, {ex['value']:.3e} beam-steps/s")
     if args.exp_attempts > 0:
-        print(f"bench: exponential stepper ({args.exp_attempts} attempts)", file=sys.stderr, flush=True)
+        say(f"exponential stepper ({args.exp_attempts} attempts)")
         ex = exp_stepper(nuosc, W, torch, args.exp_attempts)
         line["exp_stepper"] = ex
-        print(f"bench: exponential stepper: {ex['ms_per_step']:.3f} ms/attempt, {ex['value']:.3e} beam-steps/s, "
-              f"launches {ex['launch_us']} us, reductions {ex['reduce_us']} us", file=sys.stderr, flush=True)
+        say(f"exponential stepper: {ex['ms_per_step']:.3f} ms/attempt, {ex['value']:.3e} beam-steps/s, "
+            f"launches {ex['launch_us']} us, reductions {ex['reduce_us']} us")
     if args.batched_attempts > 0:
-        print(f"bench: batched workload ({args.batched_attempts} attempts)", file=sys.stderr, flush=True)
+        say(f"batched workload ({args.batched_attempts} attempts per batch step, graph replays)")
         line["batched"] = batched(nuosc, W, torch, args.batched_attempts)
-        print(f"bench: batched {line['batched']['value']:.3e} beam-steps/s", file=sys.stderr, flush=True)
+        say(f"batched {line['batched']['value']:.3e} beam-steps/s, timed steps replayed "
+            f"{line['batched']['timed_steps_replayed']}/{line['batched']['timed_steps']}")
     if args.serving_seconds > 0:
         line["serving"] = {}
         for name, prec in (("fp32", W.FP32_AMP), ("fp64", W.FP64)):
-            print(f"bench: serving {name} ({args.serving_seconds:g} s of arrivals)", file=sys.stderr, flush=True)
-            sv = served(nuosc, W, args.serving_seconds, prec)
+            say(f"serving {name} ({args.serving_seconds:g} s of arrivals)")
+            sv = served(nuosc, W, args.serving_seconds, prec, args.serving_check_fraction)
             line["serving"][name] = sv
-            print(f"bench: serving {name}: {sv['completed']}/{sv['requests']} done, p50 {sv['p50_s']:.3f} s, "
-                  f"p99 {sv['p99_s']:.3f} s, {sv['value']:.3e} beam-steps/s", file=sys.stderr, flush=True)
+            say(f"serving {name}: {sv['completed']}/{sv['requests']} done, queue max {sv['max_queue']}, "
+                f"p50 {sv['p50_s']:.3f} s, p99 {sv['p99_s']:.3f} s, {sv['value']:.3e} beam-steps/s, "
+                f"graph share {sv['graph_share']:.2f}, alone check {sv['alone_checked']} "
+                f"{'equal' if sv['mix_equals_alone'] else 'DIFFERENT'}")
     if not args.no_cpu_baseline:
-        print(f"bench: cpu baseline ({args.cpu_attempts} oracle attempts)", file=sys.stderr, flush=True)
+        say(f"cpu baseline ({args.cpu_attempts} oracle attempts, serial and OpenMP)")
         line["cpu_baseline"] = cpu_baseline(W, args.cpu_attempts)
     print(json.dumps(line), flush=True)
     return 0

@@ -347,6 +347,13 @@ int64_t nuosc_batch_num_beams(const nuosc_batch* b, int32_t slot);
  * p_out (host, NB doubles; nullable), and free its memory and slot. */
 nuosc_status nuosc_batch_retire(nuosc_batch* b, int32_t slot, double* p_out);
 
+/* How the batch's steps ran (each pointer nullable): nuosc_batch_step calls
+ * that launched work directly on the stream, calls that replayed the captured
+ * graph, and how many graphs were captured (a capture is counted in the call
+ * that replays it first). */
+nuosc_status nuosc_batch_graph_stats(const nuosc_batch* b, int64_t* eager_steps, int64_t* graph_steps,
+                                     int64_t* captures);
+
 /* Number of occupied slots. */
 int32_t nuosc_batch_occupied(const nuosc_batch* b);
 

@@ -1151,6 +1151,8 @@ struct nuosc_batch {
     int64_t graph_attempts = 0;
     std::vector<int> last_slots;
     int64_t last_attempts = 0;
+    // batch steps that launched work: directly, by graph replay, and captures
+    int64_t eager_steps = 0, graph_steps = 0, captures = 0;
     std::string err;
 };
 
@@ -1243,6 +1245,7 @@ nuosc_status graph_attempts(nuosc_batch* b, const std::vector<int>& slots, const
         b->graph = x;
         b->graph_slots = slots;
         b->graph_attempts = n;
+        b->captures += 1;
     }
     HIP_CHECK(hipGraphLaunch(b->graph, b->stream), b->err);
     return NUOSC_OK;
@@ -1356,8 +1359,10 @@ nuosc_status nuosc_batch_step(nuosc_batch* b, int64_t n_attempts, int32_t* n_fin
         if (repeat) {
             nuosc_status st = graph_attempts(b, slots, list, n_attempts);
             if (st != NUOSC_OK) return st;
+            b->graph_steps += 1;
         } else {
             HIP_CHECK(launch_attempts(b, list, n_attempts), b->err);
+            b->eager_steps += 1;
         }
         for (int i : slots)
             HIP_CHECK(hipMemcpyAsync(&b->runs[i].hctl, b->runs[i].rc.ctrl + 1, sizeof(Control), hipMemcpyDeviceToHost,
@@ -1406,6 +1411,16 @@ nuosc_status nuosc_batch_retire(nuosc_batch* b, int32_t slot, double* p_out)
     b->used[slot] = 0;
     b->runs[slot] = RunState{};
     drop_graph(b);
+    return NUOSC_OK;
+}
+
+nuosc_status nuosc_batch_graph_stats(const nuosc_batch* b, int64_t* eager_steps, int64_t* graph_steps,
+                                     int64_t* captures)
+{
+    if (!b) return bfail(nullptr, NUOSC_E_INVALID, "batch is NULL");
+    if (eager_steps) *eager_steps = b->eager_steps;
+    if (graph_steps) *graph_steps = b->graph_steps;
+    if (captures) *captures = b->captures;
     return NUOSC_OK;
 }
 

@@ -36,7 +36,8 @@ EXPORTS = (
     "nuosc_snapshot_read", "nuosc_snapshot_info", "nuosc_stats", "nuosc_num_beams",
     "nuosc_num_traj", "nuosc_last_error", "nuosc_destroy",
     "nuosc_batch_create", "nuosc_batch_admit", "nuosc_batch_step", "nuosc_batch_query",
-    "nuosc_batch_num_beams", "nuosc_batch_retire", "nuosc_batch_occupied", "nuosc_batch_last_error",
+    "nuosc_batch_num_beams", "nuosc_batch_retire", "nuosc_batch_graph_stats", "nuosc_batch_occupied",
+    "nuosc_batch_last_error",
     "nuosc_batch_destroy",
 )
 
@@ -187,6 +188,8 @@ def lib() -> C.CDLL:
     L.nuosc_batch_num_beams.restype = C.c_int64
     L.nuosc_batch_retire.argtypes = [C.c_void_p, C.c_int32, _D]
     L.nuosc_batch_retire.restype = C.c_int
+    L.nuosc_batch_graph_stats.argtypes = [C.c_void_p, _I64, _I64, _I64]
+    L.nuosc_batch_graph_stats.restype = C.c_int
     L.nuosc_batch_occupied.argtypes = [C.c_void_p]
     L.nuosc_batch_occupied.restype = C.c_int32
     L.nuosc_batch_last_error.argtypes = [C.c_void_p]
@@ -480,6 +483,13 @@ class Batch:
         else:
             self._check(lib().nuosc_batch_retire(self.h, int(slot), None))
         return p
+
+    def graph_stats(self) -> Dict:
+        """Batch steps launched directly, replayed from the captured graph, and
+        graph captures so far."""
+        e, g, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib().nuosc_batch_graph_stats(self.h, C.byref(e), C.byref(g), C.byref(c)))
+        return dict(eager=e.value, graph=g.value, captures=c.value)
 
     @property
     def occupied(self) -> int:

@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 output for the stage kernels (text for profiles/).
+"""Summaries of rocprofv3 output for the kernels (text for profiles/).
 
 Two inputs, both written by ``rocprofv3`` runs of ``bench.py``:
 
@@ -8,8 +8,10 @@ Two inputs, both written by ``rocprofv3`` runs of ``bench.py``:
   invocation that also copies a buffer of known size
   (``bench.py --copy-calibration-mib M``).  The HBM counters are scaled by
   the ratio between the bytes that copy moves (M MiB read and M MiB written)
-  and what the same counter reports for it, so the stage-kernel figures are
-  in bytes that a plain copy would count as moved.
+  and what the same counter reports for it, so the kernel figures are in
+  bytes that a plain copy would count as moved.  The JSON file keys them by
+  ``kernel_key`` (e.g. ``k_final<float,float,3,DP54,2>``), as bench.py looks
+  them up.
 
 Dispatches made after a run has reached its end radius (the attempts a host
 loop enqueues past the end) return at once; a dispatch is counted as such, and
@@ -84,24 +86,19 @@ def valu_summary(csv_path: str, command: str):
 
 
 def short_name(name: str) -> str:
-    """'void nuosc::(anonymous namespace)::k_stage_one<float, float, 3, ...TabDP54, 7, 2>(nuosc::RunConst)'
-    -> 'k_stage_one<float,float,3,DP54,7,2>'."""
+    """'void nuosc::(anonymous namespace)::k_final_one<float, float, 3, ...TabDP54, 2>(nuosc::RunConst)'
+    -> 'k_final_one<float,float,3,DP54,2>'."""
     n = name.replace("nuosc::(anonymous namespace)::", "").replace("void ", "")
     n = re.sub(r"\(nuosc::(RunConst|LaunchSet).*\)$", "", n)
     n = n.replace("TabDP54", "DP54").replace("TabRK4", "RK4").replace(" ", "")
     return n
 
 
-def stage_key(name: str):
-    """(stage, precision) of a bulb-model beam-kernel instantiation (one run or a
-    launch set), or None.  The last template argument is the number of angle
-    moments: 2 for the bulb model, 4 for the extended model (no key)."""
-    m = re.search(r"k_stage(?:_one)?<(\w+),(\w+),(\d),\w+,(\d)(?:,(\d))?>", short_name(name))
-    if not m or m.group(5) not in (None, "2"):
-        return None
-    ts, t, _, stage, _ = m.groups()
-    prec = 0 if ts == "double" else (1 if t == "float" else 2)
-    return int(stage), prec
+def kernel_key(name: str) -> str:
+    """Short name of a kernel with the single-run suffix dropped, so that the
+    one-run and launch-set instantiations of a kernel share a key:
+    'k_final_one<float,float,3,DP54,2>' -> 'k_final<float,float,3,DP54,2>'."""
+    return re.sub(r"_one<", "<", short_name(name), count=1)
 
 
 def _full(values):
@@ -158,7 +155,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_mib: float, cmd_f: str,
     scale_f = copy_bytes / (cf * 1024.0)
     scale_w = copy_bytes / (cw * 1024.0)
     per_launch = {}
-    lines = ["# HBM traffic of the stage kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+    lines = ["# HBM traffic of the kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
              "Commands:", "", "```", cmd_f, cmd_w, "```", "",
              f"Calibration: a device-to-device copy of {copy_mib:g} MiB ({COPY_KERNEL}) reads "
              f"{cf:.0f} KiB by FETCH_SIZE and writes {cw:.0f} KiB by WRITE_SIZE, so FETCH_SIZE is scaled by "
@@ -166,7 +163,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_mib: float, cmd_f: str,
              f"Kernel source sha256[:16]: `{kernel_source_hash()}`", "",
              "| kernel | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | read MB (scaled) | write MB (scaled) | total MB |",
              "|---|---|---|---|---|---|---|"]
-    for name in sorted(set(fetch) | set(write), key=lambda n: (stage_key(n) or (99, 9), n)):
+    for name in sorted(set(fetch) | set(write), key=kernel_key):
         if name == COPY_KERNEL:
             continue
         f = fetch.get(name, [])
@@ -178,9 +175,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_mib: float, cmd_f: str,
         rb, wb = fm * 1024 * scale_f, wm * 1024 * scale_w
         lines.append(f"| `{short_name(name)}` | {len(f)} | {fm:.0f} | {wm:.0f} | {rb / 1e6:.2f} | "
                      f"{wb / 1e6:.2f} | {(rb + wb) / 1e6:.2f} |")
-        k = stage_key(name)
-        if k:
-            per_launch[f"stage{k[0]}_prec{k[1]}"] = round(rb + wb)
+        per_launch[kernel_key(name)] = round(rb + wb)
     doc = {
         "kernel_source_sha256_16": kernel_source_hash(),
         "copy_calibration_mib": copy_mib,

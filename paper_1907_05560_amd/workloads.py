@@ -196,17 +196,19 @@ def batched_runs(count: int = 64) -> List[Dict]:
 
 
 def serving_requests(rate_per_s: float = 20.0, duration_s: float = 120.0,
-                     large_fraction: float = 0.1, window_km: float = 2e-6,
+                     large_fraction: float = 0.1, window_km: float = 3e-5,
                      precision: int = FP32_AMP) -> List[Dict]:
     """Poisson arrivals; each request is a batched-runs draw, 10% large.
 
     Each request evolves from the neutrinosphere over a radius window of
-    `window_km` (its r_end): near R the adaptive step of a multi-angle run is
-    about 5e-7 km x (20 / N_A) at rtol 1e-9 (nearly tangential trajectories
-    have 1 / cos(theta) up to 2 N_A), so a window of 2e-6 km takes tens of
-    steps for the smallest grids and several hundred for the 400 x 4000 ones.
-    The draws of every request (and so the sequence) do not depend on the
-    window or the precision."""
+    `window_km` (its r_end).  Near R the adaptive step of a multi-angle run is
+    about 1e-5 km / N_A at rtol 1e-9 (nearly tangential trajectories have
+    1 / cos(theta) up to 2 N_A), so a request costs about 2 N_E N_A^2 x
+    window / 1e-5 km beam-steps: with the draws below, measured ~6e13 x
+    window (km) on average.  At 20 requests/s and a window of 3e-5 km the
+    offered load is ~3e10 beam-steps/s, above what one GPU serves (~1.2e10),
+    so the queue grows over the arrival period.  The draws of every request (and so the sequence) do
+    not depend on the window or the precision."""
     rng = np.random.default_rng(SEED_BASE + 4)
     out = []
     t = 0.0

@@ -149,3 +149,33 @@ def test_a_batched_run_matches_the_oracle():
     assert ref.stats()["r_km"] == q["r_km"]
     assert abs(ref.stats()["accepted"] - q["accepted"]) <= 1
     np.testing.assert_allclose(p, ref.probabilities(), rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_AMP])
+def test_graph_replays_equal_eager_launches_bitwise(precision):
+    """One batch steps with a repeated count, so that from its second step on
+    every step replays the captured HIP graph; a twin batch of the same runs
+    steps the same attempts with alternating counts, so that it never
+    replays.  After every replay (with the twin's eager work and the host
+    synchronisations in between) both batches hold the same step counts and
+    radii, and at the end the same probabilities, bit for bit."""
+    ws = _mix(precision)
+    say(f"case: graph replay vs eager, batch of {len(ws)} prec={precision}")
+    with nuosc.Batch(8, 3, precision, W.RK_DP54, _budget(ws)) as g, \
+            nuosc.Batch(8, 3, precision, W.RK_DP54, _budget(ws)) as e:
+        gs = [g.admit(w) for w in ws]
+        es = [e.admit(w) for w in ws]
+        assert None not in gs and None not in es
+        for rep in range(6):
+            g.step(5)
+            e.step(2)
+            e.step(3)
+            for a, b in zip(gs, es):
+                qa, qb = g.query(a), e.query(b)
+                assert (qa["accepted"], qa["rejected"], qa["r_km"]) == (qb["accepted"], qb["rejected"], qb["r_km"]), rep
+        st_g, st_e = g.graph_stats(), e.graph_stats()
+        say(f"graph batch {st_g}, eager batch {st_e}")
+        assert st_g == dict(eager=1, graph=5, captures=1)
+        assert st_e["graph"] == 0 and st_e["eager"] == 12
+        for a, b in zip(gs, es):
+            np.testing.assert_array_equal(g.retire(a), e.retire(b))

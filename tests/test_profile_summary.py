@@ -10,27 +10,24 @@ from paper_1907_05560_amd import profile_summary as PS
 NS = "nuosc::(anonymous namespace)::"
 
 
-def _name(kernel, ts, t, tab, stage, arg, nj=2):
-    return f"void {NS}{kernel}<{ts}, {t}, 3, {NS}{tab}, {stage}, {nj}>(nuosc::{arg})"
+def _final(ts, t, arg="RunConst", kernel="k_final_one", nj=2):
+    return f"void {NS}{kernel}<{ts}, {t}, 3, {NS}TabDP54, {nj}>(nuosc::{arg})"
 
 
-@pytest.mark.parametrize("kernel,arg", [("k_stage_one", "RunConst"), ("k_stage", "LaunchSet")])
-@pytest.mark.parametrize("ts,t,prec", [("double", "double", 0), ("float", "float", 1), ("float", "double", 2)])
-def test_stage_key_reads_stage_and_precision(kernel, arg, ts, t, prec):
-    n = _name(kernel, ts, t, "TabDP54", 6, arg)
-    assert PS.stage_key(n) == (6, prec)
-    assert PS.short_name(n) == f"{kernel}<{ts},{t},3,DP54,6,2>"
+@pytest.mark.parametrize("kernel,arg", [("k_final_one", "RunConst"), ("k_final", "LaunchSet")])
+@pytest.mark.parametrize("ts,t", [("double", "double"), ("float", "float"), ("float", "double")])
+def test_kernel_key_drops_the_single_run_suffix(kernel, arg, ts, t):
+    n = _final(ts, t, arg, kernel)
+    assert PS.short_name(n) == f"{kernel}<{ts},{t},3,DP54,2>"
+    assert PS.kernel_key(n) == f"k_final<{ts},{t},3,DP54,2>"
 
 
-def test_extended_model_kernels_have_no_stage_key():
-    n = _name("k_stage_one", "float", "float", "TabDP54", 6, "RunConst", nj=4)
-    assert PS.stage_key(n) is None
-    assert PS.short_name(n) == "k_stage_one<float,float,3,DP54,6,4>"
-
-
-def test_other_kernels_have_no_stage_key():
-    assert PS.stage_key(f"void {NS}k_control_one<3, {NS}TabDP54, 7, 2>(nuosc::RunConst)") is None
-    assert PS.stage_key(PS.COPY_KERNEL) is None
+def test_kernel_keys_of_the_other_launches():
+    traj = f"void {NS}k_traj_one<3, {NS}TabDP54, 2, 4, float>(nuosc::RunConst)"
+    power = f"void {NS}k_power_one<float, 3, {NS}TabDP54, 2, false>(nuosc::RunConst)"
+    assert PS.kernel_key(traj) == "k_traj<3,DP54,2,4,float>"
+    assert PS.kernel_key(power) == "k_power<float,3,DP54,2,false>"
+    assert PS.kernel_key(PS.COPY_KERNEL) == PS.COPY_KERNEL
 
 
 def _write(path, counter, rows):
@@ -42,7 +39,7 @@ def _write(path, counter, rows):
 
 
 def test_traffic_is_scaled_by_the_calibration_copy(tmp_path):
-    k6 = _name("k_stage_one", "float", "float", "TabDP54", 6, "RunConst")
+    k6 = _final("float", "float")
     mib = 64
     # the copy reads 2 x its size by FETCH_SIZE and writes 1 x by WRITE_SIZE
     f_rows = [(PS.COPY_KERNEL, 2 * mib * 1024), (k6, 1000.0), (k6, 1000.0), (k6, 10.0)]  # last: early exit
@@ -53,8 +50,8 @@ def test_traffic_is_scaled_by_the_calibration_copy(tmp_path):
     text, doc = PS.traffic_summary(str(fp), str(wp), mib, "cmd f", "cmd w")
     assert doc["fetch_scale"] == pytest.approx(0.5)
     assert doc["write_scale"] == pytest.approx(1.0)
-    assert doc["bytes_per_launch"]["stage6_prec1"] == round(1000 * 1024 * 0.5 + 500 * 1024)
-    assert "k_stage_one<float,float,3,DP54,6,2>" in text
+    assert doc["bytes_per_launch"]["k_final<float,float,3,DP54,2>"] == round(1000 * 1024 * 0.5 + 500 * 1024)
+    assert "k_final_one<float,float,3,DP54,2>" in text
 
 
 def test_valu_summary_reads_the_exponential_stepper_launches(tmp_path):
