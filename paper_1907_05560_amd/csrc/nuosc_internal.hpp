@@ -58,7 +58,7 @@ struct RunConst {
     const double* flux;          // [2 ne] number flux of the slot's birth flavor in its energy bin
     const double* azi;           // [na][2] cos, sin of each trajectory's azimuth
     double* jhist;               // [kMaxStages + 1][nj n n] packed J0, J1 (J2, J3) per stage
-    double* partial;             // [2][nj n n][nblk] per-workgroup weighted sums of the last two
+    double* partial;             // [2][nj n n][pstride] per-workgroup weighted sums of the last two
                                  // moment launches (launch l uses [l & 1]), value-major
     double* errpart;             // [max(nblk, nblkf)] per-workgroup step-error maxima
     double* qbuf;                // Runge-Kutta forms: [na][qstride] power moments of the current state
@@ -70,17 +70,20 @@ struct RunConst {
                                  // attempt (else unused)
     Control* ctrl;               // [2]
     int32_t qstride, dstride;    // doubles per trajectory in qbuf, dbuf
-    int32_t fstride, pad3;       // bytes per trajectory in ftab
+    int32_t fstride;             // bytes per trajectory in ftab
+    int32_t nblkp;               // workgroups of the power-moment launch (partials it writes)
+    int32_t pstride;             // stride of one value in the partial buffer: max(nblk, nblkp)
+    int32_t pad3;
 };
 
 constexpr int kMaxStages = 8;
 constexpr int kMaxLaunches = 10;   // launches of one attempt (Runge-Kutta: stages + 2)
 constexpr int kFinBlock = 256;     // threads per small reduction workgroup
 
-// Trajectories per workgroup of the Runge-Kutta launches: the power-moment and
-// per-trajectory launches (which write the moment partials) and the state
-// update (8).
+// Trajectories per workgroup of the Runge-Kutta launches: the per-trajectory
+// launches (16), the power-moment launch (16) and the state update (8).
 constexpr int kTrajPerBlock = 16;
+constexpr int kPowerTrajPerBlock = 16;  // the power-moment launch: two trajectories per wavefront
 inline int final_traj_per_block(int) { return 8; }
 
 // The runs one launch covers.  Run i of the launch is runs[slot[i]] and owns

@@ -379,28 +379,28 @@ struct PartialRegs {
 };
 
 template <int NV, int NW>
-__device__ __forceinline__ void load_partials(const RunConst& rc, int par, PartialRegs<NV, NW>& r)
+__device__ __forceinline__ void load_partials(const RunConst& rc, int par, int nblk, PartialRegs<NV, NW>& r)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nblk = rc.nblk;
-    const double* src = rc.partial + (size_t)(par & 1) * NV * nblk;
+    const int ps = rc.pstride;
+    const double* src = rc.partial + (size_t)(par & 1) * NV * ps;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int p = lane + 64 * k;
-            r.x[i][k] = (v < NV && p < nblk) ? src[(size_t)v * nblk + p] : 0.0;
+            r.x[i][k] = (v < NV && p < nblk) ? src[(size_t)v * ps + p] : 0.0;
         }
     }
 }
 
 template <int NV, int NW>
-__device__ void finish_partials(const RunConst& rc, int par, const PartialRegs<NV, NW>& r, double* out)
+__device__ void finish_partials(const RunConst& rc, int par, int nblk, const PartialRegs<NV, NW>& r, double* out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nblk = rc.nblk;
-    const double* src = rc.partial + (size_t)(par & 1) * NV * nblk;
+    const int ps = rc.pstride;
+    const double* src = rc.partial + (size_t)(par & 1) * NV * ps;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
@@ -409,7 +409,7 @@ __device__ void finish_partials(const RunConst& rc, int par, const PartialRegs<N
         acc += r.x[i][1];
         acc += r.x[i][2];
         acc += r.x[i][3];
-        for (int p = lane + 256; p < nblk; p += 64) acc += src[(size_t)v * nblk + p];
+        for (int p = lane + 256; p < nblk; p += 64) acc += src[(size_t)v * ps + p];
         acc = wave_sum(acc);
         if (lane == 0) out[v] = acc;
     }
@@ -430,6 +430,7 @@ __device__ void finish_partials(const RunConst& rc, int par, const PartialRegs<N
 // density sum of the state itself: rotated to the lab frame and weighted at
 // the state's radius, it gives the workgroup's partial of J_0 (buffer 0).
 constexpr int kPowerWaves = kTrajPerBlock / 2;
+static_assert(kPowerTrajPerBlock == kTrajPerBlock, "the power-moment launch covers kTrajPerBlock trajectories per workgroup");
 
 template <typename TS, int N, typename TAB, int NJ, bool FORCE>
 __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
@@ -437,7 +438,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU, NV = NJ * NM;
     constexpr int NQ = Poly<TAB>::NQ;
     constexpr int H = (NQ + 1) / 2;  // powers per lane
-    constexpr int NSLOT = 2;         // beams of a lane in flight
+    constexpr int NSLOT = 4;         // beams of a lane in flight
     constexpr uint32_t STRIDE = 16;  // beam-slot stride of a lane pair
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -497,36 +498,36 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         }
     };
     auto process = [&](const TS* yv, double u, double w) __attribute__((always_inline)) {
-        double y[2 * N], wy[2 * N], r[NM];
-#pragma unroll
-        for (int x = 0; x < 2 * N; ++x) {
-            y[x] = (double)yv[x];
-            wy[x] = w * y[x];
-        }
-#pragma unroll
-        for (int a = 0; a < N; ++a) r[a] = fma(wy[2 * a], y[2 * a], wy[2 * a + 1] * y[2 * a + 1]);
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = a + 1; b < N; ++b) {
-                const int x = N + 2 * Shape<N>::up(a, b);
-                r[x] = fma(wy[2 * a], y[2 * b], wy[2 * a + 1] * y[2 * b + 1]);      // Re w y_a conj(y_b)
-                r[x + 1] = fma(wy[2 * a + 1], y[2 * b], -(wy[2 * a] * y[2 * b + 1]));  // Im
-            }
-        // u^(H hb): the second lane of the pair starts at power H
+        // the weighted powers w u^(H hb + k), k < H: the second lane of the
+        // pair starts at power H
         double uh = 1.0, bpow = u;
 #pragma unroll
         for (int e = H; e > 0; e >>= 1) {
             if (e & 1) uh *= bpow;
             bpow *= bpow;
         }
-        double pw = hb ? uh : 1.0;
+        double pw[H];
+        pw[0] = hb ? w * uh : w;
 #pragma unroll
-        for (int k = 0; k < H; ++k) {
+        for (int k = 1; k < H; ++k) pw[k] = pw[k - 1] * u;
+        double y[2 * N];
 #pragma unroll
-            for (int x = 0; x < NM; ++x) acc[k][x] = fma(r[x], pw, acc[k][x]);
-            pw *= u;
-        }
+        for (int x = 0; x < 2 * N; ++x) y[x] = (double)yv[x];
+        // each entry of y y^+ is formed and added to its H sums at once
+        auto add = [&](int x, double v) __attribute__((always_inline)) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) acc[k][x] = fma(v, pw[k], acc[k][x]);
+        };
+#pragma unroll
+        for (int a = 0; a < N; ++a) add(a, fma(y[2 * a], y[2 * a], y[2 * a + 1] * y[2 * a + 1]));
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = a + 1; b < N; ++b) {
+                const int x = N + 2 * Shape<N>::up(a, b);
+                add(x, fma(y[2 * a], y[2 * b], y[2 * a + 1] * y[2 * b + 1]));          // Re y_a conj(y_b)
+                add(x + 1, fma(y[2 * a + 1], y[2 * b], -(y[2 * a] * y[2 * b + 1])));  // Im
+            }
     };
 
     TS ys[NSLOT][2 * N];
@@ -612,7 +613,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     if (tid < NV) {
         double s = swave[0][tid];
         for (int w = 1; w < kTrajPerBlock; ++w) s += swave[w][tid];
-        rc.partial[(size_t)tid * rc.nblk + blk] = s;  // buffer 0
+        rc.partial[(size_t)tid * rc.pstride + blk] = s;  // buffer 0
     }
 }
 
@@ -693,7 +694,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         C.fresh = __hip_atomic_load(&vc->fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     PartialRegs<NV, NW> xp;
-    load_partials<NV, NW>(rc, L - 1, xp);  // L = 1: the power-moment launch's (used if fresh)
+    // L = 1: the power-moment launch's (used if fresh)
+    const int npart = L == 1 ? rc.nblkp : rc.nblk;
+    load_partials<NV, NW>(rc, L - 1, npart, xp);
     const int jl = active ? j : 0;
     double ph01[2][N], G[L][N];
     for (int a = 0; a < N; ++a) {
@@ -809,7 +812,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 
     // ---- J_{L-1}
     if (L > 1 || C.fresh) {
-        finish_partials<NV, NW>(rc, L - 1, xp, sJ);
+        finish_partials<NV, NW>(rc, L - 1, npart, xp, sJ);
         if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
     } else {
         if (tid < NV) sJ[tid] = rc.jhist[tid];
@@ -1093,7 +1096,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         if (tid < NV) {
             double s0 = swave[0][tid];
             for (int w = 1; w < TPB; ++w) s0 += swave[w][tid];
-            rc.partial[((size_t)(L & 1) * NV + tid) * rc.nblk + blk] = s0;
+            rc.partial[((size_t)(L & 1) * NV + tid) * rc.pstride + blk] = s0;
         }
     }
 }
@@ -1206,9 +1209,16 @@ __device__ __forceinline__ void powers(T u, T (&up)[D + 1])
     for (int d = 2; d <= D; ++d) up[d] = up[d - 1] * u;
 }
 
+// Eight wavefronts per workgroup, WPT of them on each trajectory (its beams
+// dealt out in turn, G x NGRP x 64 beams at a time).  The launch bounds ask
+// for four wavefronts per SIMD (at most 128 registers), which with one group
+// of beams in flight the kernel fits without spilling: every trajectory's
+// wavefront is resident at once on the 3.2M-beam grid.
 template <typename T> struct FinalShape {
-    static constexpr int traj = 8;
-    static constexpr int block = 64 * traj;
+    static constexpr int waves = 8;
+    static constexpr int wpt = 1;
+    static constexpr int traj = waves / wpt;
+    static constexpr int block = 64 * waves;
 };
 
 template <typename TS, typename T, int N, typename TAB, int NJ>
@@ -1219,16 +1229,19 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     constexpr int DN = PY::DN, DE = PY::DE;
     constexpr bool ERROR = TAB::embedded;
     constexpr int TPB = FinalShape<T>::traj;
+    constexpr int WPT = FinalShape<T>::wpt;
+    constexpr int NWV = FinalShape<T>::waves;
     constexpr int G = 2;       // beams of a lane sharing each coefficient load
-    constexpr int NGRP = 2;    // groups of a lane in flight
+    constexpr int NGRP = 1;    // groups of a lane in flight
     constexpr uint32_t STRIDE = 64;
     constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 7) / 8) * 8;  // byte offset of the error table
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int j = blk * TPB + wave;
+    const int j = blk * TPB + wave / WPT;
+    const uint32_t sub = (uint32_t)(wave % WPT);
     const bool active = j < rc.na;
-    __shared__ double swave[TPB];
+    __shared__ double swave[NWV];
 
     const Control* vc = rc.ctrl;  // ctrl[0]
     const int status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1341,18 +1354,19 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     TS ys[NGRP][G][2 * N];
     T us[NGRP][G];
     double u64s[NGRP][G] = {};
-    const uint32_t t0 = (uint32_t)lane;
+    constexpr uint32_t SPAN = NGRP * G * STRIDE;  // beams of one pass of a wavefront
+    const uint32_t t0 = (uint32_t)lane + sub * SPAN;
     static_for<0, NGRP>([&](auto Sc) {
         constexpr int sl = decltype(Sc)::value;
         fetch(t0 + sl * G * STRIDE, ys[sl], us[sl], u64s[sl]);
     });
 #pragma unroll 1
-    for (uint32_t t = t0; t < nbt; t += NGRP * G * STRIDE) {
+    for (uint32_t t = t0; t < nbt; t += WPT * SPAN) {
         static_for<0, NGRP>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
             const uint32_t ts = t + sl * G * STRIDE;
             if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
-            fetch(ts + NGRP * G * STRIDE, ys[sl], us[sl], u64s[sl]);
+            fetch(ts + WPT * SPAN, ys[sl], us[sl], u64s[sl]);
         });
     }
 
@@ -1362,7 +1376,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     __syncthreads();
     if (tid == 0) {
         double m = swave[0];
-        for (int w = 1; w < TPB; ++w) m = fmax(m, swave[w]);
+        for (int w = 1; w < NWV; ++w) m = fmax(m, swave[w]);
         rc.errpart[blk] = m;
     }
 }
@@ -1395,14 +1409,14 @@ __global__ void __launch_bounds__(64 * kTrajWaves) k_traj_one(const RunConst rc)
 }
 
 template <typename TS, typename T, int N, typename TAB, int NJ>
-__global__ void __launch_bounds__(FinalShape<T>::block) k_final(const LaunchSet ls)
+__global__ void __launch_bounds__(FinalShape<T>::block, 4) k_final(const LaunchSet ls)
 {
     int blk;
     const RunConst& rc = ls.runs[run_of_block(ls, blk)];
     final_body<TS, T, N, TAB, NJ>(rc, blk);
 }
 template <typename TS, typename T, int N, typename TAB, int NJ>
-__global__ void __launch_bounds__(FinalShape<T>::block) k_final_one(const RunConst rc)
+__global__ void __launch_bounds__(FinalShape<T>::block, 4) k_final_one(const RunConst rc)
 {
     final_body<TS, T, N, TAB, NJ>(rc, blockIdx.x);
 }
@@ -1415,8 +1429,8 @@ __device__ __forceinline__ void jsum_body(const RunConst& rc)
     constexpr int NW = kFinBlock / 64;
     __shared__ double sJ[NV];
     PartialRegs<NV, NW> x;
-    load_partials<NV, NW>(rc, 0, x);
-    finish_partials<NV, NW>(rc, 0, x, sJ);
+    load_partials<NV, NW>(rc, 0, rc.nblkp, x);
+    finish_partials<NV, NW>(rc, 0, rc.nblkp, x, sJ);
     if ((int)threadIdx.x < NV) rc.jhist[threadIdx.x] = sJ[threadIdx.x];
 }
 template <int NV>
@@ -1554,7 +1568,7 @@ struct StageKernels {
     KernFn k = nullptr, f = nullptr;
     OneFn k1 = nullptr, f1 = nullptr;
     unsigned block = 0;
-    int grid = 0;
+    int grid = 0;  // workgroups: 0 nblk (per-trajectory launches), 1 nblkf (state update), 2 nblkp (power moments)
 };
 
 template <typename TF, int N, typename TAB, int NJ, int L>
@@ -1591,6 +1605,7 @@ void pick_tab(int stage, StageKernels& K)
         K.f = (KernFn)&k_jsum<NJ * N * N>;
         K.f1 = (OneFn)&k_jsum_one<NJ * N * N>;
         K.block = 64 * kPowerWaves;
+        K.grid = 2;
     } else if (stage <= S) {
         K.k = TrajTable<T, N, TAB, NJ>::fns[stage];
         K.k1 = TrajTable<T, N, TAB, NJ>::fns1[stage];
@@ -1604,6 +1619,7 @@ void pick_tab(int stage, StageKernels& K)
         K.k = (KernFn)&k_power<TS, N, TAB, NJ, false>;
         K.k1 = (OneFn)&k_power_one<TS, N, TAB, NJ, false>;
         K.block = 64 * kPowerWaves;
+        K.grid = 2;
     }
 }
 
@@ -1696,7 +1712,9 @@ hipError_t launch_stage(const RunList& runs, int stage, hipStream_t s, hipEvent_
     }
     if (!K.k || !K.k1) return hipErrorInvalidValue;
     const bool one = runs.count == 1;
-    auto blocks = [&](const RunConst& rc) { return (long long)(K.grid ? rc.nblkf : rc.nblk); };
+    auto blocks = [&](const RunConst& rc) {
+        return (long long)(K.grid == 1 ? rc.nblkf : K.grid == 2 ? rc.nblkp : rc.nblk);
+    };
     if (ev) {
         hipError_t e = hipEventRecord(ev[0], s);
         if (e != hipSuccess) return e;

@@ -182,7 +182,7 @@ struct Layout {
     size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, qbuf, dbuf, gbuf, ftab, xbuf, flux, azi,
         ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
-    int na, nblk, nblkf;
+    int na, nblk, nblkf, nblkp, pstride;
     int nj;      // angle moments: 2 (bulb model), 4 (extended: azimuth)
     nuosc::PolySizes poly;  // Runge-Kutta per-trajectory tables (zero for the exponential stepper)
 };
@@ -252,6 +252,10 @@ Layout make_layout(const nuosc_params& p)
     const int tpbf = rk ? nuosc::final_traj_per_block(p.precision) : nuosc::kExpTrajPerBlock;
     L.nblk = (L.na + tpb - 1) / tpb;
     L.nblkf = (L.na + tpbf - 1) / tpbf;
+    // the power-moment launch writes its own count of partials (the exponential
+    // stepper's launches all use nblk)
+    L.nblkp = rk ? (L.na + nuosc::kPowerTrajPerBlock - 1) / nuosc::kPowerTrajPerBlock : L.nblk;
+    L.pstride = std::max(L.nblk, L.nblkp);
     L.poly = rk ? nuosc::poly_sizes(n, p.integrator, p.precision) : nuosc::PolySizes{0, 0, 0};
     for (int b = 0; b < 2; ++b) L.psi[b] = take(2 * n * (size_t)L.nb_pad * tsz);
     for (int b = 0; b < 2; ++b) L.phase[b] = take((size_t)L.na * n * 8);
@@ -260,7 +264,7 @@ Layout make_layout(const nuosc_params& p)
     L.wgt = take((size_t)2 * p.n_energy * 8);
     L.flux = take((size_t)2 * p.n_energy * 8);
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * L.nj * n * n * 8);
-    L.partial = take((size_t)2 * L.nj * n * n * L.nblk * 8);  // two launches' partials (alternating)
+    L.partial = take((size_t)2 * L.nj * n * n * L.pstride * 8);  // two launches' partials (alternating)
     L.azi = take((size_t)2 * L.na * 8);
     L.errpart = take((size_t)std::max(L.nblk, L.nblkf) * 8);
     L.qbuf = take((size_t)L.na * L.poly.qstride * 8);
@@ -384,6 +388,8 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.nb_pad = L.nb_pad;
     rc.nblk = L.nblk;
     rc.nblkf = L.nblkf;
+    rc.nblkp = L.nblkp;
+    rc.pstride = L.pstride;
     rc.qstride = L.poly.qstride;
     rc.dstride = L.poly.dstride;
     rc.fstride = L.poly.fstride;
