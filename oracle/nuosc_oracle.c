@@ -407,11 +407,95 @@ static cplx amp(const or_run* R, const double* y, int64_t b, int a)
  *   J0 = sum_j w_j S_j  and  J1 = sum_j w_j c_j S_j,
  * so that H_nunu on trajectory i is mu0 * traceless(J0 - c_i J1).
  * Single angle: J0 = D(r/R) S_0 and J1 = 0 (c = 1 for the radial ray). */
+/* Neumaier's compensated summation: *s + *c carries the running sum. */
+static void neu_add(double* s, double* c, double x)
+{
+    const double t = *s + x;
+    if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+    else *c += (x - t) + *s;
+    *s = t;
+}
+
+/* The density sum of trajectory j with the sum_mode order and kind (modes
+ * 1-3; mode 0 is written out in moments_at). */
+static void density_sum_mode(const or_run* R, const double* y, int j, cplx* acc)
+{
+    const int n = R->n, ne = R->ne, na = R->na;
+    const int comp = R->p.sum_mode & 1, rev = (R->p.sum_mode >> 1) & 1;
+    double sr[9], si[9], cr[9], ci[9];
+    for (int i = 0; i < n * n; ++i) sr[i] = si[i] = cr[i] = ci[i] = 0.0;
+    for (int step = 0; step < 2 * ne; ++step) {
+        const int idx = rev ? 2 * ne - 1 - step : step;
+        const int sp = idx / ne, k = idx - sp * ne;
+        const int64_t b = (int64_t)(sp * na + j) * ne + k;
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                cplx rho = c_mul(amp(R, y, b, a), c_conj(amp(R, y, b, c)));
+                cplx t = sp == 0 ? c_scale(rho, R->g[k]) : c_scale(c_conj(rho), -R->gbar[k]);
+                const int i = a * n + c;
+                if (comp) {
+                    neu_add(&sr[i], &cr[i], t.re);
+                    neu_add(&si[i], &ci[i], t.im);
+                } else {
+                    sr[i] += t.re;
+                    si[i] += t.im;
+                }
+            }
+    }
+    for (int i = 0; i < n * n; ++i) acc[i] = c_make(sr[i] + cr[i], si[i] + ci[i]);
+}
+
 static void moments_at(const or_run* R, double r, const double* y, cplx* J0, cplx* J1, cplx* J2, cplx* J3)
 {
     const int n = R->n, ne = R->ne, na = R->na;
     const double* phase = y + 2 * (int64_t)n * R->nb;
     geometry(R, r, R->c, R->w);
+    if (R->p.sum_mode != 0) {
+        OR_PARALLEL_FOR
+        for (int j = 0; j < na; ++j) {
+            cplx acc[9];
+            density_sum_mode(R, y, j, acc);
+            for (int a = 0; a < n; ++a)
+                for (int c = 0; c < n; ++c) {
+                    double dphi = phase[j * n + a] - phase[j * n + c];
+                    R->S[(j * n + a) * n + c] = c_scale(c_mul(c_expi(-dphi), acc[a * n + c]), 2.0);
+                }
+        }
+        for (int i = 0; i < n * n; ++i) {
+            J0[i] = c_make(0, 0);
+            J1[i] = c_make(0, 0);
+            J2[i] = c_make(0, 0);
+            J3[i] = c_make(0, 0);
+        }
+        if (!R->ma) {
+            for (int i = 0; i < n * n; ++i) J0[i] = c_scale(R->S[i], R->w[0]);
+            return;
+        }
+        const int comp = R->p.sum_mode & 1, rev = (R->p.sum_mode >> 1) & 1;
+        const int nm = R->np > 1 ? 4 : 2;
+        for (int i = 0; i < n * n; ++i) {
+            double s[8] = {0}, c[8] = {0};
+            for (int step = 0; step < na; ++step) {
+                const int j = rev ? na - 1 - step : step;
+                const double sn = sqrt((1.0 - R->c[j]) * (1.0 + R->c[j]));
+                const double f[4] = {R->w[j], R->w[j] * R->c[j], R->w[j] * sn * cos(R->phi[j]),
+                                     R->w[j] * sn * sin(R->phi[j])};
+                for (int m = 0; m < nm; ++m) {
+                    const cplx t = c_scale(R->S[j * n * n + i], f[m]);
+                    if (comp) {
+                        neu_add(&s[2 * m], &c[2 * m], t.re);
+                        neu_add(&s[2 * m + 1], &c[2 * m + 1], t.im);
+                    } else {
+                        s[2 * m] += t.re;
+                        s[2 * m + 1] += t.im;
+                    }
+                }
+            }
+            cplx* out[4] = {J0, J1, J2, J3};
+            for (int m = 0; m < nm; ++m) out[m][i] = c_make(s[2 * m] + c[2 * m], s[2 * m + 1] + c[2 * m + 1]);
+        }
+        return;
+    }
     OR_PARALLEL_FOR
     for (int j = 0; j < na; ++j) {
         cplx acc[9];

@@ -41,6 +41,13 @@ typedef struct {
                                accepted step (the FP32-amplitude scheme) */
     int32_t n_azimuth;      /* azimuth bins per emission angle: the extended
                                bulb model (eq 3.18); 0 or 1: the bulb model */
+    int32_t sum_mode;       /* order and kind of the moment sums (eq 3.8, 3.13):
+                               0 plain sums, energies then trajectories
+                               ascending (the reference); 1 the same order with
+                               compensated (Neumaier) sums; 2 plain sums in
+                               descending order; 3 compensated, descending.
+                               Modes 1-3 exist to measure how much of a run's
+                               sensitivity is summation rounding. */
 } or_params;
 
 typedef struct or_run or_run;

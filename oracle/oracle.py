@@ -70,6 +70,7 @@ class _Params(C.Structure):
         ("frame", C.c_int32),
         ("renormalize", C.c_int32),
         ("n_azimuth", C.c_int32),
+        ("sum_mode", C.c_int32),
     ]
 
 

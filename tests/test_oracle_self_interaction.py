@@ -128,3 +128,52 @@ def test_two_species_weights_reproduce_the_four_species_sum():
     expect = _explicit_four_species_rk4(w, w["n_fixed_steps"])
     assert np.abs(1 - expect).max() > 1e-4  # the window changes the flavor content
     np.testing.assert_allclose(p, expect, rtol=0, atol=1e-10)
+
+
+def _exact_density_sums(w, psi):
+    """Correctly rounded (math.fsum) energy sums of the single-angle density
+    terms, formed with the same IEEE products as the oracle's sums: the
+    pin of its compensated summation mode."""
+    import math
+
+    ref = O.Run(w)
+    _, g, gb, _ = ref.tables()
+    n, nb = psi.shape[0], psi.shape[2]
+    ne = nb // 2
+    ar, ai = psi[:, 0, :], psi[:, 1, :]
+    out = np.empty((n, n), dtype=complex)
+    for a in range(n):
+        for c in range(n):
+            re = ar[a] * ar[c] - ai[a] * (-ai[c])     # Re psi_a conj(psi_c), as c_mul forms it
+            im = ar[a] * (-ai[c]) + ai[a] * ar[c]
+            tre = np.concatenate([re[:ne] * g, re[ne:] * (-gb)])
+            tim = np.concatenate([im[:ne] * g, (-im[ne:]) * (-gb)])
+            out[a, c] = math.fsum(tre) + 1j * math.fsum(tim)
+    return out
+
+
+def test_compensated_sums_are_correctly_rounded_within_an_ulp():
+    """Sum mode 1 (Neumaier) gives the single-angle J0 of random states (sums
+    with heavy cancellation) within a couple of ulps of the correctly rounded
+    sum, where the plain ascending sum (mode 0) is off by far more: the
+    compensated mode, used to measure how much of a run's sensitivity is
+    summation rounding, does what it claims."""
+    w = dict(W.single_angle_2f(), n_flavors=3, n_energy=400)
+    nb = 2 * 400
+    psi = W.random_states(3, nb, seed=77)
+    r = 13.5
+    exact = _exact_density_sums(w, psi)
+    ref = O.Run(w)
+    ref.set_state(psi, None, r)
+    _, wj = ref.geometry(r)
+    target = 2.0 * exact * wj[0]
+    errs = {}
+    for mode in (0, 1, 3):
+        o = O.Run(dict(w, sum_mode=mode))
+        o.set_state(psi, None, r)
+        j0, _ = o.moments()
+        errs[mode] = np.abs(j0 - target)
+    scale = np.abs(target).max()
+    assert errs[1].max() <= 4 * np.finfo(float).eps * scale
+    assert errs[3].max() <= 4 * np.finfo(float).eps * scale
+    assert errs[0].max() > 10 * errs[1].max()
