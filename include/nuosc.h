@@ -81,11 +81,13 @@ typedef enum {
 enum { NUOSC_RK4_FIXED = 0, NUOSC_RK_DP54 = 1, NUOSC_EXP_STEPPER = 2 };
 /* Precision of a run.
  *   NUOSC_FP64                amplitudes stored and advanced in FP64.
- *   NUOSC_FP32_AMP            amplitudes stored and advanced in FP32, renormalised
- *                             at every accepted step; moments, step error and
- *                             co-rotating phases in FP64.
+ *   NUOSC_FP32_AMP            amplitudes stored in FP32 and advanced with FP32
+ *                             arithmetic (the per-beam state update), renormalised
+ *                             at every accepted step; the update coefficients,
+ *                             moments, step error, co-rotating phases and step
+ *                             control in FP64.
  *   NUOSC_FP32_AMP_FP64_MATH  amplitudes stored in FP32 (renormalised every
- *                             step), stage arithmetic in FP64 registers. */
+ *                             step), the state update in FP64 registers. */
 enum { NUOSC_FP64 = 0, NUOSC_FP32_AMP = 1, NUOSC_FP32_AMP_FP64_MATH = 2 };
 enum { NUOSC_FRAME_COROTATING = 0, NUOSC_FRAME_LAB = 1 };
 
@@ -183,22 +185,28 @@ nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted
  * is picked up by the next nuosc_step / nuosc_stats call. */
 nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts);
 
-/* Queue one launch of the current attempt: stage in 1..S, where S = 4 (RK4),
- * 7 (Dormand-Prince) or 3 (exponential stepper) and stage S forms the new
- * state, reduces the step error and runs the controller.  For the
- * exponential stepper every stage is a beam kernel followed by a reduction
- * kernel (the second timing interval below).  A full attempt is stages 1..S in order;
- * nuosc_enqueue_steps does exactly that.  For timing tools that bracket
- * individual kernels with events.  NUOSC_E_INVALID for a stage out of range. */
+/* Queue one launch of the current attempt: stage in 1..S with
+ * S = nuosc_num_stages(h).  Runge-Kutta integrators (S = stages + 2: 6 for
+ * RK4, 9 for Dormand-Prince): launches 1..S-2 complete the stages per
+ * trajectory (launch S-2 also writes the coefficient tables of the update
+ * and of the error), launch S-1 forms the new state and its step error
+ * (beam pass), launch S runs the step control and, for an accepted attempt,
+ * takes the power moments of the new state (beam pass).  Exponential
+ * stepper (S = 3): every launch is a beam kernel followed by a reduction
+ * kernel (the second timing interval below), the last one running the
+ * controller.  A full attempt is launches 1..S in order; nuosc_enqueue_steps
+ * does exactly that.  For timing tools that bracket individual kernels with
+ * events.  NUOSC_E_INVALID for a stage out of range. */
 nuosc_status nuosc_enqueue_stage(nuosc_handle* h, int32_t stage);
 
 /* Number of launches S of one step attempt. */
 int32_t nuosc_num_stages(const nuosc_handle* h);
 
-/* Kernel timing for measurement tools.  While enabled, every stage launch
- * records HIP events on the handle's stream before its beam kernel, after
- * it, and after the control kernel that follows the beam kernel of stage 0
- * and of the last stage (the second interval is empty for the other stages).
+/* Kernel timing for measurement tools.  While enabled, every launch records
+ * HIP events on the handle's stream before its main kernel, after it, and
+ * after its second kernel (the moment launch 0 and every launch of the
+ * exponential stepper have one; the second interval is empty for the
+ * others).
  * nuosc_timing_read waits for the stream, adds the elapsed times of all
  * launches recorded since the last read into per-stage sums and writes them:
  * beam_ms and fin_ms (milliseconds, nuosc_num_stages(h) + 1 entries each,

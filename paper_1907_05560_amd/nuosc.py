@@ -330,8 +330,9 @@ class Run:
         self._check(lib().nuosc_timing_enable(self.h, 1 if on else 0))
 
     def timing_read(self):
-        """Summed beam-kernel and control-kernel milliseconds and launch counts
-        per stage (index 0 = the moment launch) since the last read."""
+        """Summed milliseconds of each launch's main kernel and of its second
+        kernel, and launch counts, per launch index (0 = the moment launch)
+        since the last read."""
         n = self.num_stages + 1
         beam = np.zeros(n)
         fin = np.zeros(n)
