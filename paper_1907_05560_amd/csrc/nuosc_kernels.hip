@@ -1177,14 +1177,15 @@ __device__ __forceinline__ void powsum_row(uint64_t base, const T (&up)[G][D + 1
     });
 }
 
-// out_g = P(u_g) y_g for the G beams of a group, P a matrix polynomial of
+// (P(u_g) y_g)_a for the G beams of a group and every row a, handed to
+// sink(g, a, re, im) as soon as the row is formed; P is a matrix polynomial of
 // degree D over full complex N x N matrices, stored row by row: row a holds
 // the 2N reals (re/im of its N entries) of degree 0, then of degree 1, ...,
 // (D + 1) 2N values of type CT from byte address base + a (D + 1) 2N
 // sizeof(CT).  Each row's request waits for the previous row's result.
-template <int D, int N, int G, typename T, typename CT>
-__device__ __forceinline__ void poly_apply(uint64_t base, const T (&up)[G][D + 1], const T (&y)[G][2 * N],
-                                           T (&out)[G][2 * N])
+template <int D, int N, int G, typename T, typename CT, typename Sink>
+__device__ __forceinline__ void poly_rows(uint64_t base, const T (&up)[G][D + 1], const T (&y)[G][2 * N],
+                                          Sink&& sink)
 {
     T M[G][2 * N];
 #pragma unroll
@@ -1204,10 +1205,20 @@ __device__ __forceinline__ void poly_apply(uint64_t base, const T (&up)[G][D + 1
                 re = fma(M[g][2 * b], y[g][2 * b], fma(-M[g][2 * b + 1], y[g][2 * b + 1], re));
                 im = fma(M[g][2 * b], y[g][2 * b + 1], fma(M[g][2 * b + 1], y[g][2 * b], im));
             }
-            out[g][2 * a] = re;
-            out[g][2 * a + 1] = im;
+            sink(g, a, re, im);
         }
     }
+}
+
+// out_g = P(u_g) y_g (poly_rows with the rows stored).
+template <int D, int N, int G, typename T, typename CT>
+__device__ __forceinline__ void poly_apply(uint64_t base, const T (&up)[G][D + 1], const T (&y)[G][2 * N],
+                                           T (&out)[G][2 * N])
+{
+    poly_rows<D, N, G, T, CT>(base, up, y, [&](int g, int a, T re, T im) __attribute__((always_inline)) {
+        out[g][2 * a] = re;
+        out[g][2 * a + 1] = im;
+    });
 }
 
 // u^0 .. u^D.
@@ -1243,7 +1254,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     constexpr int WPT = FinalShape<T>::wpt;
     constexpr int NWV = FinalShape<T>::waves;
     constexpr int G = 2;       // beams of a lane sharing each coefficient load
-    constexpr int NGRP = 1;    // groups of a lane in flight
+    constexpr int NGRP = std::is_same<T, float>::value ? 2 : 1;  // groups of a lane in flight
     constexpr uint32_t STRIDE = 64;
     constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 7) / 8) * 8;  // byte offset of the error table
 
@@ -1339,7 +1350,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
             }
         }
         if constexpr (ERROR) {
-            double y64[G][2 * N], dl[G][2 * N], up[G][DE + 1];
+            double y64[G][2 * N], up[G][DE + 1];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -1347,18 +1358,15 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
                 if constexpr (std::is_same<T, double>::value) powers<DE>((double)u[g], up[g]);
                 else powers<DE>(u64v[g], up[g]);
             }
-            poly_apply<DE, N, G, double, double>(after_all(tb + EOFF, yn[0]), up, y64, dl);
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if (t + g * STRIDE < nbt) {
-#pragma unroll
-                    for (int x = 0; x < 2 * N; ++x) {
-                        const double e = fabs(dl[g][x]);
-                        bad |= !isfinite(e);
+            // the error's max-norm, each row folded in as it is formed
+            poly_rows<DE, N, G, double, double>(
+                after_all(tb + EOFF, yn[0]), up, y64, [&](int g, int, double re, double im) __attribute__((always_inline)) {
+                    if (t + g * STRIDE < nbt) {
+                        const double e = fmax(fabs(re), fabs(im));
+                        bad |= !(isfinite(re) && isfinite(im));
                         emax = fmax(emax, e);
                     }
-                }
-            }
+                });
         }
     };
 
