@@ -19,7 +19,7 @@
 // This is exact algebra on the Runge-Kutta stages (only the rounding order
 // differs from forming every stage state).  One attempt of an S-stage tableau
 // is S + 2 launches:
-//   k_traj<l>, l = 1..S-1 (one wavefront per trajectory, no beam data): J_{l-1}
+//   k_traj<l>, l = 1..S-1 (32 lanes per trajectory, no beam data): J_{l-1}
 //     as the fixed-order sum of the previous launch's partials; completion of
 //     stage l-1 (matter term, collective term, co-rotating frame rate, the
 //     coefficient matrices D_{l-1}); the coefficients C_l and the stage-l

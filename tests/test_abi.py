@@ -59,6 +59,8 @@ def test_footprint_scales_with_the_grid_and_precision():
     dict(r_start_km=5.0), dict(r_end_km=10.0), dict(integrator=7), dict(n_fixed_steps=0),
     dict(integrator=1, rtol=0.0), dict(integrator=1, safety=1.5), dict(precision=3), dict(frame=2),
     dict(mean_e_mev=[11.0, 0.0, 25.0, 25.0]),
+    dict(n_energy=1 << 27, n_angle=4),               # one amplitude component above 4 GiB
+    dict(n_energy=1 << 27, n_angle=4, precision=1),
 ])
 def test_invalid_parameters_are_rejected_without_a_device(bad):
     w = W.single_angle_2f()

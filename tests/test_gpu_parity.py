@@ -342,3 +342,35 @@ def test_nonfinite_state_is_reported():
         run.set_state(psi, ph, 10.0)
         _, st = run.step(3, check=False)
         assert st == nuosc.E_NONFINITE
+
+
+@pytest.mark.parametrize("n_angle,prec", [(0, W.FP64), (7, W.FP64), (7, W.FP32_AMP)])
+def test_two_flavor_vacuum_oscillation_matches_the_closed_form(n_angle, prec):
+    """Without matter and self-interaction every beam oscillates in vacuum:
+    P = 1 - sin^2(2 theta) sin^2(Delta_E L / 2), Delta_E = dm^2 / (2E), with L
+    the path length along the trajectory between the two radii, r c(r)
+    evaluated at both ends (eq 3.3, 3.14; L = r1 - r0 for the radial ray).  A
+    property of the adaptive GPU run at any size, independent of the oracle."""
+    w = dict(W.single_angle_2f(), integrator=W.RK_DP54, mu0_km=0.0, lambda0_km=0.0, n_energy=37,
+             n_angle=n_angle, r_start_km=10.0, r_end_km=40.0, dr_init_km=1e-3, precision=prec)
+    say(f"case: 2f vacuum closed form, n_angle {n_angle}, precision {prec}")
+    with nuosc.Run(w) as run:
+        run.evolve(w["r_end_km"])
+        p = run.probabilities()
+        assert run.stats()["r_km"] == w["r_end_km"]
+    hbarc_ev_km = 197.3269804e6 * 1e-18  # eV km
+    ne, R, r0, r1 = w["n_energy"], w["r_nu_km"], w["r_start_km"], w["r_end_km"]
+    e_mev = w["e_min_mev"] + (np.arange(ne) + 0.5) * (w["e_max_mev"] - w["e_min_mev"]) / ne
+    delta = abs(w["dm2_ev2"]) / (2.0 * e_mev * 1e6) / hbarc_ev_km  # km^-1
+    na = max(n_angle, 1)
+    if n_angle:
+        u = (np.arange(na) + 0.5) / na
+        c = lambda r: np.sqrt(1.0 - (R / r) ** 2 * (1.0 - u ** 2))
+        L = r1 * c(r1) - r0 * c(r0)
+    else:
+        L = np.array([r1 - r0])
+    pe = 1.0 - np.sin(2 * w["theta"]) ** 2 * np.sin(np.outer(L, delta) / 2.0) ** 2   # [traj, energy]
+    expect = np.concatenate([pe.ravel(), pe.ravel()])                               # nu then nubar
+    err = np.abs(p - expect).max()
+    say(f"vacuum closed form n_angle {n_angle} precision {prec}: max |dP| {err:.3e}")
+    assert err <= (1e-6 if prec == W.FP64 else 1e-4)
