@@ -46,4 +46,28 @@ __device__ __forceinline__ void fast_sincos(double x, double& s, double& c)
     if (q & 2) s = -s;
 }
 
+// x of the lane that the DPP control CTRL selects (a pattern within each row
+// of 16 lanes), the whole wavefront active; a double moves as its two halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_pick(double x)
+{
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum of x over the 16 lanes of each row, the same bits in every lane of the
+// row: rotations of the row by 8 and by 4 lanes, then the swaps of lanes 2
+// apart and 1 apart within each quad.  Cross-lane moves of the vector ALU,
+// no LDS traffic.
+__device__ __forceinline__ double row_sum16(double x)
+{
+    x += dpp_pick<0x128>(x);  // row_ror:8
+    x += dpp_pick<0x124>(x);  // row_ror:4
+    x += dpp_pick<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_pick<0xB1>(x);   // quad_perm [1,0,3,2]
+    return x;
+}
+
 }  // namespace nuosc

@@ -162,6 +162,36 @@ __device__ __forceinline__ global<T>* uniform_global(T* p)
     return reinterpret_cast<global<T>*>(((uint64_t)hi << 32) | lo);
 }
 
+// The same view of any run buffer, and plain-data structs copied through it in
+// 8-byte words.  Flat operations (generic pointers) also count against the LDS
+// counter, and one still in flight makes every later wait for a global load a
+// wait for all of them; global operations keep both counters apart.
+template <typename T>
+__device__ __forceinline__ global<T>* gview(T* p)
+{
+    return reinterpret_cast<global<T>*>(reinterpret_cast<uint64_t>(p));
+}
+template <typename T>
+__device__ __forceinline__ T gload(const T* p)
+{
+    static_assert(sizeof(T) % 8 == 0, "8-byte words");
+    T v;
+    uint64_t* d = reinterpret_cast<uint64_t*>(&v);
+    const global<const uint64_t>* s = reinterpret_cast<const global<const uint64_t>*>(reinterpret_cast<uint64_t>(p));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, const T& v)
+{
+    static_assert(sizeof(T) % 8 == 0, "8-byte words");
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(&v);
+    global<uint64_t>* d = reinterpret_cast<global<uint64_t>*>(reinterpret_cast<uint64_t>(p));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+}
+
 template <typename T>
 __device__ __forceinline__ global<T>* elem(global<T>* base, uint32_t i)
 {
@@ -433,11 +463,19 @@ __device__ __forceinline__ TS load_state(global<const TS>* p)
 // launch's error maxima and runs the controller in every workgroup (the same
 // result everywhere; workgroup 0 stores the control block); a rejected attempt
 // ends here.  Then, for the current state y (the accepted new state):
-//   Q_p[j] = sum_k w_k u_k^p y y^+,  p = 0 .. NQ-1  (packed Hermitian, FP64),
-// with two trajectories per wavefront (32 lanes each) and two lanes per beam
-// (the first adds powers 0..H-1, the second H..2H-1), 16 beams of a
-// trajectory per wavefront iteration; the lanes' sums are added by a
-// butterfly over the 16 lanes of a trajectory and parity.  Q_0 is the
+//   Q_p[j] = sum_k w_k u_k^p y y^+,  p = 0 .. NQ-1  (packed Hermitian, FP64).
+// The neutrino and the antineutrino beam of one energy bin have u = 1/E and
+// u = -1/E, so the antineutrino's u^p is (-1)^p u^p and one energy bin adds
+//   u^p (w y y^+ + (-1)^p wbar ybar ybar^+)
+// to Q_p: the even powers take one combination of the two densities and the
+// odd powers the other, half the multiply-adds of one sum per beam.  Two
+// trajectories per wavefront (32 lanes each), two lanes per energy bin (the
+// first adds the even powers 2k, the second the odd powers 2k + 1, k < H),
+// 16 energy bins of a trajectory per wavefront iteration: each row of 16 lanes
+// holds one trajectory and one parity of the powers, so that the lanes' sums
+// are row sums (cross-lane moves of the vector ALU).  The first bins are
+// requested before the step controller has decided, from the buffer an
+// accepted step makes current (a rejected attempt drops them).  Q_0 is the
 // density sum of the state itself: rotated to the lab frame and weighted at
 // the state's radius, it gives the workgroup's partial of J_0 (buffer 0).
 constexpr int kPowerWaves = kTrajPerBlock / 2;
@@ -448,9 +486,9 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 {
     constexpr int NM = Shape<N>::NM, NU = Shape<N>::NU, NV = NJ * NM;
     constexpr int NQ = Poly<TAB>::NQ;
-    constexpr int H = (NQ + 1) / 2;  // powers per lane
-    constexpr int NSLOT = 4;         // beams of a lane in flight
-    constexpr uint32_t STRIDE = 16;  // beam-slot stride of a lane pair
+    constexpr int H = (NQ + 1) / 2;  // powers per lane (p = 2k + parity)
+    constexpr int NSLOT = 2;         // energy bins of a lane in flight
+    constexpr uint32_t STRIDE = 16;  // energy-bin stride of a lane
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
@@ -458,33 +496,27 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     __shared__ double serr[kPowerWaves];
 
     Control C;
+    double m = 0.0;
     if constexpr (FORCE) {
-        C = rc.ctrl[1];
+        C = gload(rc.ctrl + 1);
     } else {
-        C = rc.ctrl[0];
+        C = gload(rc.ctrl);
         if (C.status != 0) return;  // the attempt did not run
-        double m = 0.0;
-        for (int p = tid; p < rc.nblkf; p += 64 * kPowerWaves) m = fmax(m, rc.errpart[p]);
-        m = wave_max(m);
-        if (lane == 0) serr[wave] = m;
-        __syncthreads();
-        m = serr[0];
-        for (int w = 1; w < kPowerWaves; ++w) m = fmax(m, serr[w]);
-        const bool accepted = control_step<TAB>(rc, C, m);
-        C.fresh = accepted ? 1 : 0;
-        if (blk == 0 && tid == 0) rc.ctrl[1] = C;
-        if (!accepted) return;
+        for (int p = tid; p < rc.nblkf; p += 64 * kPowerWaves) m = fmax(m, gview(rc.errpart)[p]);
     }
-
-    const int cur = C.cur;
-    const int g = lane >> 5, hb = lane & 1, q = (lane & 31) >> 1;
+    // an accepted attempt makes the other buffer current
+    const int cur = FORCE ? C.cur : (C.cur ^ 1);
+    const int g = lane >> 5, hb = (lane >> 4) & 1, q = lane & 15;
     const int jt = 2 * wave + g;
     const int j = blk * kTrajPerBlock + jt;
     const bool active = j < rc.na;
     const uint32_t ne = (uint32_t)rc.ne;
-    const uint32_t nbt = active ? 2u * ne : 0u;
-    const uint32_t base0 = (uint32_t)j * ne;
-    const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
+    // bins of the wavefront's loop (both trajectories of a wavefront are idle together)
+    const uint32_t nel = (blk * kTrajPerBlock + 2 * wave < rc.na) ? ne : 0u;
+    // neutrino and antineutrino beams of trajectory j (of trajectory 0 for an
+    // idle lane group, whose loads are never used)
+    const uint32_t base0 = active ? (uint32_t)j * ne : 0u;
+    const uint32_t base1 = active ? (uint32_t)(j + rc.na) * ne : (uint32_t)rc.na * ne;
     const size_t ld = (size_t)rc.nb_pad;
     const TS* src = reinterpret_cast<const TS*>(rc.psi[cur]);
     global<const TS>* __restrict__ srcq[2 * N];
@@ -493,86 +525,108 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     global<const double>* __restrict__ uinv = uniform_global(rc.uinv64);
     global<const double>* __restrict__ wgtp = uniform_global(rc.wgt);
 
+    // energy bin e: both amplitudes, u = 1/E, the two weights.  Unconditional
+    // (a bin past the end reads bin 0 and adds with weight 0), so that the
+    // loop is straight-line code in which each load refills the registers of
+    // its slot: no copies, and no wait for loads still in flight.
+    auto fetch = [&](uint32_t e, TS* yv, TS* zv, double& uv, double& wv, double& wb) __attribute__((always_inline)) {
+        const uint32_t ec = e < ne ? e : 0u;
+#pragma unroll
+        for (int x = 0; x < 2 * N; ++x) yv[x] = load_state(elem(srcq[x], base0 + ec));
+#pragma unroll
+        for (int x = 0; x < 2 * N; ++x) zv[x] = load_state(elem(srcq[x], base1 + ec));
+        uv = *elem(uinv, ec);
+        wv = *elem(wgtp, ec);
+        wb = *elem(wgtp, ne + ec);
+    };
+    TS ys[NSLOT][2 * N], zs[NSLOT][2 * N];
+    double us[NSLOT], ws[NSLOT], wbs[NSLOT];
+    const uint32_t e0 = (uint32_t)q;
+    static_for<0, NSLOT>([&](auto Sc) {
+        constexpr int sl = decltype(Sc)::value;
+        fetch(e0 + sl * STRIDE, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
+    });
+
+    if constexpr (!FORCE) {
+        m = wave_max(m);
+        if (lane == 0) serr[wave] = m;
+        __syncthreads();
+        m = serr[0];
+        for (int w = 1; w < kPowerWaves; ++w) m = fmax(m, serr[w]);
+        const bool accepted = control_step<TAB>(rc, C, m);
+        C.fresh = accepted ? 1 : 0;
+        if (blk == 0 && tid == 0) gstore(rc.ctrl + 1, C);
+        if (!accepted) return;
+    }
+
     double acc[H][NM];
 #pragma unroll
     for (int k = 0; k < H; ++k)
 #pragma unroll
         for (int x = 0; x < NM; ++x) acc[k][x] = 0.0;
 
-    auto fetch = [&](uint32_t t, TS* yv, double& uv, double& wv) __attribute__((always_inline)) {
-        if (t < nbt) {
-            const uint32_t off = t + base0 + (t >= ne ? delta : 0u);
-#pragma unroll
-            for (int x = 0; x < 2 * N; ++x) yv[x] = load_state(elem(srcq[x], off));
-            uv = *elem(uinv, t);
-            wv = *elem(wgtp, t);
-        }
-    };
-    auto process = [&](const TS* yv, double u, double w) __attribute__((always_inline)) {
-        // the weighted powers w u^(H hb + k), k < H: the second lane of the
-        // pair starts at power H
-        double uh = 1.0, bpow = u;
-#pragma unroll
-        for (int e = H; e > 0; e >>= 1) {
-            if (e & 1) uh *= bpow;
-            bpow *= bpow;
-        }
+    auto process = [&](uint32_t e, const TS* yv, const TS* zv, double u, double w, double wb) __attribute__((always_inline)) {
+        if (!(active && e < ne)) w = wb = 0.0;
+        // u^(2k + parity): the odd lanes start at u
+        const double u2 = u * u;
         double pw[H];
-        pw[0] = hb ? w * uh : w;
+        pw[0] = hb ? u : 1.0;
 #pragma unroll
-        for (int k = 1; k < H; ++k) pw[k] = pw[k - 1] * u;
-        double y[2 * N];
+        for (int k = 1; k < H; ++k) pw[k] = pw[k - 1] * u2;
+        // X = w y y^+ + s z z^+ with s = (-1)^parity wbar, entry by entry
+        const double s = hb ? -wb : wb;
+        double y[2 * N], z[2 * N];
 #pragma unroll
-        for (int x = 0; x < 2 * N; ++x) y[x] = (double)yv[x];
-        // each entry of y y^+ is formed and added to its H sums at once
+        for (int x = 0; x < 2 * N; ++x) {
+            y[x] = (double)yv[x];
+            z[x] = (double)zv[x];
+        }
         auto add = [&](int x, double v) __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < H; ++k) acc[k][x] = fma(v, pw[k], acc[k][x]);
         };
+        // Re and Im of v_a conj(v_b)
+        auto re = [&](const double* v, int a, int b) __attribute__((always_inline)) {
+            return fma(v[2 * a], v[2 * b], v[2 * a + 1] * v[2 * b + 1]);
+        };
+        auto im = [&](const double* v, int a, int b) __attribute__((always_inline)) {
+            return fma(v[2 * a + 1], v[2 * b], -(v[2 * a] * v[2 * b + 1]));
+        };
 #pragma unroll
-        for (int a = 0; a < N; ++a) add(a, fma(y[2 * a], y[2 * a], y[2 * a + 1] * y[2 * a + 1]));
+        for (int a = 0; a < N; ++a) add(a, fma(w, re(y, a, a), s * re(z, a, a)));
 #pragma unroll
         for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
                 const int x = N + 2 * Shape<N>::up(a, b);
-                add(x, fma(y[2 * a], y[2 * b], y[2 * a + 1] * y[2 * b + 1]));          // Re y_a conj(y_b)
-                add(x + 1, fma(y[2 * a + 1], y[2 * b], -(y[2 * a] * y[2 * b + 1])));  // Im
+                add(x, fma(w, re(y, a, b), s * re(z, a, b)));
+                add(x + 1, fma(w, im(y, a, b), s * im(z, a, b)));
             }
     };
 
-    TS ys[NSLOT][2 * N];
-    double us[NSLOT], ws[NSLOT];
-    const uint32_t t0 = (uint32_t)q;
-    static_for<0, NSLOT>([&](auto Sc) {
-        constexpr int sl = decltype(Sc)::value;
-        us[sl] = 0.0;
-        ws[sl] = 0.0;
-        fetch(t0 + sl * STRIDE, ys[sl], us[sl], ws[sl]);
-    });
 #pragma unroll 1
-    for (uint32_t t = t0; t < nbt; t += NSLOT * STRIDE) {
+    for (uint32_t e = 0; e < nel; e += NSLOT * STRIDE) {
         static_for<0, NSLOT>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
-            const uint32_t ts = t + sl * STRIDE;
-            if (sl == 0 || ts < nbt) process(ys[sl], us[sl], ws[sl]);
-            fetch(ts + NSLOT * STRIDE, ys[sl], us[sl], ws[sl]);
+            const uint32_t es = e + e0 + sl * STRIDE;
+            process(es, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
+            fetch(es + NSLOT * STRIDE, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
+            // keep the refill of this slot ahead of the next slot's work
+            __builtin_amdgcn_sched_barrier(0);
         });
     }
 
-    // sums over the 16 lanes of one trajectory and parity
+    // sums over the 16 lanes of a row (one trajectory, one parity of the powers)
 #pragma unroll
-    for (int off = 2; off < 32; off <<= 1)
+    for (int k = 0; k < H; ++k)
 #pragma unroll
-        for (int k = 0; k < H; ++k)
-#pragma unroll
-            for (int x = 0; x < NM; ++x) acc[k][x] += __shfl_xor(acc[k][x], off, 64);
+        for (int x = 0; x < NM; ++x) acc[k][x] = row_sum16(acc[k][x]);
 
     if (active && q == 0) {
-        double* dst = rc.qbuf + (size_t)j * rc.qstride;
+        global<double>* dst = gview(rc.qbuf) + (size_t)j * rc.qstride;
 #pragma unroll
         for (int k = 0; k < H; ++k) {
-            const int p = hb * H + k;
+            const int p = 2 * k + hb;
             if (p < NQ)
 #pragma unroll
                 for (int x = 0; x < NM; ++x) dst[p * NM + x] = acc[k][x];
@@ -586,7 +640,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         double ph[N], zz[2][NU > 0 ? NU : 1][2];
         for (int gg = 0; gg < 2; ++gg) {
             const int jj = blk * kTrajPerBlock + 2 * wave + gg;
-            for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? rc.phase[cur][(size_t)jj * N + a] : 0.0;
+            for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? gview(rc.phase[cur])[(size_t)jj * N + a] : 0.0;
             rotation<N>(ph, zz[gg], lane, 0);
         }
         for (int u = 0; u < NU; ++u) {
@@ -624,7 +678,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     if (tid < NV) {
         double s = swave[0][tid];
         for (int w = 1; w < kTrajPerBlock; ++w) s += swave[w][tid];
-        rc.partial[(size_t)tid * rc.pstride + blk] = s;  // buffer 0
+        gview(rc.partial)[(size_t)tid * rc.pstride + blk] = s;  // buffer 0
     }
 }
 
@@ -655,6 +709,13 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 //   4. Tables of the update 1 + sum_m b_m D_m (type TF) and of the error
 //      sum_m e_m D_m (FP64) for k_final, row by row (row a: degree 0, 1, ...
 //      of its 2n reals); RK4: the new state's phase.
+// Entry k (re, im) of a full complex matrix in LDS, row-major with re and im
+// adjacent: one 16-byte read (the matrices are 16-byte aligned).
+__device__ __forceinline__ double2 ldsc(const double* m, int k)
+{
+    return *reinterpret_cast<const double2*>(m + 2 * k);
+}
+
 constexpr int kTrajLanes = 32;
 constexpr int kTrajWaves = kTrajPerBlock * kTrajLanes / 64;
 
@@ -684,10 +745,12 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     const int j = blk * TPB + jt;
     const bool active = j < rc.na;
 
-    __shared__ double sQ[TPB][NQL * NM];                 // Q_p packed; later the X_d (packed)
-    __shared__ double sC[TPB][S * NC];                   // C_{L-1}, then C_L
-    __shared__ double sT[TPB][TABLES ? 1 : S * NC];      // T_d
-    __shared__ double sN[TPB][2 * NC];                   // N0, N1
+    // Q_p as full complex matrices (row-major, re/im adjacent, so that an
+    // entry is one 16-byte LDS read); later the X_d (packed)
+    __shared__ __align__(16) double sQ[TPB][NQL * NC];
+    __shared__ __align__(16) double sC[TPB][S * NC];                   // C_{L-1}, then C_L
+    __shared__ __align__(16) double sT[TPB][TABLES ? 2 : S * NC];      // T_d
+    __shared__ __align__(16) double sN[TPB][2 * NC];                   // N0, N1
     __shared__ double swave[TPB][NV];
     __shared__ double sJ[NV];
 
@@ -815,9 +878,26 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             nerr[it][1] = ei;
         }
         if constexpr (!TABLES) {
+            // packed value x of Q_p into the full matrix: a diagonal entry with a
+            // zero imaginary part, an upper entry and its conjugate below
 #pragma unroll
-            for (int i = 0; i < QV; ++i)
-                if (li + LT * i < NQL * NM) sQ[jt][li + LT * i] = qv[i];
+            for (int i = 0; i < QV; ++i) {
+                const int v = li + LT * i;
+                if (v < NQL * NM) {
+                    const int pp = v / NM, x = v - pp * NM;
+                    double* Qf = &sQ[jt][pp * NC];
+                    if (x < N) {
+                        Qf[2 * (x * N + x)] = qv[i];
+                        Qf[2 * (x * N + x) + 1] = 0.0;
+                    } else {
+                        int a = 0, b = 1;
+                        pair_of<N>((x - N) >> 1, a, b);
+                        const bool im = ((x - N) & 1) != 0;
+                        Qf[2 * (a * N + b) + (im ? 1 : 0)] = qv[i];
+                        Qf[2 * (b * N + a) + (im ? 1 : 0)] = im ? -qv[i] : qv[i];
+                    }
+                }
+            }
         }
     }
 
@@ -908,17 +988,14 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
                     if (d <= L - 1) {
-                        const double xr = sN[jt][2 * (a * N + c)], xi = sN[jt][2 * (a * N + c) + 1];
-                        const double yr = sC[jt][d * NC + 2 * (c * N + b)], yi = sC[jt][d * NC + 2 * (c * N + b) + 1];
-                        re = fma(xr, yr, fma(-xi, yi, re));
-                        im = fma(xr, yi, fma(xi, yr, im));
+                        const double2 x = ldsc(&sN[jt][0], a * N + c), y = ldsc(&sC[jt][d * NC], c * N + b);
+                        re = fma(x.x, y.x, fma(-x.y, y.y, re));
+                        im = fma(x.x, y.y, fma(x.y, y.x, im));
                     }
                     if (d >= 1) {
-                        const double xr = sN[jt][NC + 2 * (a * N + c)], xi = sN[jt][NC + 2 * (a * N + c) + 1];
-                        const double yr = sC[jt][(d - 1) * NC + 2 * (c * N + b)];
-                        const double yi = sC[jt][(d - 1) * NC + 2 * (c * N + b) + 1];
-                        re = fma(xr, yr, fma(-xi, yi, re));
-                        im = fma(xr, yi, fma(xi, yr, im));
+                        const double2 x = ldsc(&sN[jt][NC], a * N + c), y = ldsc(&sC[jt][(d - 1) * NC], c * N + b);
+                        re = fma(x.x, y.x, fma(-x.y, y.y, re));
+                        im = fma(x.x, y.y, fma(x.y, y.x, im));
                     }
                 }
                 Dn[it][0] = re;
@@ -994,19 +1071,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             wave_sync();
 
             // ---- T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+   (item (d, a, b))
-            auto qval = [&](int p, int a, int c, double& re, double& im) __attribute__((always_inline)) {
-                const double* Qp = &sQ[jt][p * NM];
-                if (a == c) {
-                    re = Qp[a];
-                    im = 0.0;
-                } else if (a < c) {
-                    re = Qp[N + 2 * Shape<N>::up(a, c)];
-                    im = Qp[N + 2 * Shape<N>::up(a, c) + 1];
-                } else {
-                    re = Qp[N + 2 * Shape<N>::up(c, a)];
-                    im = -Qp[N + 2 * Shape<N>::up(c, a) + 1];
-                }
-            };
+
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
@@ -1019,13 +1084,11 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                         double re = 0.0, im = 0.0;
 #pragma unroll
                         for (int c = 0; c < N; ++c) {
-                            double qr, qi;
-                            qval(d + dd, a, c, qr, qi);
-                            const double cr = sC[jt][dd * NC + 2 * (b * N + c)];
-                            const double ci = sC[jt][dd * NC + 2 * (b * N + c) + 1];
+                            const double2 q = ldsc(&sQ[jt][(d + dd) * NC], a * N + c);
+                            const double2 cc = ldsc(&sC[jt][dd * NC], b * N + c);
                             // Q_{d+dd}[a][c] conj(C_dd[b][c])
-                            re = fma(qr, cr, fma(qi, ci, re));
-                            im = fma(qi, cr, fma(-qr, ci, im));
+                            re = fma(q.x, cc.x, fma(q.y, cc.y, re));
+                            im = fma(q.y, cc.x, fma(-q.x, cc.y, im));
                         }
                         rdd[dd] = re;
                         idd[dd] = im;
@@ -1055,10 +1118,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                     double re = 0.0, im = 0.0;
 #pragma unroll
                     for (int c = 0; c < N; ++c) {
-                        const double xr = sC[jt][d * NC + 2 * (a * N + c)], xi = sC[jt][d * NC + 2 * (a * N + c) + 1];
-                        const double yr = sT[jt][d * NC + 2 * (c * N + b)], yi = sT[jt][d * NC + 2 * (c * N + b) + 1];
-                        re = fma(xr, yr, fma(-xi, yi, re));
-                        im = fma(xr, yi, fma(xi, yr, im));
+                        const double2 x = ldsc(&sC[jt][d * NC], a * N + c), y = ldsc(&sT[jt][d * NC], c * N + b);
+                        re = fma(x.x, y.x, fma(-x.y, y.y, re));
+                        im = fma(x.x, y.y, fma(x.y, y.x, im));
                     }
                     double* X = &sQ[jt][d * NM];
                     if (k < N) {
