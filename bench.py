@@ -122,8 +122,11 @@ def beam_model(form, idx):
       state update: per row of the n x n complex update matrix, 2n reals x
         (DN + 1) power-sum FMAs, then n complex multiply-adds (4 FMAs each);
         the same with degree DE in FP64 for the error; FP32 renormalisation;
-      power moments: the density entries (n diagonal, n(n-1)/2 complex
-        off-diagonal) and NQ x n^2 FMAs for Q_0 .. Q_{NQ-1}."""
+      power moments, per energy bin (its neutrino and antineutrino beam,
+        u = 1/E and -1/E): both density matrices (n diagonal, n(n-1)/2
+        complex off-diagonal entries each), their even and odd combinations
+        w rho +- wbar rhobar, the powers of u and NQ x n^2 FMAs for
+        Q_0 .. Q_{NQ-1}; half of that per beam."""
     n, nb = form["n"], form["beams"]
     state = 2 * n * form["amp_bytes"] * nb
     S = DP_S
@@ -136,7 +139,8 @@ def beam_model(form, idx):
         return 2 * state, (upd + err + ren) * nb
     nm = n * n
     dens = 2 * n + 2 * n + (n * (n - 1) // 2) * 2 * 2
-    return state, (dens + 2 * DP_NQ * nm + DP_NQ) * nb
+    pair = 2 * dens + 5 * nm + DP_NQ + 2 * DP_NQ * nm
+    return state, pair * nb // 2
 
 
 def traffic_of(name):

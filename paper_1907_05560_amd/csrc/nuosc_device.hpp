@@ -70,4 +70,32 @@ __device__ __forceinline__ double row_sum16(double x)
     return x;
 }
 
+// x of lane l (l wave-uniform), as a wave-uniform value.
+__device__ __forceinline__ double lane_value(double x, int l)
+{
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum of x over the wavefront, the same bits in every lane: the row sums,
+// then (row 0 + row 1) + (row 2 + row 3).
+__device__ __forceinline__ double wave_sum_rows(double x)
+{
+    x = row_sum16(x);
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+}
+
+// Maximum of x over the wavefront (fmax: a NaN is dropped while a number is
+// left), the same in every lane.
+__device__ __forceinline__ double wave_max_rows(double x)
+{
+    x = fmax(x, dpp_pick<0x128>(x));
+    x = fmax(x, dpp_pick<0x124>(x));
+    x = fmax(x, dpp_pick<0x4E>(x));
+    x = fmax(x, dpp_pick<0xB1>(x));
+    return fmax(fmax(lane_value(x, 0), lane_value(x, 16)), fmax(lane_value(x, 32), lane_value(x, 48)));
+}
+
 }  // namespace nuosc

@@ -122,22 +122,6 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-// Lane k < NV stores v[k] to dst[k]: NV values that every lane of the
-// wavefront holds, written with one store instruction instead of NV.
-template <int NV, typename D>
-__device__ __forceinline__ void lane_scatter(D* dst, const double (&v)[NV], int lane)
-{
-    if (lane < NV) {
-        double x = v[0];
-#pragma unroll
-        for (int k = 1; k < NV; ++k) {
-            x = (lane == k) ? v[k] : x;
-            asm volatile("" : "+v"(x));  // a select chain, not a table in scratch memory
-        }
-        dst[lane] = (D)x;
-    }
-}
-
 // Orders the LDS accesses of one wavefront (its own LDS region only).
 __device__ __forceinline__ void wave_sync()
 {
@@ -190,6 +174,22 @@ __device__ __forceinline__ void gstore(T* p, const T& v)
     global<uint64_t>* d = reinterpret_cast<global<uint64_t>*>(reinterpret_cast<uint64_t>(p));
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+}
+
+// Lane k < NV stores v[k] to dst[k]: NV values that every lane of the
+// wavefront holds, written with one store instruction instead of NV.
+template <int NV>
+__device__ __forceinline__ void lane_scatter(global<double>* dst, const double (&v)[NV], int lane)
+{
+    if (lane < NV) {
+        double x = v[0];
+#pragma unroll
+        for (int k = 1; k < NV; ++k) {
+            x = (lane == k) ? v[k] : x;
+            asm volatile("" : "+v"(x));  // a select chain, not a table in scratch memory
+        }
+        dst[lane] = x;
+    }
 }
 
 template <typename T>
@@ -413,7 +413,7 @@ __device__ __forceinline__ void load_partials(const RunConst& rc, int par, int n
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ps = rc.pstride;
-    const double* src = rc.partial + (size_t)(par & 1) * NV * ps;
+    const global<const double>* src = gview<const double>(rc.partial) + (size_t)(par & 1) * NV * ps;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
@@ -430,7 +430,7 @@ __device__ void finish_partials(const RunConst& rc, int par, int nblk, const Par
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ps = rc.pstride;
-    const double* src = rc.partial + (size_t)(par & 1) * NV * ps;
+    const global<const double>* src = gview<const double>(rc.partial) + (size_t)(par & 1) * NV * ps;
 #pragma unroll
     for (int i = 0; i < PartialRegs<NV, NW>::VPW; ++i) {
         const int v = wave + i * NW;
@@ -440,7 +440,7 @@ __device__ void finish_partials(const RunConst& rc, int par, int nblk, const Par
         acc += r.x[i][2];
         acc += r.x[i][3];
         for (int p = lane + 256; p < nblk; p += 64) acc += src[(size_t)v * ps + p];
-        acc = wave_sum(acc);
+        acc = wave_sum_rows(acc);
         if (lane == 0) out[v] = acc;
     }
     __syncthreads();
@@ -548,7 +548,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     });
 
     if constexpr (!FORCE) {
-        m = wave_max(m);
+        m = wave_max_rows(m);
         if (lane == 0) serr[wave] = m;
         __syncthreads();
         m = serr[0];
@@ -657,8 +657,8 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
             traj_geometry(rc, j, C.r, c, w);
             double cph = 1.0, sph = 0.0;
             if constexpr (NJ == 4) {
-                cph = rc.azi[2 * (size_t)j];
-                sph = rc.azi[2 * (size_t)j + 1];
+                cph = gview(rc.azi)[2 * (size_t)j];
+                sph = gview(rc.azi)[2 * (size_t)j + 1];
             }
             angle_weights<NJ>(rc, c, w, cph, sph, f);
             double Sv[NM];
@@ -760,7 +760,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     //      the earlier stages, the power moments
     Control C{};
     {
-        Control* vc = rc.ctrl + (L == 1 ? 1 : 0);
+        global<Control>* vc = gview(rc.ctrl) + (L == 1 ? 1 : 0);
         C.r = __hip_atomic_load(&vc->r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         C.h = __hip_atomic_load(&vc->h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         C.cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -774,28 +774,28 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     const int jl = active ? j : 0;
     double ph01[2][N], G[L][N];
     for (int a = 0; a < N; ++a) {
-        ph01[0][a] = rc.phase[0][(size_t)jl * N + a];
-        ph01[1][a] = rc.phase[1][(size_t)jl * N + a];
+        ph01[0][a] = gview(rc.phase[0])[(size_t)jl * N + a];
+        ph01[1][a] = gview(rc.phase[1])[(size_t)jl * N + a];
     }
     for (int m = 0; m < NH; ++m)
-        for (int a = 0; a < N; ++a) G[m][a] = rc.gbuf[((size_t)jl * kMaxStages + m) * N + a];
+        for (int a = 0; a < N; ++a) G[m][a] = gview(rc.gbuf)[((size_t)jl * kMaxStages + m) * N + a];
     double qv[QV];
     {
-        const double* qs = rc.qbuf + (size_t)jl * rc.qstride;
+        const global<double>* qs = gview(rc.qbuf) + (size_t)jl * rc.qstride;
 #pragma unroll
         for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && li + LT * i < NQL * NM) ? qs[li + LT * i] : 0.0;
     }
     // the stored coefficient matrices each item needs (in range for every lane)
     double Dh[NIT][NH > 0 ? NH : 1][2];
     {
-        const double* dsrc = rc.dbuf + (size_t)jl * rc.dstride;
+        const global<double>* dsrc = gview(rc.dbuf) + (size_t)jl * rc.dstride;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
 #pragma unroll
             for (int m = 0; m < NH; ++m) {
                 const bool have = idx < ITEMS && d <= m + 1;
-                const double* p = dsrc + (have ? (size_t)(PY::doff(m) + d) * NC + 2 * e : 0);
+                const global<double>* p = dsrc + (have ? (size_t)(PY::doff(m) + d) * NC + 2 * e : 0);
                 Dh[it][m][0] = have ? p[0] : 0.0;
                 Dh[it][m][1] = have ? p[1] : 0.0;
             }
@@ -803,10 +803,10 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     }
     double cph = 1.0, sph = 0.0;
     if constexpr (NJ == 4) {
-        cph = rc.azi[2 * (size_t)jl];
-        sph = rc.azi[2 * (size_t)jl + 1];
+        cph = gview(rc.azi)[2 * (size_t)jl];
+        sph = gview(rc.azi)[2 * (size_t)jl + 1];
     }
-    if (L == 1 && blk == 0 && tid == 0) rc.ctrl[0] = rc.ctrl[1];
+    if (L == 1 && blk == 0 && tid == 0) gstore(rc.ctrl, gload(rc.ctrl + 1));
     if (C.status != 0) return;  // run finished: attempts are no-ops
     const int cur = C.cur;
     const double h = C.h;
@@ -904,9 +904,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     // ---- J_{L-1}
     if (L > 1 || C.fresh) {
         finish_partials<NV, NW>(rc, L - 1, npart, xp, sJ);
-        if (blk == 0 && tid < NV) rc.jhist[(size_t)(L - 1) * NV + tid] = sJ[tid];
+        if (blk == 0 && tid < NV) gview(rc.jhist)[(size_t)(L - 1) * NV + tid] = sJ[tid];
     } else {
-        if (tid < NV) sJ[tid] = rc.jhist[tid];
+        if (tid < NV) sJ[tid] = gview(rc.jhist)[tid];
         __syncthreads();
     }
 
@@ -972,12 +972,12 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             sN[jt][i] = part == 0 ? h * xi : -h * xr;
         }
         if (li == 0)
-            for (int a = 0; a < N; ++a) rc.gbuf[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
+            for (int a = 0; a < N; ++a) gview(rc.gbuf)[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
         wave_sync();
 
         // ---- D_{L-1,d} = N0 C_{L-1,d} + N1 C_{L-1,d-1}
         double Dn[NIT][2];
-        double* ddst = rc.dbuf + (size_t)j * rc.dstride + (size_t)PY::doff(L - 1) * NC;
+        global<double>* ddst = gview(rc.dbuf) + (size_t)j * rc.dstride + (size_t)PY::doff(L - 1) * NC;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
@@ -1011,9 +1011,9 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         if constexpr (TABLES) {
             // ---- update and error tables for the state-update launch
             constexpr int DN = PY::DN, DE = PY::DE;
-            char* tb = reinterpret_cast<char*>(rc.ftab) + (size_t)j * rc.fstride;
-            TF* cn = reinterpret_cast<TF*>(tb);
-            double* ce = reinterpret_cast<double*>(tb + (((DN + 1) * NC * sizeof(TF) + 7) / 8) * 8);
+            global<char>* tb = gview(reinterpret_cast<char*>(rc.ftab)) + (size_t)j * rc.fstride;
+            global<TF>* cn = reinterpret_cast<global<TF>*>(tb);
+            global<double>* ce = reinterpret_cast<global<double>*>(tb + (((DN + 1) * NC * sizeof(TF) + 7) / 8) * 8);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
@@ -1045,7 +1045,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 // the new state's phase Phi_n + h sum_m b_m G_m
                 double ph[N];
                 stage_phase<TAB, N>(S, h, phn, G, ph);
-                lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, li);
+                lane_scatter(gview(rc.phase[cur ^ 1]) + (size_t)j * N, ph, li);
             }
         } else {
             // ---- C_L = (1 + sum_{m<L-1} a_Lm D_m) + a_{L,L-1} D_{L-1}
@@ -1066,7 +1066,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             // frame of stage L (its phase needs G_{L-1}), while the LDS writes land
             double zL[NUA][2], ph[N];
             stage_phase<TAB, N>(L, h, phn, G, ph);
-            if constexpr (TAB::fsal && L == S - 1) lane_scatter(rc.phase[cur ^ 1] + (size_t)j * N, ph, li);
+            if constexpr (TAB::fsal && L == S - 1) lane_scatter(gview(rc.phase[cur ^ 1]) + (size_t)j * N, ph, li);
             rotation<N>(ph, zL, li, gbase);
             wave_sync();
 
@@ -1169,7 +1169,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         if (tid < NV) {
             double s0 = swave[0][tid];
             for (int w = 1; w < TPB; ++w) s0 += swave[w][tid];
-            rc.partial[((size_t)(L & 1) * NV + tid) * rc.pstride + blk] = s0;
+            gview(rc.partial)[((size_t)(L & 1) * NV + tid) * rc.pstride + blk] = s0;
         }
     }
 }
@@ -1327,14 +1327,14 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     const bool active = j < rc.na;
     __shared__ double swave[NWV];
 
-    const Control* vc = rc.ctrl;  // ctrl[0]
+    const global<Control>* vc = gview(rc.ctrl);  // ctrl[0]
     const int status = __hip_atomic_load(&vc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     const int cur = __hip_atomic_load(&vc->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (status != 0) return;
 
     const uint32_t ne = (uint32_t)rc.ne;
     const uint32_t nbt = active ? 2u * ne : 0u;
-    const uint32_t base0 = (uint32_t)j * ne;
+    const uint32_t base0 = active ? (uint32_t)j * ne : 0u;
     const uint32_t delta = (uint32_t)(rc.na - 1) * ne;
     const size_t ld = (size_t)rc.nb_pad;
     // one scalar base per state buffer; component x of a beam at byte offset
@@ -1352,27 +1352,25 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     const uint64_t tb = ((uint64_t)tb_hi << 32) | (uint64_t)tb_lo;
 
     double emax = 0.0;
+    double chk = 0.0;  // stays 0 while every error component is finite, NaN otherwise
     bool bad = false;
     auto offset = [&](uint32_t t) __attribute__((always_inline)) { return t + base0 + (t >= ne ? delta : 0u); };
-    // one group: the G beams t, t + 64, ... of the lane (beams past the end are
-    // computed on zeros and neither stored nor counted)
+    // one group: the G beams t, t + 64, ... of the lane.  A beam past the end
+    // is replaced by the trajectory's first beam, whose update is not stored
+    // (its error is that beam's own, so the maximum is unchanged).  The loads
+    // are unconditional: each refills its slot's registers, so the loop holds
+    // no copies that would wait for loads in flight.
     auto fetch = [&](uint32_t t, TS (&yv)[G][2 * N], T (&uv)[G], double (&u64v)[G]) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const uint32_t tg = t + g * STRIDE;
-            if (tg < nbt) {
-                const uint32_t off = offset(tg) * (uint32_t)sizeof(TS);
+            const uint32_t tc = tg < nbt ? tg : 0u;
+            const uint32_t off = offset(tc) * (uint32_t)sizeof(TS);
 #pragma unroll
-                for (int x = 0; x < 2 * N; ++x)
-                    yv[g][x] = load_state(reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb)));
-                uv[g] = *elem(uinv, tg);
-                if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = *elem(uinv64, tg);
-            } else {
-#pragma unroll
-                for (int x = 0; x < 2 * N; ++x) yv[g][x] = (TS)0;
-                uv[g] = 0;
-                if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = 0.0;
-            }
+            for (int x = 0; x < 2 * N; ++x)
+                yv[g][x] = load_state(reinterpret_cast<global<const TS>*>(srcb + (uint64_t)(off + (uint32_t)x * ldb)));
+            uv[g] = *elem(uinv, tc);
+            if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = *elem(uinv64, tc);
         }
     };
     auto process = [&](uint32_t t, const TS (&yv)[G][2 * N], const T (&u)[G], const double (&u64v)[G])
@@ -1422,12 +1420,9 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
             }
             // the error's max-norm, each row folded in as it is formed
             poly_rows<DE, N, G, double, double>(
-                after_all(tb + EOFF, yn[0]), up, y64, [&](int g, int, double re, double im) __attribute__((always_inline)) {
-                    if (t + g * STRIDE < nbt) {
-                        const double e = fmax(fabs(re), fabs(im));
-                        bad |= !(isfinite(re) && isfinite(im));
-                        emax = fmax(emax, e);
-                    }
+                after_all(tb + EOFF, yn[0]), up, y64, [&](int, int, double re, double im) __attribute__((always_inline)) {
+                    emax = fmax(emax, fmax(fabs(re), fabs(im)));
+                    chk = fma(re, 0.0, fma(im, 0.0, chk));
                 });
         }
     };
@@ -1441,24 +1436,25 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
         constexpr int sl = decltype(Sc)::value;
         fetch(t0 + sl * G * STRIDE, ys[sl], us[sl], u64s[sl]);
     });
+    // wave-uniform loop over the passes; a group wholly past the end is skipped
 #pragma unroll 1
-    for (uint32_t t = t0; t < nbt; t += WPT * SPAN) {
+    for (uint32_t tw = sub * SPAN; tw < nbt; tw += WPT * SPAN) {
         static_for<0, NGRP>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
-            const uint32_t ts = t + sl * G * STRIDE;
-            if (sl == 0 || ts < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
+            const uint32_t ts = tw + (uint32_t)lane + sl * G * STRIDE;
+            if (sl == 0 || tw + sl * G * STRIDE < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
             fetch(ts + WPT * SPAN, ys[sl], us[sl], u64s[sl]);
         });
     }
 
-    double e = bad ? (double)INFINITY : emax;
-    e = wave_max(e);
+    double e = (bad || chk != chk) ? (double)INFINITY : emax;
+    e = wave_max_rows(e);
     if (lane == 0) swave[wave] = active ? e : 0.0;
     __syncthreads();
     if (tid == 0) {
         double m = swave[0];
         for (int w = 1; w < NWV; ++w) m = fmax(m, swave[w]);
-        rc.errpart[blk] = m;
+        gview(rc.errpart)[blk] = m;
     }
 }
 
@@ -1512,7 +1508,7 @@ __device__ __forceinline__ void jsum_body(const RunConst& rc)
     PartialRegs<NV, NW> x;
     load_partials<NV, NW>(rc, 0, rc.nblkp, x);
     finish_partials<NV, NW>(rc, 0, rc.nblkp, x, sJ);
-    if ((int)threadIdx.x < NV) rc.jhist[threadIdx.x] = sJ[threadIdx.x];
+    if ((int)threadIdx.x < NV) gview(rc.jhist)[threadIdx.x] = sJ[threadIdx.x];
 }
 template <int NV>
 __global__ void __launch_bounds__(kFinBlock) k_jsum(const LaunchSet ls)
