@@ -57,14 +57,18 @@ struct RunConst {
     const double* wgt;           // [2 ne] g (neutrino slots), -gbar (antineutrino slots)
     const double* flux;          // [2 ne] number flux of the slot's birth flavor in its energy bin
     const double* azi;           // [na][2] cos, sin of each trajectory's azimuth
+    const double* geo;           // [na][4] multi-angle trajectories: u^2, 1 - u^2, u du / np, 0 (u: the
+                                 // emission cosine of the trajectory's bin, du = 1 / nth)
     double* jhist;               // [kMaxStages + 1][nj n n] packed J0, J1 (J2, J3) per stage
     double* partial;             // [2][nj n n][pstride] per-workgroup weighted sums of the last two
                                  // moment launches (launch l uses [l & 1]), value-major
     double* errpart;             // [max(nblk, nblkf)] per-workgroup step-error maxima
-    double* qbuf;                // Runge-Kutta forms: [na][qstride] power moments of the current state
-                                 // (rewritten only when a new state is accepted)
+    double* qbuf;                // Runge-Kutta forms: [na][qstride] power moments of the current state as
+                                 // full complex matrices (rewritten only when a new state is accepted)
     double* dbuf;                // [na][dstride] stage-derivative coefficient matrices of the attempt
     double* gbuf;                // [na][kMaxStages][n] co-rotating frame rates of the attempt's stages
+    double* zbuf;                // [na][8] rotation factors (cos, sin per upper pair) of the stage the
+                                 // last stage launch formed
     void* ftab;                  // [na][fstride bytes] coefficients of the state update and the error
     double* xbuf;                // [2][2n][nb_pad] FP64: psi1 and psi4 of the exponential stepper's
                                  // attempt (else unused)

@@ -136,6 +136,9 @@ __device__ __forceinline__ void wave_sync()
 // with a scalar base and a 32-bit vector offset (every array indexed this way
 // is below 4 GiB).
 template <typename T> using global = __attribute__((address_space(1))) T;
+// A (re, im) pair as one 16-byte value (a plain vector type, so that it can be
+// read and written through any address space).
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
 __device__ __forceinline__ global<T>* uniform_global(T* p)
@@ -256,21 +259,25 @@ __device__ __forceinline__ double stage_radius(const Control& C, int l)
 }
 
 // Geometry of trajectory j at radius r (eq 3.14-3.15, with 1 - (R/r)^2 formed
-// as (r - R)(r + R) / r^2; single angle: c = 1, w = D(r/R) of eq 3.17).
-__device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double r, double& c, double& w)
+// as (r - R)(r + R) / r^2; single angle: c = 1, w = D(r/R) of eq 3.17), and
+// 1 / c.  The per-trajectory constants (u^2, 1 - u^2, u du / np) come from a
+// table, so a reciprocal of r and a reciprocal square root (c = c^2 / c) are
+// all the divisions.
+__device__ __forceinline__ void traj_geometry(const RunConst& rc, int j, double r, double& c, double& w, double& ic)
 {
-    const double x = (rc.r_nu / r) * (rc.r_nu / r);
-    const double y = (r - rc.r_nu) * (r + rc.r_nu) / (r * r);
+    const double ir = 1.0 / r;
+    const double xr = rc.r_nu * ir;
+    const double x = xr * xr;
+    const double y = (r - rc.r_nu) * (r + rc.r_nu) * (ir * ir);
     if (rc.ma) {
-        // trajectory j: emission-angle bin j / np, azimuth bin j % np (the
-        // azimuth bins share the emission-angle weight)
-        const double du = 1.0 / (double)rc.nth;
-        const double u = ((double)(rc.np > 1 ? j / rc.np : j) + 0.5) * du;
-        c = sqrt(fma(1.0 - u * u, y, u * u));
-        w = x * u * du / c;
-        if (rc.np > 1) w /= (double)rc.np;
+        const global<const double>* g = gview(rc.geo) + 4 * (size_t)j;
+        const double q = fma(g[1], y, g[0]);
+        ic = rsqrt(q);
+        c = q * ic;
+        w = x * g[2] * ic;
     } else {
         c = 1.0;
+        ic = 1.0;
         const double s = 1.0 - sqrt(y);
         w = 0.5 * s * s;
     }
@@ -494,6 +501,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 
     __shared__ double swave[kTrajPerBlock][NV];
     __shared__ double serr[kPowerWaves];
+    __shared__ double sq[kTrajPerBlock][NQ * NM];
 
     Control C;
     double m = 0.0;
@@ -622,14 +630,14 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 #pragma unroll
         for (int x = 0; x < NM; ++x) acc[k][x] = row_sum16(acc[k][x]);
 
-    if (active && q == 0) {
-        global<double>* dst = gview(rc.qbuf) + (size_t)j * rc.qstride;
+    // the workgroup's Q (packed) to LDS; stored as full matrices below
+    if (q == 0) {
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const int p = 2 * k + hb;
             if (p < NQ)
 #pragma unroll
-                for (int x = 0; x < NM; ++x) dst[p * NM + x] = acc[k][x];
+                for (int x = 0; x < NM; ++x) sq[jt][p * NM + x] = acc[k][x];
         }
     }
 
@@ -654,7 +662,8 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         for (int v = 0; v < NV; ++v) sl[v] = 0.0;
         if (active) {
             double c, w, f[4];
-            traj_geometry(rc, j, C.r, c, w);
+            double ic;
+            traj_geometry(rc, j, C.r, c, w, ic);
             double cph = 1.0, sph = 0.0;
             if constexpr (NJ == 4) {
                 cph = gview(rc.azi)[2 * (size_t)j];
@@ -679,6 +688,31 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         double s = swave[0][tid];
         for (int w = 1; w < kTrajPerBlock; ++w) s += swave[w][tid];
         gview(rc.partial)[(size_t)tid * rc.pstride + blk] = s;  // buffer 0
+    }
+    // Q_p as full complex matrices (row-major, re/im adjacent: the layout the
+    // stage launches compute with), one 16-byte entry per thread and pass,
+    // consecutive threads on consecutive entries
+    {
+        constexpr int NN = N * N, NC = Shape<N>::NC;
+        constexpr int UNITS = kTrajPerBlock * NQ * NN;
+        for (int u = tid; u < UNITS; u += 64 * kPowerWaves) {
+            const int t = u / (NQ * NN), r = u - t * (NQ * NN);
+            const int p = r / NN, e = r - p * NN;
+            const int a = e / N, b = e - a * N;
+            const double* P = &sq[t][p * NM];
+            double re, im = 0.0;
+            if (a == b) {
+                re = P[a];
+            } else {
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                const int x = N + 2 * Shape<N>::up(lo, hi);
+                re = P[x];
+                im = a < b ? P[x + 1] : -P[x + 1];
+            }
+            const int jj = blk * kTrajPerBlock + t;
+            if (jj < rc.na)
+                *reinterpret_cast<global<d2>*>(gview(rc.qbuf) + (size_t)jj * rc.qstride + p * NC + 2 * e) = d2{re, im};
+        }
     }
 }
 
@@ -732,7 +766,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     constexpr int NIT = (ITEMS + LT - 1) / LT;
     constexpr int NH = L - 1;                            // stored matrices D_0 .. D_{L-2}
     constexpr int NQL = TABLES ? 1 : 2 * L + 1;          // power moments stage L needs
-    constexpr int QV = (NQL * NM + LT - 1) / LT;         // of them per lane
+    constexpr int QU = NQL * NC / 2;                     // their 16-byte (re, im) entries
+    constexpr int QV = (QU + LT - 1) / LT;               // of them per lane
     constexpr int TPB = kTrajPerBlock;
     constexpr int NW = kTrajWaves;
     constexpr int NUA = NU > 0 ? NU : 1;
@@ -779,11 +814,17 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     }
     for (int m = 0; m < NH; ++m)
         for (int a = 0; a < N; ++a) G[m][a] = gview(rc.gbuf)[((size_t)jl * kMaxStages + m) * N + a];
-    double qv[QV];
+    d2 qv[QV];
     {
-        const global<double>* qs = gview(rc.qbuf) + (size_t)jl * rc.qstride;
+        const global<d2>* qs = reinterpret_cast<const global<d2>*>(gview(rc.qbuf) + (size_t)jl * rc.qstride);
 #pragma unroll
-        for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && li + LT * i < NQL * NM) ? qs[li + LT * i] : 0.0;
+        for (int i = 0; i < QV; ++i) qv[i] = (!TABLES && li + LT * i < QU) ? qs[li + LT * i] : d2{0.0, 0.0};
+    }
+    // the rotation factors of stage L-1, stored by the previous launch
+    double zl[2 * NUA];
+    if constexpr (L > 1) {
+#pragma unroll
+        for (int i = 0; i < 2 * NU; ++i) zl[i] = gview(rc.zbuf)[(size_t)jl * 8 + i];
     }
     // the stored coefficient matrices each item needs (in range for every lane)
     double Dh[NIT][NH > 0 ? NH : 1][2];
@@ -819,8 +860,8 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     //      without D_{L-1} (registers), Q to LDS
     const double rP = stage_radius<TAB>(C, L - 1);
     double cP, wP;
-    traj_geometry(rc, jl, rP, cP, wP);
-    const double icP = 1.0 / cP;
+    double icP;
+    traj_geometry(rc, jl, rP, cP, wP, icP);
     double sc = 0.0, ss = 0.0;
     if constexpr (NJ == 4) {
         const double s0 = sqrt((1.0 - cP) * (1.0 + cP));
@@ -828,13 +869,22 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
         ss = s0 * sph;
     }
     double zP[NUA][2];
-    {
+    if constexpr (L == 1) {
         double ph[N];
         stage_phase<TAB, N>(L - 1, h, phn, G, ph);
         rotation<N>(ph, zP, li, gbase);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NU; ++q) {
+            zP[q][0] = zl[2 * q];
+            zP[q][1] = zl[2 * q + 1];
+        }
     }
     double cL = 1.0, wL = 0.0;
-    if constexpr (!TABLES) traj_geometry(rc, jl, stage_radius<TAB>(C, L), cL, wL);
+    if constexpr (!TABLES) {
+        double icL;
+        traj_geometry(rc, jl, stage_radius<TAB>(C, L), cL, wL, icL);
+    }
     // per item: next = C_L without its D_{L-1} term (L < S), or the update
     // (next) and error (nerr) tables without it (L = S), each summed from the
     // identity in ascending m as C_{L-1} is
@@ -878,25 +928,10 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             nerr[it][1] = ei;
         }
         if constexpr (!TABLES) {
-            // packed value x of Q_p into the full matrix: a diagonal entry with a
-            // zero imaginary part, an upper entry and its conjugate below
 #pragma unroll
             for (int i = 0; i < QV; ++i) {
                 const int v = li + LT * i;
-                if (v < NQL * NM) {
-                    const int pp = v / NM, x = v - pp * NM;
-                    double* Qf = &sQ[jt][pp * NC];
-                    if (x < N) {
-                        Qf[2 * (x * N + x)] = qv[i];
-                        Qf[2 * (x * N + x) + 1] = 0.0;
-                    } else {
-                        int a = 0, b = 1;
-                        pair_of<N>((x - N) >> 1, a, b);
-                        const bool im = ((x - N) & 1) != 0;
-                        Qf[2 * (a * N + b) + (im ? 1 : 0)] = qv[i];
-                        Qf[2 * (b * N + a) + (im ? 1 : 0)] = im ? -qv[i] : qv[i];
-                    }
-                }
+                if (v < QU) *reinterpret_cast<d2*>(&sQ[jt][2 * v]) = qv[i];
             }
         }
     }
@@ -1068,6 +1103,16 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             stage_phase<TAB, N>(L, h, phn, G, ph);
             if constexpr (TAB::fsal && L == S - 1) lane_scatter(gview(rc.phase[cur ^ 1]) + (size_t)j * N, ph, li);
             rotation<N>(ph, zL, li, gbase);
+            {
+                // for the next launch, whose stage L-1 this is
+                double zf[2 * NUA];
+#pragma unroll
+                for (int q = 0; q < NU; ++q) {
+                    zf[2 * q] = zL[q][0];
+                    zf[2 * q + 1] = zL[q][1];
+                }
+                lane_scatter<2 * NU>(gview(rc.zbuf) + (size_t)j * 8, zf, li);
+            }
             wave_sync();
 
             // ---- T_d = sum_{d'} Q_{d+d'} C_{L,d'}^+   (item (d, a, b))
@@ -1766,7 +1811,7 @@ PolySizes poly_sizes(int n, int integrator, int precision)
     const int de = integrator == 0 ? -1 : Poly<TabDP54>::DE;
     const int tsz = precision == 1 ? 4 : 8;
     PolySizes p;
-    p.qstride = (nq * nm + 7) / 8 * 8;
+    p.qstride = nq * nc;  // full complex matrices (16-byte entries)
     p.dstride = (nd * nc + 7) / 8 * 8;
     const int cn = ((dn + 1) * nc * tsz + 7) / 8 * 8;
     const int ce = (de + 1) * nc * 8;

@@ -180,7 +180,7 @@ bool build_tables(const nuosc_params& p, Tables& t)
 // ---------------------------------------------------------------- layout
 struct Layout {
     size_t psi[2], phase[2], uinv64, uinv32, wgt, jhist, partial, errpart, qbuf, dbuf, gbuf, ftab, xbuf, flux, azi,
-        ctrl, prob, eavg, rconst, total;
+        geo, zbuf, ctrl, prob, eavg, rconst, total;
     int64_t nb, nb_pad;
     int na, nblk, nblkf, nblkp, pstride;
     int nj;      // angle moments: 2 (bulb model), 4 (extended: azimuth)
@@ -266,10 +266,12 @@ Layout make_layout(const nuosc_params& p)
     L.jhist = take((size_t)(nuosc::kMaxStages + 1) * L.nj * n * n * 8);
     L.partial = take((size_t)2 * L.nj * n * n * L.pstride * 8);  // two launches' partials (alternating)
     L.azi = take((size_t)2 * L.na * 8);
+    L.geo = take((size_t)4 * L.na * 8);
     L.errpart = take((size_t)std::max(L.nblk, L.nblkf) * 8);
     L.qbuf = take((size_t)L.na * L.poly.qstride * 8);
     L.dbuf = take((size_t)L.na * L.poly.dstride * 8);
     L.gbuf = take(rk ? (size_t)L.na * nuosc::kMaxStages * n * 8 : 0);
+    L.zbuf = take(rk ? (size_t)L.na * 8 * 8 : 0);
     L.ftab = take((size_t)L.na * L.poly.fstride);
     L.xbuf = take(p.integrator == NUOSC_EXP_STEPPER ? 2 * 2 * n * (size_t)L.nb_pad * 8 : 0);
     L.ctrl = take(2 * sizeof(Control));
@@ -421,12 +423,14 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
     rc.wgt = (const double*)(base + L.wgt);
     rc.flux = (const double*)(base + L.flux);
     rc.azi = (const double*)(base + L.azi);
+    rc.geo = (const double*)(base + L.geo);
     rc.jhist = (double*)(base + L.jhist);
     rc.partial = (double*)(base + L.partial);
     rc.errpart = (double*)(base + L.errpart);
     rc.qbuf = (double*)(base + L.qbuf);
     rc.dbuf = (double*)(base + L.dbuf);
     rc.gbuf = (double*)(base + L.gbuf);
+    rc.zbuf = (double*)(base + L.zbuf);
     rc.ftab = (void*)(base + L.ftab);
     rc.xbuf = (double*)(base + L.xbuf);
     rc.ctrl = (Control*)(base + L.ctrl);
@@ -456,6 +460,19 @@ nuosc_status init_run(RunState& r, const nuosc_params* p, char* base, RunConst* 
         azi[2 * j + 1] = std::sin(phi);
     }
     HIP_CHECK(hipMemcpyAsync((void*)rc.azi, azi.data(), azi.size() * 8, hipMemcpyHostToDevice, s), err);
+    // per-trajectory constants of the multi-angle geometry (eq 3.14-3.15):
+    // trajectory j in emission-angle bin j / np, cosine u at the bin's midpoint
+    std::vector<double> geo((size_t)4 * rc.na, 0.0);
+    if (rc.ma) {
+        const double du = 1.0 / (double)rc.nth;
+        for (int j = 0; j < rc.na; ++j) {
+            const double u = ((double)(j / rc.np) + 0.5) * du;
+            geo[4 * j] = u * u;
+            geo[4 * j + 1] = 1.0 - u * u;
+            geo[4 * j + 2] = u * du / (double)rc.np;
+        }
+    }
+    HIP_CHECK(hipMemcpyAsync((void*)rc.geo, geo.data(), geo.size() * 8, hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemsetAsync(rc.jhist, 0, (size_t)(nuosc::kMaxStages + 1) * rc.nj * rc.n * rc.n * 8, s), err);
     HIP_CHECK(hipMemcpyAsync(rc.ctrl, two, sizeof(two), hipMemcpyHostToDevice, s), err);
     HIP_CHECK(hipMemcpyAsync(runs_dev + slot, &rc, sizeof(RunConst), hipMemcpyHostToDevice, s), err);
