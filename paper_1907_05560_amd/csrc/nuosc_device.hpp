@@ -98,4 +98,23 @@ __device__ __forceinline__ double wave_max_rows(double x)
     return fmax(fmax(lane_value(x, 0), lane_value(x, 16)), fmax(lane_value(x, 32), lane_value(x, 48)));
 }
 
+// v of the even row (first) and of the odd row (second) of each pair of rows
+// (lanes 32k .. 32k+15 and 32k+16 .. 32k+31), in every lane of the pair: one
+// v_permlane16_swap per 32-bit half, the whole wavefront active.
+__device__ __forceinline__ void row_pair(float v, float& even, float& odd)
+{
+    const unsigned b = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    even = __builtin_bit_cast(float, (unsigned)r[0]);
+    odd = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void row_pair(double v, double& even, double& odd)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    even = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]);
+    odd = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]);
+}
+
 }  // namespace nuosc

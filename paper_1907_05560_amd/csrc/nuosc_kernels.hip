@@ -480,7 +480,11 @@ __device__ __forceinline__ TS load_state(global<const TS>* p)
 // first adds the even powers 2k, the second the odd powers 2k + 1, k < H),
 // 16 energy bins of a trajectory per wavefront iteration: each row of 16 lanes
 // holds one trajectory and one parity of the powers, so that the lanes' sums
-// are row sums (cross-lane moves of the vector ALU).  The first bins are
+// are row sums (cross-lane moves of the vector ALU).  FP64 amplitudes: the
+// even row loads the neutrino beams, the odd row the antineutrino beams, and a
+// row swap gives every lane both (each amplitude loaded once); FP32
+// amplitudes: both rows load both beams (measured faster: half the bytes, and
+// no swaps in the lanes' instruction stream).  The first bins are
 // requested before the step controller has decided, from the buffer an
 // accepted step makes current (a rejected attempt drops them).  Q_0 is the
 // density sum of the state itself: rotated to the lab frame and weighted at
@@ -533,26 +537,36 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     global<const double>* __restrict__ uinv = uniform_global(rc.uinv64);
     global<const double>* __restrict__ wgtp = uniform_global(rc.wgt);
 
-    // energy bin e: both amplitudes, u = 1/E, the two weights.  Unconditional
-    // (a bin past the end reads bin 0 and adds with weight 0), so that the
-    // loop is straight-line code in which each load refills the registers of
-    // its slot: no copies, and no wait for loads still in flight.
-    auto fetch = [&](uint32_t e, TS* yv, TS* zv, double& uv, double& wv, double& wb) __attribute__((always_inline)) {
+    // energy bin e: u = 1/E, and the lane's own beam (the row's species) or
+    // both beams, with their weights.  Unconditional (a bin past the end reads
+    // bin 0 and adds with weight 0), so that the loop is straight-line code in
+    // which each load refills the registers of its slot: no copies, and no
+    // wait for loads still in flight.
+    constexpr bool SWAP = sizeof(TS) == 8;
+    constexpr int NB = SWAP ? 1 : 2;  // beams a lane loads per bin
+    const uint32_t bown = hb ? base1 : base0, wown = hb ? ne : 0u;
+    auto fetch = [&](uint32_t e, TS* vv, double& uv, double* wv) __attribute__((always_inline)) {
         const uint32_t ec = e < ne ? e : 0u;
+        if constexpr (SWAP) {
 #pragma unroll
-        for (int x = 0; x < 2 * N; ++x) yv[x] = load_state(elem(srcq[x], base0 + ec));
+            for (int x = 0; x < 2 * N; ++x) vv[x] = load_state(elem(srcq[x], bown + ec));
+            wv[0] = *elem(wgtp, wown + ec);
+        } else {
 #pragma unroll
-        for (int x = 0; x < 2 * N; ++x) zv[x] = load_state(elem(srcq[x], base1 + ec));
+            for (int x = 0; x < 2 * N; ++x) vv[x] = load_state(elem(srcq[x], base0 + ec));
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) vv[2 * N + x] = load_state(elem(srcq[x], base1 + ec));
+            wv[0] = *elem(wgtp, ec);
+            wv[1] = *elem(wgtp, ne + ec);
+        }
         uv = *elem(uinv, ec);
-        wv = *elem(wgtp, ec);
-        wb = *elem(wgtp, ne + ec);
     };
-    TS ys[NSLOT][2 * N], zs[NSLOT][2 * N];
-    double us[NSLOT], ws[NSLOT], wbs[NSLOT];
+    TS vs[NSLOT][NB * 2 * N];
+    double us[NSLOT], ws[NSLOT][NB];
     const uint32_t e0 = (uint32_t)q;
     static_for<0, NSLOT>([&](auto Sc) {
         constexpr int sl = decltype(Sc)::value;
-        fetch(e0 + sl * STRIDE, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
+        fetch(e0 + sl * STRIDE, vs[sl], us[sl], ws[sl]);
     });
 
     if constexpr (!FORCE) {
@@ -573,7 +587,24 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 #pragma unroll
         for (int x = 0; x < NM; ++x) acc[k][x] = 0.0;
 
-    auto process = [&](uint32_t e, const TS* yv, const TS* zv, double u, double w, double wb) __attribute__((always_inline)) {
+    auto process = [&](uint32_t e, const TS* vv, double u, const double* wv) __attribute__((always_inline)) {
+        // both beams of the bin in every lane (swapped in: the neutrino from
+        // the even row, the antineutrino from the odd row)
+        TS yv[2 * N], zv[2 * N];
+        double w, wb;
+        if constexpr (SWAP) {
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) row_pair(vv[x], yv[x], zv[x]);
+            row_pair(wv[0], w, wb);
+        } else {
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) {
+                yv[x] = vv[x];
+                zv[x] = vv[2 * N + x];
+            }
+            w = wv[0];
+            wb = wv[1];
+        }
         if (!(active && e < ne)) w = wb = 0.0;
         // u^(2k + parity): the odd lanes start at u
         const double u2 = u * u;
@@ -617,8 +648,8 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         static_for<0, NSLOT>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
             const uint32_t es = e + e0 + sl * STRIDE;
-            process(es, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
-            fetch(es + NSLOT * STRIDE, ys[sl], zs[sl], us[sl], ws[sl], wbs[sl]);
+            process(es, vs[sl], us[sl], ws[sl]);
+            fetch(es + NSLOT * STRIDE, vs[sl], us[sl], ws[sl]);
             // keep the refill of this slot ahead of the next slot's work
             __builtin_amdgcn_sched_barrier(0);
         });
@@ -948,7 +979,10 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
     if (li == 0 && !TABLES)
         for (int v = 0; v < NV; ++v) swave[jt][v] = 0.0;
     if (active) {
-        // ---- completion of stage L-1 (the same values in every lane of the group)
+        // ---- completion of stage L-1: the diagonal in every lane of the group
+        //      (the frame rate G_{L-1} enters the phase of stage L), then lane
+        //      li < 2 n^2 forms entry li of N0 = -i h A (li < n^2) or of
+        //      N1 = -i h B (row-major) as one (re, im) pair
         const double lam = matter(rc, rP);
         auto kern = [&](int x) __attribute__((always_inline)) {
             double v = sJ[x] - cP * sJ[NM + x];
@@ -961,50 +995,49 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             Cd[a] = kern(a);
             tr += Cd[a];
         }
-        double adg[N], bdg[N];
+        double hd[N];
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            const double hd = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
-            G[L - 1][a] = (rc.frame == 0) ? hd * icP : 0.0;
-            adg[a] = (rc.frame == 0) ? 0.0 : hd * icP;
-            bdg[a] = rc.vac[a][a][0] * icP;
+            hd[a] = lam * ((a == 0 ? 1.0 : 0.0) - 1.0 / N) + rc.mu0 * (Cd[a] - tr / N);
+            G[L - 1][a] = (rc.frame == 0) ? hd[a] * icP : 0.0;
         }
-        // A_ab and B_ab (a < b), rotated: e^{i(Phi_a - Phi_b)} X_ab / c
-        double axr[NUA], axi[NUA], bxr[NUA], bxi[NUA];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            int a = 0, b = 1;
-            pair_of<N>(u, a, b);
-            const double cs = zP[u][0], sn = zP[u][1];
-            const double cr = rc.mu0 * kern(N + 2 * u) * icP, ci = rc.mu0 * kern(N + 2 * u + 1) * icP;
-            const double vr = rc.vac[a][b][0] * icP, vi = rc.vac[a][b][1] * icP;
-            axr[u] = cs * cr - sn * ci;
-            axi[u] = cs * ci + sn * cr;
-            bxr[u] = cs * vr - sn * vi;
-            bxi[u] = cs * vi + sn * vr;
-        }
-        // value i < 2 NC of N0 = -i h A (i < NC) or N1 = -i h B (row-major,
-        // re/im); -i h X has real part h Im X and imaginary part -h Re X, and the
-        // lower entries follow from X_ba = conj(X_ab)
-#pragma unroll
-        for (int i = li; i < 2 * NC; i += LT) {
-            const int mtx = i / NC, e = (i - mtx * NC) >> 1, part = i & 1;
+        if (li < 2 * NN) {
+            const int mtx = li >= NN ? 1 : 0, e = li - mtx * NN;
             const int a = e / N, b = e - (e / N) * N;
-            double xr = 0.0, xi = 0.0;
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            const int u = a == b ? 0 : Shape<N>::up(lo, hi);
+            // the values of pair u and of diagonal entry a, picked from
+            // registers (wave-uniform tables, lane-dependent index)
+            double cs = zP[0][0], sn = zP[0][1], vr = rc.vac[0][1][0], vi = rc.vac[0][1][1];
 #pragma unroll
-            for (int aa = 0; aa < N; ++aa)
-                if (a == aa && b == aa) xr = mtx == 0 ? adg[aa] : bdg[aa];
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                int lo = 0, hi = 1;
-                pair_of<N>(u, lo, hi);
-                if ((a == lo && b == hi) || (a == hi && b == lo)) {
-                    xr = mtx == 0 ? axr[u] : bxr[u];
-                    xi = mtx == 0 ? axi[u] : bxi[u];
-                    if (a > b) xi = -xi;
+            for (int q = 1; q < NU; ++q) {
+                int qa = 0, qb = 1;
+                pair_of<N>(q, qa, qb);
+                if (u == q) {
+                    cs = zP[q][0];
+                    sn = zP[q][1];
+                    vr = rc.vac[qa][qb][0];
+                    vi = rc.vac[qa][qb][1];
                 }
             }
-            sN[jt][i] = part == 0 ? h * xi : -h * xr;
+            double hda = hd[0], vda = rc.vac[0][0][0];
+#pragma unroll
+            for (int q = 1; q < N; ++q)
+                if (a == q) {
+                    hda = hd[q];
+                    vda = rc.vac[q][q][0];
+                }
+            // off the diagonal: e^{i(Phi_lo - Phi_hi)} X_lo,hi / c, conjugated below
+            const double kr = kern(N + 2 * u), ki = kern(N + 2 * u + 1);
+            const double Xr = mtx == 0 ? rc.mu0 * kr : vr, Xi = mtx == 0 ? rc.mu0 * ki : vi;
+            double xr = (cs * Xr - sn * Xi) * icP, xi = (cs * Xi + sn * Xr) * icP;
+            if (a > b) xi = -xi;
+            if (a == b) {
+                xr = (mtx == 0 ? (rc.frame == 0 ? 0.0 : hda) : vda) * icP;
+                xi = 0.0;
+            }
+            // -i h X: real part h Im X, imaginary part -h Re X
+            *reinterpret_cast<d2*>(&sN[jt][mtx * NC + 2 * e]) = d2{h * xi, -h * xr};
         }
         if (li == 0)
             for (int a = 0; a < N; ++a) gview(rc.gbuf)[((size_t)j * kMaxStages + (L - 1)) * N + a] = G[L - 1][a];
