@@ -867,9 +867,10 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
 #pragma unroll
             for (int m = 0; m < NH; ++m) {
                 const bool have = idx < ITEMS && d <= m + 1;
-                const global<double>* p = dsrc + (have ? (size_t)(PY::doff(m) + d) * NC + 2 * e : 0);
-                Dh[it][m][0] = have ? p[0] : 0.0;
-                Dh[it][m][1] = have ? p[1] : 0.0;
+                // one 16-byte (re, im) read (dbuf rows and entries are 16-byte aligned)
+                const d2 v = *reinterpret_cast<const global<d2>*>(dsrc + (have ? (size_t)(PY::doff(m) + d) * NC + 2 * e : 0));
+                Dh[it][m][0] = have ? v.x : 0.0;
+                Dh[it][m][1] = have ? v.y : 0.0;
             }
         }
     }
@@ -1068,10 +1069,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                 }
                 Dn[it][0] = re;
                 Dn[it][1] = im;
-                if constexpr (!TABLES) {
-                    ddst[(size_t)d * NC + 2 * e] = re;
-                    ddst[(size_t)d * NC + 2 * e + 1] = im;
-                }
+                if constexpr (!TABLES) *reinterpret_cast<global<d2>*>(ddst + (size_t)d * NC + 2 * e) = d2{re, im};
             }
         }
         wave_sync();
@@ -1081,7 +1079,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
             constexpr int DN = PY::DN, DE = PY::DE;
             global<char>* tb = gview(reinterpret_cast<char*>(rc.ftab)) + (size_t)j * rc.fstride;
             global<TF>* cn = reinterpret_cast<global<TF>*>(tb);
-            global<double>* ce = reinterpret_cast<global<double>*>(tb + (((DN + 1) * NC * sizeof(TF) + 7) / 8) * 8);
+            global<double>* ce = reinterpret_cast<global<double>*>(tb + (((DN + 1) * NC * sizeof(TF) + 15) / 16) * 16);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int idx = li + LT * it, d = idx / NN, e = idx - d * NN;
@@ -1103,8 +1101,7 @@ __device__ __forceinline__ void traj_body(const RunConst& rc, const int blk)
                                 re = fma(TAB::E[S - 1], Dn[it][0], re);
                                 im = fma(TAB::E[S - 1], Dn[it][1], im);
                             }
-                            ce[(a * (DE + 1) + d) * 2 * N + 2 * b] = re;
-                            ce[(a * (DE + 1) + d) * 2 * N + 2 * b + 1] = im;
+                            *reinterpret_cast<global<d2>*>(ce + (a * (DE + 1) + d) * 2 * N + 2 * b) = d2{re, im};
                         }
                     }
                 }
@@ -1396,7 +1393,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
     constexpr int G = 2;       // beams of a lane sharing each coefficient load
     constexpr int NGRP = std::is_same<T, float>::value ? 2 : 1;  // groups of a lane in flight
     constexpr uint32_t STRIDE = 64;
-    constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 7) / 8) * 8;  // byte offset of the error table
+    constexpr int EOFF = (((DN + 1) * NC * (int)sizeof(T) + 15) / 16) * 16;  // byte offset of the error table
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1471,7 +1468,7 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
                 T nn = 0;
 #pragma unroll
                 for (int x = 0; x < 2 * N; ++x) nn = fma(yn[g][x], yn[g][x], nn);
-                const T sc = T(1) / sqrt(nn);
+                const T sc = rsqrt(nn);  // renormalisation: a 1-ulp reciprocal square root suffices
 #pragma unroll
                 for (int x = 0; x < 2 * N; ++x) yn[g][x] = yn[g][x] * sc;
             }
@@ -1846,7 +1843,7 @@ PolySizes poly_sizes(int n, int integrator, int precision)
     PolySizes p;
     p.qstride = nq * nc;  // full complex matrices (16-byte entries)
     p.dstride = (nd * nc + 7) / 8 * 8;
-    const int cn = ((dn + 1) * nc * tsz + 7) / 8 * 8;
+    const int cn = ((dn + 1) * nc * tsz + 15) / 16 * 16;  // the error table starts 16-byte aligned
     const int ce = (de + 1) * nc * 8;
     p.fstride = (cn + ce + 255) / 256 * 256;
     return p;
