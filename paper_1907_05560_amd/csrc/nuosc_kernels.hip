@@ -506,15 +506,18 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
     __shared__ double swave[kTrajPerBlock][NV];
     __shared__ double serr[kPowerWaves];
     __shared__ double sq[kTrajPerBlock][NQ * NM];
+    __shared__ double sjz[kTrajPerBlock][2 * (NU > 0 ? NU : 1)];  // J_0 partial: rotation factors
+    __shared__ double sjf[kTrajPerBlock][4];                      // and angle weights
 
     Control C;
     double m = 0.0;
     if constexpr (FORCE) {
         C = gload(rc.ctrl + 1);
     } else {
+        // the control block and the error maxima requested together
         C = gload(rc.ctrl);
-        if (C.status != 0) return;  // the attempt did not run
         for (int p = tid; p < rc.nblkf; p += 64 * kPowerWaves) m = fmax(m, gview(rc.errpart)[p]);
+        if (C.status != 0) return;  // the attempt did not run
     }
     // an accepted attempt makes the other buffer current
     const int cur = FORCE ? C.cur : (C.cur ^ 1);
@@ -579,6 +582,36 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         C.fresh = accepted ? 1 : 0;
         if (blk == 0 && tid == 0) gstore(rc.ctrl + 1, C);
         if (!accepted) return;
+    }
+
+    // for the J_0 partial of the new state, before the beam loop (kept in LDS,
+    // not in registers): the rotation factors of both trajectories of the
+    // wavefront and the angle weights at the state's radius
+    {
+        double ph[N], zz[2][NU > 0 ? NU : 1][2];
+        for (int gg = 0; gg < 2; ++gg) {
+            const int jj = blk * kTrajPerBlock + 2 * wave + gg;
+            for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? gview(rc.phase[cur])[(size_t)jj * N + a] : 0.0;
+            rotation<N>(ph, zz[gg], lane, 0);
+        }
+        if ((lane & 31) == 0) {
+            for (int u = 0; u < NU; ++u) {
+                sjz[jt][2 * u] = g ? zz[1][u][0] : zz[0][u][0];
+                sjz[jt][2 * u + 1] = g ? zz[1][u][1] : zz[0][u][1];
+            }
+            double f[4] = {0.0, 0.0, 0.0, 0.0};
+            if (active) {
+                double c, w, ic;
+                traj_geometry(rc, j, C.r, c, w, ic);
+                double cph = 1.0, sph = 0.0;
+                if constexpr (NJ == 4) {
+                    cph = gview(rc.azi)[2 * (size_t)j];
+                    sph = gview(rc.azi)[2 * (size_t)j + 1];
+                }
+                angle_weights<NJ>(rc, c, w, cph, sph, f);
+            }
+            for (int m2 = 0; m2 < NJ; ++m2) sjf[jt][m2] = f[m2];
+        }
     }
 
     double acc[H][NM];
@@ -672,39 +705,18 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         }
     }
 
-    // the J_0 partial: Q_0 (lane 32 g) rotated to the lab frame and weighted;
-    // the rotation factors of both trajectories of the wavefront first
-    double z[NU > 0 ? NU : 1][2];
-    {
-        double ph[N], zz[2][NU > 0 ? NU : 1][2];
-        for (int gg = 0; gg < 2; ++gg) {
-            const int jj = blk * kTrajPerBlock + 2 * wave + gg;
-            for (int a = 0; a < N; ++a) ph[a] = jj < rc.na ? gview(rc.phase[cur])[(size_t)jj * N + a] : 0.0;
-            rotation<N>(ph, zz[gg], lane, 0);
-        }
-        for (int u = 0; u < NU; ++u) {
-            z[u][0] = g ? zz[1][u][0] : zz[0][u][0];
-            z[u][1] = g ? zz[1][u][1] : zz[0][u][1];
-        }
-    }
+    // the J_0 partial: Q_0 (lane 32 g) rotated to the lab frame and weighted
     if ((lane & 31) == 0) {
         double sl[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) sl[v] = 0.0;
         if (active) {
-            double c, w, f[4];
-            double ic;
-            traj_geometry(rc, j, C.r, c, w, ic);
-            double cph = 1.0, sph = 0.0;
-            if constexpr (NJ == 4) {
-                cph = gview(rc.azi)[2 * (size_t)j];
-                sph = gview(rc.azi)[2 * (size_t)j + 1];
-            }
-            angle_weights<NJ>(rc, c, w, cph, sph, f);
+            double f[4];
+            for (int m2 = 0; m2 < NJ; ++m2) f[m2] = sjf[jt][m2];
             double Sv[NM];
             for (int a = 0; a < N; ++a) Sv[a] = 2.0 * acc[0][a];
             for (int u = 0; u < NU; ++u) {
-                const double cs = z[u][0], sn = z[u][1];
+                const double cs = sjz[jt][2 * u], sn = sjz[jt][2 * u + 1];
                 const double xr = acc[0][N + 2 * u], xi = acc[0][N + 2 * u + 1];
                 Sv[N + 2 * u] = 2.0 * (cs * xr + sn * xi);
                 Sv[N + 2 * u + 1] = 2.0 * (cs * xi - sn * xr);
