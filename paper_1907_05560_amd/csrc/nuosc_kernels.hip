@@ -1460,21 +1460,24 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
             if constexpr (ERROR && !std::is_same<T, double>::value) u64v[g] = *elem(uinv64, tc);
         }
     };
-    auto process = [&](uint32_t t, const TS (&yv)[G][2 * N], const T (&u)[G], const double (&u64v)[G])
+    // the first GC of the group's G beams (GC = 1: a group whose second beam
+    // slot lies wholly past the end)
+    auto process = [&](auto GC, uint32_t t, const TS (&yv)[G][2 * N], const T (&u)[G], const double (&u64v)[G])
                        __attribute__((always_inline)) {
-        T y[G][2 * N], yn[G][2 * N];
+        constexpr int GG = decltype(GC)::value;
+        T y[GG][2 * N], yn[GG][2 * N];
         {
-            T up[G][DN + 1];
+            T up[GG][DN + 1];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < GG; ++g) {
 #pragma unroll
                 for (int x = 0; x < 2 * N; ++x) y[g][x] = (T)yv[g][x];
                 powers<DN>(u[g], up[g]);
             }
-            poly_apply<DN, N, G, T, T>(tb, up, y, yn);
+            poly_apply<DN, N, GG, T, T>(tb, up, y, yn);
         }
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GG; ++g) {
             if constexpr (std::is_same<TS, float>::value) {
                 // FP32 amplitudes are renormalised whenever a new state is formed
                 T nn = 0;
@@ -1497,16 +1500,16 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
             }
         }
         if constexpr (ERROR) {
-            double y64[G][2 * N], up[G][DE + 1];
+            double y64[GG][2 * N], up[GG][DE + 1];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < GG; ++g) {
 #pragma unroll
                 for (int x = 0; x < 2 * N; ++x) y64[g][x] = (double)yv[g][x];
                 if constexpr (std::is_same<T, double>::value) powers<DE>((double)u[g], up[g]);
                 else powers<DE>(u64v[g], up[g]);
             }
             // the error's max-norm, each row folded in as it is formed
-            poly_rows<DE, N, G, double, double>(
+            poly_rows<DE, N, GG, double, double>(
                 after_all(tb + EOFF, yn[0]), up, y64, [&](int, int, double re, double im) __attribute__((always_inline)) {
                     emax = fmax(emax, fmax(fabs(re), fabs(im)));
                     chk = fma(re, 0.0, fma(im, 0.0, chk));
@@ -1523,13 +1526,18 @@ __device__ __forceinline__ void final_body(const RunConst& rc, const int blk)
         constexpr int sl = decltype(Sc)::value;
         fetch(t0 + sl * G * STRIDE, ys[sl], us[sl], u64s[sl]);
     });
-    // wave-uniform loop over the passes; a group wholly past the end is skipped
+    // wave-uniform loop over the passes; a group wholly past the end is
+    // skipped, one whose later beam slots are is formed for its first only
 #pragma unroll 1
     for (uint32_t tw = sub * SPAN; tw < nbt; tw += WPT * SPAN) {
         static_for<0, NGRP>([&](auto Sc) {
             constexpr int sl = decltype(Sc)::value;
             const uint32_t ts = tw + (uint32_t)lane + sl * G * STRIDE;
-            if (sl == 0 || tw + sl * G * STRIDE < nbt) process(ts, ys[sl], us[sl], u64s[sl]);
+            const uint32_t gs = tw + sl * G * STRIDE;  // first beam slot of the group (wave-uniform)
+            if (gs + (G - 1) * STRIDE < nbt)
+                process(std::integral_constant<int, G>{}, ts, ys[sl], us[sl], u64s[sl]);
+            else if (gs < nbt)
+                process(std::integral_constant<int, 1>{}, ts, ys[sl], us[sl], u64s[sl]);
             fetch(ts + WPT * SPAN, ys[sl], us[sl], u64s[sl]);
         });
     }
