@@ -54,18 +54,10 @@ namespace {
 constexpr int kExpTraj = kExpTrajPerBlock;  // trajectories (wavefronts) per workgroup
 constexpr int kExpBlock = 64 * kExpTraj;
 
-__device__ __forceinline__ double xwave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-__device__ __forceinline__ double xwave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
+// wavefront sums and maxima: the DPP row reductions of nuosc_device.hpp
+// (cross-lane moves of the vector ALU, no LDS permutes)
+__device__ __forceinline__ double xwave_sum(double v) { return wave_sum_rows(v); }
+__device__ __forceinline__ double xwave_max(double v) { return wave_max_rows(v); }
 
 // Geometry of trajectory j at radius r (eq 3.14-3.15; single angle: c = 1,
 // w = D(r/R) of eq 3.17); the same formulas as the Runge-Kutta stage kernels.
