@@ -64,3 +64,12 @@ def test_kernel_names_of_the_three_forms():
     assert bench.kernel_names(1)[0] == "k_traj<3,DP54,2,1,double>"
     assert bench.kernel_names(1)[6] == "k_traj<3,DP54,2,7,float>"
     assert bench.kernel_names(2)[8] == "k_power<float,3,DP54,2,false>"
+
+
+def test_power_moment_flops_pair_the_species():
+    # per energy bin: both densities (24 flops each for three flavors), their
+    # even and odd combinations (5 n^2), the 13 powers and 13 n^2 FMAs; half
+    # of that per beam
+    f = _form(1)
+    assert bench.beam_model(f, 8)[1] / NB == (2 * 24 + 5 * 9 + 13 + 2 * 13 * 9) / 2 == 170
+    assert bench.beam_model(f, 8)[0] == 6 * 4 * NB
