@@ -405,8 +405,8 @@ __device__ bool control_step(const RunConst& rc, Control& C, double m)
 // ------------------------------------------------------------------ partial sums
 // Sum of the value-major partials of buffer `par` (nblk workgroups) by the NW
 // wavefronts of a workgroup: value v by wavefront v mod NW, lane l adding
-// partials l, l + 64, ... in order, then a butterfly whose lane-0 result is
-// kept (one fixed order).  Every workgroup running this gets the same bits.
+// partials l, l + 64, ... in order, then the row sums (DPP) and the four rows
+// added in one fixed order.  Every workgroup running this gets the same bits.
 // Split in two so that the loads of the first 256 partials are in flight while
 // independent work runs.
 template <int NV, int NW>
@@ -470,7 +470,8 @@ __device__ __forceinline__ TS load_state(global<const TS>* p)
 // launch's error maxima and runs the controller in every workgroup (the same
 // result everywhere; workgroup 0 stores the control block); a rejected attempt
 // ends here.  Then, for the current state y (the accepted new state):
-//   Q_p[j] = sum_k w_k u_k^p y y^+,  p = 0 .. NQ-1  (packed Hermitian, FP64).
+//   Q_p[j] = sum_k w_k u_k^p y y^+,  p = 0 .. NQ-1  (FP64, stored as full
+//   complex matrices).
 // The neutrino and the antineutrino beam of one energy bin have u = 1/E and
 // u = -1/E, so the antineutrino's u^p is (-1)^p u^p and one energy bin adds
 //   u^p (w y y^+ + (-1)^p wbar ybar ybar^+)
@@ -761,7 +762,7 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
 
 // ------------------------------------------------------------------ per-trajectory stages
 // Launch L of an attempt.  A group of kTrajLanes lanes works on one trajectory
-// (four per wavefront, kTrajPerBlock per workgroup), its lanes on items (d, e):
+// (two per wavefront, kTrajPerBlock per workgroup), its lanes on items (d, e):
 // coefficient degree d and matrix entry e = (a, b) of a full complex n x n
 // matrix.
 //   1. J_{L-1}: the fixed-order sum of the previous launch's partials (L = 1:
