@@ -177,12 +177,19 @@ nuosc_status nuosc_create_static(const nuosc_params* p, void* hip_stream, nuosc_
  * (nullable) receives the number accepted by this call.  Returns
  * NUOSC_E_NONFINITE / NUOSC_E_STEP_UNDERFLOW when the run stopped on that
  * condition (state left at the last accepted step) and NUOSC_E_LIMIT when
- * max_steps was reached.  Synchronises the stream before returning. */
+ * max_steps was reached.  Synchronises the stream before returning.
+ * Attempts in groups of 32 replay a HIP graph of 32 attempts, captured on the
+ * run's stream at the first such call and owned by the handle (released by
+ * nuosc_destroy); the rest, and every attempt while kernel timing is on, on
+ * a run made by nuosc_create_static or on a stream that cannot be captured,
+ * are launched directly.  The same holds for nuosc_evolve.  Not to be called
+ * while the stream is being captured (it synchronises). */
 nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted);
 
 /* Queue n_attempts step attempts on the stream without waiting and without
- * reading back any status (for timing loops and graph replay).  The status
- * is picked up by the next nuosc_step / nuosc_stats call. */
+ * reading back any status (for timing loops and graph replay): launched
+ * directly, so that a caller may capture them.  The status is picked up by
+ * the next nuosc_step / nuosc_stats call. */
 nuosc_status nuosc_enqueue_steps(nuosc_handle* h, int64_t n_attempts);
 
 /* Queue one launch of the current attempt: stage in 1..S with

@@ -528,6 +528,9 @@ struct nuosc_handle {
     // device memory the library's static array of that device
     bool is_static = false;
     int device = -1;
+    // kGraphAttempts attempts of the run, captured on first use by the
+    // synchronous step calls (the run's constants are fixed at creation)
+    hipGraphExec_t graph = nullptr;
 };
 
 namespace {
@@ -600,6 +603,40 @@ nuosc_status enqueue(nuosc_handle* h, int64_t n)
             if (s != NUOSC_OK) return s;
         }
     return NUOSC_OK;
+}
+
+// Attempts of the synchronous step calls: replays of a graph of
+// kGraphAttempts attempts (one launch call instead of S + 2 per attempt, which
+// bounds small runs), the rest launched directly.  Direct launches throughout
+// while timing (events around each launch), for handles in the library's
+// static memory (nothing is instantiated on their behalf) and on a stream that
+// cannot be captured.
+constexpr int64_t kGraphAttempts = 32;
+
+nuosc_status enqueue_sync(nuosc_handle* h, int64_t n)
+{
+    if (h->timing || h->is_static || n < kGraphAttempts) return enqueue(h, n);
+    if (!h->graph) {
+        if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();  // (the null stream, for one, cannot be captured)
+            return enqueue(h, n);
+        }
+        const nuosc_status s = enqueue(h, kGraphAttempts);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (s != NUOSC_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return s != NUOSC_OK ? s : fail(h, NUOSC_E_DEVICE, hip_msg(e, "capture of the attempts"));
+        }
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(h, NUOSC_E_DEVICE, hip_msg(ei, "hipGraphInstantiate"));
+        h->graph = x;
+    }
+    int64_t i = 0;
+    for (; i + kGraphAttempts <= n; i += kGraphAttempts) HIP_CHECK(hipGraphLaunch(h->graph, h->stream), h->err);
+    return enqueue(h, n - i);
 }
 
 nuosc_status hread(nuosc_handle* h) { return read_control(h->run, h->stream, h->err); }
@@ -772,7 +809,7 @@ nuosc_status nuosc_step(nuosc_handle* h, int64_t n_attempts, int64_t* n_accepted
     nuosc_status st = hread(h);
     if (st != NUOSC_OK) return st;
     const int64_t before = h->run.hctl.nacc;
-    st = enqueue(h, n_attempts);
+    st = enqueue_sync(h, n_attempts);
     if (st != NUOSC_OK) return st;
     st = hread(h);
     if (st != NUOSC_OK) return st;
@@ -800,7 +837,7 @@ nuosc_status nuosc_evolve(nuosc_handle* h, double r_target_km)
     const auto t0 = std::chrono::steady_clock::now();
     int64_t batch = 8;
     for (;;) {
-        st = enqueue(h, batch);
+        st = enqueue_sync(h, batch);
         if (st != NUOSC_OK) return st;
         st = hread(h);
         if (st != NUOSC_OK) return st;
@@ -1146,6 +1183,7 @@ void nuosc_destroy(nuosc_handle* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (auto& x : h->ev)
         if (x) (void)hipEventDestroy(x);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
