@@ -162,21 +162,25 @@ template <typename T>
 __device__ __forceinline__ T gload(const T* p)
 {
     static_assert(sizeof(T) % 8 == 0, "8-byte words");
-    T v;
-    uint64_t* d = reinterpret_cast<uint64_t*>(&v);
+    constexpr int NW = (int)(sizeof(T) / 8);
+    uint64_t w[NW];
     const global<const uint64_t>* s = reinterpret_cast<const global<const uint64_t>*>(reinterpret_cast<uint64_t>(p));
 #pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+    for (int i = 0; i < NW; ++i) w[i] = s[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
     return v;
 }
 template <typename T>
 __device__ __forceinline__ void gstore(T* p, const T& v)
 {
     static_assert(sizeof(T) % 8 == 0, "8-byte words");
-    const uint64_t* s = reinterpret_cast<const uint64_t*>(&v);
+    constexpr int NW = (int)(sizeof(T) / 8);
+    uint64_t w[NW];
+    __builtin_memcpy(w, &v, sizeof(T));
     global<uint64_t>* d = reinterpret_cast<global<uint64_t>*>(reinterpret_cast<uint64_t>(p));
 #pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) d[i] = s[i];
+    for (int i = 0; i < NW; ++i) d[i] = w[i];
 }
 
 // Lane k < NV stores v[k] to dst[k]: NV values that every lane of the
