@@ -606,6 +606,19 @@ def main() -> int:
         del a, b
     form_list = args.forms.split(",")
     order = [FORM_NAMES[f] for f in form_list]
+    # The accuracy windows run first, so that the timed forms do not start on
+    # a GPU that has been idle since the process began (measured: a 20-attempt
+    # window timed right after creation and 5 warm-up attempts runs about 8%
+    # slower than the same window after 0.3 s of load; short windows still
+    # read a few percent above the long-run attempt time, as the run's
+    # creation leaves the GPU idle again for a moment).
+    acc = None
+    if not args.no_accuracy and 0 in order:
+        say(f"accuracy windows {W.ACCURACY_WINDOWS} km on the 400x4000 grid")
+        acc = accuracy(nuosc, W, form_list)
+        for e in acc:
+            say(f"window {e['window_km']}: fp64 {e['fp64_accepted']} steps, P moves {e['max_dP_over_window']:.3e}; "
+                + ", ".join(f"{k} max {v['max']:.3e} rms {v['rms']:.3e}" for k, v in e["forms"].items()))
     forms = {}
     averages = {}
     for name, prec in zip(form_list, order):
@@ -650,12 +663,8 @@ def main() -> int:
         "energy_average": averages,
         "host": host_info(),
     }
-    if not args.no_accuracy and 0 in order:
-        say(f"accuracy windows {W.ACCURACY_WINDOWS} km on the 400x4000 grid")
-        line["accuracy"] = accuracy(nuosc, W, form_list)
-        for e in line["accuracy"]:
-            say(f"window {e['window_km']}: fp64 {e['fp64_accepted']} steps, P moves {e['max_dP_over_window']:.3e}; "
-                + ", ".join(f"{k} max {v['max']:.3e} rms {v['rms']:.3e}" for k, v in e["forms"].items()))
+    if acc is not None:
+        line["accuracy"] = acc
     if args.small_attempts > 0:
         say("small workloads (2f single-angle RK4 run, 200x1000 FP64 window) and their oracle times")
         line["small_workloads"] = small_configs(nuosc, W, torch, args.small_attempts)
