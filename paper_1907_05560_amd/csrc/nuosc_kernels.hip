@@ -486,10 +486,11 @@ __device__ __forceinline__ TS load_state(global<const TS>* p)
 // 16 energy bins of a trajectory per wavefront iteration: each row of 16 lanes
 // holds one trajectory and one parity of the powers, so that the lanes' sums
 // are row sums (cross-lane moves of the vector ALU).  FP64 amplitudes: the
-// even row loads the neutrino beams, the odd row the antineutrino beams, and a
-// row swap gives every lane both (each amplitude loaded once); FP32
-// amplitudes: both rows load both beams (measured faster: half the bytes, and
-// no swaps in the lanes' instruction stream).  The first bins are
+// even row loads the neutrino beams, the odd row the antineutrino beams (each
+// amplitude loaded once), each row forms its own beam's weighted density and
+// a row swap gives every lane both densities; FP32 amplitudes: both rows load
+// both beams and form both densities (measured faster for them: half the
+// bytes, and no swaps in the lanes' instruction stream).  The first bins are
 // requested before the step controller has decided, from the buffer an
 // accepted step makes current (a rejected attempt drops them).  Q_0 is the
 // density sum of the state itself: rotated to the lab frame and weighted at
@@ -626,59 +627,74 @@ __device__ __forceinline__ void power_body(const RunConst& rc, const int blk)
         for (int x = 0; x < NM; ++x) acc[k][x] = 0.0;
 
     auto process = [&](uint32_t e, const TS* vv, double u, const double* wv) __attribute__((always_inline)) {
-        // both beams of the bin in every lane (swapped in: the neutrino from
-        // the even row, the antineutrino from the odd row)
-        TS yv[2 * N], zv[2 * N];
-        double w, wb;
-        if constexpr (SWAP) {
-#pragma unroll
-            for (int x = 0; x < 2 * N; ++x) row_pair(vv[x], yv[x], zv[x]);
-            row_pair(wv[0], w, wb);
-        } else {
-#pragma unroll
-            for (int x = 0; x < 2 * N; ++x) {
-                yv[x] = vv[x];
-                zv[x] = vv[2 * N + x];
-            }
-            w = wv[0];
-            wb = wv[1];
-        }
-        if (!(active && e < ne)) w = wb = 0.0;
         // u^(2k + parity): the odd lanes start at u
         const double u2 = u * u;
         double pw[H];
         pw[0] = hb ? u : 1.0;
 #pragma unroll
         for (int k = 1; k < H; ++k) pw[k] = pw[k - 1] * u2;
-        // X = w y y^+ + s z z^+ with s = (-1)^parity wbar, entry by entry
-        const double s = hb ? -wb : wb;
-        double y[2 * N], z[2 * N];
-#pragma unroll
-        for (int x = 0; x < 2 * N; ++x) {
-            y[x] = (double)yv[x];
-            z[x] = (double)zv[x];
-        }
         auto add = [&](int x, double v) __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < H; ++k) acc[k][x] = fma(v, pw[k], acc[k][x]);
         };
-        // Re and Im of v_a conj(v_b)
-        auto re = [&](const double* v, int a, int b) __attribute__((always_inline)) {
-            return fma(v[2 * a], v[2 * b], v[2 * a + 1] * v[2 * b + 1]);
+        // Re and Im of v_a conj(t_b)
+        auto re = [&](const double* v, const double* t, int a, int b) __attribute__((always_inline)) {
+            return fma(v[2 * a], t[2 * b], v[2 * a + 1] * t[2 * b + 1]);
         };
-        auto im = [&](const double* v, int a, int b) __attribute__((always_inline)) {
-            return fma(v[2 * a + 1], v[2 * b], -(v[2 * a] * v[2 * b + 1]));
+        auto im = [&](const double* v, const double* t, int a, int b) __attribute__((always_inline)) {
+            return fma(v[2 * a + 1], t[2 * b], -(v[2 * a] * t[2 * b + 1]));
         };
+        if constexpr (SWAP) {
+            // each row forms its own beam's weighted density (w y y^+ in the
+            // even row, wbar z z^+ in the odd one); a row swap gives both in
+            // every lane, combined with the sign (-1)^parity
+            double ww = wv[0];
+            if (!(active && e < ne)) ww = 0.0;
+            double y[2 * N], yw[2 * N];
 #pragma unroll
-        for (int a = 0; a < N; ++a) add(a, fma(w, re(y, a, a), s * re(z, a, a)));
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = a + 1; b < N; ++b) {
-                const int x = N + 2 * Shape<N>::up(a, b);
-                add(x, fma(w, re(y, a, b), s * re(z, a, b)));
-                add(x + 1, fma(w, im(y, a, b), s * im(z, a, b)));
+            for (int x = 0; x < 2 * N; ++x) {
+                y[x] = (double)vv[x];
+                yw[x] = ww * y[x];
             }
+            const double sg = hb ? -1.0 : 1.0;
+            auto put = [&](int x, double own) __attribute__((always_inline)) {
+                double ev, od;
+                row_pair(own, ev, od);
+                add(x, fma(sg, od, ev));
+            };
+#pragma unroll
+            for (int a = 0; a < N; ++a) put(a, re(yw, y, a, a));
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = a + 1; b < N; ++b) {
+                    const int x = N + 2 * Shape<N>::up(a, b);
+                    put(x, re(yw, y, a, b));
+                    put(x + 1, im(yw, y, a, b));
+                }
+        } else {
+            // both beams in every lane: X = w y y^+ + s z z^+ with
+            // s = (-1)^parity wbar, entry by entry
+            double w = wv[0], wb = wv[1];
+            if (!(active && e < ne)) w = wb = 0.0;
+            const double s = hb ? -wb : wb;
+            double y[2 * N], z[2 * N];
+#pragma unroll
+            for (int x = 0; x < 2 * N; ++x) {
+                y[x] = (double)vv[x];
+                z[x] = (double)vv[2 * N + x];
+            }
+#pragma unroll
+            for (int a = 0; a < N; ++a) add(a, fma(w, re(y, y, a, a), s * re(z, z, a, a)));
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = a + 1; b < N; ++b) {
+                    const int x = N + 2 * Shape<N>::up(a, b);
+                    add(x, fma(w, re(y, y, a, b), s * re(z, z, a, b)));
+                    add(x + 1, fma(w, im(y, y, a, b), s * im(z, z, a, b)));
+                }
+        }
     };
 
 #pragma unroll 1
