@@ -73,3 +73,14 @@ def test_power_moment_flops_pair_the_species():
     f = _form(1)
     assert bench.beam_model(f, 8)[1] / NB == (2 * 24 + 5 * 9 + 13 + 2 * 13 * 9) / 2 == 170
     assert bench.beam_model(f, 8)[0] == 6 * 4 * NB
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    # the timed path runs on one GPU; asking for more exits before any device work
+    import subprocess, sys, os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert not r.stdout.strip().startswith("{")
